@@ -1,0 +1,165 @@
+"""Benchmark: full non-hydrostatic time steps (FV + pressure solve) on one GPU.
+
+Workload (default): the 512 x 512 island basin, FP64 -- seeded bathymetry of
+depth 2-20 m with a dry island, Gaussian hump of 0.5 m, walls, CFL 0.9,
+relaxed-Jacobi solve with a 64-sweep Chebyshev/Leja schedule, tolerance 1e-10
+on the plain-Jacobi update size.  Inputs are synthetic (seeded generators).
+
+A step is one full TVD-RK2 step: two finite-volume stages, two pressure
+assemblies, two solves and two corrections, plus the CFL reduction.  The
+timed region starts from the workload's initial state already resident in
+device memory (the warmup runs first and the state is then reset).
+
+Prints one JSON line with the metric, the roofline of the dominant kernel
+(the relaxation sweep) and the CPU oracle's rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
+ALG_BYTES_SWEEP = {"f64": 40, "f32": 20}   # per corner per sweep (matrix-free
+                                           # minimum: r p, h, H, rhs; w p)
+
+
+def alg_bytes_per_cell_step(kbar: float, prec: str) -> float:
+    """Compulsory bytes per cell-step with ideal stencil reuse:
+    flux stages 56 + 88, assembly 2 x 48, corrections 2 x 72, sweeps
+    2 x Kbar x 40 (FP64); FP32 bulk halves every term."""
+    b = 384.0 + 80.0 * kbar
+    return b if prec == "f64" else b / 2.0
+
+
+def workload(name: str, prec: str):
+    from paper_1706_04551_amd import inputs
+    if name == "c2":
+        c = inputs.case_c2(precision=prec)
+        desc = (f"island basin 512x512 dx=1m, depth 2-20 m + dry island, "
+                f"hump 0.5 m, walls, {prec.upper()}, Jacobi+SRJ(64) "
+                f"tol={c.solve_tol:g}")
+        return c, desc
+    if name == "c3":
+        c = inputs.case_c3()
+        return c, "plane beach 2048x2048 dx=0.05m, solitary wave A=0.3, breaking, FP32"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(case, steps: int):
+    """The FP64 oracle as it stands, single-threaded, on the first `steps`
+    steps of the same workload."""
+    from oracle.oracle import Oracle, Params
+    kw = case.param_dict()
+    o = Oracle(Params(**kw))
+    o.set_bathymetry(case.H)
+    o.set_state(case.h, case.hu, case.hv)
+    t0 = time.perf_counter()
+    st = o.run(steps)
+    t = time.perf_counter() - t0
+    if st != 0:
+        return None
+    s = o.stats()
+    value = case.nx * case.ny * steps / t / 1e6
+    return {"value": round(value, 4), "unit": "Mcell-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"first {steps} steps of the same workload "
+                       f"({case.nx}x{case.ny}, FP64 oracle, "
+                       f"{s['sweeps_total'] / max(1, s['solves']):.0f} sweeps/solve), "
+                       f"{t:.1f} s")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the time step of one "
+              "grid on one device); --gpus must be 1", file=sys.stderr)
+        raise SystemExit(2)
+
+    import torch
+    from paper_1706_04551_amd import Solver
+
+    assert torch.cuda.is_available(), "no HIP device visible"
+    torch.cuda.set_device(0)
+    case, desc = workload(args.workload, args.precision)
+    stream = torch.cuda.current_stream()
+    s = Solver.from_case(case, stream=stream.cuda_stream)
+    ncell = case.nx * case.ny
+
+    # warmup, then reset to the initial state (uploads are outside the timing)
+    s.run(args.warmup)
+    s.set_state(case.h, case.hu, case.hv)
+    torch.cuda.synchronize()
+    s.profile(True)
+    t0 = time.perf_counter()
+    s.run(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = s.stats()
+    pr = s.get_profile()
+    s.profile(False)
+
+    kbar = st["sweeps_total"] / max(1, st["solves"])
+    value = ncell * args.steps / elapsed / 1e6
+    ms_step = elapsed * 1e3 / args.steps
+    ncorn = (case.nx + 1) * (case.ny + 1)
+
+    # roofline of the dominant kernel: the relaxation sweep
+    sweep_ms = pr["sweep_kernel_ms"] / max(1, pr["sweep_kernel_launches"])
+    alg = ALG_BYTES_SWEEP[args.precision] * ncorn
+    achieved = alg / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else None
+    roof = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+            "traffic": None,
+            "kernel": "k_sweep", "avg_launch_us": round(sweep_ms * 1e3, 3),
+            "alg_bytes_per_launch": alg}
+    full_step_bytes = alg_bytes_per_cell_step(kbar, args.precision) * ncell
+    step_roof_frac = full_step_bytes / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(case, args.cpu_steps)
+
+    out = {
+        "metric": "Mcell-steps/s per full step (flux+pressure solve), % HBM roofline, vs FP64 plain",
+        "value": round(value, 3),
+        "unit": "Mcell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": desc, "cells": ncell, "steps": args.steps,
+                   "mean_sweeps_per_solve": round(kbar, 2),
+                   "full_step_hbm_roofline_frac": round(step_roof_frac, 4),
+                   "phase_ms": {k: round(pr[k], 2) for k in
+                                ("fv_ms", "assemble_ms", "solve_ms",
+                                 "correct_ms")}},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+/*
+ * nhswe.h -- C ABI of the MI355X (gfx950) time stepper for the
+ * depth-integrated non-hydrostatic shallow-water system solved by the
+ * projection-correction scheme of Escalante, Morales de Luna & Castro
+ * (arXiv 1706.04551).
+ *
+ * One call of nh_step advances the state by one second-order TVD Runge-Kutta
+ * step (Section 4.3 / Section 6: the projection-correction stage run twice and
+ * averaged).  Each stage runs, on the device:
+ *   - the second-order well-balanced PVM path-conservative finite-volume
+ *     update of (h, hu, hv) with MUSCL-minmod reconstruction, desingularised
+ *     velocities and the wet-dry treatment (Sections 4.1, 4.5, 5, eq. 16-22,30);
+ *   - optionally the breaking terms of the eddy viscosity (Section 3, eq. 9-12);
+ *   - the compact finite-difference non-hydrostatic pressure system at the
+ *     cell corners: assembly (eq. 28-29, 37-41, 43), solve (Thomas in 1D,
+ *     scheduled-relaxation Jacobi in 2D, eq. 32) and the correction of the
+ *     discharges and of the vertical velocity w (eq. 26-28, 36, 41);
+ * and the next time step comes from the CFL condition (eq. 23), reduced on the
+ * device.
+ *
+ * Grid and layout.  nx x ny cells of size dx x dy; ny == 1 selects the 1D
+ * channel of Section 4.  Host arrays passed through this interface are FP64,
+ * row-major, x fastest:
+ *   cells   [ny][nx]                  h, hu, hv, H (still-water depth, > 0 in
+ *                                     water, <= 0 on dry land)
+ *   corners [ny+1][nx+1] (1D: [nx+1]) w (depth-averaged vertical velocity),
+ *                                     p (non-hydrostatic bottom pressure)
+ * Corner (k, l) sits at x = k dx, y = l dy.  Walls bound the domain on every
+ * side.
+ *
+ * Ownership.  The solver owns its device buffers.  Host arrays are always
+ * owned by the caller and are copied in (set_*) or out (read_state); the
+ * state stays in device memory between steps.
+ *
+ * Errors.  Every call returns an nh_status; no exception crosses the ABI.
+ * nh_last_error() returns a thread-local message for the last failing call.
+ * A step that fails (non-finite state) leaves the solver in NH_ESTATE until
+ * the next nh_set_state.
+ *
+ * Threading.  A solver is bound to one HIP stream and is not thread-safe;
+ * different solvers may be used from different threads.
+ */
+#ifndef NHSWE_H
+#define NHSWE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NH_OK = 0,
+  NH_EINVAL = -1,      /* bad argument (sizes, parameters, null pointer) */
+  NH_ENOMEM = -2,      /* device allocation failed */
+  NH_EDEVICE = -3,     /* HIP runtime error */
+  NH_ENOCONV = -4,     /* pressure solve reached solve_max_iter */
+  NH_ENONFINITE = -5,  /* NaN or Inf in the state after a step */
+  NH_ENEGDEPTH = -6,   /* negative depth passed to nh_set_state */
+  NH_ESTATE = -8       /* solver not ready (no state / failed earlier) */
+} nh_status;
+
+enum { NH_FP64 = 0, NH_FP32 = 1 };
+
+typedef struct nh_solver nh_solver;
+
+typedef struct {
+  int32_t nx, ny; /* cells; ny == 1: 1D channel */
+  double dx, dy;  /* cell sizes [m] (dy ignored in 1D) */
+} nh_grid;
+
+typedef struct {
+  double g;            /* gravity [m/s^2] */
+  double cfl;          /* CFL number of eq. (23), 0 < cfl <= 1 */
+  double delta;        /* desingularisation depth of Section 4.5 (1e-5) */
+  double dry_eps;      /* h <= dry_eps is dry (1e-10 FP64, 1e-5 FP32) */
+  int32_t precision;   /* NH_FP64, or NH_FP32: bulk state and stencils in
+                          FP32; solver residuals, convergence measure and
+                          dt in FP64 */
+  int32_t nh_on;       /* 0: hydrostatic shallow water only */
+  int32_t breaking_on; /* eddy-viscosity breaking terms (Section 3) */
+  double b1, b2;       /* breaking coefficients of eq. (9) */
+  int32_t solve_max_iter; /* cap on relaxation sweeps per solve (2D) */
+  int32_t check_every;    /* convergence measure every this many sweeps; a
+                             multiple of n_omega */
+  double solve_tol;    /* stop when max_c |(rhs - A p)_c / diag_c| < tol, the
+                          size of a plain Jacobi update (eq. 32) */
+  const double *omega_schedule; /* relaxation factors applied cyclically,
+                                   copied at create; NULL => {1.0} */
+  int32_t n_omega;
+  int32_t fixed_dt;    /* 1: every step uses dt below instead of the CFL */
+  double dt;
+} nh_params;
+
+typedef struct {
+  double t;             /* simulated time */
+  double dt_next;       /* dt the next step will use */
+  double dt_last;       /* dt of the last step */
+  int64_t step;         /* steps taken since nh_set_state */
+  int32_t sweeps[2];    /* relaxation sweeps of the two stages of the last
+                           step */
+  double measure;       /* convergence measure at the end of the last solve */
+  int64_t sweeps_total; /* sweeps since nh_set_state */
+  int64_t solves_total; /* pressure solves since nh_set_state */
+  double clamped_mass;  /* mass added by the positivity clamp [m^3] */
+  int32_t last_status;
+} nh_stats;
+
+/* Per-phase device time (ms) accumulated between events on the solver's
+ * stream while profiling is on (nh_profile). */
+typedef struct {
+  double fv_ms;        /* finite-volume stages */
+  double assemble_ms;  /* breaking + assembly of the pressure system */
+  double solve_ms;     /* whole solves, including host convergence checks */
+  double correct_ms;   /* corrections, RK average and dt reduction */
+  int64_t fv_launches, assemble_launches, solve_launches, correct_launches;
+  double sweep_kernel_ms;  /* back-to-back relaxation-sweep launches only */
+  int64_t sweep_kernel_launches;
+} nh_profile_t;
+
+/* Create a solver for the grid and parameters on `hip_stream` (a hipStream_t;
+ * NULL = the solver creates its own).  Allocates all device memory. */
+nh_status nh_create(const nh_grid *grid, const nh_params *params,
+                    void *hip_stream, nh_solver **out);
+
+/* Bathymetry H, cells [ny][nx] (host, FP64). */
+nh_status nh_set_bathymetry(nh_solver *s, const double *H);
+
+/* State: h, hu, hv cells (hv ignored in 1D, may be NULL = 0), w and p corners
+ * (NULL = 0; p is the warm start of the first solve).  Resets t, step and
+ * statistics and computes the first dt.  h must be >= 0 (NH_ENEGDEPTH). */
+nh_status nh_set_state(nh_solver *s, const double *h, const double *hu,
+                       const double *hv, const double *w, const double *p);
+
+/* One time step.  dt_used (nullable) receives the step's dt. */
+nh_status nh_step(nh_solver *s, double *dt_used);
+
+/* nsteps time steps; stops at the first failing step. */
+nh_status nh_run(nh_solver *s, int64_t nsteps);
+
+/* Copy the state to the host (each pointer nullable). */
+nh_status nh_read_state(nh_solver *s, double *h, double *hu, double *hv,
+                        double *w, double *p);
+
+nh_status nh_get_stats(const nh_solver *s, nh_stats *out);
+
+/* Turn per-phase event timing on (1) or off (0); turning it on clears the
+ * accumulated times. */
+nh_status nh_profile(nh_solver *s, int32_t on);
+nh_status nh_get_profile(nh_solver *s, nh_profile_t *out);
+
+void nh_destroy(nh_solver *s);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *nh_last_error(void);
+
+/* Library version string. */
+const char *nh_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NHSWE_H */

@@ -1,0 +1,214 @@
+"""ctypes binding of libnhswe.so (include/nhswe.h): argument marshalling only.
+
+Every step of the time stepper runs in the library's HIP kernels; this module
+converts numpy arrays to host pointers and back.  It raises if the library has
+not been built (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libnhswe.so")
+
+NH_FP64, NH_FP32 = 0, 1
+STATUS = {0: "NH_OK", -1: "NH_EINVAL", -2: "NH_ENOMEM", -3: "NH_EDEVICE",
+          -4: "NH_ENOCONV", -5: "NH_ENONFINITE", -6: "NH_ENEGDEPTH",
+          -8: "NH_ESTATE"}
+
+_DP = C.POINTER(C.c_double)
+
+
+class NhGrid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("dx", C.c_double),
+                ("dy", C.c_double)]
+
+
+class NhParams(C.Structure):
+    _fields_ = [("g", C.c_double), ("cfl", C.c_double),
+                ("delta", C.c_double), ("dry_eps", C.c_double),
+                ("precision", C.c_int32), ("nh_on", C.c_int32),
+                ("breaking_on", C.c_int32), ("b1", C.c_double),
+                ("b2", C.c_double), ("solve_max_iter", C.c_int32),
+                ("check_every", C.c_int32), ("solve_tol", C.c_double),
+                ("omega_schedule", _DP), ("n_omega", C.c_int32),
+                ("fixed_dt", C.c_int32), ("dt", C.c_double)]
+
+
+class NhStats(C.Structure):
+    _fields_ = [("t", C.c_double), ("dt_next", C.c_double),
+                ("dt_last", C.c_double), ("step", C.c_int64),
+                ("sweeps", C.c_int32 * 2), ("measure", C.c_double),
+                ("sweeps_total", C.c_int64), ("solves_total", C.c_int64),
+                ("clamped_mass", C.c_double), ("last_status", C.c_int32)]
+
+
+class NhProfile(C.Structure):
+    _fields_ = [("fv_ms", C.c_double), ("assemble_ms", C.c_double),
+                ("solve_ms", C.c_double), ("correct_ms", C.c_double),
+                ("fv_launches", C.c_int64), ("assemble_launches", C.c_int64),
+                ("solve_launches", C.c_int64),
+                ("correct_launches", C.c_int64),
+                ("sweep_kernel_ms", C.c_double),
+                ("sweep_kernel_launches", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libnhswe.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.nh_create.argtypes = [C.POINTER(NhGrid), C.POINTER(NhParams), vp,
+                                C.POINTER(vp)]
+        L.nh_set_bathymetry.argtypes = [vp, _DP]
+        L.nh_set_state.argtypes = [vp, _DP, _DP, _DP, _DP, _DP]
+        L.nh_step.argtypes = [vp, _DP]
+        L.nh_run.argtypes = [vp, C.c_int64]
+        L.nh_read_state.argtypes = [vp, _DP, _DP, _DP, _DP, _DP]
+        L.nh_get_stats.argtypes = [vp, C.POINTER(NhStats)]
+        L.nh_profile.argtypes = [vp, C.c_int32]
+        L.nh_get_profile.argtypes = [vp, C.POINTER(NhProfile)]
+        L.nh_destroy.argtypes = [vp]
+        L.nh_destroy.restype = None
+        L.nh_last_error.restype = C.c_char_p
+        L.nh_version.restype = C.c_char_p
+        for f in ("nh_create", "nh_set_bathymetry", "nh_set_state", "nh_step",
+                  "nh_run", "nh_read_state", "nh_get_stats", "nh_profile",
+                  "nh_get_profile"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class NhError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = lib().nh_last_error().decode()
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({msg})")
+        self.status = status
+
+
+def _check(st, where):
+    if st != 0:
+        raise NhError(st, where)
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_DP)
+
+
+def _f64(a, shape):
+    if a is None:
+        return None
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(shape))
+
+
+class Solver:
+    """One grid on one HIP stream (see include/nhswe.h)."""
+
+    def __init__(self, nx, ny, dx, dy, *, g=9.81, cfl=0.9, delta=1e-5,
+                 dry_eps=1e-10, precision="f64", nh_on=1, breaking_on=0,
+                 b1=0.15, b2=0.5, solve_max_iter=200000, check_every=1,
+                 solve_tol=1e-10, omega=None, fixed_dt=0, dt_fixed=0.0,
+                 stream=None):
+        self.nx, self.ny = int(nx), int(ny)
+        self.is1d = self.ny == 1
+        self.cshape = (self.nx + 1,) if self.is1d else (self.ny + 1,
+                                                         self.nx + 1)
+        self._omega = None if omega is None else np.ascontiguousarray(
+            np.asarray(omega, dtype=np.float64).ravel())
+        grid = NhGrid(self.nx, self.ny, float(dx), float(dy))
+        prec = {"f64": NH_FP64, "f32": NH_FP32}[precision]
+        par = NhParams(g, cfl, delta, dry_eps, prec, nh_on, breaking_on, b1,
+                       b2, solve_max_iter, check_every, solve_tol,
+                       _ptr(self._omega),
+                       0 if self._omega is None else len(self._omega),
+                       fixed_dt, dt_fixed)
+        h = C.c_void_p()
+        st = lib().nh_create(C.byref(grid), C.byref(par),
+                             C.c_void_p(stream) if stream else None,
+                             C.byref(h))
+        _check(st, "nh_create")
+        self._h = h
+
+    @classmethod
+    def from_case(cls, case, **over):
+        kw = case.param_dict()
+        kw.pop("nx"), kw.pop("ny"), kw.pop("dx"), kw.pop("dy")
+        kw["precision"] = case.precision
+        kw.update(over)
+        s = cls(case.nx, case.ny, case.dx, case.dy, **kw)
+        s.set_bathymetry(case.H)
+        s.set_state(case.h, case.hu, case.hv)
+        return s
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nh_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    @property
+    def shape(self):
+        return (self.ny, self.nx)
+
+    def set_bathymetry(self, H):
+        H = _f64(H, self.shape)
+        _check(lib().nh_set_bathymetry(self._h, _ptr(H)), "nh_set_bathymetry")
+
+    def set_state(self, h, hu, hv=None, w=None, p=None):
+        h, hu = _f64(h, self.shape), _f64(hu, self.shape)
+        hv = _f64(hv, self.shape)
+        w, p = _f64(w, self.cshape), _f64(p, self.cshape)
+        _check(lib().nh_set_state(self._h, _ptr(h), _ptr(hu), _ptr(hv),
+                                  _ptr(w), _ptr(p)), "nh_set_state")
+
+    def step(self) -> float:
+        dt = C.c_double(0.0)
+        _check(lib().nh_step(self._h, C.byref(dt)), "nh_step")
+        return dt.value
+
+    def run(self, n: int):
+        _check(lib().nh_run(self._h, int(n)), "nh_run")
+
+    def run_status(self, n: int) -> int:
+        return lib().nh_run(self._h, int(n))
+
+    def state(self):
+        out = {k: np.zeros(self.shape) for k in ("h", "hu", "hv")}
+        out["w"] = np.zeros(self.cshape)
+        out["p"] = np.zeros(self.cshape)
+        _check(lib().nh_read_state(self._h, _ptr(out["h"]), _ptr(out["hu"]),
+                                   _ptr(out["hv"]), _ptr(out["w"]),
+                                   _ptr(out["p"])), "nh_read_state")
+        return out
+
+    def stats(self) -> dict:
+        s = NhStats()
+        _check(lib().nh_get_stats(self._h, C.byref(s)), "nh_get_stats")
+        return dict(t=s.t, dt=s.dt_next, dt_last=s.dt_last, step=s.step,
+                    sweeps1=s.sweeps[0], sweeps2=s.sweeps[1],
+                    measure=s.measure, sweeps_total=s.sweeps_total,
+                    solves=s.solves_total, clamped=s.clamped_mass,
+                    status=s.last_status)
+
+    def profile(self, on: bool = True):
+        _check(lib().nh_profile(self._h, 1 if on else 0), "nh_profile")
+
+    def get_profile(self) -> dict:
+        p = NhProfile()
+        _check(lib().nh_get_profile(self._h, C.byref(p)), "nh_get_profile")
+        return {k: getattr(p, k) for k, _ in NhProfile._fields_}

@@ -1,0 +1,702 @@
+// kernels.hpp -- gfx950 device code of the non-hydrostatic shallow-water step
+// (Escalante, Morales de Luna & Castro, arXiv 1706.04551).
+//
+// All kernels are templated on the storage/arithmetic type T of the bulk
+// state (double, or float for the FP32-bulk mode).  The pressure solve always
+// evaluates residuals, updates and its convergence measure in FP64.
+//
+// Layout: structure of arrays, row-major, x fastest.  Cells [ny][nx],
+// corners [ny+1][nx+1] (1D: [nx+1]).  There are no ghost cells in memory:
+// walls are applied by mirrored indexing (ghost -1 <-> cell 0, -2 <-> 1, the
+// discharge normal to the wall changes sign, everything else is even).
+//
+// Every formula is evaluated in the same operation order as the plain
+// statement of the scheme, so that FP64 results agree with a sequential
+// evaluation to rounding.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nh {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ int mirror(int i, int n) {
+  return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i);
+}
+
+template <typename T>
+__device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+template <typename T>
+__device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
+
+// minmod limiter of the MUSCL reconstruction (Section 4.1)
+template <typename T>
+__device__ __forceinline__ T minmod(T a, T b) {
+  if (a > T(0) && b > T(0)) return tmin(a, b);
+  if (a < T(0) && b < T(0)) return tmax(a, b);
+  return T(0);
+}
+
+// desingularised velocity u = sqrt(2) h q / sqrt(h^4 + max(h^4, delta^4))
+// (Section 4.5); also used for the division of the corner update by h_c.
+template <typename T>
+__device__ __forceinline__ T desing(T h, T q, T delta) {
+  T h4 = h * h * h * h;
+  T d4 = delta * delta * delta * delta;
+  return sqrt(T(2)) * h * q / sqrt(h4 + tmax(h4, d4));
+}
+
+// cell state with wall mirroring
+template <typename T>
+struct Cell {
+  T h, q1, q2, H;
+};
+
+template <typename T>
+__device__ __forceinline__ Cell<T> load_cell(const T* __restrict__ h,
+                                             const T* __restrict__ q1,
+                                             const T* __restrict__ q2,
+                                             const T* __restrict__ H, int i,
+                                             int j, int nx, int ny,
+                                             bool one_d) {
+  int mi = mirror(i, nx);
+  int mj = one_d ? 0 : mirror(j, ny);
+  int idx = mj * nx + mi;
+  Cell<T> c;
+  c.h = h[idx];
+  c.H = H[idx];
+  c.q1 = q1[idx];
+  c.q2 = one_d ? T(0) : q2[idx];
+  if (mi != i) c.q1 = -c.q1;
+  if (mj != j) c.q2 = -c.q2;
+  return c;
+}
+
+// reconstructed state at one side of an edge, in edge-normal coordinates
+template <typename T>
+struct Face {
+  T h, qn, qt, un, ut, eta, H;
+};
+
+// primitive values of a cell along a direction: n = normal discharge index
+template <typename T>
+struct Prim {
+  T h, un, ut, eta;
+};
+
+template <typename T>
+__device__ __forceinline__ Prim<T> prim(const Cell<T>& c, bool xdir, T delta,
+                                        bool one_d) {
+  Prim<T> p;
+  p.h = c.h;
+  T u = desing(c.h, c.q1, delta);
+  T v = one_d ? T(0) : desing(c.h, c.q2, delta);
+  p.un = xdir ? u : v;
+  p.ut = xdir ? v : u;
+  p.eta = c.h - c.H;
+  return p;
+}
+
+// MUSCL-minmod reconstruction of the middle cell c from its neighbours m, p:
+// L = value at its minus-side edge, R = value at its plus-side edge.  Slopes
+// of eta and of the velocities vanish next to a dry cell (Section 4.1, 4.5).
+template <typename T>
+__device__ __forceinline__ void reconstruct(const Prim<T>& m, const Prim<T>& c,
+                                            const Prim<T>& p, T dry_eps,
+                                            Face<T>& L, Face<T>& R) {
+  T sh = minmod(p.h - c.h, c.h - m.h);
+  T se = T(0), su = T(0), sv = T(0);
+  if (m.h > dry_eps && c.h > dry_eps && p.h > dry_eps) {
+    se = minmod(p.eta - c.eta, c.eta - m.eta);
+    su = minmod(p.un - c.un, c.un - m.un);
+    sv = minmod(p.ut - c.ut, c.ut - m.ut);
+  }
+  R.h = c.h + T(0.5) * sh;
+  L.h = c.h - T(0.5) * sh;
+  R.eta = c.eta + T(0.5) * se;
+  L.eta = c.eta - T(0.5) * se;
+  R.un = c.un + T(0.5) * su;
+  L.un = c.un - T(0.5) * su;
+  R.ut = c.ut + T(0.5) * sv;
+  L.ut = c.ut - T(0.5) * sv;
+  R.qn = R.h * R.un;
+  L.qn = L.h * L.un;
+  R.qt = R.h * R.ut;
+  L.qt = L.h * L.ut;
+  R.H = R.h - R.eta;
+  L.H = L.h - L.eta;
+}
+
+// PVM fluctuations of eq. (18)-(19) with the A* matrix, HLL speeds and the
+// emerging-bottom rule (Section 4.5).  Dm goes to the left cell, Dp to the
+// right one; components (h, normal, tangential).
+template <typename T>
+__device__ __forceinline__ void pvm(const Face<T>& L, const Face<T>& R, T g,
+                                    T dry_eps, T Dm[3], T Dp[3]) {
+  Dm[0] = Dm[1] = Dm[2] = T(0);
+  Dp[0] = Dp[1] = Dp[2] = T(0);
+  if (L.h <= dry_eps && R.h <= dry_eps) return;
+  T he = T(0.5) * (L.h + R.h);
+  T sL = sqrt(L.h), sR = sqrt(R.h);
+  T ue = (L.un * sL + R.un * sR) / (sL + sR);
+  T ce = sqrt(g * he);
+  T SL = tmin(ue - ce, L.un - sqrt(g * L.h));
+  T SR = tmax(ue + ce, R.un + sqrt(g * R.h));
+  if (!(SR - SL > T(0))) return;
+  T a0 = (SR * fabs(SL) - SL * fabs(SR)) / (SR - SL);
+  T a1 = (fabs(SR) - fabs(SL)) / (SR - SL);
+  T deta = R.eta - L.eta;
+  if (R.h <= dry_eps && L.eta < -R.H) deta = T(0);
+  if (L.h <= dry_eps && R.eta < -L.H) deta = T(0);
+  T Rv[3], dU[3];
+  Rv[0] = R.qn - L.qn;
+  Rv[1] = (R.qn * R.un - L.qn * L.un) + g * he * deta;
+  Rv[2] = R.qn * R.ut - L.qn * L.ut;
+  dU[0] = deta;
+  dU[1] = R.qn - L.qn;
+  dU[2] = R.qt - L.qt;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    Dm[m] = T(0.5) * ((T(1) - a1) * Rv[m] - a0 * dU[m]);
+    Dp[m] = T(0.5) * ((T(1) + a1) * Rv[m] + a0 * dU[m]);
+  }
+}
+
+// volume term of eq. (22) in its mid-point form (eq. 30): the hydrostatic
+// part 1/2 g (h-^2 - h+^2) - g h_i (H- - H+) equals g h_i (eta- - eta+) for
+// the linear reconstruction; exact for the lake at rest.
+template <typename T>
+__device__ __forceinline__ void interior(const Face<T>& L, const Face<T>& R,
+                                         T h0, T g, T I[3]) {
+  I[0] = R.qn - L.qn;
+  I[1] = (R.qn * R.un - L.qn * L.un) + g * h0 * (R.eta - L.eta);
+  I[2] = R.qn * R.ut - L.qn * L.ut;
+}
+
+// -------------------------------------------------------------------------
+// reductions of non-negative doubles: wavefront shuffle + LDS tree, then one
+// 64-bit atomic max on the bit pattern (monotone for non-negative doubles)
+// -------------------------------------------------------------------------
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    double o = __shfl_xor(v, off, 64);
+    v = (o > v || o != o) ? o : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ void block_max_to(double v,
+                                             unsigned long long* dst) {
+  __shared__ double part[kBlock / 64];
+  v = wave_max(v);
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) part[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = part[0];
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k)
+      m = (part[k] > m || part[k] != part[k]) ? part[k] : m;
+    if (m > 0.0 || m != m)
+      atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double part[kBlock / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) part[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += part[k];
+  return s;
+}
+
+// -------------------------------------------------------------------------
+// finite-volume stage: U* = V - dt (fluctuations + volume terms), eq. (20),
+// (30); positivity clamp and dry discharge.
+// -------------------------------------------------------------------------
+template <typename T, bool ONE_D>
+__global__ void __launch_bounds__(kBlock)
+    k_fv(int nx, int ny, T dx, T dy, T g, T delta, T dry_eps,
+         const T* __restrict__ h, const T* __restrict__ q1,
+         const T* __restrict__ q2, const T* __restrict__ H,
+         const double* __restrict__ dtp, T* __restrict__ oh,
+         T* __restrict__ oq1, T* __restrict__ oq2, double* clamped) {
+  int n = blockIdx.x * blockDim.x + threadIdx.x;
+  int ncell = nx * ny;
+  double clamp_local = 0.0;
+  if (n < ncell) {
+    int i = n % nx, j = n / nx;
+    T dt = (T)(*dtp);
+    Prim<T> P[5];
+    Cell<T> c0;
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+      Cell<T> c = load_cell(h, q1, q2, H, i - 2 + s, j, nx, ny, ONE_D);
+      if (s == 2) c0 = c;
+      P[s] = prim(c, true, delta, ONE_D);
+    }
+    Face<T> Lm, Rm, L0, R0, Lp, Rp;
+    reconstruct(P[0], P[1], P[2], dry_eps, Lm, Rm);
+    reconstruct(P[1], P[2], P[3], dry_eps, L0, R0);
+    reconstruct(P[2], P[3], P[4], dry_eps, Lp, Rp);
+    T Dm_e[3], Dp_e[3], Dm_w[3], Dp_w[3], I[3];
+    pvm(R0, Lp, g, dry_eps, Dm_e, Dp_e);
+    pvm(Rm, L0, g, dry_eps, Dm_w, Dp_w);
+    interior(L0, R0, c0.h, g, I);
+    T fx[3], fy[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int m = 0; m < 3; ++m) fx[m] = (Dm_e[m] + Dp_w[m]) + I[m];
+    if (!ONE_D) {
+#pragma unroll
+      for (int s = 0; s < 5; ++s) {
+        Cell<T> c = load_cell(h, q1, q2, H, i, j - 2 + s, nx, ny, false);
+        P[s] = prim(c, false, delta, false);
+      }
+      reconstruct(P[0], P[1], P[2], dry_eps, Lm, Rm);
+      reconstruct(P[1], P[2], P[3], dry_eps, L0, R0);
+      reconstruct(P[2], P[3], P[4], dry_eps, Lp, Rp);
+      pvm(R0, Lp, g, dry_eps, Dm_e, Dp_e);
+      pvm(Rm, L0, g, dry_eps, Dm_w, Dp_w);
+      interior(L0, R0, c0.h, g, I);
+#pragma unroll
+      for (int m = 0; m < 3; ++m) fy[m] = (Dm_e[m] + Dp_w[m]) + I[m];
+    }
+    T hs, a, b;
+    if (ONE_D) {
+      hs = c0.h - dt * (fx[0] / dx);
+      a = c0.q1 - dt * (fx[1] / dx);
+      b = T(0);
+    } else {
+      hs = c0.h - dt * (fx[0] / dx + fy[0] / dy);
+      a = c0.q1 - dt * (fx[1] / dx + fy[2] / dy);
+      b = c0.q2 - dt * (fx[2] / dx + fy[1] / dy);
+    }
+    if (hs < T(0)) {
+      clamp_local = -(double)hs * (double)dx * (ONE_D ? 1.0 : (double)dy);
+      hs = T(0);
+    }
+    if (hs <= dry_eps) {
+      a = T(0);
+      b = T(0);
+    }
+    oh[n] = hs;
+    oq1[n] = a;
+    if (!ONE_D) oq2[n] = b;
+  }
+  double s = block_sum(clamp_local);
+  if (threadIdx.x == 0 && s > 0.0) atomicAdd(clamped, s);
+}
+
+// -------------------------------------------------------------------------
+// breaking terms (Section 3): nu = max(0, 1 - div q / U1) h |div q|,
+// U1 = B1 sqrt(g h); q += dt 2 nu (div u) grad H; rw = 2 nu div u at cells.
+// -------------------------------------------------------------------------
+template <typename T, bool ONE_D>
+__global__ void __launch_bounds__(kBlock)
+    k_break_cells(int nx, int ny, T dx, T dy, T g, T delta, T dry_eps, T b1,
+                  const T* __restrict__ h, const T* __restrict__ q1,
+                  const T* __restrict__ q2, const T* __restrict__ H,
+                  const double* __restrict__ dtp, T* __restrict__ oq1,
+                  T* __restrict__ oq2, T* __restrict__ rw) {
+  int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nx * ny) return;
+  int i = n % nx, j = n / nx;
+  T dt = (T)(*dtp);
+  Cell<T> e = load_cell(h, q1, q2, H, i + 1, j, nx, ny, ONE_D);
+  Cell<T> w = load_cell(h, q1, q2, H, i - 1, j, nx, ny, ONE_D);
+  T divq = (e.q1 - w.q1) / (T(2) * dx);
+  T divu = (desing(e.h, e.q1, delta) - desing(w.h, w.q1, delta)) / (T(2) * dx);
+  T Hx = (e.H - w.H) / (T(2) * dx);
+  T Hy = T(0);
+  if (!ONE_D) {
+    Cell<T> nn = load_cell(h, q1, q2, H, i, j + 1, nx, ny, false);
+    Cell<T> ss = load_cell(h, q1, q2, H, i, j - 1, nx, ny, false);
+    divq += (nn.q2 - ss.q2) / (T(2) * dy);
+    divu += (desing(nn.h, nn.q2, delta) - desing(ss.h, ss.q2, delta)) /
+            (T(2) * dy);
+    Hy = (nn.H - ss.H) / (T(2) * dy);
+  }
+  T hc = h[n];
+  T nu = T(0);
+  if (hc > dry_eps) {
+    T U1 = b1 * sqrt(g * hc);
+    T B = T(1) - divq / U1;
+    if (B > T(0)) nu = B * hc * fabs(divq);
+  }
+  T r = T(2) * nu * divu;
+  rw[n] = r;
+  oq1[n] = q1[n] + dt * r * Hx;
+  if (!ONE_D) oq2[n] = q2[n] + dt * r * Hy;
+}
+
+template <typename T, bool ONE_D>
+__global__ void __launch_bounds__(kBlock)
+    k_break_corners(int nx, int ny, T delta, const T* __restrict__ h,
+                    const T* __restrict__ rw, const double* __restrict__ dtp,
+                    const T* __restrict__ w_in, T* __restrict__ w_out) {
+  int ncx = nx + 1, ncy = ONE_D ? 1 : ny + 1;
+  int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= ncx * ncy) return;
+  int k = n % ncx, l = n / ncx;
+  T dt = (T)(*dtp);
+  T hc, rwc;
+  if (ONE_D) {
+    int W = mirror(k - 1, nx), E = mirror(k, nx);
+    hc = T(0.5) * (h[W] + h[E]);
+    rwc = T(0.5) * (rw[W] + rw[E]);
+  } else {
+    int im = mirror(k - 1, nx), ip = mirror(k, nx);
+    int jm = mirror(l - 1, ny), jp = mirror(l, ny);
+    int SW = jm * nx + im, SE = jm * nx + ip, NW = jp * nx + im,
+        NE = jp * nx + ip;
+    hc = T(0.25) * (h[SW] + h[SE] + h[NW] + h[NE]);
+    rwc = T(0.25) * (rw[SW] + rw[SE] + rw[NW] + rw[NE]);
+  }
+  w_out[n] = w_in[n] + dt * desing(hc, rwc, delta);
+}
+
+// -------------------------------------------------------------------------
+// pressure system, 2D: closed-form 5-point coefficients at every corner.
+// zeta = h - 2H, X = (zeta_{i+1} - zeta_{i-1})/2, Y alike; pair averages
+// over the east/west/north/south cells of the corner; walls folded.
+// -------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T zeta_at(const T* __restrict__ h,
+                                     const T* __restrict__ H, int i, int j,
+                                     int nx, int ny) {
+  int idx = mirror(j, ny) * nx + mirror(i, nx);
+  return h[idx] - T(2) * H[idx];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_assemble2d(int nx, int ny, T dx, T dy, const T* __restrict__ h,
+                 const T* __restrict__ q1, const T* __restrict__ q2,
+                 const T* __restrict__ H, const T* __restrict__ w,
+                 const double* __restrict__ dtp, T* __restrict__ diag,
+                 T* __restrict__ cE, T* __restrict__ cW, T* __restrict__ cN,
+                 T* __restrict__ cS, T* __restrict__ rhs) {
+  int ncx = nx + 1, ncy = ny + 1;
+  int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= ncx * ncy) return;
+  int k = n % ncx, l = n / ncx;
+  T dt = (T)(*dtp);
+  const int ci[4] = {k - 1, k, k - 1, k};  // SW, SE, NW, NE
+  const int cj[4] = {l - 1, l - 1, l, l};
+  T hh[4], zz[4], XX[4], YY[4], a1[4], a2[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    Cell<T> c = load_cell(h, q1, q2, H, ci[s], cj[s], nx, ny, false);
+    hh[s] = c.h;
+    a1[s] = c.q1;
+    a2[s] = c.q2;
+    zz[s] = c.h - T(2) * c.H;
+    XX[s] = (zeta_at(h, H, ci[s] + 1, cj[s], nx, ny) -
+             zeta_at(h, H, ci[s] - 1, cj[s], nx, ny)) / T(2);
+    YY[s] = (zeta_at(h, H, ci[s], cj[s] + 1, nx, ny) -
+             zeta_at(h, H, ci[s], cj[s] - 1, nx, ny)) / T(2);
+  }
+  const int SW = 0, SE = 1, NW = 2, NE = 3;
+  T hc = T(0.25) * (hh[SW] + hh[SE] + hh[NW] + hh[NE]);
+  T hE = T(0.5) * (hh[SE] + hh[NE]), hW = T(0.5) * (hh[SW] + hh[NW]);
+  T hN = T(0.5) * (hh[NW] + hh[NE]), hS = T(0.5) * (hh[SW] + hh[SE]);
+  T XE = T(0.5) * (XX[SE] + XX[NE]), XW = T(0.5) * (XX[SW] + XX[NW]);
+  T YN = T(0.5) * (YY[NW] + YY[NE]), YS = T(0.5) * (YY[SW] + YY[SE]);
+  T sx = T(0.5) * (zz[SE] + zz[NE]) - T(0.5) * (zz[SW] + zz[NW]);
+  T sy = T(0.5) * (zz[NW] + zz[NE]) - T(0.5) * (zz[SW] + zz[SE]);
+  T q1E = T(0.5) * (a1[SE] + a1[NE]), q1W = T(0.5) * (a1[SW] + a1[NW]);
+  T q2N = T(0.5) * (a2[NW] + a2[NE]), q2S = T(0.5) * (a2[SW] + a2[SE]);
+  T dx2 = dx * dx, dy2 = dy * dy;
+  T d = T(16) +
+        ((T(2) * hc + sx) * (XW + T(2) * hW) -
+         (T(2) * hc - sx) * (XE - T(2) * hE)) / dx2 +
+        ((T(2) * hc + sy) * (YS + T(2) * hS) -
+         (T(2) * hc - sy) * (YN - T(2) * hN)) / dy2;
+  T e = -(T(2) * hc - sx) * (XE + T(2) * hE) / dx2;
+  T wv = (T(2) * hc + sx) * (XW - T(2) * hW) / dx2;
+  T nn = -(T(2) * hc - sy) * (YN + T(2) * hN) / dy2;
+  T ss = (T(2) * hc + sy) * (YS - T(2) * hS) / dy2;
+  T Bs = ((T(2) * hc - sx) * q1E - (T(2) * hc + sx) * q1W) / dx +
+         ((T(2) * hc - sy) * q2N - (T(2) * hc + sy) * q2S) / dy +
+         T(4) * hc * w[n];
+  T r = -(T(4) / dt) * Bs;
+  if (k == 0) { e = e + wv; wv = T(0); }
+  if (k == nx) { wv = wv + e; e = T(0); }
+  if (l == 0) { nn = nn + ss; ss = T(0); }
+  if (l == ny) { ss = ss + nn; nn = T(0); }
+  diag[n] = d;
+  cE[n] = e;
+  cW[n] = wv;
+  cN[n] = nn;
+  cS[n] = ss;
+  rhs[n] = r;
+}
+
+// 1D: eq. (43) coefficients, rows scaled by dx^2, with the right-hand side
+// -(8 dx^2/dt)(h q_x - q (2 eta - h)_x + 2 h w) at the corner.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_assemble1d(int nx, T dx, const T* __restrict__ h,
+                 const T* __restrict__ q, const T* __restrict__ H,
+                 const T* __restrict__ w, const double* __restrict__ dtp,
+                 T* __restrict__ a, T* __restrict__ b, T* __restrict__ c,
+                 T* __restrict__ rhs) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > nx) return;
+  T dt = (T)(*dtp);
+  auto zeta = [&](int i) {
+    int m = mirror(i, nx);
+    return h[m] - T(2) * H[m];
+  };
+  auto qv = [&](int i) {
+    int m = mirror(i, nx);
+    return m != i ? -q[m] : q[m];
+  };
+  int Wi = mirror(k - 1, nx), Ei = mirror(k, nx);
+  T hW = h[Wi], hE = h[Ei];
+  T hc = T(0.5) * (hE + hW);
+  T zW = zeta(k - 1), zE = zeta(k);
+  T xiW = dx * ((zE - zeta(k - 2)) / (T(2) * dx));
+  T xiE = dx * ((zeta(k + 1) - zW) / (T(2) * dx));
+  T xic = dx * ((zE - zW) / dx);
+  T ai = (xiW - T(2) * hW) * (xic + T(2) * hc);
+  T bi = T(16) * dx * dx + xic * (xiW + xiE + T(2) * hW - T(2) * hE) +
+         T(2) * hc * (xiW - xiE + T(4) * hc);
+  T ci = (xiE + T(2) * hE) * (xic - T(2) * hc);
+  T qE = qv(k), qW = qv(k - 1);
+  T qc = T(0.5) * (qE + qW);
+  T qxc = (qE - qW) / dx;
+  T zxc = (zE - zW) / dx;
+  T Bc = hc * qxc - qc * zxc + T(2) * hc * w[k];
+  T r = -(T(8) * dx * dx / dt) * Bc;
+  if (k == 0) { ci = ci + ai; ai = T(0); }
+  if (k == nx) { ai = ai + ci; ci = T(0); }
+  a[k] = ai;
+  b[k] = bi;
+  c[k] = ci;
+  rhs[k] = r;
+}
+
+// Thomas algorithm (Section 4.3) for the tridiagonal system (42), in FP64 by
+// one thread: the 1D channel is small and the elimination is sequential.
+template <typename T>
+__global__ void k_thomas(int n, const T* __restrict__ a, const T* __restrict__ b,
+                         const T* __restrict__ c, const T* __restrict__ d,
+                         double* __restrict__ x, double* __restrict__ cp,
+                         double* __restrict__ dp, int* __restrict__ flags) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double b0 = (double)b[0];
+  if (!(b0 != 0.0)) { atomicOr(flags, 2); return; }
+  cp[0] = (double)c[0] / b0;
+  dp[0] = (double)d[0] / b0;
+  for (int k = 1; k < n; ++k) {
+    double m = (double)b[k] - (double)a[k] * cp[k - 1];
+    if (!(m != 0.0)) { atomicOr(flags, 2); return; }
+    cp[k] = (double)c[k] / m;
+    dp[k] = ((double)d[k] - (double)a[k] * dp[k - 1]) / m;
+  }
+  double xn = dp[n - 1];
+  x[n - 1] = xn;
+  for (int k = n - 2; k >= 0; --k) {
+    xn = dp[k] - cp[k] * xn;
+    x[k] = xn;
+  }
+}
+
+// -------------------------------------------------------------------------
+// one relaxed Jacobi sweep of the 2D pressure system (FP64 arithmetic and
+// FP64 iterate in both precision modes; coefficients in the bulk type):
+//   p_new = p + omega (rhs - A p)/diag
+// With check, the convergence measure max |(rhs - A p)/diag| of the input
+// iterate is max-reduced into *meas.
+// -------------------------------------------------------------------------
+template <typename T, bool CHECK>
+__global__ void __launch_bounds__(kBlock)
+    k_sweep(int ncx, int ncy, double omega, const T* __restrict__ diag,
+            const T* __restrict__ cE, const T* __restrict__ cW,
+            const T* __restrict__ cN, const T* __restrict__ cS,
+            const T* __restrict__ rhs, const double* __restrict__ p,
+            double* __restrict__ pn, unsigned long long* meas) {
+  int n = blockIdx.x * blockDim.x + threadIdx.x;
+  double e = 0.0;
+  if (n < ncx * ncy) {
+    int k = n % ncx, l = n / ncx;
+    double dg = (double)diag[n];
+    double Ap = dg * p[n];
+    if (k + 1 < ncx) Ap += (double)cE[n] * p[n + 1];
+    if (k - 1 >= 0) Ap += (double)cW[n] * p[n - 1];
+    if (l + 1 < ncy) Ap += (double)cN[n] * p[n + ncx];
+    if (l - 1 >= 0) Ap += (double)cS[n] * p[n - ncx];
+    double r = (double)rhs[n] - Ap;
+    if (CHECK) e = fabs(r / dg);
+    pn[n] = p[n] + omega * (r / dg);
+  }
+  if (CHECK) block_max_to(e, meas);
+}
+
+// -------------------------------------------------------------------------
+// correction (eq. 26-27 in 1D, eq. 36 in 2D) of the cell discharges, the
+// second-stage Runge-Kutta average and the CFL measure of the new state.
+// With have_p == 0 (hydrostatic mode) the discharges pass through.
+// -------------------------------------------------------------------------
+template <typename T, bool ONE_D, bool COMBINE>
+__global__ void __launch_bounds__(kBlock)
+    k_correct_cells(int nx, int ny, T dx, T dy, T g, T delta, T dry_eps,
+                    int have_p, const T* __restrict__ hs,
+                    const T* __restrict__ q1s, const T* __restrict__ q2s,
+                    const T* __restrict__ H, const double* __restrict__ p,
+                    const double* __restrict__ dtp, T* __restrict__ oq1,
+                    T* __restrict__ oq2, T* __restrict__ h_n,
+                    T* __restrict__ q1_n, T* __restrict__ q2_n,
+                    unsigned long long* lam, int* flags) {
+  int n = blockIdx.x * blockDim.x + threadIdx.x;
+  double lam_local = 0.0;
+  if (n < nx * ny) {
+    int i = n % nx, j = n / nx;
+    T dt = (T)(*dtp);
+    T hc = hs[n];
+    T a = q1s[n], b = ONE_D ? T(0) : q2s[n];
+    if (have_p) {
+      T zx = (zeta_at(hs, H, i + 1, j, nx, ONE_D ? 1 : ny) -
+              zeta_at(hs, H, i - 1, j, nx, ONE_D ? 1 : ny)) / (T(2) * dx);
+      if (ONE_D) {
+        T pR = (T)p[i + 1], pL = (T)p[i];
+        T Tn = -T(0.5) * (hc * ((pR - pL) / dx) + (T(0.5) * (pR + pL)) * zx);
+        a = a + dt * Tn;
+        b = T(0);
+      } else {
+        int ncx = nx + 1;
+        T zy = (zeta_at(hs, H, i, j + 1, nx, ny) -
+                zeta_at(hs, H, i, j - 1, nx, ny)) / (T(2) * dy);
+        T pSW = (T)p[j * ncx + i], pSE = (T)p[j * ncx + i + 1];
+        T pNW = (T)p[(j + 1) * ncx + i], pNE = (T)p[(j + 1) * ncx + i + 1];
+        T TN = -T(0.5) * hc * (pNE - pNW) / dx -
+               T(0.5) * (T(0.5) * (pNE + pNW)) * zx;
+        T TS = -T(0.5) * hc * (pSE - pSW) / dx -
+               T(0.5) * (T(0.5) * (pSE + pSW)) * zx;
+        T TE = -T(0.5) * hc * (pNE - pSE) / dy -
+               T(0.5) * (T(0.5) * (pNE + pSE)) * zy;
+        T TW = -T(0.5) * hc * (pNW - pSW) / dy -
+               T(0.5) * (T(0.5) * (pNW + pSW)) * zy;
+        a = a + dt * (T(0.5) * (TN + TS));
+        b = b + dt * (T(0.5) * (TE + TW));
+      }
+      if (hc <= dry_eps) {
+        a = T(0);
+        b = T(0);
+      }
+    }
+    if (!COMBINE) {
+      oq1[n] = a;
+      if (!ONE_D) oq2[n] = b;
+    } else {
+      T hn = T(0.5) * (h_n[n] + hc);
+      T an = T(0.5) * (q1_n[n] + a);
+      T bn = ONE_D ? T(0) : T(0.5) * (q2_n[n] + b);
+      h_n[n] = hn;
+      q1_n[n] = an;
+      if (!ONE_D) q2_n[n] = bn;
+      if (!isfinite((double)hn) || !isfinite((double)an) ||
+          !isfinite((double)bn))
+        atomicOr(flags, 1);
+      if (hn > dry_eps) {
+        T cel = sqrt(g * hn);
+        T u = desing(hn, an, delta);
+        T l = (fabs(u) + cel) / dx;
+        if (!ONE_D) {
+          T v = desing(hn, bn, delta);
+          l = l + (fabs(v) + cel) / dy;
+        }
+        lam_local = (double)l;
+      }
+    }
+  }
+  if (COMBINE) block_max_to(lam_local, lam);
+}
+
+// corner update w = w* + dt p / h_c (desingularised division), and the
+// second-stage average of w.
+template <typename T, bool ONE_D, bool COMBINE>
+__global__ void __launch_bounds__(kBlock)
+    k_correct_corners(int nx, int ny, T delta, int have_p,
+                      const T* __restrict__ hs, const T* __restrict__ ws,
+                      const double* __restrict__ p,
+                      const double* __restrict__ dtp,
+                      T* __restrict__ w_out) {
+  int ncx = nx + 1, ncy = ONE_D ? 1 : ny + 1;
+  int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= ncx * ncy) return;
+  int k = n % ncx, l = n / ncx;
+  T wv = ws[n];
+  if (have_p) {
+    T dt = (T)(*dtp);
+    T hc;
+    if (ONE_D) {
+      hc = T(0.5) * (hs[mirror(k - 1, nx)] + hs[mirror(k, nx)]);
+    } else {
+      int im = mirror(k - 1, nx), ip = mirror(k, nx);
+      int jm = mirror(l - 1, ny), jp = mirror(l, ny);
+      hc = T(0.25) * (hs[jm * nx + im] + hs[jm * nx + ip] + hs[jp * nx + im] +
+                      hs[jp * nx + ip]);
+    }
+    wv = wv + dt * desing(hc, (T)p[n], delta);
+  }
+  if (COMBINE)
+    w_out[n] = T(0.5) * (w_out[n] + wv);
+  else
+    w_out[n] = wv;
+}
+
+// CFL measure of a state (used once at set_state)
+template <typename T, bool ONE_D>
+__global__ void __launch_bounds__(kBlock)
+    k_lambda(int nx, int ny, T dx, T dy, T g, T delta, T dry_eps,
+             const T* __restrict__ h, const T* __restrict__ q1,
+             const T* __restrict__ q2, unsigned long long* lam) {
+  int n = blockIdx.x * blockDim.x + threadIdx.x;
+  double lam_local = 0.0;
+  if (n < nx * ny) {
+    T hn = h[n];
+    if (hn > dry_eps) {
+      T cel = sqrt(g * hn);
+      T u = desing(hn, q1[n], delta);
+      T l = (fabs(u) + cel) / dx;
+      if (!ONE_D) {
+        T v = desing(hn, q2[n], delta);
+        l = l + (fabs(v) + cel) / dy;
+      }
+      lam_local = (double)l;
+    }
+  }
+  block_max_to(lam_local, lam);
+}
+
+// dt = CFL / lambda_max (stays on the device); lambda reset for the next step
+__global__ void k_finalize_dt(double cfl, unsigned long long* lam, double* dt,
+                              int* flags) {
+  double l = __longlong_as_double((long long)*lam);
+  if (l > 0.0 && isfinite(l))
+    *dt = cfl / l;
+  else {
+    *dt = 0.0;
+    atomicOr(flags, 4);
+  }
+  *lam = 0ull;
+}
+
+__global__ void k_zero_u64(unsigned long long* a) { *a = 0ull; }
+
+template <typename Tdst, typename Tsrc>
+__global__ void k_convert(int n, const Tsrc* __restrict__ s,
+                          Tdst* __restrict__ d) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = (Tdst)s[i];
+}
+
+}  // namespace nh

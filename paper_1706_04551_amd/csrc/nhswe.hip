@@ -1,0 +1,694 @@
+// nhswe.hip -- host orchestration and C ABI of the non-hydrostatic
+// shallow-water time stepper for gfx950 (see include/nhswe.h).
+//
+// One step = two projection-correction stages (TVD-RK2, Section 6) and the
+// device-side CFL reduction.  Each stage launches, on the solver's stream:
+//   k_fv                                  finite-volume update (eq. 20, 30)
+//   k_break_cells, k_break_corners        breaking terms (Section 3), if on
+//   k_assemble2d | k_assemble1d           pressure system (eq. 37-41, 43)
+//   k_sweep x K | k_thomas                solve (eq. 32) / Thomas (1D)
+//   k_correct_cells, k_correct_corners    correction (eq. 36, 28, 41)
+// The second stage's correction also forms the Runge-Kutta average and the
+// CFL measure of the new state; k_finalize_dt turns it into the next dt.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/nhswe.h"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+nh_status fail(nh_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return fail(NH_EDEVICE, std::string(#expr) + ": " +                    \
+                                  hipGetErrorString(e_));                    \
+  } while (0)
+
+inline unsigned nblocks(long n) {
+  return (unsigned)((n + nh::kBlock - 1) / nh::kBlock);
+}
+
+}  // namespace
+
+struct nh_solver {
+  nh_grid grid{};
+  nh_params par{};
+  std::vector<double> omega;
+  bool one_d = false;
+  bool fp32 = false;
+  size_t esize = 8;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  long ncell = 0, ncorn = 0;
+
+  // device buffers (element type double or float, see esize)
+  void *H = nullptr, *h = nullptr, *q1 = nullptr, *q2 = nullptr;   // U^n
+  void *hs = nullptr, *q1s = nullptr, *q2s = nullptr;              // U*
+  void *q1b = nullptr, *q2b = nullptr, *rw = nullptr;              // breaking
+  void *h1 = nullptr, *q11 = nullptr, *q21 = nullptr;              // U^(1)
+  void *w = nullptr, *ws = nullptr, *w1 = nullptr;                 // corners
+  void *pa = nullptr, *pb = nullptr;       // p (FP64 in both modes)
+  void *cdiag = nullptr, *cE = nullptr, *cW = nullptr, *cN = nullptr,
+       *cS = nullptr, *crhs = nullptr;
+  double *thomas_cp = nullptr, *thomas_dp = nullptr;
+  void *stage_buf = nullptr;   // FP64 staging for host copies
+  // device scalars
+  double* dt = nullptr;
+  unsigned long long* lam = nullptr;
+  unsigned long long* meas = nullptr;
+  double* clamped = nullptr;
+  int* flags = nullptr;
+  // host mirrors
+  unsigned long long* h_meas = nullptr;  // pinned
+  bool p_in_a = true;
+  bool have_state = false, have_H = false;
+  nh_stats st{};
+  // profiling
+  bool prof = false;
+  hipEvent_t ev[8]{};
+  nh_profile_t pr{};
+
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+nh_status dalloc(nh_solver* s, void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) return fail(NH_ENOMEM, "hipMalloc failed");
+  s->allocs.push_back(*p);
+  hipMemsetAsync(*p, 0, bytes, s->stream);
+  return NH_OK;
+}
+
+// copy a host FP64 array into a device array of the solver's type
+nh_status upload(nh_solver* s, void* dst, const double* src, long n) {
+  if (!s->fp32) {
+    HIP_TRY(hipMemcpyAsync(dst, src, n * sizeof(double),
+                           hipMemcpyHostToDevice, s->stream));
+  } else {
+    HIP_TRY(hipMemcpyAsync(s->stage_buf, src, n * sizeof(double),
+                           hipMemcpyHostToDevice, s->stream));
+    hipLaunchKernelGGL((nh::k_convert<float, double>), dim3(nblocks(n)),
+                       dim3(nh::kBlock), 0, s->stream, (int)n,
+                       (const double*)s->stage_buf, (float*)dst);
+  }
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return NH_OK;
+}
+
+nh_status download(nh_solver* s, double* dst, const void* src, long n) {
+  if (!s->fp32) {
+    HIP_TRY(hipMemcpyAsync(dst, src, n * sizeof(double),
+                           hipMemcpyDeviceToHost, s->stream));
+  } else {
+    hipLaunchKernelGGL((nh::k_convert<double, float>), dim3(nblocks(n)),
+                       dim3(nh::kBlock), 0, s->stream, (int)n,
+                       (const float*)src, (double*)s->stage_buf);
+    HIP_TRY(hipMemcpyAsync(dst, s->stage_buf, n * sizeof(double),
+                           hipMemcpyDeviceToHost, s->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return NH_OK;
+}
+
+void prof_mark(nh_solver* s, int slot) {
+  if (s->prof) hipEventRecord(s->ev[slot], s->stream);
+}
+
+void prof_accum(nh_solver* s, int a, int b, double* acc) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, s->ev[a], s->ev[b]) == hipSuccess) *acc += ms;
+}
+
+// ---------------------------------------------------------------------------
+// typed launch helpers
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Launch {
+  static T* P(void* p) { return static_cast<T*>(p); }
+
+  static void fv(nh_solver* s, void* h, void* q1, void* q2) {
+    const auto& g = s->grid;
+    const auto& pr = s->par;
+    if (s->one_d)
+      hipLaunchKernelGGL((nh::k_fv<T, true>), dim3(nblocks(s->ncell)),
+                         dim3(nh::kBlock), 0, s->stream, g.nx, g.ny,
+                         (T)g.dx, (T)g.dy, (T)pr.g, (T)pr.delta,
+                         (T)pr.dry_eps, P(h), P(q1), P(q2), P(s->H), s->dt,
+                         P(s->hs), P(s->q1s), P(s->q2s), s->clamped);
+    else
+      hipLaunchKernelGGL((nh::k_fv<T, false>), dim3(nblocks(s->ncell)),
+                         dim3(nh::kBlock), 0, s->stream, g.nx, g.ny,
+                         (T)g.dx, (T)g.dy, (T)pr.g, (T)pr.delta,
+                         (T)pr.dry_eps, P(h), P(q1), P(q2), P(s->H), s->dt,
+                         P(s->hs), P(s->q1s), P(s->q2s), s->clamped);
+  }
+
+  static void breaking(nh_solver* s, void* w_in) {
+    const auto& g = s->grid;
+    const auto& pr = s->par;
+    if (s->one_d) {
+      hipLaunchKernelGGL((nh::k_break_cells<T, true>), dim3(nblocks(s->ncell)),
+                         dim3(nh::kBlock), 0, s->stream, g.nx, g.ny,
+                         (T)g.dx, (T)g.dy, (T)pr.g, (T)pr.delta,
+                         (T)pr.dry_eps, (T)pr.b1, P(s->hs), P(s->q1s),
+                         P(s->q2s), P(s->H), s->dt, P(s->q1b), P(s->q2b),
+                         P(s->rw));
+      hipLaunchKernelGGL((nh::k_break_corners<T, true>),
+                         dim3(nblocks(s->ncorn)), dim3(nh::kBlock), 0,
+                         s->stream, g.nx, g.ny, (T)pr.delta, P(s->hs),
+                         P(s->rw), s->dt, P(w_in), P(s->ws));
+    } else {
+      hipLaunchKernelGGL((nh::k_break_cells<T, false>),
+                         dim3(nblocks(s->ncell)), dim3(nh::kBlock), 0,
+                         s->stream, g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g,
+                         (T)pr.delta, (T)pr.dry_eps, (T)pr.b1, P(s->hs),
+                         P(s->q1s), P(s->q2s), P(s->H), s->dt, P(s->q1b),
+                         P(s->q2b), P(s->rw));
+      hipLaunchKernelGGL((nh::k_break_corners<T, false>),
+                         dim3(nblocks(s->ncorn)), dim3(nh::kBlock), 0,
+                         s->stream, g.nx, g.ny, (T)pr.delta, P(s->hs),
+                         P(s->rw), s->dt, P(w_in), P(s->ws));
+    }
+  }
+
+  static void assemble(nh_solver* s, void* q1, void* q2, void* wst) {
+    const auto& g = s->grid;
+    if (s->one_d)
+      hipLaunchKernelGGL((nh::k_assemble1d<T>), dim3(nblocks(s->ncorn)),
+                         dim3(nh::kBlock), 0, s->stream, g.nx, (T)g.dx,
+                         P(s->hs), P(q1), P(s->H), P(wst), s->dt, P(s->cW),
+                         P(s->cdiag), P(s->cE), P(s->crhs));
+    else
+      hipLaunchKernelGGL((nh::k_assemble2d<T>), dim3(nblocks(s->ncorn)),
+                         dim3(nh::kBlock), 0, s->stream, g.nx, g.ny, (T)g.dx,
+                         (T)g.dy, P(s->hs), P(q1), P(q2), P(s->H), P(wst),
+                         s->dt, P(s->cdiag), P(s->cE), P(s->cW), P(s->cN),
+                         P(s->cS), P(s->crhs));
+  }
+
+  static void sweep(nh_solver* s, bool check, double om, void* pin,
+                    void* pout) {
+    int ncx = s->grid.nx + 1, ncy = s->grid.ny + 1;
+    if (check)
+      hipLaunchKernelGGL((nh::k_sweep<T, true>), dim3(nblocks(s->ncorn)),
+                         dim3(nh::kBlock), 0, s->stream, ncx, ncy, om,
+                         P(s->cdiag), P(s->cE), P(s->cW), P(s->cN), P(s->cS),
+                         P(s->crhs), (double*)pin, (double*)pout, s->meas);
+    else
+      hipLaunchKernelGGL((nh::k_sweep<T, false>), dim3(nblocks(s->ncorn)),
+                         dim3(nh::kBlock), 0, s->stream, ncx, ncy, om,
+                         P(s->cdiag), P(s->cE), P(s->cW), P(s->cN), P(s->cS),
+                         P(s->crhs), (double*)pin, (double*)pout, s->meas);
+  }
+
+  static void thomas(nh_solver* s, void* pout) {
+    hipLaunchKernelGGL((nh::k_thomas<T>), dim3(1), dim3(64), 0, s->stream,
+                       (int)s->ncorn, P(s->cW), P(s->cdiag), P(s->cE),
+                       P(s->crhs), (double*)pout, s->thomas_cp, s->thomas_dp,
+                       s->flags);
+  }
+
+  template <bool COMBINE>
+  static void correct(nh_solver* s, int have_p, void* q1, void* q2, void* wst,
+                      void* p, void* oq1, void* oq2, void* w_out) {
+    const auto& g = s->grid;
+    const auto& pr = s->par;
+    if (s->one_d) {
+      hipLaunchKernelGGL((nh::k_correct_cells<T, true, COMBINE>),
+                         dim3(nblocks(s->ncell)), dim3(nh::kBlock), 0,
+                         s->stream, g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g,
+                         (T)pr.delta, (T)pr.dry_eps, have_p, P(s->hs), P(q1),
+                         P(q2), P(s->H), (double*)p, s->dt, P(oq1), P(oq2), P(s->h),
+                         P(s->q1), P(s->q2), s->lam, s->flags);
+      hipLaunchKernelGGL((nh::k_correct_corners<T, true, COMBINE>),
+                         dim3(nblocks(s->ncorn)), dim3(nh::kBlock), 0,
+                         s->stream, g.nx, g.ny, (T)pr.delta, have_p, P(s->hs),
+                         P(wst), (double*)p, s->dt, P(w_out));
+    } else {
+      hipLaunchKernelGGL((nh::k_correct_cells<T, false, COMBINE>),
+                         dim3(nblocks(s->ncell)), dim3(nh::kBlock), 0,
+                         s->stream, g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g,
+                         (T)pr.delta, (T)pr.dry_eps, have_p, P(s->hs), P(q1),
+                         P(q2), P(s->H), (double*)p, s->dt, P(oq1), P(oq2), P(s->h),
+                         P(s->q1), P(s->q2), s->lam, s->flags);
+      hipLaunchKernelGGL((nh::k_correct_corners<T, false, COMBINE>),
+                         dim3(nblocks(s->ncorn)), dim3(nh::kBlock), 0,
+                         s->stream, g.nx, g.ny, (T)pr.delta, have_p, P(s->hs),
+                         P(wst), (double*)p, s->dt, P(w_out));
+    }
+  }
+
+  static void lambda(nh_solver* s) {
+    const auto& g = s->grid;
+    const auto& pr = s->par;
+    if (s->one_d)
+      hipLaunchKernelGGL((nh::k_lambda<T, true>), dim3(nblocks(s->ncell)),
+                         dim3(nh::kBlock), 0, s->stream, g.nx, g.ny, (T)g.dx,
+                         (T)g.dy, (T)pr.g, (T)pr.delta, (T)pr.dry_eps,
+                         P(s->h), P(s->q1), P(s->q2), s->lam);
+    else
+      hipLaunchKernelGGL((nh::k_lambda<T, false>), dim3(nblocks(s->ncell)),
+                         dim3(nh::kBlock), 0, s->stream, g.nx, g.ny, (T)g.dx,
+                         (T)g.dy, (T)pr.g, (T)pr.delta, (T)pr.dry_eps,
+                         P(s->h), P(s->q1), P(s->q2), s->lam);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// the pressure solve of one stage (2D): relaxed Jacobi with the schedule.
+// Mirrors the semantics of the plain statement: at sweep k the convergence
+// measure of the iterate p^k is taken whenever k is a multiple of
+// check_every (or k reached the cap); if it is below the tolerance p^k is the
+// solution, at the cap the solve stops with NH_ENOCONV.
+// ---------------------------------------------------------------------------
+template <typename T>
+nh_status solve2d(nh_solver* s, int32_t* sweeps, double* measure) {
+  const int ce = s->par.check_every > 0 ? s->par.check_every : 1;
+  const int kmax = s->par.solve_max_iter;
+  const int nom = (int)s->omega.size();
+  int k = 0;
+  double E = 0.0;
+  nh_status st = NH_OK;
+  for (;;) {
+    void* cur = s->p_in_a ? s->pa : s->pb;
+    void* nxt = s->p_in_a ? s->pb : s->pa;
+    // check sweep: measure of p^k, and p^{k+1} into the other buffer
+    hipLaunchKernelGGL(nh::k_zero_u64, dim3(1), dim3(1), 0, s->stream,
+                       s->meas);
+    Launch<T>::sweep(s, true, s->omega[k % nom], cur, nxt);
+    HIP_TRY(hipMemcpyAsync(s->h_meas, s->meas, sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->pr.solve_launches += 1;
+    long long bits = (long long)*s->h_meas;
+    std::memcpy(&E, &bits, sizeof(double));
+    if (E < s->par.solve_tol) break;           // p^k (in cur) is the result
+    if (k >= kmax) {
+      st = NH_ENOCONV;
+      break;
+    }
+    s->p_in_a = !s->p_in_a;                    // accept p^{k+1}
+    ++k;
+    int run = ce - 1;
+    if (k + run > kmax) run = kmax - k;
+    if (s->prof && run > 0) hipEventRecord(s->ev[6], s->stream);
+    for (int r = 0; r < run; ++r) {
+      void* c2 = s->p_in_a ? s->pa : s->pb;
+      void* n2 = s->p_in_a ? s->pb : s->pa;
+      Launch<T>::sweep(s, false, s->omega[k % nom], c2, n2);
+      s->p_in_a = !s->p_in_a;
+      ++k;
+    }
+    if (s->prof && run > 0) {
+      hipEventRecord(s->ev[7], s->stream);
+      HIP_TRY(hipEventSynchronize(s->ev[7]));
+      prof_accum(s, 6, 7, &s->pr.sweep_kernel_ms);
+      s->pr.sweep_kernel_launches += run;
+    }
+    s->pr.solve_launches += run;
+  }
+  *sweeps = k;
+  *measure = E;
+  return st;
+}
+
+template <typename T>
+nh_status stage(nh_solver* s, int idx, void* Vh, void* Vq1, void* Vq2,
+                void* w_in, void* oq1, void* oq2, void* w_out,
+                int32_t* sweeps, double* measure) {
+  const bool combine = idx == 1;
+  prof_mark(s, 0);
+  Launch<T>::fv(s, Vh, Vq1, Vq2);
+  prof_mark(s, 1);
+  void *qa = s->q1s, *qb = s->q2s, *wst = w_in;
+  if (s->par.breaking_on) {
+    Launch<T>::breaking(s, w_in);
+    qa = s->q1b;
+    qb = s->q2b;
+    wst = s->ws;
+  }
+  nh_status st = NH_OK;
+  *sweeps = 0;
+  *measure = 0.0;
+  void* p = nullptr;
+  if (s->par.nh_on) {
+    Launch<T>::assemble(s, qa, qb, wst);
+    prof_mark(s, 2);
+    if (s->one_d) {
+      void* cur = s->p_in_a ? s->pa : s->pb;
+      Launch<T>::thomas(s, cur);
+      s->pr.solve_launches += 1;
+    } else {
+      st = solve2d<T>(s, sweeps, measure);
+    }
+    prof_mark(s, 3);
+    p = s->p_in_a ? s->pa : s->pb;
+  } else {
+    prof_mark(s, 2);
+    prof_mark(s, 3);
+  }
+  int have_p = s->par.nh_on ? 1 : 0;
+  void* pp = p ? p : s->pa;
+  if (combine)
+    Launch<T>::template correct<true>(s, have_p, qa, qb, wst, pp, nullptr,
+                                      nullptr, w_out);
+  else
+    Launch<T>::template correct<false>(s, have_p, qa, qb, wst, pp, oq1, oq2,
+                                       w_out);
+  prof_mark(s, 4);
+  if (s->prof) {
+    HIP_TRY(hipEventSynchronize(s->ev[4]));
+    prof_accum(s, 0, 1, &s->pr.fv_ms);
+    prof_accum(s, 1, 2, &s->pr.assemble_ms);
+    prof_accum(s, 2, 3, &s->pr.solve_ms);
+    prof_accum(s, 3, 4, &s->pr.correct_ms);
+  }
+  s->pr.fv_launches += 1;
+  s->pr.assemble_launches += (s->par.breaking_on ? 2 : 0) + (s->par.nh_on ? 1 : 0);
+  s->pr.correct_launches += 2;
+  (void)Vh;
+  return st;
+}
+
+template <typename T>
+nh_status step_impl(nh_solver* s, double* dt_used) {
+  int32_t sw1 = 0, sw2 = 0;
+  double m1 = 0.0, m2 = 0.0;
+  // stage 1: U^n -> U^(1)
+  nh_status st = stage<T>(s, 0, s->h, s->q1, s->q2, s->w, s->q11, s->q21,
+                          s->w1, &sw1, &m1);
+  // the first stage's h* is the stage's h: keep it as U^(1)'s depth
+  HIP_TRY(hipMemcpyAsync(s->h1, s->hs, s->ncell * s->esize,
+                         hipMemcpyDeviceToDevice, s->stream));
+  if (st != NH_OK && st != NH_ENOCONV) return st;
+  nh_status st2 = stage<T>(s, 1, s->h1, s->q11, s->q21, s->w1, nullptr,
+                           nullptr, s->w, &sw2, &m2);
+  if (st == NH_OK) st = st2;
+  if (!s->par.fixed_dt) {
+    prof_mark(s, 5);
+    hipLaunchKernelGGL(nh::k_finalize_dt, dim3(1), dim3(1), 0, s->stream,
+                       s->par.cfl, s->lam, s->dt, s->flags);
+  } else {
+    hipLaunchKernelGGL(nh::k_zero_u64, dim3(1), dim3(1), 0, s->stream,
+                       s->lam);
+  }
+  double dt_used_v = 0.0, dt_next = 0.0;
+  int flags = 0;
+  double clamped = 0.0;
+  // dt of this step is the one read before finalisation; keep it on host
+  dt_used_v = s->st.dt_next;
+  HIP_TRY(hipMemcpyAsync(&dt_next, s->dt, sizeof(double),
+                         hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipMemcpyAsync(&flags, s->flags, sizeof(int), hipMemcpyDeviceToHost,
+                         s->stream));
+  HIP_TRY(hipMemcpyAsync(&clamped, s->clamped, sizeof(double),
+                         hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->st.t += dt_used_v;
+  s->st.dt_last = dt_used_v;
+  s->st.dt_next = dt_next;
+  s->st.step += 1;
+  s->st.sweeps[0] = sw1;
+  s->st.sweeps[1] = sw2;
+  s->st.sweeps_total += sw1 + sw2;
+  s->st.solves_total += s->par.nh_on ? 2 : 0;
+  s->st.measure = m2;
+  s->st.clamped_mass = clamped;
+  if (flags & 1) st = fail(NH_ENONFINITE, "non-finite value in the state");
+  if (flags & 2 && st == NH_OK)
+    st = fail(NH_EDEVICE, "singular tridiagonal system");
+  if (flags & 4 && st == NH_OK)
+    st = fail(NH_ESTATE, "no wet cell: the CFL time step is undefined");
+  if (st == NH_ENOCONV) fail(st, "pressure solve reached solve_max_iter");
+  s->st.last_status = st;
+  if (st != NH_OK && st != NH_ENOCONV) s->have_state = false;
+  if (dt_used) *dt_used = dt_used_v;
+  return st;
+}
+
+nh_status check_params(const nh_grid* g, const nh_params* p) {
+  if (!g || !p) return fail(NH_EINVAL, "null grid or params");
+  if (g->nx < 2 || g->ny < 1)
+    return fail(NH_EINVAL, "need nx >= 2 and ny == 1 or ny >= 2");
+  if ((long)g->nx * (long)(g->ny + 1) > (1L << 30))
+    return fail(NH_EINVAL, "grid too large");
+  if (!(g->dx > 0) || (g->ny > 1 && !(g->dy > 0)))
+    return fail(NH_EINVAL, "dx, dy must be > 0");
+  if (!(p->g > 0) || !(p->cfl > 0) || p->cfl > 1.0)
+    return fail(NH_EINVAL, "need g > 0 and 0 < cfl <= 1");
+  if (!(p->delta > 0) || !(p->dry_eps >= 0))
+    return fail(NH_EINVAL, "need delta > 0 and dry_eps >= 0");
+  if (p->precision != NH_FP64 && p->precision != NH_FP32)
+    return fail(NH_EINVAL, "precision must be NH_FP64 or NH_FP32");
+  if (p->nh_on && g->ny > 1) {
+    if (p->solve_max_iter < 0) return fail(NH_EINVAL, "solve_max_iter < 0");
+    int nom = (p->omega_schedule && p->n_omega > 0) ? p->n_omega : 1;
+    int ce = p->check_every > 0 ? p->check_every : 1;
+    if (ce % nom != 0)
+      return fail(NH_EINVAL, "check_every must be a multiple of n_omega");
+    if (p->omega_schedule && p->n_omega > 0)
+      for (int i = 0; i < p->n_omega; ++i)
+        if (!(p->omega_schedule[i] > 0) || !std::isfinite(p->omega_schedule[i]))
+          return fail(NH_EINVAL, "relaxation factors must be finite and > 0");
+  }
+  if (p->fixed_dt && !(p->dt > 0)) return fail(NH_EINVAL, "fixed dt must be > 0");
+  return NH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nh_last_error(void) { return g_err.c_str(); }
+
+const char* nh_version(void) { return "nhswe-gfx950 0.1"; }
+
+nh_status nh_create(const nh_grid* grid, const nh_params* params,
+                    void* hip_stream, nh_solver** out) {
+  if (!out) return fail(NH_EINVAL, "null output pointer");
+  *out = nullptr;
+  nh_status st = check_params(grid, params);
+  if (st != NH_OK) return st;
+  nh_solver* s = new nh_solver();
+  s->grid = *grid;
+  s->par = *params;
+  if (params->omega_schedule && params->n_omega > 0)
+    s->omega.assign(params->omega_schedule,
+                    params->omega_schedule + params->n_omega);
+  else
+    s->omega.assign(1, 1.0);
+  s->par.omega_schedule = nullptr;
+  s->one_d = grid->ny == 1;
+  s->fp32 = params->precision == NH_FP32;
+  s->esize = s->fp32 ? 4 : 8;
+  if (hip_stream) {
+    s->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreate(&s->stream) != hipSuccess) {
+      delete s;
+      return fail(NH_EDEVICE, "hipStreamCreate failed");
+    }
+    s->own_stream = true;
+  }
+  s->ncell = (long)grid->nx * grid->ny;
+  s->ncorn = (long)(grid->nx + 1) * (s->one_d ? 1 : grid->ny + 1);
+  size_t cb = s->ncell * s->esize, kb = s->ncorn * s->esize;
+  void** cells[] = {&s->H,   &s->h,   &s->q1,  &s->q2,  &s->hs,  &s->q1s,
+                    &s->q2s, &s->q1b, &s->q2b, &s->rw,  &s->h1,  &s->q11,
+                    &s->q21};
+  void** corners[] = {&s->w,  &s->ws, &s->w1, &s->cdiag,
+                      &s->cE, &s->cW, &s->cN, &s->cS, &s->crhs};
+  for (auto c : cells)
+    if ((st = dalloc(s, c, cb)) != NH_OK) { nh_destroy(s); return st; }
+  for (auto c : corners)
+    if ((st = dalloc(s, c, kb)) != NH_OK) { nh_destroy(s); return st; }
+  for (auto c : {&s->pa, &s->pb})
+    if ((st = dalloc(s, c, s->ncorn * sizeof(double))) != NH_OK) {
+      nh_destroy(s);
+      return st;
+    }
+  long nstage = s->ncell > s->ncorn ? s->ncell : s->ncorn;
+  if ((st = dalloc(s, &s->stage_buf, nstage * sizeof(double))) != NH_OK ||
+      (st = dalloc(s, (void**)&s->thomas_cp, s->ncorn * sizeof(double))) != NH_OK ||
+      (st = dalloc(s, (void**)&s->thomas_dp, s->ncorn * sizeof(double))) != NH_OK ||
+      (st = dalloc(s, (void**)&s->dt, sizeof(double))) != NH_OK ||
+      (st = dalloc(s, (void**)&s->lam, sizeof(unsigned long long))) != NH_OK ||
+      (st = dalloc(s, (void**)&s->meas, sizeof(unsigned long long))) != NH_OK ||
+      (st = dalloc(s, (void**)&s->clamped, sizeof(double))) != NH_OK ||
+      (st = dalloc(s, (void**)&s->flags, sizeof(int))) != NH_OK) {
+    nh_destroy(s);
+    return st;
+  }
+  if (hipHostMalloc((void**)&s->h_meas, sizeof(unsigned long long),
+                    hipHostMallocDefault) != hipSuccess) {
+    nh_destroy(s);
+    return fail(NH_ENOMEM, "hipHostMalloc failed");
+  }
+  for (auto& e : s->ev) hipEventCreate(&e);
+  if (hipStreamSynchronize(s->stream) != hipSuccess) {
+    nh_destroy(s);
+    return fail(NH_EDEVICE, "stream synchronisation failed");
+  }
+  *out = s;
+  return NH_OK;
+}
+
+nh_status nh_set_bathymetry(nh_solver* s, const double* H) {
+  if (!s || !H) return fail(NH_EINVAL, "null argument");
+  for (long i = 0; i < s->ncell; ++i)
+    if (!std::isfinite(H[i])) return fail(NH_EINVAL, "non-finite bathymetry");
+  nh_status st = upload(s, s->H, H, s->ncell);
+  if (st == NH_OK) s->have_H = true;
+  return st;
+}
+
+nh_status nh_set_state(nh_solver* s, const double* h, const double* hu,
+                       const double* hv, const double* w, const double* p) {
+  if (!s || !h || !hu) return fail(NH_EINVAL, "null argument");
+  if (!s->have_H) return fail(NH_ESTATE, "set the bathymetry first");
+  for (long i = 0; i < s->ncell; ++i) {
+    if (!std::isfinite(h[i]) || !std::isfinite(hu[i]) ||
+        (hv && !s->one_d && !std::isfinite(hv[i])))
+      return fail(NH_EINVAL, "non-finite state");
+    if (h[i] < 0.0) return fail(NH_ENEGDEPTH, "negative depth");
+  }
+  nh_status st;
+  if ((st = upload(s, s->h, h, s->ncell)) != NH_OK) return st;
+  if ((st = upload(s, s->q1, hu, s->ncell)) != NH_OK) return st;
+  if (hv && !s->one_d) {
+    if ((st = upload(s, s->q2, hv, s->ncell)) != NH_OK) return st;
+  } else {
+    HIP_TRY(hipMemsetAsync(s->q2, 0, s->ncell * s->esize, s->stream));
+  }
+  if (w) {
+    if ((st = upload(s, s->w, w, s->ncorn)) != NH_OK) return st;
+  } else {
+    HIP_TRY(hipMemsetAsync(s->w, 0, s->ncorn * s->esize, s->stream));
+  }
+  s->p_in_a = true;
+  if (p) {
+    HIP_TRY(hipMemcpyAsync(s->pa, p, s->ncorn * sizeof(double),
+                           hipMemcpyHostToDevice, s->stream));
+  } else {
+    HIP_TRY(hipMemsetAsync(s->pa, 0, s->ncorn * sizeof(double), s->stream));
+  }
+  HIP_TRY(hipMemsetAsync(s->flags, 0, sizeof(int), s->stream));
+  HIP_TRY(hipMemsetAsync(s->clamped, 0, sizeof(double), s->stream));
+  HIP_TRY(hipMemsetAsync(s->lam, 0, sizeof(unsigned long long), s->stream));
+  double dt0 = 0.0;
+  if (s->par.fixed_dt) {
+    dt0 = s->par.dt;
+    HIP_TRY(hipMemcpyAsync(s->dt, &dt0, sizeof(double), hipMemcpyHostToDevice,
+                           s->stream));
+  } else {
+    if (s->fp32)
+      Launch<float>::lambda(s);
+    else
+      Launch<double>::lambda(s);
+    hipLaunchKernelGGL(nh::k_finalize_dt, dim3(1), dim3(1), 0, s->stream,
+                       s->par.cfl, s->lam, s->dt, s->flags);
+    HIP_TRY(hipMemcpyAsync(&dt0, s->dt, sizeof(double), hipMemcpyDeviceToHost,
+                           s->stream));
+  }
+  int flags = 0;
+  HIP_TRY(hipMemcpyAsync(&flags, s->flags, sizeof(int), hipMemcpyDeviceToHost,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(hipMemsetAsync(s->flags, 0, sizeof(int), s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  std::memset(&s->st, 0, sizeof(s->st));
+  s->st.dt_next = dt0;
+  if (flags & 4) {
+    s->have_state = false;
+    return fail(NH_ESTATE, "no wet cell: the CFL time step is undefined");
+  }
+  s->have_state = true;
+  return NH_OK;
+}
+
+nh_status nh_step(nh_solver* s, double* dt_used) {
+  if (!s) return fail(NH_EINVAL, "null solver");
+  if (!s->have_state) return fail(NH_ESTATE, "no valid state (set_state)");
+  if (!(s->st.dt_next > 0)) return fail(NH_ESTATE, "dt is not positive");
+  return s->fp32 ? step_impl<float>(s, dt_used) : step_impl<double>(s, dt_used);
+}
+
+nh_status nh_run(nh_solver* s, int64_t nsteps) {
+  if (!s) return fail(NH_EINVAL, "null solver");
+  if (nsteps < 0) return fail(NH_EINVAL, "nsteps < 0");
+  for (int64_t n = 0; n < nsteps; ++n) {
+    nh_status st = nh_step(s, nullptr);
+    if (st != NH_OK) return st;
+  }
+  return NH_OK;
+}
+
+nh_status nh_read_state(nh_solver* s, double* h, double* hu, double* hv,
+                        double* w, double* p) {
+  if (!s) return fail(NH_EINVAL, "null solver");
+  nh_status st;
+  if (h && (st = download(s, h, s->h, s->ncell)) != NH_OK) return st;
+  if (hu && (st = download(s, hu, s->q1, s->ncell)) != NH_OK) return st;
+  if (hv) {
+    if (s->one_d)
+      std::memset(hv, 0, s->ncell * sizeof(double));
+    else if ((st = download(s, hv, s->q2, s->ncell)) != NH_OK)
+      return st;
+  }
+  if (w && (st = download(s, w, s->w, s->ncorn)) != NH_OK) return st;
+  if (p) {
+    HIP_TRY(hipMemcpyAsync(p, s->p_in_a ? s->pa : s->pb,
+                           s->ncorn * sizeof(double), hipMemcpyDeviceToHost,
+                           s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  }
+  return NH_OK;
+}
+
+nh_status nh_get_stats(const nh_solver* s, nh_stats* out) {
+  if (!s || !out) return fail(NH_EINVAL, "null argument");
+  *out = s->st;
+  return NH_OK;
+}
+
+nh_status nh_profile(nh_solver* s, int32_t on) {
+  if (!s) return fail(NH_EINVAL, "null solver");
+  s->prof = on != 0;
+  if (s->prof) std::memset(&s->pr, 0, sizeof(s->pr));
+  return NH_OK;
+}
+
+nh_status nh_get_profile(nh_solver* s, nh_profile_t* out) {
+  if (!s || !out) return fail(NH_EINVAL, "null argument");
+  *out = s->pr;
+  return NH_OK;
+}
+
+void nh_destroy(nh_solver* s) {
+  if (!s) return;
+  if (s->stream) hipStreamSynchronize(s->stream);
+  for (void* p : s->allocs) hipFree(p);
+  if (s->h_meas) hipHostFree(s->h_meas);
+  for (auto& e : s->ev)
+    if (e) hipEventDestroy(e);
+  if (s->own_stream) hipStreamDestroy(s->stream);
+  delete s;
+}
+
+}  // extern "C"
