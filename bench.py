@@ -121,14 +121,16 @@ def main():
 
     # roofline of the dominant kernel: the relaxation sweep
     sweep_ms = pr["sweep_kernel_ms"] / max(1, pr["sweep_kernel_launches"])
-    alg = ALG_BYTES_SWEEP[args.precision] * ncorn
+    sweeps_per_launch = pr["sweep_kernel_sweeps"] / max(1, pr["sweep_kernel_launches"])
+    alg = ALG_BYTES_SWEEP[args.precision] * ncorn * sweeps_per_launch
     achieved = alg / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
             "traffic": None,
-            "kernel": "k_sweep", "avg_launch_us": round(sweep_ms * 1e3, 3),
-            "alg_bytes_per_launch": alg}
+            "kernel": "k_sweep_tb", "avg_launch_us": round(sweep_ms * 1e3, 3),
+            "sweeps_per_launch": round(sweeps_per_launch, 3),
+            "alg_bytes_per_launch": int(alg)}
     full_step_bytes = alg_bytes_per_cell_step(kbar, args.precision) * ncell
     step_roof_frac = full_step_bytes / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9)
 

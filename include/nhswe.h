@@ -116,6 +116,7 @@ typedef struct {
   int64_t fv_launches, assemble_launches, solve_launches, correct_launches;
   double sweep_kernel_ms;  /* back-to-back relaxation-sweep launches only */
   int64_t sweep_kernel_launches;
+  int64_t sweep_kernel_sweeps; /* sweeps done by those launches */
 } nh_profile_t;
 
 /* Create a solver for the grid and parameters on `hip_stream` (a hipStream_t;

@@ -53,7 +53,8 @@ class NhProfile(C.Structure):
                 ("solve_launches", C.c_int64),
                 ("correct_launches", C.c_int64),
                 ("sweep_kernel_ms", C.c_double),
-                ("sweep_kernel_launches", C.c_int64)]
+                ("sweep_kernel_launches", C.c_int64),
+                ("sweep_kernel_sweeps", C.c_int64)]
 
 
 _lib = None

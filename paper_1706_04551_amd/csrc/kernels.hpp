@@ -430,12 +430,13 @@ __global__ void __launch_bounds__(kBlock)
   if (k == nx) { wv = wv + e; e = T(0); }
   if (l == 0) { nn = nn + ss; ss = T(0); }
   if (l == ny) { ss = ss + nn; nn = T(0); }
+  // rows normalised by the diagonal for the relaxation sweeps
   diag[n] = d;
-  cE[n] = e;
-  cW[n] = wv;
-  cN[n] = nn;
-  cS[n] = ss;
-  rhs[n] = r;
+  cE[n] = e / d;
+  cW[n] = wv / d;
+  cN[n] = nn / d;
+  cS[n] = ss / d;
+  rhs[n] = r / d;
 }
 
 // 1D: eq. (43) coefficients, rows scaled by dx^2, with the right-hand side
@@ -510,34 +511,114 @@ __global__ void k_thomas(int n, const T* __restrict__ a, const T* __restrict__ b
 }
 
 // -------------------------------------------------------------------------
-// one relaxed Jacobi sweep of the 2D pressure system (FP64 arithmetic and
-// FP64 iterate in both precision modes; coefficients in the bulk type):
-//   p_new = p + omega (rhs - A p)/diag
-// With check, the convergence measure max |(rhs - A p)/diag| of the input
-// iterate is max-reduced into *meas.
+// relaxed Jacobi sweeps of the 2D pressure system, several per launch.
+// Rows are normalised by their diagonal at assembly, so sweep k is
+//   r = rhs' - (p + cE' pE + cW' pW + cN' pN + cS' pS),   p <- p + omega_k r
+// in FP64 with an FP64 iterate (coefficients in the bulk type).  A workgroup
+// owns a BX x BY tile of corners and loads it with a halo of S corners; the
+// iterate ping-pongs in LDS and the coefficients stay in registers.  After t
+// sweeps the values are exact on the region shrunk by t, so nsw <= S sweeps in
+// one launch give the same iterates as nsw separate sweeps.  Outside the
+// domain everything is zero (walls are folded into the boundary rows).
+// With check, the first sweep max-reduces |r| over the tile -- the size of a
+// plain Jacobi update of the input iterate (eq. 32) -- into one of
+// kMeasSlots slots; nsw == 0 only measures.
+// Tiles are assigned XCD-major: workgroup b runs on XCD b % 8, and each XCD
+// gets a contiguous band of tile rows, so the halos and the coefficients of
+// its band stay in its own L2 from one launch to the next.
 // -------------------------------------------------------------------------
-template <typename T, bool CHECK>
+constexpr int kMeasSlots = 32;
+constexpr int kSweepS = 8;   // sweeps per launch (= halo width)
+constexpr int kSweepM = 9;   // region points per thread: (BX+2S)(BY+2S) <= 256 M
+
+template <typename T, int S, int M>
 __global__ void __launch_bounds__(kBlock)
-    k_sweep(int ncx, int ncy, double omega, const T* __restrict__ diag,
-            const T* __restrict__ cE, const T* __restrict__ cW,
-            const T* __restrict__ cN, const T* __restrict__ cS,
-            const T* __restrict__ rhs, const double* __restrict__ p,
-            double* __restrict__ pn, unsigned long long* meas) {
-  int n = blockIdx.x * blockDim.x + threadIdx.x;
-  double e = 0.0;
-  if (n < ncx * ncy) {
-    int k = n % ncx, l = n / ncx;
-    double dg = (double)diag[n];
-    double Ap = dg * p[n];
-    if (k + 1 < ncx) Ap += (double)cE[n] * p[n + 1];
-    if (k - 1 >= 0) Ap += (double)cW[n] * p[n - 1];
-    if (l + 1 < ncy) Ap += (double)cN[n] * p[n + ncx];
-    if (l - 1 >= 0) Ap += (double)cS[n] * p[n - ncx];
-    double r = (double)rhs[n] - Ap;
-    if (CHECK) e = fabs(r / dg);
-    pn[n] = p[n] + omega * (r / dg);
+    k_sweep_tb(int ncx, int ncy, int BX, int BY, int ntx, int ntiles,
+               const T* __restrict__ cE, const T* __restrict__ cW,
+               const T* __restrict__ cN, const T* __restrict__ cS,
+               const T* __restrict__ rhs, const double* __restrict__ pin,
+               double* __restrict__ pout, const double* __restrict__ omega,
+               int nom, int k0, int nsw, int check,
+               unsigned long long* __restrict__ meas) {
+  extern __shared__ double lds[];
+  const int per = (int)gridDim.x / 8;
+  const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (tile >= ntiles) return;  // uniform over the workgroup
+  const int tx = tile % ntx, ty = tile / ntx;
+  const int RW = BX + 2 * S, RH = BY + 2 * S, R = RW * RH;
+  const int x0 = tx * BX - S, y0 = ty * BY - S;
+  double* P0 = lds;
+  double* P1 = lds + R;
+  double ce[M], cw[M], cn[M], cs[M], cr[M];
+  int rx[M], ry[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    int idx = (int)threadIdx.x + kBlock * m;
+    ce[m] = cw[m] = cn[m] = cs[m] = cr[m] = 0.0;
+    rx[m] = -1;
+    ry[m] = -1;
+    if (idx < R) {
+      rx[m] = idx % RW;
+      ry[m] = idx / RW;
+      int gx = x0 + rx[m], gy = y0 + ry[m];
+      double pv = 0.0;
+      if (gx >= 0 && gx < ncx && gy >= 0 && gy < ncy) {
+        int g = gy * ncx + gx;
+        pv = pin[g];
+        ce[m] = (double)cE[g];
+        cw[m] = (double)cW[g];
+        cn[m] = (double)cN[g];
+        cs[m] = (double)cS[g];
+        cr[m] = (double)rhs[g];
+      }
+      P0[idx] = pv;
+    }
   }
-  if (CHECK) block_max_to(e, meas);
+  __syncthreads();
+  double e = 0.0;
+  const int iters = nsw > 0 ? nsw : 1;
+  for (int t = 0; t < iters; ++t) {
+    const double om = omega[(k0 + t) % nom];
+    const double* src = (t & 1) ? P1 : P0;
+    double* dst = (t & 1) ? P0 : P1;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int x = rx[m], y = ry[m];
+      if (x > t && x < RW - 1 - t && y > t && y < RH - 1 - t) {
+        const int idx = (int)threadIdx.x + kBlock * m;
+        const double pc = src[idx];
+        double a = pc + ce[m] * src[idx + 1];
+        a += cw[m] * src[idx - 1];
+        a += cn[m] * src[idx + RW];
+        a += cs[m] * src[idx - RW];
+        const double r = cr[m] - a;
+        if (t == 0 && check && x >= S && x < S + BX && y >= S && y < S + BY) {
+          double ar = fabs(r);
+          e = (ar > e || ar != ar) ? ar : e;
+        }
+        if (nsw > 0) dst[idx] = pc + om * r;
+      }
+    }
+    __syncthreads();
+  }
+  if (nsw > 0) {
+    const double* fin = (nsw & 1) ? P1 : P0;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int x = rx[m], y = ry[m];
+      if (x >= S && x < S + BX && y >= S && y < S + BY) {
+        int gx = x0 + x, gy = y0 + y;
+        if (gx < ncx && gy < ncy)
+          pout[gy * ncx + gx] = fin[(int)threadIdx.x + kBlock * m];
+      }
+    }
+  }
+  if (check) block_max_to(e, meas + (tile % kMeasSlots));
+}
+
+__global__ void k_zero_slots(unsigned long long* a, int n) {
+  int i = threadIdx.x;
+  if (i < n) a[i] = 0ull;
 }
 
 // -------------------------------------------------------------------------

@@ -14,6 +14,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -69,11 +70,13 @@ struct nh_solver {
   // device scalars
   double* dt = nullptr;
   unsigned long long* lam = nullptr;
-  unsigned long long* meas = nullptr;
+  unsigned long long* meas = nullptr;    // kMeasSlots slots
+  double* omega_dev = nullptr;
+  int tbx = 32, tby = 32, ntx = 1, nty = 1;  // sweep tiles
   double* clamped = nullptr;
   int* flags = nullptr;
   // host mirrors
-  unsigned long long* h_meas = nullptr;  // pinned
+  unsigned long long* h_meas = nullptr;  // pinned, kMeasSlots
   bool p_in_a = true;
   bool have_state = false, have_H = false;
   nh_stats st{};
@@ -202,19 +205,21 @@ struct Launch {
                          P(s->cS), P(s->crhs));
   }
 
-  static void sweep(nh_solver* s, bool check, double om, void* pin,
-                    void* pout) {
+  // nsw <= kSweepS relaxation sweeps starting at sweep index k0; with check
+  // the convergence measure of the input iterate goes to the slots
+  static void sweeps(nh_solver* s, bool check, int k0, int nsw, void* pin,
+                     void* pout) {
     int ncx = s->grid.nx + 1, ncy = s->grid.ny + 1;
-    if (check)
-      hipLaunchKernelGGL((nh::k_sweep<T, true>), dim3(nblocks(s->ncorn)),
-                         dim3(nh::kBlock), 0, s->stream, ncx, ncy, om,
-                         P(s->cdiag), P(s->cE), P(s->cW), P(s->cN), P(s->cS),
-                         P(s->crhs), (double*)pin, (double*)pout, s->meas);
-    else
-      hipLaunchKernelGGL((nh::k_sweep<T, false>), dim3(nblocks(s->ncorn)),
-                         dim3(nh::kBlock), 0, s->stream, ncx, ncy, om,
-                         P(s->cdiag), P(s->cE), P(s->cW), P(s->cN), P(s->cS),
-                         P(s->crhs), (double*)pin, (double*)pout, s->meas);
+    int ntiles = s->ntx * s->nty;
+    int nb = 8 * ((ntiles + 7) / 8);
+    size_t lds = 2 * sizeof(double) * (s->tbx + 2 * nh::kSweepS) *
+                 (s->tby + 2 * nh::kSweepS);
+    hipLaunchKernelGGL((nh::k_sweep_tb<T, nh::kSweepS, nh::kSweepM>),
+                       dim3(nb), dim3(nh::kBlock), lds, s->stream, ncx, ncy,
+                       s->tbx, s->tby, s->ntx, ntiles, P(s->cE), P(s->cW),
+                       P(s->cN), P(s->cS), P(s->crhs), (const double*)pin,
+                       (double*)pout, s->omega_dev, (int)s->omega.size(), k0,
+                       nsw, check ? 1 : 0, s->meas);
   }
 
   static void thomas(nh_solver* s, void* pout) {
@@ -281,47 +286,58 @@ template <typename T>
 nh_status solve2d(nh_solver* s, int32_t* sweeps, double* measure) {
   const int ce = s->par.check_every > 0 ? s->par.check_every : 1;
   const int kmax = s->par.solve_max_iter;
-  const int nom = (int)s->omega.size();
+  const int S = nh::kSweepS;
   int k = 0;
   double E = 0.0;
   nh_status st = NH_OK;
   for (;;) {
     void* cur = s->p_in_a ? s->pa : s->pb;
     void* nxt = s->p_in_a ? s->pb : s->pa;
-    // check sweep: measure of p^k, and p^{k+1} into the other buffer
-    hipLaunchKernelGGL(nh::k_zero_u64, dim3(1), dim3(1), 0, s->stream,
-                       s->meas);
-    Launch<T>::sweep(s, true, s->omega[k % nom], cur, nxt);
-    HIP_TRY(hipMemcpyAsync(s->h_meas, s->meas, sizeof(unsigned long long),
+    int nsw = k >= kmax ? 0 : std::min(std::min(S, ce), kmax - k);
+    // measure of p^k (and the first sweeps of the cycle into the other
+    // buffer); the host decides before the rest of the cycle is launched
+    hipLaunchKernelGGL(nh::k_zero_slots, dim3(1), dim3(64), 0, s->stream,
+                       s->meas, nh::kMeasSlots);
+    Launch<T>::sweeps(s, true, k, nsw, cur, nxt);
+    HIP_TRY(hipMemcpyAsync(s->h_meas, s->meas,
+                           nh::kMeasSlots * sizeof(unsigned long long),
                            hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->pr.solve_launches += 1;
-    long long bits = (long long)*s->h_meas;
-    std::memcpy(&E, &bits, sizeof(double));
+    E = 0.0;
+    for (int i = 0; i < nh::kMeasSlots; ++i) {
+      double v;
+      long long bits = (long long)s->h_meas[i];
+      std::memcpy(&v, &bits, sizeof(double));
+      if (v > E || v != v) E = v;
+    }
     if (E < s->par.solve_tol) break;           // p^k (in cur) is the result
     if (k >= kmax) {
       st = NH_ENOCONV;
       break;
     }
-    s->p_in_a = !s->p_in_a;                    // accept p^{k+1}
-    ++k;
-    int run = ce - 1;
-    if (k + run > kmax) run = kmax - k;
-    if (s->prof && run > 0) hipEventRecord(s->ev[6], s->stream);
-    for (int r = 0; r < run; ++r) {
+    s->p_in_a = !s->p_in_a;
+    k += nsw;
+    int run_sweeps = 0, run_launches = 0;
+    if (s->prof) hipEventRecord(s->ev[6], s->stream);
+    while (k % ce != 0 && k < kmax) {
+      int n2 = std::min(std::min(S, ce - k % ce), kmax - k);
       void* c2 = s->p_in_a ? s->pa : s->pb;
-      void* n2 = s->p_in_a ? s->pb : s->pa;
-      Launch<T>::sweep(s, false, s->omega[k % nom], c2, n2);
+      void* o2 = s->p_in_a ? s->pb : s->pa;
+      Launch<T>::sweeps(s, false, k, n2, c2, o2);
       s->p_in_a = !s->p_in_a;
-      ++k;
+      k += n2;
+      run_sweeps += n2;
+      run_launches += 1;
     }
-    if (s->prof && run > 0) {
+    if (s->prof && run_launches > 0) {
       hipEventRecord(s->ev[7], s->stream);
       HIP_TRY(hipEventSynchronize(s->ev[7]));
       prof_accum(s, 6, 7, &s->pr.sweep_kernel_ms);
-      s->pr.sweep_kernel_launches += run;
+      s->pr.sweep_kernel_launches += run_launches;
+      s->pr.sweep_kernel_sweeps += run_sweeps;
     }
-    s->pr.solve_launches += run;
+    s->pr.solve_launches += run_launches;
   }
   *sweeps = k;
   *measure = E;
@@ -529,18 +545,39 @@ nh_status nh_create(const nh_grid* grid, const nh_params* params,
       (st = dalloc(s, (void**)&s->thomas_dp, s->ncorn * sizeof(double))) != NH_OK ||
       (st = dalloc(s, (void**)&s->dt, sizeof(double))) != NH_OK ||
       (st = dalloc(s, (void**)&s->lam, sizeof(unsigned long long))) != NH_OK ||
-      (st = dalloc(s, (void**)&s->meas, sizeof(unsigned long long))) != NH_OK ||
+      (st = dalloc(s, (void**)&s->meas,
+                   nh::kMeasSlots * sizeof(unsigned long long))) != NH_OK ||
+      (st = dalloc(s, (void**)&s->omega_dev,
+                   s->omega.size() * sizeof(double))) != NH_OK ||
       (st = dalloc(s, (void**)&s->clamped, sizeof(double))) != NH_OK ||
       (st = dalloc(s, (void**)&s->flags, sizeof(int))) != NH_OK) {
     nh_destroy(s);
     return st;
   }
-  if (hipHostMalloc((void**)&s->h_meas, sizeof(unsigned long long),
+  if (hipHostMalloc((void**)&s->h_meas,
+                    nh::kMeasSlots * sizeof(unsigned long long),
                     hipHostMallocDefault) != hipSuccess) {
     nh_destroy(s);
     return fail(NH_ENOMEM, "hipHostMalloc failed");
   }
   for (auto& e : s->ev) hipEventCreate(&e);
+  if (hipMemcpyAsync(s->omega_dev, s->omega.data(),
+                     s->omega.size() * sizeof(double), hipMemcpyHostToDevice,
+                     s->stream) != hipSuccess) {
+    nh_destroy(s);
+    return fail(NH_EDEVICE, "copy of the relaxation schedule failed");
+  }
+  // sweep tiles: 32 x 32 corners with a halo of kSweepS; the region must fit
+  // kBlock * kSweepM points (checked here, assumed by the kernel)
+  s->tbx = 32;
+  s->tby = 32;
+  if ((s->tbx + 2 * nh::kSweepS) * (s->tby + 2 * nh::kSweepS) >
+      nh::kBlock * nh::kSweepM) {
+    nh_destroy(s);
+    return fail(NH_EINVAL, "sweep tile does not fit the workgroup");
+  }
+  s->ntx = (grid->nx + 1 + s->tbx - 1) / s->tbx;
+  s->nty = s->one_d ? 1 : (grid->ny + 1 + s->tby - 1) / s->tby;
   if (hipStreamSynchronize(s->stream) != hipSuccess) {
     nh_destroy(s);
     return fail(NH_EDEVICE, "stream synchronisation failed");

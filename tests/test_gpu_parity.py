@@ -92,7 +92,7 @@ def test_ragged_wet_fp64_several_tiles():
     nx, ny, dx, dy = 301, 77, 0.5, 0.7
     H, h, hu, hv = I.random_wet_state(rng, nx, ny, dx, dy)
     rho = I.jacobi_radius_bound(h.max(), dx, dy)
-    c = I.Case("ragged", nx, ny, dx, dy, H, h, hu, hv, 12,
+    c = I.Case("ragged", nx, ny, dx, dy, H, h, hu, hv, 12, cfl=I.CFL_2D,
                omega=I.srj_schedule(rho, 32), check_every=32)
     g, r, gs, os_ = compare(c, 12, TOL64, fields=("h", "hu", "hv", "w", "p"))
     assert gs["sweeps_total"] == os_["sweeps_total"]
@@ -155,7 +155,7 @@ def test_mass_conservation_on_gpu():
     rng = np.random.default_rng(5)
     H, h, hu, hv = I.random_wet_state(rng, 200, 150, 1.0, 1.0)
     rho = I.jacobi_radius_bound(h.max(), 1.0, 1.0)
-    c = I.Case("wet", 200, 150, 1.0, 1.0, H, h, hu, hv, 50,
+    c = I.Case("wet", 200, 150, 1.0, 1.0, H, h, hu, hv, 50, cfl=I.CFL_2D,
                omega=I.srj_schedule(rho, 64), check_every=64)
     say("[case] mass 200x150 fp64")
     s = gpu_solver(c)
