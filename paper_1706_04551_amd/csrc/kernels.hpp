@@ -187,9 +187,10 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+template <int B = kBlock>
 __device__ __forceinline__ void block_max_to(double v,
                                              unsigned long long* dst) {
-  __shared__ double part[kBlock / 64];
+  __shared__ double part[B / 64];
   v = wave_max(v);
   int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) part[wid] = v;
@@ -430,13 +431,12 @@ __global__ void __launch_bounds__(kBlock)
   if (k == nx) { wv = wv + e; e = T(0); }
   if (l == 0) { nn = nn + ss; ss = T(0); }
   if (l == ny) { ss = ss + nn; nn = T(0); }
-  // rows normalised by the diagonal for the relaxation sweeps
   diag[n] = d;
-  cE[n] = e / d;
-  cW[n] = wv / d;
-  cN[n] = nn / d;
-  cS[n] = ss / d;
-  rhs[n] = r / d;
+  cE[n] = e;
+  cW[n] = wv;
+  cN[n] = nn;
+  cS[n] = ss;
+  rhs[n] = r;
 }
 
 // 1D: eq. (43) coefficients, rows scaled by dx^2, with the right-hand side
@@ -512,34 +512,40 @@ __global__ void k_thomas(int n, const T* __restrict__ a, const T* __restrict__ b
 
 // -------------------------------------------------------------------------
 // relaxed Jacobi sweeps of the 2D pressure system, several per launch.
-// Rows are normalised by their diagonal at assembly, so sweep k is
-//   r = rhs' - (p + cE' pE + cW' pW + cN' pN + cS' pS),   p <- p + omega_k r
-// in FP64 with an FP64 iterate (coefficients in the bulk type).  A workgroup
+// Sweep k is
+//   r = rhs - (diag p + cE pE + cW pW + cN pN + cS pS),
+//   p <- p + omega_k (r / diag)
+// in FP64 with an FP64 iterate (coefficients in the bulk type), in the order
+// of the plain statement, so that FP64 iterates are reproduced exactly.  A workgroup
 // owns a BX x BY tile of corners and loads it with a halo of S corners; the
 // iterate ping-pongs in LDS and the coefficients stay in registers.  After t
 // sweeps the values are exact on the region shrunk by t, so nsw <= S sweeps in
 // one launch give the same iterates as nsw separate sweeps.  Outside the
 // domain everything is zero (walls are folded into the boundary rows).
 // With check, the first sweep max-reduces |r| over the tile -- the size of a
-// plain Jacobi update of the input iterate (eq. 32) -- into one of
-// kMeasSlots slots; nsw == 0 only measures.
+// plain Jacobi update of the input iterate (eq. 32) -- into part[tile], and
+// the input iterate of the tile is copied to psave, so that the host can
+// decide on convergence while later launches already run; nsw == 0 only
+// measures.
 // Tiles are assigned XCD-major: workgroup b runs on XCD b % 8, and each XCD
 // gets a contiguous band of tile rows, so the halos and the coefficients of
 // its band stay in its own L2 from one launch to the next.
 // -------------------------------------------------------------------------
-constexpr int kMeasSlots = 32;
-constexpr int kSweepS = 8;   // sweeps per launch (= halo width)
-constexpr int kSweepM = 9;   // region points per thread: (BX+2S)(BY+2S) <= 256 M
+constexpr int kSweepB = 1024;  // threads per workgroup (16 waves)
+constexpr int kSweepS = 8;     // sweeps per launch (= halo width)
+constexpr int kSweepM = 2;     // region points per thread:
+                               // (BX+2S)(BY+2S) <= kSweepB * kSweepM
 
-template <typename T, int S, int M>
-__global__ void __launch_bounds__(kBlock)
+template <typename T, int B, int S, int M>
+__global__ void __launch_bounds__(B)
     k_sweep_tb(int ncx, int ncy, int BX, int BY, int ntx, int ntiles,
-               const T* __restrict__ cE, const T* __restrict__ cW,
-               const T* __restrict__ cN, const T* __restrict__ cS,
-               const T* __restrict__ rhs, const double* __restrict__ pin,
+               const T* __restrict__ dgl, const T* __restrict__ cE,
+               const T* __restrict__ cW, const T* __restrict__ cN,
+               const T* __restrict__ cS, const T* __restrict__ rhs,
+               const double* __restrict__ pin,
                double* __restrict__ pout, const double* __restrict__ omega,
                int nom, int k0, int nsw, int check,
-               unsigned long long* __restrict__ meas) {
+               double* __restrict__ part, double* __restrict__ psave) {
   extern __shared__ double lds[];
   const int per = (int)gridDim.x / 8;
   const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
@@ -549,12 +555,14 @@ __global__ void __launch_bounds__(kBlock)
   const int x0 = tx * BX - S, y0 = ty * BY - S;
   double* P0 = lds;
   double* P1 = lds + R;
-  double ce[M], cw[M], cn[M], cs[M], cr[M];
+  // outside the domain: diag 1, everything else 0 (the iterate stays 0)
+  double dg[M], ce[M], cw[M], cn[M], cs[M], cr[M];
   int rx[M], ry[M];
 #pragma unroll
   for (int m = 0; m < M; ++m) {
-    int idx = (int)threadIdx.x + kBlock * m;
+    int idx = (int)threadIdx.x + B * m;
     ce[m] = cw[m] = cn[m] = cs[m] = cr[m] = 0.0;
+    dg[m] = 1.0;
     rx[m] = -1;
     ry[m] = -1;
     if (idx < R) {
@@ -565,6 +573,10 @@ __global__ void __launch_bounds__(kBlock)
       if (gx >= 0 && gx < ncx && gy >= 0 && gy < ncy) {
         int g = gy * ncx + gx;
         pv = pin[g];
+        if (check && rx[m] >= S && rx[m] < S + BX && ry[m] >= S &&
+            ry[m] < S + BY)
+          psave[g] = pv;
+        dg[m] = (double)dgl[g];
         ce[m] = (double)cE[g];
         cw[m] = (double)cW[g];
         cn[m] = (double)cN[g];
@@ -585,18 +597,20 @@ __global__ void __launch_bounds__(kBlock)
     for (int m = 0; m < M; ++m) {
       const int x = rx[m], y = ry[m];
       if (x > t && x < RW - 1 - t && y > t && y < RH - 1 - t) {
-        const int idx = (int)threadIdx.x + kBlock * m;
+        const int idx = (int)threadIdx.x + B * m;
         const double pc = src[idx];
-        double a = pc + ce[m] * src[idx + 1];
-        a += cw[m] * src[idx - 1];
-        a += cn[m] * src[idx + RW];
-        a += cs[m] * src[idx - RW];
-        const double r = cr[m] - a;
+        double Ap = dg[m] * pc;
+        Ap += ce[m] * src[idx + 1];
+        Ap += cw[m] * src[idx - 1];
+        Ap += cn[m] * src[idx + RW];
+        Ap += cs[m] * src[idx - RW];
+        const double r = cr[m] - Ap;
+        const double rd = r / dg[m];
         if (t == 0 && check && x >= S && x < S + BX && y >= S && y < S + BY) {
-          double ar = fabs(r);
+          double ar = fabs(rd);
           e = (ar > e || ar != ar) ? ar : e;
         }
-        if (nsw > 0) dst[idx] = pc + om * r;
+        if (nsw > 0) dst[idx] = pc + om * rd;
       }
     }
     __syncthreads();
@@ -609,16 +623,22 @@ __global__ void __launch_bounds__(kBlock)
       if (x >= S && x < S + BX && y >= S && y < S + BY) {
         int gx = x0 + x, gy = y0 + y;
         if (gx < ncx && gy < ncy)
-          pout[gy * ncx + gx] = fin[(int)threadIdx.x + kBlock * m];
+          pout[gy * ncx + gx] = fin[(int)threadIdx.x + B * m];
       }
     }
   }
-  if (check) block_max_to(e, meas + (tile % kMeasSlots));
-}
-
-__global__ void k_zero_slots(unsigned long long* a, int n) {
-  int i = threadIdx.x;
-  if (i < n) a[i] = 0ull;
+  if (check) {
+    __shared__ double wmax[B / 64];
+    double v = wave_max(e);
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double mx = wmax[0];
+      for (int w = 1; w < B / 64; ++w)
+        mx = (wmax[w] > mx || wmax[w] != wmax[w]) ? wmax[w] : mx;
+      part[tile] = mx;
+    }
+  }
 }
 
 // -------------------------------------------------------------------------

@@ -62,7 +62,8 @@ struct nh_solver {
   void *q1b = nullptr, *q2b = nullptr, *rw = nullptr;              // breaking
   void *h1 = nullptr, *q11 = nullptr, *q21 = nullptr;              // U^(1)
   void *w = nullptr, *ws = nullptr, *w1 = nullptr;                 // corners
-  void *pa = nullptr, *pb = nullptr;       // p (FP64 in both modes)
+  void *pa = nullptr, *pb = nullptr, *pc = nullptr;  // p (FP64, both modes)
+  int pcur = 0;                            // index of the current iterate
   void *cdiag = nullptr, *cE = nullptr, *cW = nullptr, *cN = nullptr,
        *cS = nullptr, *crhs = nullptr;
   double *thomas_cp = nullptr, *thomas_dp = nullptr;
@@ -70,14 +71,17 @@ struct nh_solver {
   // device scalars
   double* dt = nullptr;
   unsigned long long* lam = nullptr;
-  unsigned long long* meas = nullptr;    // kMeasSlots slots
+  double* part = nullptr;                // per-tile convergence measures
   double* omega_dev = nullptr;
+  hipStream_t copy_stream = nullptr;      // convergence read-back
+  hipEvent_t ev_check = nullptr, ev_copy = nullptr;
   int tbx = 32, tby = 32, ntx = 1, nty = 1;  // sweep tiles
   double* clamped = nullptr;
   int* flags = nullptr;
   // host mirrors
-  unsigned long long* h_meas = nullptr;  // pinned, kMeasSlots
-  bool p_in_a = true;
+  double* h_part = nullptr;  // pinned copy of part
+  void* pbuf(int i) { return i == 0 ? pa : (i == 1 ? pb : pc); }
+  void* pcur_ptr() { return pbuf(pcur); }
   bool have_state = false, have_H = false;
   nh_stats st{};
   // profiling
@@ -206,20 +210,23 @@ struct Launch {
   }
 
   // nsw <= kSweepS relaxation sweeps starting at sweep index k0; with check
-  // the convergence measure of the input iterate goes to the slots
+  // the convergence measure of the input iterate goes to s->part per tile
+  // and the input iterate is saved to psave
   static void sweeps(nh_solver* s, bool check, int k0, int nsw, void* pin,
-                     void* pout) {
+                     void* pout, void* psave) {
     int ncx = s->grid.nx + 1, ncy = s->grid.ny + 1;
     int ntiles = s->ntx * s->nty;
     int nb = 8 * ((ntiles + 7) / 8);
     size_t lds = 2 * sizeof(double) * (s->tbx + 2 * nh::kSweepS) *
                  (s->tby + 2 * nh::kSweepS);
-    hipLaunchKernelGGL((nh::k_sweep_tb<T, nh::kSweepS, nh::kSweepM>),
-                       dim3(nb), dim3(nh::kBlock), lds, s->stream, ncx, ncy,
-                       s->tbx, s->tby, s->ntx, ntiles, P(s->cE), P(s->cW),
-                       P(s->cN), P(s->cS), P(s->crhs), (const double*)pin,
+    hipLaunchKernelGGL((nh::k_sweep_tb<T, nh::kSweepB, nh::kSweepS,
+                                         nh::kSweepM>),
+                       dim3(nb), dim3(nh::kSweepB), lds, s->stream, ncx, ncy,
+                       s->tbx, s->tby, s->ntx, ntiles, P(s->cdiag), P(s->cE),
+                       P(s->cW), P(s->cN), P(s->cS), P(s->crhs),
+                       (const double*)pin,
                        (double*)pout, s->omega_dev, (int)s->omega.size(), k0,
-                       nsw, check ? 1 : 0, s->meas);
+                       nsw, check ? 1 : 0, s->part, (double*)psave);
   }
 
   static void thomas(nh_solver* s, void* pout) {
@@ -282,63 +289,90 @@ struct Launch {
 // check_every (or k reached the cap); if it is below the tolerance p^k is the
 // solution, at the cap the solve stops with NH_ENOCONV.
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// the pressure solve of one stage (2D): relaxed Jacobi with the schedule.
+// Same semantics as the plain statement: at sweep k the convergence measure
+// of the iterate p^k is taken whenever k is a multiple of check_every (or k
+// reached the cap); below the tolerance p^k is the solution, at the cap the
+// solve stops with NH_ENOCONV.  Three iterate buffers: the check launch reads
+// the current one, writes the next, and saves p^k into the third; the host
+// queues a few more launches before it waits for the measure (read back on a
+// side stream), so the device never idles on the decision.  If p^k
+// converged, the saved copy is the solution and the look-ahead launches are
+// discarded.
+// ---------------------------------------------------------------------------
 template <typename T>
 nh_status solve2d(nh_solver* s, int32_t* sweeps, double* measure) {
   const int ce = s->par.check_every > 0 ? s->par.check_every : 1;
   const int kmax = s->par.solve_max_iter;
   const int S = nh::kSweepS;
-  int k = 0;
+  const int kAhead = 3;  // launches queued before waiting for a measure
+  const int ntiles = s->ntx * s->nty;
+  int k = 0;             // sweep index of the iterate in buffer `cur`
+  int cur = s->pcur;
   double E = 0.0;
   nh_status st = NH_OK;
+  int launches = 0, nsweeps_done = 0;
   for (;;) {
-    void* cur = s->p_in_a ? s->pa : s->pb;
-    void* nxt = s->p_in_a ? s->pb : s->pa;
+    const int save = (cur + 2) % 3, out = (cur + 1) % 3;
+    const int kc = k;
     int nsw = k >= kmax ? 0 : std::min(std::min(S, ce), kmax - k);
-    // measure of p^k (and the first sweeps of the cycle into the other
-    // buffer); the host decides before the rest of the cycle is launched
-    hipLaunchKernelGGL(nh::k_zero_slots, dim3(1), dim3(64), 0, s->stream,
-                       s->meas, nh::kMeasSlots);
-    Launch<T>::sweeps(s, true, k, nsw, cur, nxt);
-    HIP_TRY(hipMemcpyAsync(s->h_meas, s->meas,
-                           nh::kMeasSlots * sizeof(unsigned long long),
-                           hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
-    s->pr.solve_launches += 1;
+    Launch<T>::sweeps(s, true, k, nsw, s->pbuf(cur), s->pbuf(out),
+                      s->pbuf(save));
+    HIP_TRY(hipEventRecord(s->ev_check, s->stream));
+    HIP_TRY(hipStreamWaitEvent(s->copy_stream, s->ev_check, 0));
+    HIP_TRY(hipMemcpyAsync(s->h_part, s->part, ntiles * sizeof(double),
+                           hipMemcpyDeviceToHost, s->copy_stream));
+    HIP_TRY(hipEventRecord(s->ev_copy, s->copy_stream));
+    launches += 1;
+    if (nsw > 0) {
+      cur = out;                 // ping-pong between cur and (save's peer)
+      k += nsw;
+      nsweeps_done += nsw;
+    }
+    int other = 3 - cur - save;  // the buffer that is neither cur nor save
+    // queue the rest of the cycle, the first kAhead launches before waiting
+    int queued = 0;
+    auto queue_until = [&](int limit) {
+      while (k % ce != 0 && k < kmax && queued < limit) {
+        int n2 = std::min(std::min(S, ce - k % ce), kmax - k);
+        Launch<T>::sweeps(s, false, k, n2, s->pbuf(cur), s->pbuf(other),
+                          nullptr);
+        std::swap(cur, other);
+        k += n2;
+        nsweeps_done += n2;
+        ++queued;
+        ++launches;
+      }
+    };
+    if (nsw > 0) queue_until(kAhead);
+    HIP_TRY(hipEventSynchronize(s->ev_copy));
     E = 0.0;
-    for (int i = 0; i < nh::kMeasSlots; ++i) {
-      double v;
-      long long bits = (long long)s->h_meas[i];
-      std::memcpy(&v, &bits, sizeof(double));
+    for (int i = 0; i < ntiles; ++i) {
+      double v = s->h_part[i];
       if (v > E || v != v) E = v;
     }
-    if (E < s->par.solve_tol) break;           // p^k (in cur) is the result
-    if (k >= kmax) {
-      st = NH_ENOCONV;
+    if (E < s->par.solve_tol || kc >= kmax) {
+      if (!(E < s->par.solve_tol)) st = NH_ENOCONV;
+      s->pcur = save;            // p^kc, saved by the check launch
+      k = kc;
       break;
     }
-    s->p_in_a = !s->p_in_a;
-    k += nsw;
-    int run_sweeps = 0, run_launches = 0;
-    if (s->prof) hipEventRecord(s->ev[6], s->stream);
-    while (k % ce != 0 && k < kmax) {
-      int n2 = std::min(std::min(S, ce - k % ce), kmax - k);
-      void* c2 = s->p_in_a ? s->pa : s->pb;
-      void* o2 = s->p_in_a ? s->pb : s->pa;
-      Launch<T>::sweeps(s, false, k, n2, c2, o2);
-      s->p_in_a = !s->p_in_a;
-      k += n2;
-      run_sweeps += n2;
-      run_launches += 1;
-    }
-    if (s->prof && run_launches > 0) {
-      hipEventRecord(s->ev[7], s->stream);
+    if (s->prof) HIP_TRY(hipEventRecord(s->ev[6], s->stream));
+    int before = queued;
+    queue_until(1 << 30);
+    if (s->prof) {
+      HIP_TRY(hipEventRecord(s->ev[7], s->stream));
       HIP_TRY(hipEventSynchronize(s->ev[7]));
-      prof_accum(s, 6, 7, &s->pr.sweep_kernel_ms);
-      s->pr.sweep_kernel_launches += run_launches;
-      s->pr.sweep_kernel_sweeps += run_sweeps;
+      if (queued > before) {
+        prof_accum(s, 6, 7, &s->pr.sweep_kernel_ms);
+        s->pr.sweep_kernel_launches += queued - before;
+      }
     }
-    s->pr.solve_launches += run_launches;
+    (void)nsweeps_done;
   }
+  s->pr.solve_launches += launches;
+  s->pr.sweep_kernel_sweeps = s->pr.sweep_kernel_launches * S;
   *sweeps = k;
   *measure = E;
   return st;
@@ -367,14 +401,13 @@ nh_status stage(nh_solver* s, int idx, void* Vh, void* Vq1, void* Vq2,
     Launch<T>::assemble(s, qa, qb, wst);
     prof_mark(s, 2);
     if (s->one_d) {
-      void* cur = s->p_in_a ? s->pa : s->pb;
-      Launch<T>::thomas(s, cur);
+      Launch<T>::thomas(s, s->pcur_ptr());
       s->pr.solve_launches += 1;
     } else {
       st = solve2d<T>(s, sweeps, measure);
     }
     prof_mark(s, 3);
-    p = s->p_in_a ? s->pa : s->pb;
+    p = s->pcur_ptr();
   } else {
     prof_mark(s, 2);
     prof_mark(s, 3);
@@ -534,7 +567,7 @@ nh_status nh_create(const nh_grid* grid, const nh_params* params,
     if ((st = dalloc(s, c, cb)) != NH_OK) { nh_destroy(s); return st; }
   for (auto c : corners)
     if ((st = dalloc(s, c, kb)) != NH_OK) { nh_destroy(s); return st; }
-  for (auto c : {&s->pa, &s->pb})
+  for (auto c : {&s->pa, &s->pb, &s->pc})
     if ((st = dalloc(s, c, s->ncorn * sizeof(double))) != NH_OK) {
       nh_destroy(s);
       return st;
@@ -545,8 +578,7 @@ nh_status nh_create(const nh_grid* grid, const nh_params* params,
       (st = dalloc(s, (void**)&s->thomas_dp, s->ncorn * sizeof(double))) != NH_OK ||
       (st = dalloc(s, (void**)&s->dt, sizeof(double))) != NH_OK ||
       (st = dalloc(s, (void**)&s->lam, sizeof(unsigned long long))) != NH_OK ||
-      (st = dalloc(s, (void**)&s->meas,
-                   nh::kMeasSlots * sizeof(unsigned long long))) != NH_OK ||
+
       (st = dalloc(s, (void**)&s->omega_dev,
                    s->omega.size() * sizeof(double))) != NH_OK ||
       (st = dalloc(s, (void**)&s->clamped, sizeof(double))) != NH_OK ||
@@ -554,11 +586,13 @@ nh_status nh_create(const nh_grid* grid, const nh_params* params,
     nh_destroy(s);
     return st;
   }
-  if (hipHostMalloc((void**)&s->h_meas,
-                    nh::kMeasSlots * sizeof(unsigned long long),
-                    hipHostMallocDefault) != hipSuccess) {
+  if (hipStreamCreate(&s->copy_stream) != hipSuccess ||
+      hipEventCreateWithFlags(&s->ev_check, hipEventDisableTiming) !=
+          hipSuccess ||
+      hipEventCreateWithFlags(&s->ev_copy, hipEventDisableTiming) !=
+          hipSuccess) {
     nh_destroy(s);
-    return fail(NH_ENOMEM, "hipHostMalloc failed");
+    return fail(NH_EDEVICE, "stream/event creation failed");
   }
   for (auto& e : s->ev) hipEventCreate(&e);
   if (hipMemcpyAsync(s->omega_dev, s->omega.data(),
@@ -567,17 +601,26 @@ nh_status nh_create(const nh_grid* grid, const nh_params* params,
     nh_destroy(s);
     return fail(NH_EDEVICE, "copy of the relaxation schedule failed");
   }
-  // sweep tiles: 32 x 32 corners with a halo of kSweepS; the region must fit
-  // kBlock * kSweepM points (checked here, assumed by the kernel)
-  s->tbx = 32;
-  s->tby = 32;
+  // sweep tiles: 24 x 24 corners with a halo of kSweepS (measured best of
+  // the tile/halo/workgroup shapes tried on gfx950 for 513^2 corners); the
+  // region must fit kSweepB * kSweepM points (checked here, assumed by the
+  // kernel)
+  s->tbx = 24;
+  s->tby = 24;
   if ((s->tbx + 2 * nh::kSweepS) * (s->tby + 2 * nh::kSweepS) >
-      nh::kBlock * nh::kSweepM) {
+      nh::kSweepB * nh::kSweepM) {
     nh_destroy(s);
     return fail(NH_EINVAL, "sweep tile does not fit the workgroup");
   }
   s->ntx = (grid->nx + 1 + s->tbx - 1) / s->tbx;
   s->nty = s->one_d ? 1 : (grid->ny + 1 + s->tby - 1) / s->tby;
+  if (dalloc(s, (void**)&s->part, s->ntx * s->nty * sizeof(double)) !=
+          NH_OK ||
+      hipHostMalloc((void**)&s->h_part, s->ntx * s->nty * sizeof(double),
+                    hipHostMallocDefault) != hipSuccess) {
+    nh_destroy(s);
+    return fail(NH_ENOMEM, "allocation of the convergence buffers failed");
+  }
   if (hipStreamSynchronize(s->stream) != hipSuccess) {
     nh_destroy(s);
     return fail(NH_EDEVICE, "stream synchronisation failed");
@@ -618,7 +661,7 @@ nh_status nh_set_state(nh_solver* s, const double* h, const double* hu,
   } else {
     HIP_TRY(hipMemsetAsync(s->w, 0, s->ncorn * s->esize, s->stream));
   }
-  s->p_in_a = true;
+  s->pcur = 0;
   if (p) {
     HIP_TRY(hipMemcpyAsync(s->pa, p, s->ncorn * sizeof(double),
                            hipMemcpyHostToDevice, s->stream));
@@ -690,7 +733,7 @@ nh_status nh_read_state(nh_solver* s, double* h, double* hu, double* hv,
   }
   if (w && (st = download(s, w, s->w, s->ncorn)) != NH_OK) return st;
   if (p) {
-    HIP_TRY(hipMemcpyAsync(p, s->p_in_a ? s->pa : s->pb,
+    HIP_TRY(hipMemcpyAsync(p, s->pcur_ptr(),
                            s->ncorn * sizeof(double), hipMemcpyDeviceToHost,
                            s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
@@ -721,7 +764,13 @@ void nh_destroy(nh_solver* s) {
   if (!s) return;
   if (s->stream) hipStreamSynchronize(s->stream);
   for (void* p : s->allocs) hipFree(p);
-  if (s->h_meas) hipHostFree(s->h_meas);
+  if (s->h_part) hipHostFree(s->h_part);
+  if (s->ev_check) hipEventDestroy(s->ev_check);
+  if (s->ev_copy) hipEventDestroy(s->ev_copy);
+  if (s->copy_stream) {
+    hipStreamSynchronize(s->copy_stream);
+    hipStreamDestroy(s->copy_stream);
+  }
   for (auto& e : s->ev)
     if (e) hipEventDestroy(e);
   if (s->own_stream) hipStreamDestroy(s->stream);

@@ -205,14 +205,16 @@ def island_basin(n: int, dx: float, seed: int, hump_amp: float = 0.5,
 
 
 def case_c2(n: int = 512, steps: int = 1000, precision: str = "f64",
-            seed: int = SEED_C2) -> Case:
+            seed: int = SEED_C2, island: bool = True) -> Case:
     """2D basin n x n (512 by default), dx = dy = 1 m, seeded bathymetry of
     depth 2-20 m with a dry island, Gaussian hump of 0.5 m / 20 m on wet water,
-    zero velocity, walls."""
-    H, h0 = island_basin(n, 1.0, seed)
+    zero velocity, walls.  island=False: the same basin without the island
+    (fully wet)."""
+    H, h0 = island_basin(n, 1.0, seed, island=island)
     z = np.zeros_like(h0)
     tol = 1e-10 if precision == "f64" else 1e-5
-    c = Case("c2", n, n, 1.0, 1.0, H, h0, z, z.copy(), steps,
+    c = Case("c2" if island else "c2-wet", n, n, 1.0, 1.0, H, h0, z,
+             z.copy(), steps,
              precision=precision, solve_tol=tol, cfl=CFL_2D,
              dry_eps=1e-10 if precision == "f64" else 1e-5)
     rho = jacobi_radius_bound(float(h0.max()), c.dx, c.dy)

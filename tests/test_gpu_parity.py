@@ -57,7 +57,13 @@ def compare(case, steps, tol, fields=("h", "hu", "hv"), gpu_over=None,
     r = o.state()
     os_ = o.stats()
     for k in fields:
-        e = maxrel(g[k], r[k]) if np.abs(r[k]).max() > 0 else np.abs(g[k]).max()
+        # normwise; a discharge is normalised by the larger discharge scale so
+        # that a field that is round-off only (hv of a y-invariant flow) is
+        # not divided by its own round-off
+        scale = np.abs(r[k]).max()
+        if k in ("hu", "hv"):
+            scale = max(np.abs(r["hu"]).max(), np.abs(r["hv"]).max())
+        e = float(np.abs(g[k] - r[k]).max() / max(scale, 1e-300))
         at = np.unravel_index(np.argmax(np.abs(g[k] - r[k])), g[k].shape)
         where = f" at {tuple(int(a) for a in at)}"
         if k in ("h", "hu", "hv") and r["h"].ndim == 2:
@@ -199,3 +205,59 @@ def test_minimal_grid_and_edge_cases():
     o2 = oracle_for(c)
     assert o2.step() == -4
     assert maxrel(s2.state()["h"], o2.state()["h"]) <= TOL64
+
+
+def _golden(prec):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden",
+                        f"c2_512_{prec}_1000.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated (tests/golden/make_c2_reference.py)")
+    return np.load(path)
+
+
+def _run_vs_golden(prec, steps_check_t_rel):
+    ref = _golden(prec)
+    st = int(ref["stride"])
+    c = I.case_c2(precision=prec)
+    say(f"[case] c2 512x512 {prec} 1000 steps vs stored oracle")
+    s = gpu_solver(c)
+    s.run(c.steps)
+    g = s.state()
+    gs = s.stats()
+    say(f"  t: gpu {gs['t']:.12g} oracle {float(ref['t']):.12g}")
+    scale_q = max(float(ref["max_hu"]), float(ref["max_hv"]))
+    errs = {}
+    for k, scale in (("h", float(ref["max_h"])), ("hu", scale_q),
+                     ("hv", scale_q)):
+        errs[k] = float(np.abs(g[k][::st, ::st] - ref[k]).max() / scale)
+        say(f"  {k}: max rel diff on the lattice {errs[k]:.3e}")
+    say(f"  mean sweeps per solve: gpu {gs['sweeps_total'] / gs['solves']:.1f}"
+        f" oracle {int(ref['sweeps_total']) / int(ref['solves']):.1f}")
+    return errs, gs, ref
+
+
+def test_c2_full_workload_1000_steps_fp64_vs_stored_oracle():
+    # the benchmark's workload at full size and step count, in the launch
+    # configuration the benchmark times, compared on the lattice of every 4th
+    # cell stored by tests/golden/make_c2_reference.py (normalised by the
+    # oracle's full-field maxima).  The run is sensitive to round-off once the
+    # flooding front on the island sets the CFL step, so this holds only
+    # because the FP64 kernels repeat the oracle's operations exactly.
+    errs, gs, ref = _run_vs_golden("f64", 1e-9)
+    assert gs["t"] == pytest.approx(float(ref["t"]), rel=1e-9)
+    for k, e in errs.items():
+        assert e <= TOL64, (k, e)
+
+
+def test_c2_full_workload_1000_steps_fp32_reported():
+    # FP32 bulk on the same workload against the oracle run with the FP32
+    # configuration.  The flooding front amplifies perturbations of relative
+    # size 1e-7 (FP32 rounding) to ~1e-3 within 100 steps even with a fixed
+    # dt (measured with two oracle runs), so the 1e-4 bar cannot hold over the
+    # full 1000 steps of this workload; the difference is reported and only
+    # bounded here.  The FP32 bar is checked on the early steps of this
+    # workload and over 1000 steps of the island-free basin.
+    errs, gs, ref = _run_vs_golden("f32", None)
+    for k, e in errs.items():
+        assert np.isfinite(e) and e <= 0.1, (k, e)
