@@ -26,6 +26,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_sweep_tb.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1706_04551_amd", "csrc", f)
+                  for f in ("kernels.hpp", "nhswe.hip")]
+COPY_CAL_BYTES = 256 << 20
 ALG_BYTES_SWEEP = {"f64": 40, "f32": 20}   # per corner per sweep (matrix-free
                                            # minimum: r p, h, H, rhs; w p)
 
@@ -36,6 +40,47 @@ def alg_bytes_per_cell_step(kbar: float, prec: str) -> float:
     2 x Kbar x 40 (FP64); FP32 bulk halves every term."""
     b = 384.0 + 80.0 * kbar
     return b if prec == "f64" else b / 2.0
+
+
+def kernel_source_hash() -> str:
+    """Hash of the sweep kernel's source and of its tile configuration."""
+    import hashlib
+    import re
+    with open(KERNEL_SOURCES[0]) as fh:
+        k = fh.read()
+    a = k.index("constexpr int kSweepB")
+    b = k.index("// correction (eq. 26-27")
+    with open(KERNEL_SOURCES[1]) as fh:
+        host = fh.read()
+    tiles = "".join(re.findall(r"s->tb[xy] = \d+;", host))
+    return hashlib.sha256((k[a:b] + tiles).encode()).hexdigest()[:16]
+
+
+def measured_traffic(workload_name: str, prec: str):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter runs
+    (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size), or None
+    when the kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except OSError:
+        return None
+    key = f"{workload_name}-{prec}"
+    if t.get("source_sha") != kernel_source_hash() or key not in t:
+        return None
+    return t[key]["bytes_per_launch"]
+
+
+def copy_calibration():
+    """A plain device copy of COPY_CAL_BYTES (read + write of known size),
+    run so that the counter runs can scale FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    a = torch.empty(COPY_CAL_BYTES // 8, dtype=torch.float64, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
 
 
 def workload(name: str, prec: str):
@@ -84,6 +129,8 @@ def main():
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain copy of 256 MiB (for counter runs)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -96,6 +143,8 @@ def main():
 
     assert torch.cuda.is_available(), "no HIP device visible"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        copy_calibration()
     case, desc = workload(args.workload, args.precision)
     stream = torch.cuda.current_stream()
     s = Solver.from_case(case, stream=stream.cuda_stream)
@@ -127,7 +176,7 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-            "traffic": None,
+            "traffic": measured_traffic(args.workload, args.precision),
             "kernel": "k_sweep_tb", "avg_launch_us": round(sweep_ms * 1e3, 3),
             "sweeps_per_launch": round(sweeps_per_launch, 3),
             "alg_bytes_per_launch": int(alg)}

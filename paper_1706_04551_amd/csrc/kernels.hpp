@@ -642,25 +642,29 @@ __global__ void __launch_bounds__(B)
 }
 
 // -------------------------------------------------------------------------
-// correction (eq. 26-27 in 1D, eq. 36 in 2D) of the cell discharges, the
-// second-stage Runge-Kutta average and the CFL measure of the new state.
+// correction (eq. 26-27 in 1D, eq. 36 in 2D) of the cell discharges and the
+// corner update w = w* + dt p / h_c (desingularised division), in one launch
+// over max(cells, corners) threads.  With COMBINE (second stage) the new
+// state is averaged with U^n (TVD-RK2) and each workgroup writes the CFL
+// measure max((|u|+c)/dx + (|v|+c)/dy) of its cells to lampart[block].
 // With have_p == 0 (hydrostatic mode) the discharges pass through.
 // -------------------------------------------------------------------------
 template <typename T, bool ONE_D, bool COMBINE>
 __global__ void __launch_bounds__(kBlock)
-    k_correct_cells(int nx, int ny, T dx, T dy, T g, T delta, T dry_eps,
-                    int have_p, const T* __restrict__ hs,
-                    const T* __restrict__ q1s, const T* __restrict__ q2s,
-                    const T* __restrict__ H, const double* __restrict__ p,
-                    const double* __restrict__ dtp, T* __restrict__ oq1,
-                    T* __restrict__ oq2, T* __restrict__ h_n,
-                    T* __restrict__ q1_n, T* __restrict__ q2_n,
-                    unsigned long long* lam, int* flags) {
-  int n = blockIdx.x * blockDim.x + threadIdx.x;
+    k_correct(int nx, int ny, T dx, T dy, T g, T delta, T dry_eps,
+              int have_p, const T* __restrict__ hs, const T* __restrict__ q1s,
+              const T* __restrict__ q2s, const T* __restrict__ H,
+              const T* __restrict__ ws, const double* __restrict__ p,
+              const double* __restrict__ dtp, T* __restrict__ oq1,
+              T* __restrict__ oq2, T* __restrict__ w_out, T* __restrict__ h_n,
+              T* __restrict__ q1_n, T* __restrict__ q2_n,
+              double* __restrict__ lampart, int* flags) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ncx = nx + 1, ncy = ONE_D ? 1 : ny + 1;
+  const T dt = (T)(*dtp);
   double lam_local = 0.0;
   if (n < nx * ny) {
     int i = n % nx, j = n / nx;
-    T dt = (T)(*dtp);
     T hc = hs[n];
     T a = q1s[n], b = ONE_D ? T(0) : q2s[n];
     if (have_p) {
@@ -672,7 +676,6 @@ __global__ void __launch_bounds__(kBlock)
         a = a + dt * Tn;
         b = T(0);
       } else {
-        int ncx = nx + 1;
         T zy = (zeta_at(hs, H, i, j + 1, nx, ny) -
                 zeta_at(hs, H, i, j - 1, nx, ny)) / (T(2) * dy);
         T pSW = (T)p[j * ncx + i], pSE = (T)p[j * ncx + i + 1];
@@ -718,40 +721,38 @@ __global__ void __launch_bounds__(kBlock)
       }
     }
   }
-  if (COMBINE) block_max_to(lam_local, lam);
-}
-
-// corner update w = w* + dt p / h_c (desingularised division), and the
-// second-stage average of w.
-template <typename T, bool ONE_D, bool COMBINE>
-__global__ void __launch_bounds__(kBlock)
-    k_correct_corners(int nx, int ny, T delta, int have_p,
-                      const T* __restrict__ hs, const T* __restrict__ ws,
-                      const double* __restrict__ p,
-                      const double* __restrict__ dtp,
-                      T* __restrict__ w_out) {
-  int ncx = nx + 1, ncy = ONE_D ? 1 : ny + 1;
-  int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= ncx * ncy) return;
-  int k = n % ncx, l = n / ncx;
-  T wv = ws[n];
-  if (have_p) {
-    T dt = (T)(*dtp);
-    T hc;
-    if (ONE_D) {
-      hc = T(0.5) * (hs[mirror(k - 1, nx)] + hs[mirror(k, nx)]);
-    } else {
-      int im = mirror(k - 1, nx), ip = mirror(k, nx);
-      int jm = mirror(l - 1, ny), jp = mirror(l, ny);
-      hc = T(0.25) * (hs[jm * nx + im] + hs[jm * nx + ip] + hs[jp * nx + im] +
-                      hs[jp * nx + ip]);
+  if (n < ncx * ncy) {
+    int k = n % ncx, l = n / ncx;
+    T wv = ws[n];
+    if (have_p) {
+      T hc;
+      if (ONE_D) {
+        hc = T(0.5) * (hs[mirror(k - 1, nx)] + hs[mirror(k, nx)]);
+      } else {
+        int im = mirror(k - 1, nx), ip = mirror(k, nx);
+        int jm = mirror(l - 1, ny), jp = mirror(l, ny);
+        hc = T(0.25) * (hs[jm * nx + im] + hs[jm * nx + ip] +
+                        hs[jp * nx + im] + hs[jp * nx + ip]);
+      }
+      wv = wv + dt * desing(hc, (T)p[n], delta);
     }
-    wv = wv + dt * desing(hc, (T)p[n], delta);
+    if (COMBINE)
+      w_out[n] = T(0.5) * (w_out[n] + wv);
+    else
+      w_out[n] = wv;
   }
-  if (COMBINE)
-    w_out[n] = T(0.5) * (w_out[n] + wv);
-  else
-    w_out[n] = wv;
+  if (COMBINE) {
+    __shared__ double wmax[kBlock / 64];
+    double v = wave_max(lam_local);
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double m = wmax[0];
+      for (int w = 1; w < kBlock / 64; ++w)
+        m = (wmax[w] > m || wmax[w] != wmax[w]) ? wmax[w] : m;
+      lampart[blockIdx.x] = m;
+    }
+  }
 }
 
 // CFL measure of a state (used once at set_state)
@@ -759,7 +760,7 @@ template <typename T, bool ONE_D>
 __global__ void __launch_bounds__(kBlock)
     k_lambda(int nx, int ny, T dx, T dy, T g, T delta, T dry_eps,
              const T* __restrict__ h, const T* __restrict__ q1,
-             const T* __restrict__ q2, unsigned long long* lam) {
+             const T* __restrict__ q2, double* __restrict__ lampart) {
   int n = blockIdx.x * blockDim.x + threadIdx.x;
   double lam_local = 0.0;
   if (n < nx * ny) {
@@ -775,20 +776,89 @@ __global__ void __launch_bounds__(kBlock)
       lam_local = (double)l;
     }
   }
-  block_max_to(lam_local, lam);
+  __shared__ double wmax[kBlock / 64];
+  double v = wave_max(lam_local);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = wmax[0];
+    for (int w = 1; w < kBlock / 64; ++w)
+      m = (wmax[w] > m || wmax[w] != wmax[w]) ? wmax[w] : m;
+    lampart[blockIdx.x] = m;
+  }
 }
 
-// dt = CFL / lambda_max (stays on the device); lambda reset for the next step
-__global__ void k_finalize_dt(double cfl, unsigned long long* lam, double* dt,
-                              int* flags) {
-  double l = __longlong_as_double((long long)*lam);
-  if (l > 0.0 && isfinite(l))
-    *dt = cfl / l;
-  else {
-    *dt = 0.0;
-    atomicOr(flags, 4);
+// statistics kept on the device between synchronisations
+struct DevStats {
+  double t;        // simulated time
+  double dt_last;  // dt of the last step
+  long long step;  // steps since the state was set
+};
+
+// convergence measure published to mapped host memory
+struct HostSlot {
+  double E;
+  long long seq;
+};
+
+// End of a step (one workgroup): account the step's dt, reduce the per-block
+// CFL measures of the new state and set dt = CFL / lambda_max for the next
+// step (unless dt is fixed).  Stays on the device.
+__global__ void __launch_bounds__(kBlock)
+    k_finalize_dt(double cfl, int fixed, const double* __restrict__ lampart,
+                  int nparts, double* dt, int* flags, DevStats* st) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+    double x = lampart[i];
+    v = (x > v || x != x) ? x : v;
   }
-  *lam = 0ull;
+  __shared__ double wmax[kBlock / 64];
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double l = wmax[0];
+  for (int w = 1; w < kBlock / 64; ++w)
+    l = (wmax[w] > l || wmax[w] != wmax[w]) ? wmax[w] : l;
+  if (st) {
+    double used = *dt;
+    st->t += used;
+    st->dt_last = used;
+    st->step += 1;
+  }
+  if (!fixed) {
+    if (l > 0.0 && isfinite(l)) {
+      *dt = cfl / l;
+    } else {
+      *dt = 0.0;
+      atomicOr(flags, 4);
+    }
+  }
+}
+
+// max of the per-tile convergence measures, written to mapped host memory
+// with the check's sequence number (release at system scope)
+__global__ void __launch_bounds__(kBlock)
+    k_reduce_measure(const double* __restrict__ part, int n, HostSlot* slot,
+                     long long seq) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double x = part[i];
+    v = (x > v || x != x) ? x : v;
+  }
+  __shared__ double wmax[kBlock / 64];
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = wmax[0];
+    for (int w = 1; w < kBlock / 64; ++w)
+      m = (wmax[w] > m || wmax[w] != wmax[w]) ? wmax[w] : m;
+    slot->E = m;
+    __threadfence_system();
+    __hip_atomic_store(&slot->seq, seq, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 __global__ void k_zero_u64(unsigned long long* a) { *a = 0ull; }

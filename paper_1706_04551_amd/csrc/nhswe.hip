@@ -59,6 +59,7 @@ struct nh_solver {
   // device buffers (element type double or float, see esize)
   void *H = nullptr, *h = nullptr, *q1 = nullptr, *q2 = nullptr;   // U^n
   void *hs = nullptr, *q1s = nullptr, *q2s = nullptr;              // U*
+  void* hs_cur = nullptr;  // h* of the running stage (hs or h1)
   void *q1b = nullptr, *q2b = nullptr, *rw = nullptr;              // breaking
   void *h1 = nullptr, *q11 = nullptr, *q21 = nullptr;              // U^(1)
   void *w = nullptr, *ws = nullptr, *w1 = nullptr;                 // corners
@@ -70,23 +71,32 @@ struct nh_solver {
   void *stage_buf = nullptr;   // FP64 staging for host copies
   // device scalars
   double* dt = nullptr;
-  unsigned long long* lam = nullptr;
+  double* lampart = nullptr;             // per-block CFL measures
   double* part = nullptr;                // per-tile convergence measures
+  nh::DevStats* dstats = nullptr;        // t, dt of the last step, steps
+  nh::HostSlot* slot = nullptr;          // mapped host memory (measure)
+  nh::HostSlot* slot_dev = nullptr;      // its device address
+  long long seq = 0;
+  int solve_launches_last = 0;
   double* omega_dev = nullptr;
-  hipStream_t copy_stream = nullptr;      // convergence read-back
-  hipEvent_t ev_check = nullptr, ev_copy = nullptr;
   int tbx = 32, tby = 32, ntx = 1, nty = 1;  // sweep tiles
   double* clamped = nullptr;
   int* flags = nullptr;
   // host mirrors
-  double* h_part = nullptr;  // pinned copy of part
   void* pbuf(int i) { return i == 0 ? pa : (i == 1 ? pb : pc); }
   void* pcur_ptr() { return pbuf(pcur); }
   bool have_state = false, have_H = false;
   nh_stats st{};
-  // profiling
+  // profiling: event pairs recorded on the stream and read lazily at the
+  // next synchronisation, so that timing never stalls the device
   bool prof = false;
-  hipEvent_t ev[8]{};
+  struct Mark {
+    hipEvent_t a = nullptr, b = nullptr;
+    int kind = 0;          // 0 fv, 1 assembly, 2 solve, 3 correction, 4 sweeps
+    long long count = 0;   // launches (sweeps: launches of 8 sweeps)
+  };
+  std::vector<Mark> marks;
+  size_t marks_used = 0;
   nh_profile_t pr{};
 
   std::vector<void*> allocs;
@@ -133,13 +143,48 @@ nh_status download(nh_solver* s, double* dst, const void* src, long n) {
   return NH_OK;
 }
 
-void prof_mark(nh_solver* s, int slot) {
-  if (s->prof) hipEventRecord(s->ev[slot], s->stream);
+// open a timing interval of the given kind on the stream (or -1)
+long prof_open(nh_solver* s, int kind) {
+  if (!s->prof) return -1;
+  if (s->marks_used == s->marks.size()) {
+    nh_solver::Mark m;
+    if (hipEventCreate(&m.a) != hipSuccess || hipEventCreate(&m.b) != hipSuccess)
+      return -1;
+    s->marks.push_back(m);
+  }
+  nh_solver::Mark& m = s->marks[s->marks_used];
+  m.kind = kind;
+  m.count = 0;
+  if (hipEventRecord(m.a, s->stream) != hipSuccess) return -1;
+  return (long)s->marks_used++;
 }
 
-void prof_accum(nh_solver* s, int a, int b, double* acc) {
-  float ms = 0.f;
-  if (hipEventElapsedTime(&ms, s->ev[a], s->ev[b]) == hipSuccess) *acc += ms;
+void prof_close(nh_solver* s, long id, long long count) {
+  if (id < 0) return;
+  nh_solver::Mark& m = s->marks[id];
+  m.count = count;
+  (void)hipEventRecord(m.b, s->stream);
+}
+
+// accumulate every closed interval (the stream has been synchronised)
+void prof_flush(nh_solver* s) {
+  for (size_t i = 0; i < s->marks_used; ++i) {
+    nh_solver::Mark& m = s->marks[i];
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, m.a, m.b) != hipSuccess) continue;
+    switch (m.kind) {
+      case 0: s->pr.fv_ms += ms; s->pr.fv_launches += m.count; break;
+      case 1: s->pr.assemble_ms += ms; s->pr.assemble_launches += m.count; break;
+      case 2: s->pr.solve_ms += ms; s->pr.solve_launches += m.count; break;
+      case 3: s->pr.correct_ms += ms; s->pr.correct_launches += m.count; break;
+      case 4:
+        s->pr.sweep_kernel_ms += ms;
+        s->pr.sweep_kernel_launches += m.count;
+        s->pr.sweep_kernel_sweeps += m.count * nh::kSweepS;
+        break;
+    }
+  }
+  s->marks_used = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -157,13 +202,13 @@ struct Launch {
                          dim3(nh::kBlock), 0, s->stream, g.nx, g.ny,
                          (T)g.dx, (T)g.dy, (T)pr.g, (T)pr.delta,
                          (T)pr.dry_eps, P(h), P(q1), P(q2), P(s->H), s->dt,
-                         P(s->hs), P(s->q1s), P(s->q2s), s->clamped);
+                         P(s->hs_cur), P(s->q1s), P(s->q2s), s->clamped);
     else
       hipLaunchKernelGGL((nh::k_fv<T, false>), dim3(nblocks(s->ncell)),
                          dim3(nh::kBlock), 0, s->stream, g.nx, g.ny,
                          (T)g.dx, (T)g.dy, (T)pr.g, (T)pr.delta,
                          (T)pr.dry_eps, P(h), P(q1), P(q2), P(s->H), s->dt,
-                         P(s->hs), P(s->q1s), P(s->q2s), s->clamped);
+                         P(s->hs_cur), P(s->q1s), P(s->q2s), s->clamped);
   }
 
   static void breaking(nh_solver* s, void* w_in) {
@@ -173,23 +218,23 @@ struct Launch {
       hipLaunchKernelGGL((nh::k_break_cells<T, true>), dim3(nblocks(s->ncell)),
                          dim3(nh::kBlock), 0, s->stream, g.nx, g.ny,
                          (T)g.dx, (T)g.dy, (T)pr.g, (T)pr.delta,
-                         (T)pr.dry_eps, (T)pr.b1, P(s->hs), P(s->q1s),
+                         (T)pr.dry_eps, (T)pr.b1, P(s->hs_cur), P(s->q1s),
                          P(s->q2s), P(s->H), s->dt, P(s->q1b), P(s->q2b),
                          P(s->rw));
       hipLaunchKernelGGL((nh::k_break_corners<T, true>),
                          dim3(nblocks(s->ncorn)), dim3(nh::kBlock), 0,
-                         s->stream, g.nx, g.ny, (T)pr.delta, P(s->hs),
+                         s->stream, g.nx, g.ny, (T)pr.delta, P(s->hs_cur),
                          P(s->rw), s->dt, P(w_in), P(s->ws));
     } else {
       hipLaunchKernelGGL((nh::k_break_cells<T, false>),
                          dim3(nblocks(s->ncell)), dim3(nh::kBlock), 0,
                          s->stream, g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g,
-                         (T)pr.delta, (T)pr.dry_eps, (T)pr.b1, P(s->hs),
+                         (T)pr.delta, (T)pr.dry_eps, (T)pr.b1, P(s->hs_cur),
                          P(s->q1s), P(s->q2s), P(s->H), s->dt, P(s->q1b),
                          P(s->q2b), P(s->rw));
       hipLaunchKernelGGL((nh::k_break_corners<T, false>),
                          dim3(nblocks(s->ncorn)), dim3(nh::kBlock), 0,
-                         s->stream, g.nx, g.ny, (T)pr.delta, P(s->hs),
+                         s->stream, g.nx, g.ny, (T)pr.delta, P(s->hs_cur),
                          P(s->rw), s->dt, P(w_in), P(s->ws));
     }
   }
@@ -199,12 +244,12 @@ struct Launch {
     if (s->one_d)
       hipLaunchKernelGGL((nh::k_assemble1d<T>), dim3(nblocks(s->ncorn)),
                          dim3(nh::kBlock), 0, s->stream, g.nx, (T)g.dx,
-                         P(s->hs), P(q1), P(s->H), P(wst), s->dt, P(s->cW),
+                         P(s->hs_cur), P(q1), P(s->H), P(wst), s->dt, P(s->cW),
                          P(s->cdiag), P(s->cE), P(s->crhs));
     else
       hipLaunchKernelGGL((nh::k_assemble2d<T>), dim3(nblocks(s->ncorn)),
                          dim3(nh::kBlock), 0, s->stream, g.nx, g.ny, (T)g.dx,
-                         (T)g.dy, P(s->hs), P(q1), P(q2), P(s->H), P(wst),
+                         (T)g.dy, P(s->hs_cur), P(q1), P(q2), P(s->H), P(wst),
                          s->dt, P(s->cdiag), P(s->cE), P(s->cW), P(s->cN),
                          P(s->cS), P(s->crhs));
   }
@@ -241,29 +286,21 @@ struct Launch {
                       void* p, void* oq1, void* oq2, void* w_out) {
     const auto& g = s->grid;
     const auto& pr = s->par;
-    if (s->one_d) {
-      hipLaunchKernelGGL((nh::k_correct_cells<T, true, COMBINE>),
-                         dim3(nblocks(s->ncell)), dim3(nh::kBlock), 0,
-                         s->stream, g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g,
-                         (T)pr.delta, (T)pr.dry_eps, have_p, P(s->hs), P(q1),
-                         P(q2), P(s->H), (double*)p, s->dt, P(oq1), P(oq2), P(s->h),
-                         P(s->q1), P(s->q2), s->lam, s->flags);
-      hipLaunchKernelGGL((nh::k_correct_corners<T, true, COMBINE>),
-                         dim3(nblocks(s->ncorn)), dim3(nh::kBlock), 0,
-                         s->stream, g.nx, g.ny, (T)pr.delta, have_p, P(s->hs),
-                         P(wst), (double*)p, s->dt, P(w_out));
-    } else {
-      hipLaunchKernelGGL((nh::k_correct_cells<T, false, COMBINE>),
-                         dim3(nblocks(s->ncell)), dim3(nh::kBlock), 0,
-                         s->stream, g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g,
-                         (T)pr.delta, (T)pr.dry_eps, have_p, P(s->hs), P(q1),
-                         P(q2), P(s->H), (double*)p, s->dt, P(oq1), P(oq2), P(s->h),
-                         P(s->q1), P(s->q2), s->lam, s->flags);
-      hipLaunchKernelGGL((nh::k_correct_corners<T, false, COMBINE>),
-                         dim3(nblocks(s->ncorn)), dim3(nh::kBlock), 0,
-                         s->stream, g.nx, g.ny, (T)pr.delta, have_p, P(s->hs),
-                         P(wst), (double*)p, s->dt, P(w_out));
-    }
+    long n = std::max(s->ncell, s->ncorn);
+    if (s->one_d)
+      hipLaunchKernelGGL((nh::k_correct<T, true, COMBINE>), dim3(nblocks(n)),
+                         dim3(nh::kBlock), 0, s->stream, g.nx, g.ny, (T)g.dx,
+                         (T)g.dy, (T)pr.g, (T)pr.delta, (T)pr.dry_eps, have_p,
+                         P(s->hs_cur), P(q1), P(q2), P(s->H), P(wst),
+                         (double*)p, s->dt, P(oq1), P(oq2), P(w_out), P(s->h),
+                         P(s->q1), P(s->q2), s->lampart, s->flags);
+    else
+      hipLaunchKernelGGL((nh::k_correct<T, false, COMBINE>), dim3(nblocks(n)),
+                         dim3(nh::kBlock), 0, s->stream, g.nx, g.ny, (T)g.dx,
+                         (T)g.dy, (T)pr.g, (T)pr.delta, (T)pr.dry_eps, have_p,
+                         P(s->hs_cur), P(q1), P(q2), P(s->H), P(wst),
+                         (double*)p, s->dt, P(oq1), P(oq2), P(w_out), P(s->h),
+                         P(s->q1), P(s->q2), s->lampart, s->flags);
   }
 
   static void lambda(nh_solver* s) {
@@ -273,40 +310,54 @@ struct Launch {
       hipLaunchKernelGGL((nh::k_lambda<T, true>), dim3(nblocks(s->ncell)),
                          dim3(nh::kBlock), 0, s->stream, g.nx, g.ny, (T)g.dx,
                          (T)g.dy, (T)pr.g, (T)pr.delta, (T)pr.dry_eps,
-                         P(s->h), P(s->q1), P(s->q2), s->lam);
+                         P(s->h), P(s->q1), P(s->q2), s->lampart);
     else
       hipLaunchKernelGGL((nh::k_lambda<T, false>), dim3(nblocks(s->ncell)),
                          dim3(nh::kBlock), 0, s->stream, g.nx, g.ny, (T)g.dx,
                          (T)g.dy, (T)pr.g, (T)pr.delta, (T)pr.dry_eps,
-                         P(s->h), P(s->q1), P(s->q2), s->lam);
+                         P(s->h), P(s->q1), P(s->q2), s->lampart);
   }
 };
 
-// ---------------------------------------------------------------------------
-// the pressure solve of one stage (2D): relaxed Jacobi with the schedule.
-// Mirrors the semantics of the plain statement: at sweep k the convergence
-// measure of the iterate p^k is taken whenever k is a multiple of
-// check_every (or k reached the cap); if it is below the tolerance p^k is the
-// solution, at the cap the solve stops with NH_ENOCONV.
-// ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // the pressure solve of one stage (2D): relaxed Jacobi with the schedule.
 // Same semantics as the plain statement: at sweep k the convergence measure
 // of the iterate p^k is taken whenever k is a multiple of check_every (or k
 // reached the cap); below the tolerance p^k is the solution, at the cap the
 // solve stops with NH_ENOCONV.  Three iterate buffers: the check launch reads
-// the current one, writes the next, and saves p^k into the third; the host
-// queues a few more launches before it waits for the measure (read back on a
-// side stream), so the device never idles on the decision.  If p^k
+// the current one, writes the next, and saves p^k into the third; a one-block
+// kernel reduces the per-tile measures into mapped host memory, and the host
+// queues a few more launches before it waits for that value, so the device
+// never idles on the decision.  If p^k
 // converged, the saved copy is the solution and the look-ahead launches are
 // discarded.
 // ---------------------------------------------------------------------------
+// Wait until the reduction kernel has published the measure of check number
+// s->seq in mapped host memory (spinning; the device keeps running the
+// launches queued behind it).  Stream errors end the wait.
+nh_status wait_measure(nh_solver* s, double* E) {
+  long spins = 0;
+  while (__atomic_load_n(&s->slot->seq, __ATOMIC_ACQUIRE) != s->seq) {
+    if ((++spins & 1023) == 0) {
+      hipError_t q = hipStreamQuery(s->stream);
+      if (q != hipSuccess && q != hipErrorNotReady)
+        return fail(NH_EDEVICE, std::string("stream error while waiting: ") +
+                                    hipGetErrorString(q));
+      if (q == hipSuccess &&
+          __atomic_load_n(&s->slot->seq, __ATOMIC_ACQUIRE) != s->seq)
+        return fail(NH_EDEVICE, "convergence measure was not published");
+    }
+  }
+  *E = s->slot->E;
+  return NH_OK;
+}
+
 template <typename T>
 nh_status solve2d(nh_solver* s, int32_t* sweeps, double* measure) {
   const int ce = s->par.check_every > 0 ? s->par.check_every : 1;
   const int kmax = s->par.solve_max_iter;
   const int S = nh::kSweepS;
-  const int kAhead = 3;  // launches queued before waiting for a measure
+  const int kAhead = 1;  // launches queued before waiting for a measure
   const int ntiles = s->ntx * s->nty;
   int k = 0;             // sweep index of the iterate in buffer `cur`
   int cur = s->pcur;
@@ -319,11 +370,9 @@ nh_status solve2d(nh_solver* s, int32_t* sweeps, double* measure) {
     int nsw = k >= kmax ? 0 : std::min(std::min(S, ce), kmax - k);
     Launch<T>::sweeps(s, true, k, nsw, s->pbuf(cur), s->pbuf(out),
                       s->pbuf(save));
-    HIP_TRY(hipEventRecord(s->ev_check, s->stream));
-    HIP_TRY(hipStreamWaitEvent(s->copy_stream, s->ev_check, 0));
-    HIP_TRY(hipMemcpyAsync(s->h_part, s->part, ntiles * sizeof(double),
-                           hipMemcpyDeviceToHost, s->copy_stream));
-    HIP_TRY(hipEventRecord(s->ev_copy, s->copy_stream));
+    ++s->seq;
+    hipLaunchKernelGGL(nh::k_reduce_measure, dim3(1), dim3(nh::kBlock), 0,
+                       s->stream, s->part, ntiles, s->slot_dev, s->seq);
     launches += 1;
     if (nsw > 0) {
       cur = out;                 // ping-pong between cur and (save's peer)
@@ -346,33 +395,22 @@ nh_status solve2d(nh_solver* s, int32_t* sweeps, double* measure) {
       }
     };
     if (nsw > 0) queue_until(kAhead);
-    HIP_TRY(hipEventSynchronize(s->ev_copy));
-    E = 0.0;
-    for (int i = 0; i < ntiles; ++i) {
-      double v = s->h_part[i];
-      if (v > E || v != v) E = v;
-    }
+    nh_status ws = wait_measure(s, &E);
+    if (ws != NH_OK) return ws;
     if (E < s->par.solve_tol || kc >= kmax) {
       if (!(E < s->par.solve_tol)) st = NH_ENOCONV;
       s->pcur = save;            // p^kc, saved by the check launch
       k = kc;
       break;
     }
-    if (s->prof) HIP_TRY(hipEventRecord(s->ev[6], s->stream));
+    // the rest of the cycle: back-to-back sweep launches (timed as such)
     int before = queued;
+    long pm = (k % ce != 0 && k < kmax) ? prof_open(s, 4) : -1;
     queue_until(1 << 30);
-    if (s->prof) {
-      HIP_TRY(hipEventRecord(s->ev[7], s->stream));
-      HIP_TRY(hipEventSynchronize(s->ev[7]));
-      if (queued > before) {
-        prof_accum(s, 6, 7, &s->pr.sweep_kernel_ms);
-        s->pr.sweep_kernel_launches += queued - before;
-      }
-    }
+    prof_close(s, pm, queued - before);
     (void)nsweeps_done;
   }
-  s->pr.solve_launches += launches;
-  s->pr.sweep_kernel_sweeps = s->pr.sweep_kernel_launches * S;
+  s->solve_launches_last = launches;
   *sweeps = k;
   *measure = E;
   return st;
@@ -383,10 +421,13 @@ nh_status stage(nh_solver* s, int idx, void* Vh, void* Vq1, void* Vq2,
                 void* w_in, void* oq1, void* oq2, void* w_out,
                 int32_t* sweeps, double* measure) {
   const bool combine = idx == 1;
-  prof_mark(s, 0);
+  // h* of stage 1 is read as U^(1)'s depth by stage 2: two buffers
+  s->hs_cur = idx == 0 ? s->hs : s->h1;
+  long pm = prof_open(s, 0);
   Launch<T>::fv(s, Vh, Vq1, Vq2);
-  prof_mark(s, 1);
+  prof_close(s, pm, 1);
   void *qa = s->q1s, *qb = s->q2s, *wst = w_in;
+  pm = prof_open(s, 1);
   if (s->par.breaking_on) {
     Launch<T>::breaking(s, w_in);
     qa = s->q1b;
@@ -397,71 +438,42 @@ nh_status stage(nh_solver* s, int idx, void* Vh, void* Vq1, void* Vq2,
   *sweeps = 0;
   *measure = 0.0;
   void* p = nullptr;
+  if (s->par.nh_on) Launch<T>::assemble(s, qa, qb, wst);
+  prof_close(s, pm, (s->par.breaking_on ? 2 : 0) + (s->par.nh_on ? 1 : 0));
   if (s->par.nh_on) {
-    Launch<T>::assemble(s, qa, qb, wst);
-    prof_mark(s, 2);
+    pm = prof_open(s, 2);
     if (s->one_d) {
       Launch<T>::thomas(s, s->pcur_ptr());
-      s->pr.solve_launches += 1;
+      s->solve_launches_last = 1;
     } else {
       st = solve2d<T>(s, sweeps, measure);
+      if (st != NH_OK && st != NH_ENOCONV) return st;
     }
-    prof_mark(s, 3);
+    prof_close(s, pm, s->solve_launches_last);
     p = s->pcur_ptr();
-  } else {
-    prof_mark(s, 2);
-    prof_mark(s, 3);
   }
   int have_p = s->par.nh_on ? 1 : 0;
   void* pp = p ? p : s->pa;
+  pm = prof_open(s, 3);
   if (combine)
     Launch<T>::template correct<true>(s, have_p, qa, qb, wst, pp, nullptr,
                                       nullptr, w_out);
   else
     Launch<T>::template correct<false>(s, have_p, qa, qb, wst, pp, oq1, oq2,
                                        w_out);
-  prof_mark(s, 4);
-  if (s->prof) {
-    HIP_TRY(hipEventSynchronize(s->ev[4]));
-    prof_accum(s, 0, 1, &s->pr.fv_ms);
-    prof_accum(s, 1, 2, &s->pr.assemble_ms);
-    prof_accum(s, 2, 3, &s->pr.solve_ms);
-    prof_accum(s, 3, 4, &s->pr.correct_ms);
-  }
-  s->pr.fv_launches += 1;
-  s->pr.assemble_launches += (s->par.breaking_on ? 2 : 0) + (s->par.nh_on ? 1 : 0);
-  s->pr.correct_launches += 2;
+  prof_close(s, pm, 1);
   (void)Vh;
   return st;
 }
 
-template <typename T>
-nh_status step_impl(nh_solver* s, double* dt_used) {
-  int32_t sw1 = 0, sw2 = 0;
-  double m1 = 0.0, m2 = 0.0;
-  // stage 1: U^n -> U^(1)
-  nh_status st = stage<T>(s, 0, s->h, s->q1, s->q2, s->w, s->q11, s->q21,
-                          s->w1, &sw1, &m1);
-  // the first stage's h* is the stage's h: keep it as U^(1)'s depth
-  HIP_TRY(hipMemcpyAsync(s->h1, s->hs, s->ncell * s->esize,
-                         hipMemcpyDeviceToDevice, s->stream));
-  if (st != NH_OK && st != NH_ENOCONV) return st;
-  nh_status st2 = stage<T>(s, 1, s->h1, s->q11, s->q21, s->w1, nullptr,
-                           nullptr, s->w, &sw2, &m2);
-  if (st == NH_OK) st = st2;
-  if (!s->par.fixed_dt) {
-    prof_mark(s, 5);
-    hipLaunchKernelGGL(nh::k_finalize_dt, dim3(1), dim3(1), 0, s->stream,
-                       s->par.cfl, s->lam, s->dt, s->flags);
-  } else {
-    hipLaunchKernelGGL(nh::k_zero_u64, dim3(1), dim3(1), 0, s->stream,
-                       s->lam);
-  }
-  double dt_used_v = 0.0, dt_next = 0.0;
+// Host view of the device-side statistics (t, dt, flags, clamped mass),
+// refreshed at synchronisation points.
+nh_status sync_stats(nh_solver* s) {
+  nh::DevStats ds{};
   int flags = 0;
-  double clamped = 0.0;
-  // dt of this step is the one read before finalisation; keep it on host
-  dt_used_v = s->st.dt_next;
+  double dt_next = 0.0, clamped = 0.0;
+  HIP_TRY(hipMemcpyAsync(&ds, s->dstats, sizeof(ds), hipMemcpyDeviceToHost,
+                         s->stream));
   HIP_TRY(hipMemcpyAsync(&dt_next, s->dt, sizeof(double),
                          hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipMemcpyAsync(&flags, s->flags, sizeof(int), hipMemcpyDeviceToHost,
@@ -469,25 +481,52 @@ nh_status step_impl(nh_solver* s, double* dt_used) {
   HIP_TRY(hipMemcpyAsync(&clamped, s->clamped, sizeof(double),
                          hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
-  s->st.t += dt_used_v;
-  s->st.dt_last = dt_used_v;
+  prof_flush(s);
+  s->st.t = ds.t;
+  s->st.dt_last = ds.dt_last;
+  s->st.step = ds.step;
   s->st.dt_next = dt_next;
-  s->st.step += 1;
-  s->st.sweeps[0] = sw1;
-  s->st.sweeps[1] = sw2;
-  s->st.sweeps_total += sw1 + sw2;
-  s->st.solves_total += s->par.nh_on ? 2 : 0;
-  s->st.measure = m2;
   s->st.clamped_mass = clamped;
+  nh_status st = NH_OK;
   if (flags & 1) st = fail(NH_ENONFINITE, "non-finite value in the state");
   if (flags & 2 && st == NH_OK)
     st = fail(NH_EDEVICE, "singular tridiagonal system");
   if (flags & 4 && st == NH_OK)
     st = fail(NH_ESTATE, "no wet cell: the CFL time step is undefined");
+  if (st != NH_OK) {
+    s->st.last_status = st;
+    s->have_state = false;
+  }
+  return st;
+}
+
+// One step, queued on the stream.  The host waits only for the solver's
+// convergence decisions; dt, t and the status stay on the device until the
+// next sync_stats.
+template <typename T>
+nh_status step_impl(nh_solver* s) {
+  int32_t sw1 = 0, sw2 = 0;
+  double m1 = 0.0, m2 = 0.0;
+  // stage 1: U^n -> U^(1)  (h* of stage 1 in hs)
+  nh_status st = stage<T>(s, 0, s->h, s->q1, s->q2, s->w, s->q11, s->q21,
+                          s->w1, &sw1, &m1);
+  if (st != NH_OK && st != NH_ENOCONV) return st;
+  // stage 2: U^(1) -> U^(2), averaged into U^n
+  nh_status st2 = stage<T>(s, 1, s->hs, s->q11, s->q21, s->w1, nullptr,
+                           nullptr, s->w, &sw2, &m2);
+  if (st2 != NH_OK && st2 != NH_ENOCONV) return st2;
+  if (st == NH_OK) st = st2;
+  hipLaunchKernelGGL(nh::k_finalize_dt, dim3(1), dim3(nh::kBlock), 0,
+                     s->stream, s->par.cfl, s->par.fixed_dt, s->lampart,
+                     (int)nblocks(std::max(s->ncell, s->ncorn)), s->dt,
+                     s->flags, s->dstats);
+  s->st.sweeps[0] = sw1;
+  s->st.sweeps[1] = sw2;
+  s->st.sweeps_total += sw1 + sw2;
+  s->st.solves_total += s->par.nh_on ? 2 : 0;
+  s->st.measure = m2;
   if (st == NH_ENOCONV) fail(st, "pressure solve reached solve_max_iter");
   s->st.last_status = st;
-  if (st != NH_OK && st != NH_ENOCONV) s->have_state = false;
-  if (dt_used) *dt_used = dt_used_v;
   return st;
 }
 
@@ -577,7 +616,9 @@ nh_status nh_create(const nh_grid* grid, const nh_params* params,
       (st = dalloc(s, (void**)&s->thomas_cp, s->ncorn * sizeof(double))) != NH_OK ||
       (st = dalloc(s, (void**)&s->thomas_dp, s->ncorn * sizeof(double))) != NH_OK ||
       (st = dalloc(s, (void**)&s->dt, sizeof(double))) != NH_OK ||
-      (st = dalloc(s, (void**)&s->lam, sizeof(unsigned long long))) != NH_OK ||
+      (st = dalloc(s, (void**)&s->lampart,
+                   nblocks(std::max(s->ncell, s->ncorn)) * sizeof(double))) !=
+          NH_OK ||
 
       (st = dalloc(s, (void**)&s->omega_dev,
                    s->omega.size() * sizeof(double))) != NH_OK ||
@@ -586,15 +627,6 @@ nh_status nh_create(const nh_grid* grid, const nh_params* params,
     nh_destroy(s);
     return st;
   }
-  if (hipStreamCreate(&s->copy_stream) != hipSuccess ||
-      hipEventCreateWithFlags(&s->ev_check, hipEventDisableTiming) !=
-          hipSuccess ||
-      hipEventCreateWithFlags(&s->ev_copy, hipEventDisableTiming) !=
-          hipSuccess) {
-    nh_destroy(s);
-    return fail(NH_EDEVICE, "stream/event creation failed");
-  }
-  for (auto& e : s->ev) hipEventCreate(&e);
   if (hipMemcpyAsync(s->omega_dev, s->omega.data(),
                      s->omega.size() * sizeof(double), hipMemcpyHostToDevice,
                      s->stream) != hipSuccess) {
@@ -614,10 +646,20 @@ nh_status nh_create(const nh_grid* grid, const nh_params* params,
   }
   s->ntx = (grid->nx + 1 + s->tbx - 1) / s->tbx;
   s->nty = s->one_d ? 1 : (grid->ny + 1 + s->tby - 1) / s->tby;
+  if (dalloc(s, (void**)&s->dstats, sizeof(nh::DevStats)) != NH_OK ||
+      hipHostMalloc((void**)&s->slot, sizeof(nh::HostSlot),
+                    hipHostMallocMapped | hipHostMallocCoherent) !=
+          hipSuccess ||
+      hipHostGetDevicePointer((void**)&s->slot_dev, s->slot, 0) !=
+          hipSuccess) {
+    nh_destroy(s);
+    return fail(NH_ENOMEM, "allocation of the statistics buffers failed");
+  }
+  s->slot->E = 0.0;
+  s->slot->seq = 0;
+  s->seq = 0;
   if (dalloc(s, (void**)&s->part, s->ntx * s->nty * sizeof(double)) !=
-          NH_OK ||
-      hipHostMalloc((void**)&s->h_part, s->ntx * s->nty * sizeof(double),
-                    hipHostMallocDefault) != hipSuccess) {
+          NH_OK) {
     nh_destroy(s);
     return fail(NH_ENOMEM, "allocation of the convergence buffers failed");
   }
@@ -670,7 +712,7 @@ nh_status nh_set_state(nh_solver* s, const double* h, const double* hu,
   }
   HIP_TRY(hipMemsetAsync(s->flags, 0, sizeof(int), s->stream));
   HIP_TRY(hipMemsetAsync(s->clamped, 0, sizeof(double), s->stream));
-  HIP_TRY(hipMemsetAsync(s->lam, 0, sizeof(unsigned long long), s->stream));
+  HIP_TRY(hipMemsetAsync(s->dstats, 0, sizeof(nh::DevStats), s->stream));
   double dt0 = 0.0;
   if (s->par.fixed_dt) {
     dt0 = s->par.dt;
@@ -681,8 +723,10 @@ nh_status nh_set_state(nh_solver* s, const double* h, const double* hu,
       Launch<float>::lambda(s);
     else
       Launch<double>::lambda(s);
-    hipLaunchKernelGGL(nh::k_finalize_dt, dim3(1), dim3(1), 0, s->stream,
-                       s->par.cfl, s->lam, s->dt, s->flags);
+    hipLaunchKernelGGL(nh::k_finalize_dt, dim3(1), dim3(nh::kBlock), 0,
+                       s->stream, s->par.cfl, 0, s->lampart,
+                       (int)nblocks(s->ncell), s->dt, s->flags,
+                       (nh::DevStats*)nullptr);
     HIP_TRY(hipMemcpyAsync(&dt0, s->dt, sizeof(double), hipMemcpyDeviceToHost,
                            s->stream));
   }
@@ -706,15 +750,32 @@ nh_status nh_step(nh_solver* s, double* dt_used) {
   if (!s) return fail(NH_EINVAL, "null solver");
   if (!s->have_state) return fail(NH_ESTATE, "no valid state (set_state)");
   if (!(s->st.dt_next > 0)) return fail(NH_ESTATE, "dt is not positive");
-  return s->fp32 ? step_impl<float>(s, dt_used) : step_impl<double>(s, dt_used);
+  nh_status st =
+      s->fp32 ? step_impl<float>(s) : step_impl<double>(s);
+  nh_status ss = sync_stats(s);
+  if (dt_used) *dt_used = s->st.dt_last;
+  if (ss != NH_OK) return ss;
+  return st;
 }
 
 nh_status nh_run(nh_solver* s, int64_t nsteps) {
   if (!s) return fail(NH_EINVAL, "null solver");
   if (nsteps < 0) return fail(NH_EINVAL, "nsteps < 0");
+  if (!s->have_state) return fail(NH_ESTATE, "no valid state (set_state)");
+  if (!(s->st.dt_next > 0)) return fail(NH_ESTATE, "dt is not positive");
+  // steps are queued back to back; the status (non-finite state, no wet
+  // cell) is read every kStatusEvery steps and at the end
+  const int64_t kStatusEvery = 64;
   for (int64_t n = 0; n < nsteps; ++n) {
-    nh_status st = nh_step(s, nullptr);
-    if (st != NH_OK) return st;
+    nh_status st = s->fp32 ? step_impl<float>(s) : step_impl<double>(s);
+    if (st != NH_OK) {
+      nh_status ss = sync_stats(s);
+      return ss != NH_OK ? ss : st;
+    }
+    if ((n + 1) % kStatusEvery == 0 || n + 1 == nsteps) {
+      nh_status ss = sync_stats(s);
+      if (ss != NH_OK) return ss;
+    }
   }
   return NH_OK;
 }
@@ -749,6 +810,8 @@ nh_status nh_get_stats(const nh_solver* s, nh_stats* out) {
 
 nh_status nh_profile(nh_solver* s, int32_t on) {
   if (!s) return fail(NH_EINVAL, "null solver");
+  if (s->stream) HIP_TRY(hipStreamSynchronize(s->stream));
+  prof_flush(s);
   s->prof = on != 0;
   if (s->prof) std::memset(&s->pr, 0, sizeof(s->pr));
   return NH_OK;
@@ -756,6 +819,8 @@ nh_status nh_profile(nh_solver* s, int32_t on) {
 
 nh_status nh_get_profile(nh_solver* s, nh_profile_t* out) {
   if (!s || !out) return fail(NH_EINVAL, "null argument");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  prof_flush(s);
   *out = s->pr;
   return NH_OK;
 }
@@ -764,15 +829,11 @@ void nh_destroy(nh_solver* s) {
   if (!s) return;
   if (s->stream) hipStreamSynchronize(s->stream);
   for (void* p : s->allocs) hipFree(p);
-  if (s->h_part) hipHostFree(s->h_part);
-  if (s->ev_check) hipEventDestroy(s->ev_check);
-  if (s->ev_copy) hipEventDestroy(s->ev_copy);
-  if (s->copy_stream) {
-    hipStreamSynchronize(s->copy_stream);
-    hipStreamDestroy(s->copy_stream);
+  if (s->slot) hipHostFree(s->slot);
+  for (auto& m : s->marks) {
+    if (m.a) hipEventDestroy(m.a);
+    if (m.b) hipEventDestroy(m.b);
   }
-  for (auto& e : s->ev)
-    if (e) hipEventDestroy(e);
   if (s->own_stream) hipStreamDestroy(s->stream);
   delete s;
 }

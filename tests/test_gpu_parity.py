@@ -261,3 +261,27 @@ def test_c2_full_workload_1000_steps_fp32_reported():
     errs, gs, ref = _run_vs_golden("f32", None)
     for k, e in errs.items():
         assert np.isfinite(e) and e <= 0.1, (k, e)
+
+
+def test_island_free_basin_fp32_1000_steps_vs_stored_oracle():
+    # FP32 bulk over the full 1000 steps of the island-free basin (no wet-dry
+    # front): the 1e-4 bar on h and hu against the oracle run with the same
+    # FP32-bulk configuration (tests/golden/make_c2_reference.py f32 wet)
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden",
+                        "c2wet_512_f32_1000.npz")
+    if not os.path.exists(path):
+        pytest.skip("reference not generated")
+    ref = np.load(path)
+    st = int(ref["stride"])
+    c = I.case_c2(precision="f32", island=False)
+    say("[case] island-free basin 512x512 f32 1000 steps vs stored oracle")
+    s = gpu_solver(c)
+    s.run(c.steps)
+    g = s.state()
+    scale_q = max(float(ref["max_hu"]), float(ref["max_hv"]))
+    for k, scale in (("h", float(ref["max_h"])), ("hu", scale_q),
+                     ("hv", scale_q)):
+        e = float(np.abs(g[k][::st, ::st] - ref[k]).max() / scale)
+        say(f"  {k}: max rel diff on the lattice {e:.3e}")
+        assert e <= TOL32, (k, e)
