@@ -221,19 +221,31 @@ __device__ __forceinline__ double block_sum(double v) {
 // finite-volume stage: U* = V - dt (fluctuations + volume terms), eq. (20),
 // (30); positivity clamp and dry discharge.
 // -------------------------------------------------------------------------
+template <typename T>
+struct FvArgs {
+  int nx, ny;
+  T dx, dy, g, delta, dry_eps;
+  const T *h, *q1, *q2, *H;
+  const double* dtp;
+  T *oh, *oq1, *oq2;
+  double* clamped;
+  __host__ __device__ int nblocks() const { return (nx * ny + kBlock - 1) / kBlock; }
+};
+
 template <typename T, bool ONE_D>
-__global__ void __launch_bounds__(kBlock)
-    k_fv(int nx, int ny, T dx, T dy, T g, T delta, T dry_eps,
-         const T* __restrict__ h, const T* __restrict__ q1,
-         const T* __restrict__ q2, const T* __restrict__ H,
-         const double* __restrict__ dtp, T* __restrict__ oh,
-         T* __restrict__ oq1, T* __restrict__ oq2, double* clamped) {
-  int n = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void fv_body(const FvArgs<T>& a, int bid) {
+  const int n = bid * kBlock + (int)threadIdx.x;
+  const int nx = a.nx, ny = a.ny;
+  const T dx = a.dx, dy = a.dy, g = a.g, delta = a.delta, dry_eps = a.dry_eps;
+  const T* __restrict__ h = a.h;
+  const T* __restrict__ q1 = a.q1;
+  const T* __restrict__ q2 = a.q2;
+  const T* __restrict__ H = a.H;
   int ncell = nx * ny;
   double clamp_local = 0.0;
   if (n < ncell) {
     int i = n % nx, j = n / nx;
-    T dt = (T)(*dtp);
+    T dt = (T)(*a.dtp);
     Prim<T> P[5];
     Cell<T> c0;
 #pragma unroll
@@ -268,47 +280,60 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
       for (int m = 0; m < 3; ++m) fy[m] = (Dm_e[m] + Dp_w[m]) + I[m];
     }
-    T hs, a, b;
+    T hs, qa, qb;
     if (ONE_D) {
       hs = c0.h - dt * (fx[0] / dx);
-      a = c0.q1 - dt * (fx[1] / dx);
-      b = T(0);
+      qa = c0.q1 - dt * (fx[1] / dx);
+      qb = T(0);
     } else {
       hs = c0.h - dt * (fx[0] / dx + fy[0] / dy);
-      a = c0.q1 - dt * (fx[1] / dx + fy[2] / dy);
-      b = c0.q2 - dt * (fx[2] / dx + fy[1] / dy);
+      qa = c0.q1 - dt * (fx[1] / dx + fy[2] / dy);
+      qb = c0.q2 - dt * (fx[2] / dx + fy[1] / dy);
     }
     if (hs < T(0)) {
       clamp_local = -(double)hs * (double)dx * (ONE_D ? 1.0 : (double)dy);
       hs = T(0);
     }
     if (hs <= dry_eps) {
-      a = T(0);
-      b = T(0);
+      qa = T(0);
+      qb = T(0);
     }
-    oh[n] = hs;
-    oq1[n] = a;
-    if (!ONE_D) oq2[n] = b;
+    a.oh[n] = hs;
+    a.oq1[n] = qa;
+    if (!ONE_D) a.oq2[n] = qb;
   }
   double s = block_sum(clamp_local);
-  if (threadIdx.x == 0 && s > 0.0) atomicAdd(clamped, s);
+  if (threadIdx.x == 0 && s > 0.0) atomicAdd(a.clamped, s);
 }
 
 // -------------------------------------------------------------------------
 // breaking terms (Section 3): nu = max(0, 1 - div q / U1) h |div q|,
 // U1 = B1 sqrt(g h); q += dt 2 nu (div u) grad H; rw = 2 nu div u at cells.
 // -------------------------------------------------------------------------
+template <typename T>
+struct BreakCellsArgs {
+  int nx, ny;
+  T dx, dy, g, delta, dry_eps, b1;
+  const T *h, *q1, *q2, *H;
+  const double* dtp;
+  T *oq1, *oq2, *rw;
+  __host__ __device__ int nblocks() const { return (nx * ny + kBlock - 1) / kBlock; }
+};
+
 template <typename T, bool ONE_D>
-__global__ void __launch_bounds__(kBlock)
-    k_break_cells(int nx, int ny, T dx, T dy, T g, T delta, T dry_eps, T b1,
-                  const T* __restrict__ h, const T* __restrict__ q1,
-                  const T* __restrict__ q2, const T* __restrict__ H,
-                  const double* __restrict__ dtp, T* __restrict__ oq1,
-                  T* __restrict__ oq2, T* __restrict__ rw) {
-  int n = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void break_cells_body(const BreakCellsArgs<T>& a,
+                                                 int bid) {
+  const int n = bid * kBlock + (int)threadIdx.x;
+  const int nx = a.nx, ny = a.ny;
+  const T dx = a.dx, dy = a.dy, g = a.g, delta = a.delta, dry_eps = a.dry_eps,
+          b1 = a.b1;
+  const T* __restrict__ h = a.h;
+  const T* __restrict__ q1 = a.q1;
+  const T* __restrict__ q2 = a.q2;
+  const T* __restrict__ H = a.H;
   if (n >= nx * ny) return;
   int i = n % nx, j = n / nx;
-  T dt = (T)(*dtp);
+  T dt = (T)(*a.dtp);
   Cell<T> e = load_cell(h, q1, q2, H, i + 1, j, nx, ny, ONE_D);
   Cell<T> w = load_cell(h, q1, q2, H, i - 1, j, nx, ny, ONE_D);
   T divq = (e.q1 - w.q1) / (T(2) * dx);
@@ -331,21 +356,36 @@ __global__ void __launch_bounds__(kBlock)
     if (B > T(0)) nu = B * hc * fabs(divq);
   }
   T r = T(2) * nu * divu;
-  rw[n] = r;
-  oq1[n] = q1[n] + dt * r * Hx;
-  if (!ONE_D) oq2[n] = q2[n] + dt * r * Hy;
+  a.rw[n] = r;
+  a.oq1[n] = q1[n] + dt * r * Hx;
+  if (!ONE_D) a.oq2[n] = q2[n] + dt * r * Hy;
 }
 
+template <typename T>
+struct BreakCornersArgs {
+  int nx, ny;
+  T delta;
+  const T *h, *rw;
+  const double* dtp;
+  const T* w_in;
+  T* w_out;
+  __host__ __device__ int nblocks(bool one_d) const {
+    return ((nx + 1) * (one_d ? 1 : ny + 1) + kBlock - 1) / kBlock;
+  }
+};
+
 template <typename T, bool ONE_D>
-__global__ void __launch_bounds__(kBlock)
-    k_break_corners(int nx, int ny, T delta, const T* __restrict__ h,
-                    const T* __restrict__ rw, const double* __restrict__ dtp,
-                    const T* __restrict__ w_in, T* __restrict__ w_out) {
+__device__ __forceinline__ void break_corners_body(
+    const BreakCornersArgs<T>& a, int bid) {
+  const int nx = a.nx, ny = a.ny;
+  const T delta = a.delta;
+  const T* __restrict__ h = a.h;
+  const T* __restrict__ rw = a.rw;
   int ncx = nx + 1, ncy = ONE_D ? 1 : ny + 1;
-  int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = bid * kBlock + (int)threadIdx.x;
   if (n >= ncx * ncy) return;
   int k = n % ncx, l = n / ncx;
-  T dt = (T)(*dtp);
+  T dt = (T)(*a.dtp);
   T hc, rwc;
   if (ONE_D) {
     int W = mirror(k - 1, nx), E = mirror(k, nx);
@@ -359,7 +399,7 @@ __global__ void __launch_bounds__(kBlock)
     hc = T(0.25) * (h[SW] + h[SE] + h[NW] + h[NE]);
     rwc = T(0.25) * (rw[SW] + rw[SE] + rw[NW] + rw[NE]);
   }
-  w_out[n] = w_in[n] + dt * desing(hc, rwc, delta);
+  a.w_out[n] = a.w_in[n] + dt * desing(hc, rwc, delta);
 }
 
 // -------------------------------------------------------------------------
@@ -376,21 +416,32 @@ __device__ __forceinline__ T zeta_at(const T* __restrict__ h,
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock)
-    k_assemble2d(int nx, int ny, T dx, T dy, const T* __restrict__ h,
-                 const T* __restrict__ q1, const T* __restrict__ q2,
-                 const T* __restrict__ H, const T* __restrict__ w,
-                 const double* __restrict__ dtp, T* __restrict__ diag,
-                 T* __restrict__ cE, T* __restrict__ cW, T* __restrict__ cN,
-                 T* __restrict__ cS, T* __restrict__ rhs) {
+struct AssembleArgs {
+  int nx, ny;
+  T dx, dy;
+  const T *h, *q1, *q2, *H, *w;
+  const double* dtp;
+  T *diag, *cE, *cW, *cN, *cS, *rhs;
+  __host__ __device__ int nblocks() const { return ((nx + 1) * (ny + 1) + kBlock - 1) / kBlock; }
+};
+
+template <typename T>
+__device__ __forceinline__ void assemble2d_body(const AssembleArgs<T>& a,
+                                                int bid) {
+  const int nx = a.nx, ny = a.ny;
+  const T dx = a.dx, dy = a.dy;
+  const T* __restrict__ h = a.h;
+  const T* __restrict__ q1 = a.q1;
+  const T* __restrict__ q2 = a.q2;
+  const T* __restrict__ H = a.H;
   int ncx = nx + 1, ncy = ny + 1;
-  int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = bid * kBlock + (int)threadIdx.x;
   if (n >= ncx * ncy) return;
   int k = n % ncx, l = n / ncx;
-  T dt = (T)(*dtp);
+  T dt = (T)(*a.dtp);
   const int ci[4] = {k - 1, k, k - 1, k};  // SW, SE, NW, NE
   const int cj[4] = {l - 1, l - 1, l, l};
-  T hh[4], zz[4], XX[4], YY[4], a1[4], a2[4];
+  T hh[4], zz[4], XX[4], YY[4], a1[4], a2[4];  // a1, a2: q1, q2 of the cells
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     Cell<T> c = load_cell(h, q1, q2, H, ci[s], cj[s], nx, ny, false);
@@ -425,18 +476,18 @@ __global__ void __launch_bounds__(kBlock)
   T ss = (T(2) * hc + sy) * (YS - T(2) * hS) / dy2;
   T Bs = ((T(2) * hc - sx) * q1E - (T(2) * hc + sx) * q1W) / dx +
          ((T(2) * hc - sy) * q2N - (T(2) * hc + sy) * q2S) / dy +
-         T(4) * hc * w[n];
+         T(4) * hc * a.w[n];
   T r = -(T(4) / dt) * Bs;
   if (k == 0) { e = e + wv; wv = T(0); }
   if (k == nx) { wv = wv + e; e = T(0); }
   if (l == 0) { nn = nn + ss; ss = T(0); }
   if (l == ny) { ss = ss + nn; nn = T(0); }
-  diag[n] = d;
-  cE[n] = e;
-  cW[n] = wv;
-  cN[n] = nn;
-  cS[n] = ss;
-  rhs[n] = r;
+  a.diag[n] = d;
+  a.cE[n] = e;
+  a.cW[n] = wv;
+  a.cN[n] = nn;
+  a.cS[n] = ss;
+  a.rhs[n] = r;
 }
 
 // 1D: eq. (43) coefficients, rows scaled by dx^2, with the right-hand side
@@ -536,20 +587,43 @@ constexpr int kSweepS = 8;     // sweeps per launch (= halo width)
 constexpr int kSweepM = 2;     // region points per thread:
                                // (BX+2S)(BY+2S) <= kSweepB * kSweepM
 
+// per-grid arguments of the sweep kernel
+template <typename T>
+struct SweepArgs {
+  int ncx, ncy, BX, BY, ntx, ntiles;
+  const T *diag, *cE, *cW, *cN, *cS, *rhs;
+  double* p[3];          // iterate buffers
+  const double* omega;   // relaxation schedule
+  int nom;
+  double* part;          // per-tile convergence measures
+  __host__ __device__ int nblocks() const { return 8 * ((ntiles + 7) / 8); }
+};
+
+// per-launch arguments (common to every grid of a batch)
+struct SweepLaunch {
+  int iin, iout, isave;  // buffers read, written, saved (check launch)
+  int k0, nsw, check;
+};
+
 template <typename T, int B, int S, int M>
-__global__ void __launch_bounds__(B)
-    k_sweep_tb(int ncx, int ncy, int BX, int BY, int ntx, int ntiles,
-               const T* __restrict__ dgl, const T* __restrict__ cE,
-               const T* __restrict__ cW, const T* __restrict__ cN,
-               const T* __restrict__ cS, const T* __restrict__ rhs,
-               const double* __restrict__ pin,
-               double* __restrict__ pout, const double* __restrict__ omega,
-               int nom, int k0, int nsw, int check,
-               double* __restrict__ part, double* __restrict__ psave) {
-  extern __shared__ double lds[];
-  const int per = (int)gridDim.x / 8;
-  const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-  if (tile >= ntiles) return;  // uniform over the workgroup
+__device__ __forceinline__ void sweep_body(const SweepArgs<T>& a,
+                                           const SweepLaunch& L, int bid,
+                                           double* lds) {
+  const int ncx = a.ncx, ncy = a.ncy, BX = a.BX, BY = a.BY, ntx = a.ntx;
+  const T* __restrict__ dgl = a.diag;
+  const T* __restrict__ cE = a.cE;
+  const T* __restrict__ cW = a.cW;
+  const T* __restrict__ cN = a.cN;
+  const T* __restrict__ cS = a.cS;
+  const T* __restrict__ rhs = a.rhs;
+  const double* __restrict__ pin = a.p[L.iin];
+  double* __restrict__ pout = a.p[L.iout];
+  double* __restrict__ psave = a.p[L.isave];
+  const double* __restrict__ omega = a.omega;
+  const int nom = a.nom, k0 = L.k0, nsw = L.nsw, check = L.check;
+  const int per = a.nblocks() / 8;
+  const int tile = (bid % 8) * per + (bid / 8);
+  if (tile >= a.ntiles) return;  // uniform over the workgroup
   const int tx = tile % ntx, ty = tile / ntx;
   const int RW = BX + 2 * S, RH = BY + 2 * S, R = RW * RH;
   const int x0 = tx * BX - S, y0 = ty * BY - S;
@@ -636,7 +710,7 @@ __global__ void __launch_bounds__(B)
       double mx = wmax[0];
       for (int w = 1; w < B / 64; ++w)
         mx = (wmax[w] > mx || wmax[w] != wmax[w]) ? wmax[w] : mx;
-      part[tile] = mx;
+      a.part[tile] = mx;
     }
   }
 }
@@ -649,32 +723,47 @@ __global__ void __launch_bounds__(B)
 // measure max((|u|+c)/dx + (|v|+c)/dy) of its cells to lampart[block].
 // With have_p == 0 (hydrostatic mode) the discharges pass through.
 // -------------------------------------------------------------------------
+template <typename T>
+struct CorrectArgs {
+  int nx, ny;
+  T dx, dy, g, delta, dry_eps;
+  int have_p;
+  const T *hs, *q1s, *q2s, *H, *ws;
+  const double* p;
+  const double* dtp;
+  T *oq1, *oq2, *w_out, *h_n, *q1_n, *q2_n;
+  double* lampart;
+  int* flags;
+  __host__ __device__ int nblocks(bool one_d) const {
+    int nc = nx * ny, nk = (nx + 1) * (one_d ? 1 : ny + 1);
+    return ((nc > nk ? nc : nk) + kBlock - 1) / kBlock;
+  }
+};
+
 template <typename T, bool ONE_D, bool COMBINE>
-__global__ void __launch_bounds__(kBlock)
-    k_correct(int nx, int ny, T dx, T dy, T g, T delta, T dry_eps,
-              int have_p, const T* __restrict__ hs, const T* __restrict__ q1s,
-              const T* __restrict__ q2s, const T* __restrict__ H,
-              const T* __restrict__ ws, const double* __restrict__ p,
-              const double* __restrict__ dtp, T* __restrict__ oq1,
-              T* __restrict__ oq2, T* __restrict__ w_out, T* __restrict__ h_n,
-              T* __restrict__ q1_n, T* __restrict__ q2_n,
-              double* __restrict__ lampart, int* flags) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void correct_body(const CorrectArgs<T>& a,
+                                             int bid) {
+  const int n = bid * kBlock + (int)threadIdx.x;
+  const int nx = a.nx, ny = a.ny, have_p = a.have_p;
+  const T dx = a.dx, dy = a.dy, g = a.g, delta = a.delta, dry_eps = a.dry_eps;
+  const T* __restrict__ hs = a.hs;
+  const T* __restrict__ H = a.H;
+  const double* __restrict__ p = a.p;
   const int ncx = nx + 1, ncy = ONE_D ? 1 : ny + 1;
-  const T dt = (T)(*dtp);
+  const T dt = (T)(*a.dtp);
   double lam_local = 0.0;
   if (n < nx * ny) {
     int i = n % nx, j = n / nx;
     T hc = hs[n];
-    T a = q1s[n], b = ONE_D ? T(0) : q2s[n];
+    T qa = a.q1s[n], qb = ONE_D ? T(0) : a.q2s[n];
     if (have_p) {
       T zx = (zeta_at(hs, H, i + 1, j, nx, ONE_D ? 1 : ny) -
               zeta_at(hs, H, i - 1, j, nx, ONE_D ? 1 : ny)) / (T(2) * dx);
       if (ONE_D) {
         T pR = (T)p[i + 1], pL = (T)p[i];
         T Tn = -T(0.5) * (hc * ((pR - pL) / dx) + (T(0.5) * (pR + pL)) * zx);
-        a = a + dt * Tn;
-        b = T(0);
+        qa = qa + dt * Tn;
+        qb = T(0);
       } else {
         T zy = (zeta_at(hs, H, i, j + 1, nx, ny) -
                 zeta_at(hs, H, i, j - 1, nx, ny)) / (T(2) * dy);
@@ -688,27 +777,27 @@ __global__ void __launch_bounds__(kBlock)
                T(0.5) * (T(0.5) * (pNE + pSE)) * zy;
         T TW = -T(0.5) * hc * (pNW - pSW) / dy -
                T(0.5) * (T(0.5) * (pNW + pSW)) * zy;
-        a = a + dt * (T(0.5) * (TN + TS));
-        b = b + dt * (T(0.5) * (TE + TW));
+        qa = qa + dt * (T(0.5) * (TN + TS));
+        qb = qb + dt * (T(0.5) * (TE + TW));
       }
       if (hc <= dry_eps) {
-        a = T(0);
-        b = T(0);
+        qa = T(0);
+        qb = T(0);
       }
     }
     if (!COMBINE) {
-      oq1[n] = a;
-      if (!ONE_D) oq2[n] = b;
+      a.oq1[n] = qa;
+      if (!ONE_D) a.oq2[n] = qb;
     } else {
-      T hn = T(0.5) * (h_n[n] + hc);
-      T an = T(0.5) * (q1_n[n] + a);
-      T bn = ONE_D ? T(0) : T(0.5) * (q2_n[n] + b);
-      h_n[n] = hn;
-      q1_n[n] = an;
-      if (!ONE_D) q2_n[n] = bn;
+      T hn = T(0.5) * (a.h_n[n] + hc);
+      T an = T(0.5) * (a.q1_n[n] + qa);
+      T bn = ONE_D ? T(0) : T(0.5) * (a.q2_n[n] + qb);
+      a.h_n[n] = hn;
+      a.q1_n[n] = an;
+      if (!ONE_D) a.q2_n[n] = bn;
       if (!isfinite((double)hn) || !isfinite((double)an) ||
           !isfinite((double)bn))
-        atomicOr(flags, 1);
+        atomicOr(a.flags, 1);
       if (hn > dry_eps) {
         T cel = sqrt(g * hn);
         T u = desing(hn, an, delta);
@@ -723,7 +812,7 @@ __global__ void __launch_bounds__(kBlock)
   }
   if (n < ncx * ncy) {
     int k = n % ncx, l = n / ncx;
-    T wv = ws[n];
+    T wv = a.ws[n];
     if (have_p) {
       T hc;
       if (ONE_D) {
@@ -737,9 +826,9 @@ __global__ void __launch_bounds__(kBlock)
       wv = wv + dt * desing(hc, (T)p[n], delta);
     }
     if (COMBINE)
-      w_out[n] = T(0.5) * (w_out[n] + wv);
+      a.w_out[n] = T(0.5) * (a.w_out[n] + wv);
     else
-      w_out[n] = wv;
+      a.w_out[n] = wv;
   }
   if (COMBINE) {
     __shared__ double wmax[kBlock / 64];
@@ -750,28 +839,35 @@ __global__ void __launch_bounds__(kBlock)
       double m = wmax[0];
       for (int w = 1; w < kBlock / 64; ++w)
         m = (wmax[w] > m || wmax[w] != wmax[w]) ? wmax[w] : m;
-      lampart[blockIdx.x] = m;
+      a.lampart[bid] = m;
     }
   }
 }
 
-// CFL measure of a state (used once at set_state)
+// CFL measure of a state (used at set_state): per-block maxima of
+// (|u|+c)/dx + (|v|+c)/dy over the wet cells into lampart[block]
+template <typename T>
+struct LambdaArgs {
+  int nx, ny;
+  T dx, dy, g, delta, dry_eps;
+  const T *h, *q1, *q2;
+  double* lampart;
+  __host__ __device__ int nblocks() const { return (nx * ny + kBlock - 1) / kBlock; }
+};
+
 template <typename T, bool ONE_D>
-__global__ void __launch_bounds__(kBlock)
-    k_lambda(int nx, int ny, T dx, T dy, T g, T delta, T dry_eps,
-             const T* __restrict__ h, const T* __restrict__ q1,
-             const T* __restrict__ q2, double* __restrict__ lampart) {
-  int n = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void lambda_body(const LambdaArgs<T>& a, int bid) {
+  const int n = bid * kBlock + (int)threadIdx.x;
   double lam_local = 0.0;
-  if (n < nx * ny) {
-    T hn = h[n];
-    if (hn > dry_eps) {
-      T cel = sqrt(g * hn);
-      T u = desing(hn, q1[n], delta);
-      T l = (fabs(u) + cel) / dx;
+  if (n < a.nx * a.ny) {
+    T hn = a.h[n];
+    if (hn > a.dry_eps) {
+      T cel = sqrt(a.g * hn);
+      T u = desing(hn, a.q1[n], a.delta);
+      T l = (fabs(u) + cel) / a.dx;
       if (!ONE_D) {
-        T v = desing(hn, q2[n], delta);
-        l = l + (fabs(v) + cel) / dy;
+        T v = desing(hn, a.q2[n], a.delta);
+        l = l + (fabs(v) + cel) / a.dy;
       }
       lam_local = (double)l;
     }
@@ -784,7 +880,7 @@ __global__ void __launch_bounds__(kBlock)
     double m = wmax[0];
     for (int w = 1; w < kBlock / 64; ++w)
       m = (wmax[w] > m || wmax[w] != wmax[w]) ? wmax[w] : m;
-    lampart[blockIdx.x] = m;
+    a.lampart[bid] = m;
   }
 }
 
@@ -795,21 +891,24 @@ struct DevStats {
   long long step;  // steps since the state was set
 };
 
-// convergence measure published to mapped host memory
-struct HostSlot {
-  double E;
-  long long seq;
-};
 
 // End of a step (one workgroup): account the step's dt, reduce the per-block
 // CFL measures of the new state and set dt = CFL / lambda_max for the next
 // step (unless dt is fixed).  Stays on the device.
-__global__ void __launch_bounds__(kBlock)
-    k_finalize_dt(double cfl, int fixed, const double* __restrict__ lampart,
-                  int nparts, double* dt, int* flags, DevStats* st) {
+struct FinalizeArgs {
+  double cfl;
+  int fixed;
+  const double* lampart;
+  int nparts;
+  double* dt;
+  int* flags;
+  DevStats* st;
+};
+
+__device__ __forceinline__ void finalize_body(const FinalizeArgs& a) {
   double v = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
-    double x = lampart[i];
+  for (int i = threadIdx.x; i < a.nparts; i += blockDim.x) {
+    double x = a.lampart[i];
     v = (x > v || x != x) ? x : v;
   }
   __shared__ double wmax[kBlock / 64];
@@ -820,43 +919,51 @@ __global__ void __launch_bounds__(kBlock)
   double l = wmax[0];
   for (int w = 1; w < kBlock / 64; ++w)
     l = (wmax[w] > l || wmax[w] != wmax[w]) ? wmax[w] : l;
-  if (st) {
-    double used = *dt;
-    st->t += used;
-    st->dt_last = used;
-    st->step += 1;
+  if (a.st) {
+    double used = *a.dt;
+    a.st->t += used;
+    a.st->dt_last = used;
+    a.st->step += 1;
   }
-  if (!fixed) {
+  if (!a.fixed) {
     if (l > 0.0 && isfinite(l)) {
-      *dt = cfl / l;
+      *a.dt = a.cfl / l;
     } else {
-      *dt = 0.0;
-      atomicOr(flags, 4);
+      *a.dt = 0.0;
+      atomicOr(a.flags, 4);
     }
   }
 }
 
-// max of the per-tile convergence measures, written to mapped host memory
-// with the check's sequence number (release at system scope)
+// max of the per-tile convergence measures of each grid, written to mapped
+// host memory, then the check's sequence number (release at system scope)
 __global__ void __launch_bounds__(kBlock)
-    k_reduce_measure(const double* __restrict__ part, int n, HostSlot* slot,
+    k_reduce_measure(const double* const* __restrict__ parts,
+                     const int* __restrict__ nparts, int ngrids,
+                     double* __restrict__ E, long long* seq_slot,
                      long long seq) {
-  double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    double x = part[i];
-    v = (x > v || x != x) ? x : v;
-  }
   __shared__ double wmax[kBlock / 64];
-  v = wave_max(v);
-  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
-  __syncthreads();
+  for (int gi = 0; gi < ngrids; ++gi) {
+    const double* part = parts[gi];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nparts[gi]; i += blockDim.x) {
+      double x = part[i];
+      v = (x > v || x != x) ? x : v;
+    }
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double m = wmax[0];
+      for (int w = 1; w < kBlock / 64; ++w)
+        m = (wmax[w] > m || wmax[w] != wmax[w]) ? wmax[w] : m;
+      E[gi] = m;
+    }
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
-    double m = wmax[0];
-    for (int w = 1; w < kBlock / 64; ++w)
-      m = (wmax[w] > m || wmax[w] != wmax[w]) ? wmax[w] : m;
-    slot->E = m;
     __threadfence_system();
-    __hip_atomic_store(&slot->seq, seq, __ATOMIC_RELEASE,
+    __hip_atomic_store(seq_slot, seq, __ATOMIC_RELEASE,
                        __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
@@ -868,6 +975,122 @@ __global__ void k_convert(int n, const Tsrc* __restrict__ s,
                           Tdst* __restrict__ d) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) d[i] = (Tdst)s[i];
+}
+
+// -------------------------------------------------------------------------
+// kernel entry points: one grid, or a batch of grids in one launch.  A batch
+// maps its workgroups onto the grids through an exclusive prefix sum of the
+// per-grid workgroup counts (prefix[g] <= block < prefix[g+1]); every grid is
+// processed by exactly the arithmetic of its single-grid launch.
+// -------------------------------------------------------------------------
+__device__ __forceinline__ int batch_grid(const int* __restrict__ prefix,
+                                          int ngrids, int block) {
+  int lo = 0, hi = ngrids - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= block) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T, bool ONE_D>
+__global__ void __launch_bounds__(kBlock) k_fv(FvArgs<T> a) {
+  fv_body<T, ONE_D>(a, (int)blockIdx.x);
+}
+template <typename T, bool ONE_D>
+__global__ void __launch_bounds__(kBlock)
+    k_fv_batch(const FvArgs<T>* __restrict__ as, const int* __restrict__ pre,
+               int ngrids) {
+  int g = batch_grid(pre, ngrids, (int)blockIdx.x);
+  fv_body<T, ONE_D>(as[g], (int)blockIdx.x - pre[g]);
+}
+
+template <typename T, bool ONE_D>
+__global__ void __launch_bounds__(kBlock) k_break_cells(BreakCellsArgs<T> a) {
+  break_cells_body<T, ONE_D>(a, (int)blockIdx.x);
+}
+template <typename T, bool ONE_D>
+__global__ void __launch_bounds__(kBlock)
+    k_break_cells_batch(const BreakCellsArgs<T>* __restrict__ as,
+                        const int* __restrict__ pre, int ngrids) {
+  int g = batch_grid(pre, ngrids, (int)blockIdx.x);
+  break_cells_body<T, ONE_D>(as[g], (int)blockIdx.x - pre[g]);
+}
+
+template <typename T, bool ONE_D>
+__global__ void __launch_bounds__(kBlock)
+    k_break_corners(BreakCornersArgs<T> a) {
+  break_corners_body<T, ONE_D>(a, (int)blockIdx.x);
+}
+template <typename T, bool ONE_D>
+__global__ void __launch_bounds__(kBlock)
+    k_break_corners_batch(const BreakCornersArgs<T>* __restrict__ as,
+                          const int* __restrict__ pre, int ngrids) {
+  int g = batch_grid(pre, ngrids, (int)blockIdx.x);
+  break_corners_body<T, ONE_D>(as[g], (int)blockIdx.x - pre[g]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_assemble2d(AssembleArgs<T> a) {
+  assemble2d_body<T>(a, (int)blockIdx.x);
+}
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_assemble2d_batch(const AssembleArgs<T>* __restrict__ as,
+                       const int* __restrict__ pre, int ngrids) {
+  int g = batch_grid(pre, ngrids, (int)blockIdx.x);
+  assemble2d_body<T>(as[g], (int)blockIdx.x - pre[g]);
+}
+
+template <typename T, int B, int S, int M>
+__global__ void __launch_bounds__(B)
+    k_sweep_tb(SweepArgs<T> a, SweepLaunch L) {
+  extern __shared__ double lds[];
+  sweep_body<T, B, S, M>(a, L, (int)blockIdx.x, lds);
+}
+// batch: grids whose active flag is 0 (converged) are skipped
+template <typename T, int B, int S, int M>
+__global__ void __launch_bounds__(B)
+    k_sweep_tb_batch(const SweepArgs<T>* __restrict__ as,
+                     const int* __restrict__ pre, int ngrids,
+                     const int* __restrict__ active, SweepLaunch L) {
+  extern __shared__ double lds[];
+  int g = batch_grid(pre, ngrids, (int)blockIdx.x);
+  if (!active[g]) return;
+  sweep_body<T, B, S, M>(as[g], L, (int)blockIdx.x - pre[g], lds);
+}
+
+template <typename T, bool ONE_D, bool COMBINE>
+__global__ void __launch_bounds__(kBlock) k_correct(CorrectArgs<T> a) {
+  correct_body<T, ONE_D, COMBINE>(a, (int)blockIdx.x);
+}
+template <typename T, bool ONE_D, bool COMBINE>
+__global__ void __launch_bounds__(kBlock)
+    k_correct_batch(const CorrectArgs<T>* __restrict__ as,
+                    const int* __restrict__ pre, int ngrids) {
+  int g = batch_grid(pre, ngrids, (int)blockIdx.x);
+  correct_body<T, ONE_D, COMBINE>(as[g], (int)blockIdx.x - pre[g]);
+}
+
+template <typename T, bool ONE_D>
+__global__ void __launch_bounds__(kBlock) k_lambda(LambdaArgs<T> a) {
+  lambda_body<T, ONE_D>(a, (int)blockIdx.x);
+}
+template <typename T, bool ONE_D>
+__global__ void __launch_bounds__(kBlock)
+    k_lambda_batch(const LambdaArgs<T>* __restrict__ as,
+                   const int* __restrict__ pre, int ngrids) {
+  int g = batch_grid(pre, ngrids, (int)blockIdx.x);
+  lambda_body<T, ONE_D>(as[g], (int)blockIdx.x - pre[g]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_finalize_dt(FinalizeArgs a) {
+  finalize_body(a);
+}
+// batch: one workgroup per grid
+__global__ void __launch_bounds__(kBlock)
+    k_finalize_dt_batch(const FinalizeArgs* __restrict__ as) {
+  finalize_body(as[blockIdx.x]);
 }
 
 }  // namespace nh

@@ -43,6 +43,12 @@ inline unsigned nblocks(long n) {
   return (unsigned)((n + nh::kBlock - 1) / nh::kBlock);
 }
 
+// convergence measures published by the device to mapped host memory
+struct HostSlot {
+  long long seq;
+  double E[1];
+};
+
 }  // namespace
 
 struct nh_solver {
@@ -74,8 +80,11 @@ struct nh_solver {
   double* lampart = nullptr;             // per-block CFL measures
   double* part = nullptr;                // per-tile convergence measures
   nh::DevStats* dstats = nullptr;        // t, dt of the last step, steps
-  nh::HostSlot* slot = nullptr;          // mapped host memory (measure)
-  nh::HostSlot* slot_dev = nullptr;      // its device address
+  HostSlot* slot = nullptr;              // mapped host memory (measure)
+  HostSlot* slot_dev = nullptr;          // its device address
+  double* E_dev = nullptr;               // = &slot_dev->E[0]
+  double** part_list = nullptr;          // device: {part}
+  int* ntiles_list = nullptr;            // device: {ntiles}
   long long seq = 0;
   int solve_launches_last = 0;
   double* omega_dev = nullptr;
@@ -197,81 +206,87 @@ struct Launch {
   static void fv(nh_solver* s, void* h, void* q1, void* q2) {
     const auto& g = s->grid;
     const auto& pr = s->par;
+    nh::FvArgs<T> a{g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g, (T)pr.delta,
+                    (T)pr.dry_eps, P(h), P(q1), P(q2), P(s->H), s->dt,
+                    P(s->hs_cur), P(s->q1s), P(s->q2s), s->clamped};
     if (s->one_d)
-      hipLaunchKernelGGL((nh::k_fv<T, true>), dim3(nblocks(s->ncell)),
-                         dim3(nh::kBlock), 0, s->stream, g.nx, g.ny,
-                         (T)g.dx, (T)g.dy, (T)pr.g, (T)pr.delta,
-                         (T)pr.dry_eps, P(h), P(q1), P(q2), P(s->H), s->dt,
-                         P(s->hs_cur), P(s->q1s), P(s->q2s), s->clamped);
+      hipLaunchKernelGGL((nh::k_fv<T, true>), dim3(a.nblocks()),
+                         dim3(nh::kBlock), 0, s->stream, a);
     else
-      hipLaunchKernelGGL((nh::k_fv<T, false>), dim3(nblocks(s->ncell)),
-                         dim3(nh::kBlock), 0, s->stream, g.nx, g.ny,
-                         (T)g.dx, (T)g.dy, (T)pr.g, (T)pr.delta,
-                         (T)pr.dry_eps, P(h), P(q1), P(q2), P(s->H), s->dt,
-                         P(s->hs_cur), P(s->q1s), P(s->q2s), s->clamped);
+      hipLaunchKernelGGL((nh::k_fv<T, false>), dim3(a.nblocks()),
+                         dim3(nh::kBlock), 0, s->stream, a);
   }
 
   static void breaking(nh_solver* s, void* w_in) {
     const auto& g = s->grid;
     const auto& pr = s->par;
+    nh::BreakCellsArgs<T> c{g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g,
+                            (T)pr.delta, (T)pr.dry_eps, (T)pr.b1,
+                            P(s->hs_cur), P(s->q1s), P(s->q2s), P(s->H),
+                            s->dt, P(s->q1b), P(s->q2b), P(s->rw)};
+    nh::BreakCornersArgs<T> k{g.nx, g.ny, (T)pr.delta, P(s->hs_cur),
+                              P(s->rw), s->dt, P(w_in), P(s->ws)};
     if (s->one_d) {
-      hipLaunchKernelGGL((nh::k_break_cells<T, true>), dim3(nblocks(s->ncell)),
-                         dim3(nh::kBlock), 0, s->stream, g.nx, g.ny,
-                         (T)g.dx, (T)g.dy, (T)pr.g, (T)pr.delta,
-                         (T)pr.dry_eps, (T)pr.b1, P(s->hs_cur), P(s->q1s),
-                         P(s->q2s), P(s->H), s->dt, P(s->q1b), P(s->q2b),
-                         P(s->rw));
+      hipLaunchKernelGGL((nh::k_break_cells<T, true>), dim3(c.nblocks()),
+                         dim3(nh::kBlock), 0, s->stream, c);
       hipLaunchKernelGGL((nh::k_break_corners<T, true>),
-                         dim3(nblocks(s->ncorn)), dim3(nh::kBlock), 0,
-                         s->stream, g.nx, g.ny, (T)pr.delta, P(s->hs_cur),
-                         P(s->rw), s->dt, P(w_in), P(s->ws));
+                         dim3(k.nblocks(true)), dim3(nh::kBlock), 0,
+                         s->stream, k);
     } else {
-      hipLaunchKernelGGL((nh::k_break_cells<T, false>),
-                         dim3(nblocks(s->ncell)), dim3(nh::kBlock), 0,
-                         s->stream, g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g,
-                         (T)pr.delta, (T)pr.dry_eps, (T)pr.b1, P(s->hs_cur),
-                         P(s->q1s), P(s->q2s), P(s->H), s->dt, P(s->q1b),
-                         P(s->q2b), P(s->rw));
+      hipLaunchKernelGGL((nh::k_break_cells<T, false>), dim3(c.nblocks()),
+                         dim3(nh::kBlock), 0, s->stream, c);
       hipLaunchKernelGGL((nh::k_break_corners<T, false>),
-                         dim3(nblocks(s->ncorn)), dim3(nh::kBlock), 0,
-                         s->stream, g.nx, g.ny, (T)pr.delta, P(s->hs_cur),
-                         P(s->rw), s->dt, P(w_in), P(s->ws));
+                         dim3(k.nblocks(false)), dim3(nh::kBlock), 0,
+                         s->stream, k);
     }
   }
 
   static void assemble(nh_solver* s, void* q1, void* q2, void* wst) {
     const auto& g = s->grid;
-    if (s->one_d)
+    if (s->one_d) {
       hipLaunchKernelGGL((nh::k_assemble1d<T>), dim3(nblocks(s->ncorn)),
                          dim3(nh::kBlock), 0, s->stream, g.nx, (T)g.dx,
                          P(s->hs_cur), P(q1), P(s->H), P(wst), s->dt, P(s->cW),
                          P(s->cdiag), P(s->cE), P(s->crhs));
-    else
-      hipLaunchKernelGGL((nh::k_assemble2d<T>), dim3(nblocks(s->ncorn)),
-                         dim3(nh::kBlock), 0, s->stream, g.nx, g.ny, (T)g.dx,
-                         (T)g.dy, P(s->hs_cur), P(q1), P(q2), P(s->H), P(wst),
-                         s->dt, P(s->cdiag), P(s->cE), P(s->cW), P(s->cN),
-                         P(s->cS), P(s->crhs));
+    } else {
+      nh::AssembleArgs<T> a{g.nx, g.ny, (T)g.dx, (T)g.dy, P(s->hs_cur),
+                            P(q1), P(q2), P(s->H), P(wst), s->dt,
+                            P(s->cdiag), P(s->cE), P(s->cW), P(s->cN),
+                            P(s->cS), P(s->crhs)};
+      hipLaunchKernelGGL((nh::k_assemble2d<T>), dim3(a.nblocks()),
+                         dim3(nh::kBlock), 0, s->stream, a);
+    }
   }
 
-  // nsw <= kSweepS relaxation sweeps starting at sweep index k0; with check
-  // the convergence measure of the input iterate goes to s->part per tile
-  // and the input iterate is saved to psave
-  static void sweeps(nh_solver* s, bool check, int k0, int nsw, void* pin,
-                     void* pout, void* psave) {
-    int ncx = s->grid.nx + 1, ncy = s->grid.ny + 1;
-    int ntiles = s->ntx * s->nty;
-    int nb = 8 * ((ntiles + 7) / 8);
+  // nsw <= kSweepS relaxation sweeps starting at sweep index k0 from buffer
+  // iin into iout; with check the convergence measure of the input iterate
+  // goes to s->part per tile and the input iterate is saved to isave
+  static void sweeps(nh_solver* s, bool check, int k0, int nsw, int iin,
+                     int iout, int isave) {
+    nh::SweepArgs<T> a;
+    a.ncx = s->grid.nx + 1;
+    a.ncy = s->grid.ny + 1;
+    a.BX = s->tbx;
+    a.BY = s->tby;
+    a.ntx = s->ntx;
+    a.ntiles = s->ntx * s->nty;
+    a.diag = P(s->cdiag);
+    a.cE = P(s->cE);
+    a.cW = P(s->cW);
+    a.cN = P(s->cN);
+    a.cS = P(s->cS);
+    a.rhs = P(s->crhs);
+    for (int i = 0; i < 3; ++i) a.p[i] = (double*)s->pbuf(i);
+    a.omega = s->omega_dev;
+    a.nom = (int)s->omega.size();
+    a.part = s->part;
+    nh::SweepLaunch L{iin, iout, isave, k0, nsw, check ? 1 : 0};
     size_t lds = 2 * sizeof(double) * (s->tbx + 2 * nh::kSweepS) *
                  (s->tby + 2 * nh::kSweepS);
     hipLaunchKernelGGL((nh::k_sweep_tb<T, nh::kSweepB, nh::kSweepS,
                                          nh::kSweepM>),
-                       dim3(nb), dim3(nh::kSweepB), lds, s->stream, ncx, ncy,
-                       s->tbx, s->tby, s->ntx, ntiles, P(s->cdiag), P(s->cE),
-                       P(s->cW), P(s->cN), P(s->cS), P(s->crhs),
-                       (const double*)pin,
-                       (double*)pout, s->omega_dev, (int)s->omega.size(), k0,
-                       nsw, check ? 1 : 0, s->part, (double*)psave);
+                       dim3(a.nblocks()), dim3(nh::kSweepB), lds, s->stream, a,
+                       L);
   }
 
   static void thomas(nh_solver* s, void* pout) {
@@ -286,52 +301,36 @@ struct Launch {
                       void* p, void* oq1, void* oq2, void* w_out) {
     const auto& g = s->grid;
     const auto& pr = s->par;
-    long n = std::max(s->ncell, s->ncorn);
+    nh::CorrectArgs<T> a{g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g, (T)pr.delta,
+                         (T)pr.dry_eps, have_p, P(s->hs_cur), P(q1), P(q2),
+                         P(s->H), P(wst), (const double*)p, s->dt, P(oq1),
+                         P(oq2), P(w_out), P(s->h), P(s->q1), P(s->q2),
+                         s->lampart, s->flags};
     if (s->one_d)
-      hipLaunchKernelGGL((nh::k_correct<T, true, COMBINE>), dim3(nblocks(n)),
-                         dim3(nh::kBlock), 0, s->stream, g.nx, g.ny, (T)g.dx,
-                         (T)g.dy, (T)pr.g, (T)pr.delta, (T)pr.dry_eps, have_p,
-                         P(s->hs_cur), P(q1), P(q2), P(s->H), P(wst),
-                         (double*)p, s->dt, P(oq1), P(oq2), P(w_out), P(s->h),
-                         P(s->q1), P(s->q2), s->lampart, s->flags);
+      hipLaunchKernelGGL((nh::k_correct<T, true, COMBINE>),
+                         dim3(a.nblocks(true)), dim3(nh::kBlock), 0,
+                         s->stream, a);
     else
-      hipLaunchKernelGGL((nh::k_correct<T, false, COMBINE>), dim3(nblocks(n)),
-                         dim3(nh::kBlock), 0, s->stream, g.nx, g.ny, (T)g.dx,
-                         (T)g.dy, (T)pr.g, (T)pr.delta, (T)pr.dry_eps, have_p,
-                         P(s->hs_cur), P(q1), P(q2), P(s->H), P(wst),
-                         (double*)p, s->dt, P(oq1), P(oq2), P(w_out), P(s->h),
-                         P(s->q1), P(s->q2), s->lampart, s->flags);
+      hipLaunchKernelGGL((nh::k_correct<T, false, COMBINE>),
+                         dim3(a.nblocks(false)), dim3(nh::kBlock), 0,
+                         s->stream, a);
   }
 
   static void lambda(nh_solver* s) {
     const auto& g = s->grid;
     const auto& pr = s->par;
+    nh::LambdaArgs<T> a{g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g, (T)pr.delta,
+                        (T)pr.dry_eps, P(s->h), P(s->q1), P(s->q2),
+                        s->lampart};
     if (s->one_d)
-      hipLaunchKernelGGL((nh::k_lambda<T, true>), dim3(nblocks(s->ncell)),
-                         dim3(nh::kBlock), 0, s->stream, g.nx, g.ny, (T)g.dx,
-                         (T)g.dy, (T)pr.g, (T)pr.delta, (T)pr.dry_eps,
-                         P(s->h), P(s->q1), P(s->q2), s->lampart);
+      hipLaunchKernelGGL((nh::k_lambda<T, true>), dim3(a.nblocks()),
+                         dim3(nh::kBlock), 0, s->stream, a);
     else
-      hipLaunchKernelGGL((nh::k_lambda<T, false>), dim3(nblocks(s->ncell)),
-                         dim3(nh::kBlock), 0, s->stream, g.nx, g.ny, (T)g.dx,
-                         (T)g.dy, (T)pr.g, (T)pr.delta, (T)pr.dry_eps,
-                         P(s->h), P(s->q1), P(s->q2), s->lampart);
+      hipLaunchKernelGGL((nh::k_lambda<T, false>), dim3(a.nblocks()),
+                         dim3(nh::kBlock), 0, s->stream, a);
   }
 };
 
-// ---------------------------------------------------------------------------
-// the pressure solve of one stage (2D): relaxed Jacobi with the schedule.
-// Same semantics as the plain statement: at sweep k the convergence measure
-// of the iterate p^k is taken whenever k is a multiple of check_every (or k
-// reached the cap); below the tolerance p^k is the solution, at the cap the
-// solve stops with NH_ENOCONV.  Three iterate buffers: the check launch reads
-// the current one, writes the next, and saves p^k into the third; a one-block
-// kernel reduces the per-tile measures into mapped host memory, and the host
-// queues a few more launches before it waits for that value, so the device
-// never idles on the decision.  If p^k
-// converged, the saved copy is the solution and the look-ahead launches are
-// discarded.
-// ---------------------------------------------------------------------------
 // Wait until the reduction kernel has published the measure of check number
 // s->seq in mapped host memory (spinning; the device keeps running the
 // launches queued behind it).  Stream errors end the wait.
@@ -348,7 +347,7 @@ nh_status wait_measure(nh_solver* s, double* E) {
         return fail(NH_EDEVICE, "convergence measure was not published");
     }
   }
-  *E = s->slot->E;
+  *E = s->slot->E[0];
   return NH_OK;
 }
 
@@ -358,7 +357,6 @@ nh_status solve2d(nh_solver* s, int32_t* sweeps, double* measure) {
   const int kmax = s->par.solve_max_iter;
   const int S = nh::kSweepS;
   const int kAhead = 1;  // launches queued before waiting for a measure
-  const int ntiles = s->ntx * s->nty;
   int k = 0;             // sweep index of the iterate in buffer `cur`
   int cur = s->pcur;
   double E = 0.0;
@@ -368,11 +366,12 @@ nh_status solve2d(nh_solver* s, int32_t* sweeps, double* measure) {
     const int save = (cur + 2) % 3, out = (cur + 1) % 3;
     const int kc = k;
     int nsw = k >= kmax ? 0 : std::min(std::min(S, ce), kmax - k);
-    Launch<T>::sweeps(s, true, k, nsw, s->pbuf(cur), s->pbuf(out),
-                      s->pbuf(save));
+    Launch<T>::sweeps(s, true, k, nsw, cur, out, save);
     ++s->seq;
     hipLaunchKernelGGL(nh::k_reduce_measure, dim3(1), dim3(nh::kBlock), 0,
-                       s->stream, s->part, ntiles, s->slot_dev, s->seq);
+                       s->stream, (const double* const*)s->part_list,
+                       (const int*)s->ntiles_list, 1, s->E_dev,
+                       &s->slot_dev->seq, s->seq);
     launches += 1;
     if (nsw > 0) {
       cur = out;                 // ping-pong between cur and (save's peer)
@@ -385,8 +384,7 @@ nh_status solve2d(nh_solver* s, int32_t* sweeps, double* measure) {
     auto queue_until = [&](int limit) {
       while (k % ce != 0 && k < kmax && queued < limit) {
         int n2 = std::min(std::min(S, ce - k % ce), kmax - k);
-        Launch<T>::sweeps(s, false, k, n2, s->pbuf(cur), s->pbuf(other),
-                          nullptr);
+        Launch<T>::sweeps(s, false, k, n2, cur, other, other);
         std::swap(cur, other);
         k += n2;
         nsweeps_done += n2;
@@ -516,10 +514,11 @@ nh_status step_impl(nh_solver* s) {
                            nullptr, s->w, &sw2, &m2);
   if (st2 != NH_OK && st2 != NH_ENOCONV) return st2;
   if (st == NH_OK) st = st2;
+  nh::FinalizeArgs fa{s->par.cfl, s->par.fixed_dt, s->lampart,
+                      (int)nblocks(std::max(s->ncell, s->ncorn)), s->dt,
+                      s->flags, s->dstats};
   hipLaunchKernelGGL(nh::k_finalize_dt, dim3(1), dim3(nh::kBlock), 0,
-                     s->stream, s->par.cfl, s->par.fixed_dt, s->lampart,
-                     (int)nblocks(std::max(s->ncell, s->ncorn)), s->dt,
-                     s->flags, s->dstats);
+                     s->stream, fa);
   s->st.sweeps[0] = sw1;
   s->st.sweeps[1] = sw2;
   s->st.sweeps_total += sw1 + sw2;
@@ -647,7 +646,7 @@ nh_status nh_create(const nh_grid* grid, const nh_params* params,
   s->ntx = (grid->nx + 1 + s->tbx - 1) / s->tbx;
   s->nty = s->one_d ? 1 : (grid->ny + 1 + s->tby - 1) / s->tby;
   if (dalloc(s, (void**)&s->dstats, sizeof(nh::DevStats)) != NH_OK ||
-      hipHostMalloc((void**)&s->slot, sizeof(nh::HostSlot),
+      hipHostMalloc((void**)&s->slot, sizeof(HostSlot),
                     hipHostMallocMapped | hipHostMallocCoherent) !=
           hipSuccess ||
       hipHostGetDevicePointer((void**)&s->slot_dev, s->slot, 0) !=
@@ -655,11 +654,19 @@ nh_status nh_create(const nh_grid* grid, const nh_params* params,
     nh_destroy(s);
     return fail(NH_ENOMEM, "allocation of the statistics buffers failed");
   }
-  s->slot->E = 0.0;
+  s->slot->E[0] = 0.0;
   s->slot->seq = 0;
   s->seq = 0;
+  s->E_dev = &s->slot_dev->E[0];
+  int ntiles_h = s->ntx * s->nty;
   if (dalloc(s, (void**)&s->part, s->ntx * s->nty * sizeof(double)) !=
-          NH_OK) {
+          NH_OK ||
+      dalloc(s, (void**)&s->part_list, sizeof(double*)) != NH_OK ||
+      dalloc(s, (void**)&s->ntiles_list, sizeof(int)) != NH_OK ||
+      hipMemcpy(s->part_list, &s->part, sizeof(double*),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(s->ntiles_list, &ntiles_h, sizeof(int),
+                hipMemcpyHostToDevice) != hipSuccess) {
     nh_destroy(s);
     return fail(NH_ENOMEM, "allocation of the convergence buffers failed");
   }
@@ -723,10 +730,10 @@ nh_status nh_set_state(nh_solver* s, const double* h, const double* hu,
       Launch<float>::lambda(s);
     else
       Launch<double>::lambda(s);
+    nh::FinalizeArgs fa{s->par.cfl, 0, s->lampart, (int)nblocks(s->ncell),
+                        s->dt, s->flags, nullptr};
     hipLaunchKernelGGL(nh::k_finalize_dt, dim3(1), dim3(nh::kBlock), 0,
-                       s->stream, s->par.cfl, 0, s->lampart,
-                       (int)nblocks(s->ncell), s->dt, s->flags,
-                       (nh::DevStats*)nullptr);
+                       s->stream, fa);
     HIP_TRY(hipMemcpyAsync(&dt0, s->dt, sizeof(double), hipMemcpyDeviceToHost,
                            s->stream));
   }
