@@ -117,6 +117,8 @@ typedef struct {
   double sweep_kernel_ms;  /* back-to-back relaxation-sweep launches only */
   int64_t sweep_kernel_launches;
   int64_t sweep_kernel_sweeps; /* sweeps done by those launches */
+  double sweep_kernel_corner_sweeps; /* corners x sweeps of those launches,
+                                        summed over the grids they covered */
 } nh_profile_t;
 
 /* Create a solver for the grid and parameters on `hip_stream` (a hipStream_t;
@@ -151,6 +153,64 @@ nh_status nh_profile(nh_solver *s, int32_t on);
 nh_status nh_get_profile(nh_solver *s, nh_profile_t *out);
 
 void nh_destroy(nh_solver *s);
+
+/* ---- Ensembles -----------------------------------------------------------
+ * n independent 2D grids ("members", e.g. scenarios of one basin or of
+ * different basins) advanced together on one stream.  Each phase of a time
+ * step (Section 6: two projection-correction stages and the CFL reduction,
+ * eq. 23) is one launch over all members; the relaxation solves (eq. 32) of
+ * all members run in lockstep cycles of sweeps, and each member leaves them at
+ * its own convergence check.  A member computes exactly what a single solver
+ * with its grid and parameters computes (same kernels, same arithmetic, bit
+ * for bit), with its own dt, sweep counts and status.
+ *
+ * Members must be 2D (ny >= 2) and share precision, nh_on, breaking_on,
+ * solve_max_iter and check_every; everything else (grid, dt or CFL, dry
+ * threshold, tolerance, relaxation schedule) may differ.  Arrays have the
+ * layout of the single-grid calls for the member's grid.  A member whose state
+ * fails (non-finite values, no wet cell) leaves the ensemble until its state
+ * is set again; the others go on.
+ */
+typedef struct nh_ensemble nh_ensemble;
+
+/* grids[n], params[n] (copied).  Allocates every member's device memory. */
+nh_status nh_ensemble_create(int32_t n, const nh_grid *grids,
+                             const nh_params *params, void *hip_stream,
+                             nh_ensemble **out);
+nh_status nh_ensemble_set_bathymetry(nh_ensemble *e, int32_t member,
+                                     const double *H);
+/* As nh_set_state, for one member (resets its time, steps and statistics). */
+nh_status nh_ensemble_set_state(nh_ensemble *e, int32_t member,
+                                const double *h, const double *hu,
+                                const double *hv, const double *w,
+                                const double *p);
+/* Sweep tile of a member, bx x by corners per workgroup, with
+ * (bx + 16)(by + 16) <= 2048 and bx, by >= 4.  The tile changes only the
+ * speed, never the result.  Default 24 x 24. */
+nh_status nh_ensemble_set_tile(nh_ensemble *e, int32_t member, int32_t bx,
+                               int32_t by);
+nh_status nh_ensemble_get_tile(const nh_ensemble *e, int32_t member,
+                               int32_t *bx, int32_t *by);
+/* Autotuner: for every distinct grid shape, times one launch of 8 sweeps
+ * for each candidate tile on a synthetic system of that shape (best of
+ * `reps` after a warm-up) and gives the fastest tile to the members of that
+ * shape. */
+nh_status nh_ensemble_tune(nh_ensemble *e, int32_t reps);
+/* nsteps steps of every member that has a valid state.  Returns NH_OK, or
+ * the first status of a member that failed (the others still completed the
+ * steps). */
+nh_status nh_ensemble_run(nh_ensemble *e, int64_t nsteps);
+nh_status nh_ensemble_read_state(nh_ensemble *e, int32_t member, double *h,
+                                 double *hu, double *hv, double *w, double *p);
+/* Member statistics as of the end of the last run.  last_status is the
+ * member's failure status, else NH_ENOCONV if one of its solves since its
+ * state was set reached solve_max_iter, else NH_OK. */
+nh_status nh_ensemble_get_stats(const nh_ensemble *e, int32_t member,
+                                nh_stats *out);
+/* Per-phase timing summed over all members (as nh_profile). */
+nh_status nh_ensemble_profile(nh_ensemble *e, int32_t on);
+nh_status nh_ensemble_get_profile(nh_ensemble *e, nh_profile_t *out);
+void nh_ensemble_destroy(nh_ensemble *e);
 
 /* Thread-local message of the last failing call ("" if none). */
 const char *nh_last_error(void);

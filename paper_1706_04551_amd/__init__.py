@@ -1,9 +1,10 @@
 """MI355X (gfx950) time stepper for the non-hydrostatic shallow-water scheme of
 Escalante, Morales de Luna & Castro (arXiv 1706.04551).
 
-The library is libnhswe.so (C ABI in include/nhswe.h); `Solver` is its thin
-ctypes binding.  `inputs` builds the seeded synthetic workloads.
+The library is libnhswe.so (C ABI in include/nhswe.h); `Solver` (one grid)
+and `Ensemble` (many grids advanced together) are its thin ctypes binding.
+`inputs` builds the seeded synthetic workloads.
 """
-from .binding import Solver, NhError, lib  # noqa: F401
+from .binding import Ensemble, Solver, NhError, lib  # noqa: F401
 
-__all__ = ["Solver", "NhError", "lib"]
+__all__ = ["Ensemble", "Solver", "NhError", "lib"]

@@ -54,7 +54,8 @@ class NhProfile(C.Structure):
                 ("correct_launches", C.c_int64),
                 ("sweep_kernel_ms", C.c_double),
                 ("sweep_kernel_launches", C.c_int64),
-                ("sweep_kernel_sweeps", C.c_int64)]
+                ("sweep_kernel_sweeps", C.c_int64),
+                ("sweep_kernel_corner_sweeps", C.c_double)]
 
 
 _lib = None
@@ -82,11 +83,34 @@ def lib():
         L.nh_get_profile.argtypes = [vp, C.POINTER(NhProfile)]
         L.nh_destroy.argtypes = [vp]
         L.nh_destroy.restype = None
+        i32 = C.c_int32
+        L.nh_ensemble_create.argtypes = [i32, C.POINTER(NhGrid),
+                                         C.POINTER(NhParams), vp,
+                                         C.POINTER(vp)]
+        L.nh_ensemble_set_bathymetry.argtypes = [vp, i32, _DP]
+        L.nh_ensemble_set_state.argtypes = [vp, i32, _DP, _DP, _DP, _DP, _DP]
+        L.nh_ensemble_set_tile.argtypes = [vp, i32, i32, i32]
+        L.nh_ensemble_get_tile.argtypes = [vp, i32, C.POINTER(i32),
+                                           C.POINTER(i32)]
+        L.nh_ensemble_tune.argtypes = [vp, i32]
+        L.nh_ensemble_run.argtypes = [vp, C.c_int64]
+        L.nh_ensemble_read_state.argtypes = [vp, i32, _DP, _DP, _DP, _DP,
+                                             _DP]
+        L.nh_ensemble_get_stats.argtypes = [vp, i32, C.POINTER(NhStats)]
+        L.nh_ensemble_profile.argtypes = [vp, i32]
+        L.nh_ensemble_get_profile.argtypes = [vp, C.POINTER(NhProfile)]
+        L.nh_ensemble_destroy.argtypes = [vp]
+        L.nh_ensemble_destroy.restype = None
         L.nh_last_error.restype = C.c_char_p
         L.nh_version.restype = C.c_char_p
         for f in ("nh_create", "nh_set_bathymetry", "nh_set_state", "nh_step",
                   "nh_run", "nh_read_state", "nh_get_stats", "nh_profile",
-                  "nh_get_profile"):
+                  "nh_get_profile", "nh_ensemble_create",
+                  "nh_ensemble_set_bathymetry", "nh_ensemble_set_state",
+                  "nh_ensemble_set_tile", "nh_ensemble_get_tile",
+                  "nh_ensemble_tune", "nh_ensemble_run",
+                  "nh_ensemble_read_state", "nh_ensemble_get_stats",
+                  "nh_ensemble_profile", "nh_ensemble_get_profile"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -116,27 +140,38 @@ def _f64(a, shape):
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(shape))
 
 
+def _params(*, g=9.81, cfl=0.9, delta=1e-5, dry_eps=1e-10, precision="f64",
+            nh_on=1, breaking_on=0, b1=0.15, b2=0.5, solve_max_iter=200000,
+            check_every=1, solve_tol=1e-10, omega=None, fixed_dt=0,
+            dt_fixed=0.0):
+    """nh_params and the relaxation schedule array it points to (the caller
+    keeps the array alive until the create call returns)."""
+    om = None if omega is None else np.ascontiguousarray(
+        np.asarray(omega, dtype=np.float64).ravel())
+    prec = {"f64": NH_FP64, "f32": NH_FP32}[precision]
+    par = NhParams(g, cfl, delta, dry_eps, prec, nh_on, breaking_on, b1, b2,
+                   solve_max_iter, check_every, solve_tol, _ptr(om),
+                   0 if om is None else len(om), fixed_dt, dt_fixed)
+    return par, om
+
+
+def _stats_dict(s: "NhStats") -> dict:
+    return dict(t=s.t, dt=s.dt_next, dt_last=s.dt_last, step=s.step,
+                sweeps1=s.sweeps[0], sweeps2=s.sweeps[1], measure=s.measure,
+                sweeps_total=s.sweeps_total, solves=s.solves_total,
+                clamped=s.clamped_mass, status=s.last_status)
+
+
 class Solver:
     """One grid on one HIP stream (see include/nhswe.h)."""
 
-    def __init__(self, nx, ny, dx, dy, *, g=9.81, cfl=0.9, delta=1e-5,
-                 dry_eps=1e-10, precision="f64", nh_on=1, breaking_on=0,
-                 b1=0.15, b2=0.5, solve_max_iter=200000, check_every=1,
-                 solve_tol=1e-10, omega=None, fixed_dt=0, dt_fixed=0.0,
-                 stream=None):
+    def __init__(self, nx, ny, dx, dy, *, stream=None, **params):
         self.nx, self.ny = int(nx), int(ny)
         self.is1d = self.ny == 1
         self.cshape = (self.nx + 1,) if self.is1d else (self.ny + 1,
                                                          self.nx + 1)
-        self._omega = None if omega is None else np.ascontiguousarray(
-            np.asarray(omega, dtype=np.float64).ravel())
         grid = NhGrid(self.nx, self.ny, float(dx), float(dy))
-        prec = {"f64": NH_FP64, "f32": NH_FP32}[precision]
-        par = NhParams(g, cfl, delta, dry_eps, prec, nh_on, breaking_on, b1,
-                       b2, solve_max_iter, check_every, solve_tol,
-                       _ptr(self._omega),
-                       0 if self._omega is None else len(self._omega),
-                       fixed_dt, dt_fixed)
+        par, self._omega = _params(**params)
         h = C.c_void_p()
         st = lib().nh_create(C.byref(grid), C.byref(par),
                              C.c_void_p(stream) if stream else None,
@@ -200,11 +235,7 @@ class Solver:
     def stats(self) -> dict:
         s = NhStats()
         _check(lib().nh_get_stats(self._h, C.byref(s)), "nh_get_stats")
-        return dict(t=s.t, dt=s.dt_next, dt_last=s.dt_last, step=s.step,
-                    sweeps1=s.sweeps[0], sweeps2=s.sweeps[1],
-                    measure=s.measure, sweeps_total=s.sweeps_total,
-                    solves=s.solves_total, clamped=s.clamped_mass,
-                    status=s.last_status)
+        return _stats_dict(s)
 
     def profile(self, on: bool = True):
         _check(lib().nh_profile(self._h, 1 if on else 0), "nh_profile")
@@ -212,4 +243,115 @@ class Solver:
     def get_profile(self) -> dict:
         p = NhProfile()
         _check(lib().nh_get_profile(self._h, C.byref(p)), "nh_get_profile")
+        return {k: getattr(p, k) for k, _ in NhProfile._fields_}
+
+
+class Ensemble:
+    """Independent 2D grids advanced together (nh_ensemble_* in
+    include/nhswe.h).  Member k has the layout of a Solver on its grid."""
+
+    def __init__(self, grids, params, stream=None):
+        """grids: list of (nx, ny, dx, dy); params: list of keyword dicts of
+        Solver (one per member)."""
+        n = len(grids)
+        if n != len(params) or n == 0:
+            raise ValueError("need one parameter dict per grid")
+        G = (NhGrid * n)()
+        P = (NhParams * n)()
+        keep = []
+        self.shapes, self.cshapes = [], []
+        for k, ((nx, ny, dx, dy), kw) in enumerate(zip(grids, params)):
+            G[k] = NhGrid(int(nx), int(ny), float(dx), float(dy))
+            par, om = _params(**kw)
+            P[k] = par
+            keep.append(om)
+            self.shapes.append((int(ny), int(nx)))
+            self.cshapes.append((int(ny) + 1, int(nx) + 1))
+        h = C.c_void_p()
+        st = lib().nh_ensemble_create(n, G, P,
+                                      C.c_void_p(stream) if stream else None,
+                                      C.byref(h))
+        _check(st, "nh_ensemble_create")
+        self._h = h
+        self.n = n
+
+    @classmethod
+    def from_cases(cls, cases, stream=None, **over):
+        grids, params = [], []
+        for c in cases:
+            kw = c.param_dict()
+            grids.append((kw.pop("nx"), kw.pop("ny"), kw.pop("dx"),
+                          kw.pop("dy")))
+            kw["precision"] = c.precision
+            kw.update(over)
+            params.append(kw)
+        e = cls(grids, params, stream=stream)
+        for k, c in enumerate(cases):
+            e.set_bathymetry(k, c.H)
+            e.set_state(k, c.h, c.hu, c.hv)
+        return e
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nh_ensemble_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def set_bathymetry(self, k, H):
+        H = _f64(H, self.shapes[k])
+        _check(lib().nh_ensemble_set_bathymetry(self._h, k, _ptr(H)),
+               "nh_ensemble_set_bathymetry")
+
+    def set_state(self, k, h, hu, hv=None, w=None, p=None):
+        sh, cs = self.shapes[k], self.cshapes[k]
+        h, hu, hv = _f64(h, sh), _f64(hu, sh), _f64(hv, sh)
+        w, p = _f64(w, cs), _f64(p, cs)
+        _check(lib().nh_ensemble_set_state(self._h, k, _ptr(h), _ptr(hu),
+                                           _ptr(hv), _ptr(w), _ptr(p)),
+               "nh_ensemble_set_state")
+
+    def set_tile(self, k, bx, by):
+        _check(lib().nh_ensemble_set_tile(self._h, k, bx, by),
+               "nh_ensemble_set_tile")
+
+    def tile(self, k):
+        bx, by = C.c_int32(), C.c_int32()
+        _check(lib().nh_ensemble_get_tile(self._h, k, C.byref(bx),
+                                          C.byref(by)), "nh_ensemble_get_tile")
+        return bx.value, by.value
+
+    def tune(self, reps: int = 3):
+        _check(lib().nh_ensemble_tune(self._h, reps), "nh_ensemble_tune")
+
+    def run(self, n: int):
+        _check(lib().nh_ensemble_run(self._h, int(n)), "nh_ensemble_run")
+
+    def run_status(self, n: int) -> int:
+        return lib().nh_ensemble_run(self._h, int(n))
+
+    def state(self, k):
+        sh, cs = self.shapes[k], self.cshapes[k]
+        out = {q: np.zeros(sh) for q in ("h", "hu", "hv")}
+        out["w"] = np.zeros(cs)
+        out["p"] = np.zeros(cs)
+        _check(lib().nh_ensemble_read_state(
+            self._h, k, _ptr(out["h"]), _ptr(out["hu"]), _ptr(out["hv"]),
+            _ptr(out["w"]), _ptr(out["p"])), "nh_ensemble_read_state")
+        return out
+
+    def stats(self, k) -> dict:
+        s = NhStats()
+        _check(lib().nh_ensemble_get_stats(self._h, k, C.byref(s)),
+               "nh_ensemble_get_stats")
+        return _stats_dict(s)
+
+    def profile(self, on: bool = True):
+        _check(lib().nh_ensemble_profile(self._h, 1 if on else 0),
+               "nh_ensemble_profile")
+
+    def get_profile(self) -> dict:
+        p = NhProfile()
+        _check(lib().nh_ensemble_get_profile(self._h, C.byref(p)),
+               "nh_ensemble_get_profile")
         return {k: getattr(p, k) for k, _ in NhProfile._fields_}

@@ -1,0 +1,732 @@
+// ensemble_impl.hpp -- ensembles of independent 2D grids advanced together
+// (part of the nhswe.hip translation unit; see include/nhswe.h).
+//
+// Every phase of a time step is one launch over all members: the batched
+// kernels map their workgroups onto the members through per-kernel prefix
+// tables of workgroup counts, and every member runs exactly the arithmetic of
+// its single-grid launch.  The pressure solves of all members run in
+// lockstep relaxation cycles; k_ens_check decides on the device which
+// members leave at each convergence check, so the members' results and sweep
+// counts are those of their own single-grid solves.  Each member is an
+// nh_solver (its buffers, dt, statistics) bound to the ensemble's stream.
+
+// ensemble slot in mapped host memory: sequence number of the last check,
+// members still active, per-member measures and active flags
+struct EnsSlot {
+  long long seq;
+  int nactive;
+  int pad;
+  // followed by double E[n], int active[n]
+};
+
+struct nh_ensemble {
+  int n = 0;
+  bool fp32 = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int nh_on = 1, breaking_on = 0, kmax = 0, check_every = 1;
+  std::vector<nh_solver*> mem;
+  std::vector<int> live;       // members in the batch tables (state set, ok)
+  std::vector<char> failed;    // member stopped by an error
+  std::vector<nh_status> member_status;
+  bool dirty = true;           // tables must be rebuilt
+
+  // device tables, indexed by position in `live`
+  void* table = nullptr;       // one allocation holding everything below
+  size_t table_bytes = 0;
+  void *fv[2] = {}, *brc[2] = {}, *brk[2] = {}, *asmb[2] = {}, *corr[2] = {};
+  void *sweep = nullptr, *fin = nullptr;
+  int *pre_fv = nullptr, *pre_brc = nullptr, *pre_brk = nullptr,
+      *pre_asm = nullptr, *pre_sweep = nullptr, *pre_corr = nullptr;
+  int tot_fv = 0, tot_brc = 0, tot_brk = 0, tot_asm = 0, tot_sweep = 0,
+      tot_corr = 0;
+  size_t sweep_lds = 0;
+  std::vector<long> live_corners;  // corners of each live member
+
+  nh::EnsMember* dmem = nullptr;   // per member (all n, not only live)
+  nh::EnsMember* dmem_live = nullptr;  // gathered copy for the batch order
+  bool live_current = false;       // dmem_live holds the current records
+  EnsSlot* slot = nullptr;         // mapped host memory
+  EnsSlot* slot_dev = nullptr;
+  double* E_host = nullptr;
+  int* active_host = nullptr;
+  long long seq = 0;
+  ProfPool prof;
+};
+
+namespace {
+
+double* slot_E(EnsSlot* s) { return reinterpret_cast<double*>(s + 1); }
+int* slot_active(EnsSlot* s, int n) {
+  return reinterpret_cast<int*>(slot_E(s) + n);
+}
+
+// candidate sweep tiles (corners); every region (BX+2S)(BY+2S) fits the
+// workgroup's kSweepB * kSweepM points
+constexpr int kTiles[][2] = {{24, 24}, {28, 28}, {32, 24}, {40, 16},
+                             {48, 16}, {64, 8},  {16, 16}};
+
+bool tile_ok(int bx, int by) {
+  return bx >= 4 && by >= 4 &&
+         (bx + 2 * nh::kSweepS) * (by + 2 * nh::kSweepS) <=
+             nh::kSweepB * nh::kSweepM;
+}
+
+// (re)allocate the per-tile measures for the member's tile shape
+nh_status set_member_tile(nh_solver* m, int bx, int by) {
+  if (!tile_ok(bx, by)) return fail(NH_EINVAL, "tile does not fit the workgroup");
+  int ntx = (m->grid.nx + 1 + bx - 1) / bx;
+  int nty = (m->grid.ny + 1 + by - 1) / by;
+  if ((long)ntx * nty > (long)m->ntx * m->nty) {
+    nh_status st = dalloc(m, (void**)&m->part, (size_t)ntx * nty * sizeof(double));
+    if (st != NH_OK) return st;
+  }
+  m->tbx = bx;
+  m->tby = by;
+  m->ntx = ntx;
+  m->nty = nty;
+  return NH_OK;
+}
+
+// Build the batch tables of the live members and upload them (synchronous).
+template <typename T>
+nh_status ens_build(nh_ensemble* e) {
+  const int L = (int)e->live.size();
+  std::vector<nh::FvArgs<T>> fv[2];
+  std::vector<nh::BreakCellsArgs<T>> brc[2];
+  std::vector<nh::BreakCornersArgs<T>> brk[2];
+  std::vector<nh::AssembleArgs<T>> asmb[2];
+  std::vector<nh::CorrectArgs<T>> corr[2];
+  std::vector<nh::SweepArgs<T>> sw;
+  std::vector<nh::FinalizeArgs> fin;
+  std::vector<int> pre[6];
+  int tot[6] = {0, 0, 0, 0, 0, 0};
+  e->sweep_lds = 0;
+  e->live_corners.clear();
+  for (int i = 0; i < L; ++i) {
+    nh_solver* m = e->mem[e->live[i]];
+    for (int st = 0; st < 2; ++st) {
+      StagePlan S = stage_plan(m, st);
+      fv[st].push_back(Args<T>::fv(m, S));
+      brc[st].push_back(Args<T>::break_cells(m, S));
+      brk[st].push_back(Args<T>::break_corners(m, S));
+      asmb[st].push_back(Args<T>::assemble(m, S));
+      corr[st].push_back(Args<T>::correct(m, S, m->pa));
+    }
+    sw.push_back(Args<T>::sweep(m));
+    fin.push_back(finalize_args(m, true));
+    const int nb[6] = {fv[0].back().nblocks(), brc[0].back().nblocks(),
+                       brk[0].back().nblocks(false), asmb[0].back().nblocks(),
+                       sw.back().nblocks(), corr[0].back().nblocks(false)};
+    for (int k = 0; k < 6; ++k) {
+      pre[k].push_back(tot[k]);
+      if ((long)tot[k] + nb[k] > (1L << 30))
+        return fail(NH_EINVAL, "ensemble too large for one launch");
+      tot[k] += nb[k];
+    }
+    e->sweep_lds = std::max(e->sweep_lds, sweep_lds_bytes(m->tbx, m->tby));
+    e->live_corners.push_back(m->ncorn);
+  }
+  for (int k = 0; k < 6; ++k) pre[k].push_back(tot[k]);
+  // layout: every block 256-byte aligned
+  std::vector<char> buf;
+  auto put = [&](const void* src, size_t bytes) {
+    size_t off = (buf.size() + 255) & ~size_t(255);
+    buf.resize(off + bytes);
+    if (bytes) std::memcpy(buf.data() + off, src, bytes);
+    return off;
+  };
+  size_t o_fv[2], o_brc[2], o_brk[2], o_asm[2], o_corr[2], o_pre[6];
+  for (int st = 0; st < 2; ++st) {
+    o_fv[st] = put(fv[st].data(), fv[st].size() * sizeof(fv[st][0]));
+    o_brc[st] = put(brc[st].data(), brc[st].size() * sizeof(brc[st][0]));
+    o_brk[st] = put(brk[st].data(), brk[st].size() * sizeof(brk[st][0]));
+    o_asm[st] = put(asmb[st].data(), asmb[st].size() * sizeof(asmb[st][0]));
+    o_corr[st] = put(corr[st].data(), corr[st].size() * sizeof(corr[st][0]));
+  }
+  size_t o_sw = put(sw.data(), sw.size() * sizeof(sw[0]));
+  size_t o_fin = put(fin.data(), fin.size() * sizeof(fin[0]));
+  for (int k = 0; k < 6; ++k)
+    o_pre[k] = put(pre[k].data(), pre[k].size() * sizeof(int));
+  if (buf.size() > e->table_bytes) {
+    if (e->table) hipFree(e->table);
+    e->table = nullptr;
+    e->table_bytes = 0;
+    if (hipMalloc(&e->table, buf.size()) != hipSuccess)
+      return fail(NH_ENOMEM, "allocation of the ensemble tables failed");
+    e->table_bytes = buf.size();
+  }
+  HIP_TRY(hipStreamSynchronize(e->stream));
+  HIP_TRY(hipMemcpy(e->table, buf.data(), buf.size(), hipMemcpyHostToDevice));
+  char* base = static_cast<char*>(e->table);
+  for (int st = 0; st < 2; ++st) {
+    e->fv[st] = base + o_fv[st];
+    e->brc[st] = base + o_brc[st];
+    e->brk[st] = base + o_brk[st];
+    e->asmb[st] = base + o_asm[st];
+    e->corr[st] = base + o_corr[st];
+  }
+  e->sweep = base + o_sw;
+  e->fin = base + o_fin;
+  int** pres[6] = {&e->pre_fv, &e->pre_brc, &e->pre_brk,
+                   &e->pre_asm, &e->pre_sweep, &e->pre_corr};
+  for (int k = 0; k < 6; ++k) *pres[k] = (int*)(base + o_pre[k]);
+  e->tot_fv = tot[0];
+  e->tot_brc = tot[1];
+  e->tot_brk = tot[2];
+  e->tot_asm = tot[3];
+  e->tot_sweep = tot[4];
+  e->tot_corr = tot[5];
+  e->dirty = false;
+  return NH_OK;
+}
+
+// Member records in batch order <-> per-member records.  The batch kernels
+// index records by position in `live`; the records of all n members live in
+// dmem and are gathered before a run and scattered back after it.
+nh_status ens_gather(nh_ensemble* e, bool to_live) {
+  if (!to_live && !e->live_current) return NH_OK;
+  e->live_current = to_live;
+  for (size_t i = 0; i < e->live.size(); ++i) {
+    nh::EnsMember* a = e->dmem + e->live[i];
+    nh::EnsMember* b = e->dmem_live + i;
+    HIP_TRY(hipMemcpyAsync(to_live ? b : a, to_live ? a : b,
+                           sizeof(nh::EnsMember), hipMemcpyDeviceToDevice,
+                           e->stream));
+  }
+  return NH_OK;
+}
+
+template <typename T>
+void ens_sweeps(nh_ensemble* e, bool check, int k0, int nsw, int iin, int iout,
+                int isave) {
+  nh::SweepLaunch Lc{iin, iout, isave, k0, nsw, check ? 1 : 0};
+  hipLaunchKernelGGL((nh::k_sweep_tb_batch<T, nh::kSweepB, nh::kSweepS,
+                                             nh::kSweepM>),
+                     dim3(e->tot_sweep), dim3(nh::kSweepB), e->sweep_lds,
+                     e->stream, (const nh::SweepArgs<T>*)e->sweep,
+                     (const int*)e->pre_sweep, (int)e->live.size(),
+                     (const nh::EnsMember*)e->dmem_live, Lc);
+}
+
+// Lockstep solve of every live member (the same cycle structure as the
+// single-grid solve, see solve2d).
+template <typename T>
+nh_status ens_solve(nh_ensemble* e, int stage) {
+  const int L = (int)e->live.size();
+  const int ce = e->check_every > 0 ? e->check_every : 1;
+  const int kmax = e->kmax;
+  const int S = nh::kSweepS;
+  const int kAhead = 1;
+  hipLaunchKernelGGL(nh::k_ens_begin, dim3(1), dim3(256), 0, e->stream,
+                     e->dmem_live, L);
+  int k = 0, cur = 0;
+  int* act = e->active_host;
+  for (;;) {
+    const int save = (cur + 2) % 3, out = (cur + 1) % 3;
+    const int kc = k;
+    int nsw = k >= kmax ? 0 : std::min(std::min(S, ce), kmax - k);
+    ens_sweeps<T>(e, true, k, nsw, cur, out, save);
+    ++e->seq;
+    hipLaunchKernelGGL((nh::k_ens_check<T>), dim3(1), dim3(nh::kBlock), 0,
+                       e->stream, (const nh::SweepArgs<T>*)e->sweep,
+                       e->dmem_live, L, kc, kmax, save, stage,
+                       slot_E(e->slot_dev), slot_active(e->slot_dev, e->n),
+                       &e->slot_dev->nactive, &e->slot_dev->seq, e->seq);
+    if (nsw > 0) {
+      cur = out;
+      k += nsw;
+    }
+    int other = 3 - cur - save;
+    int queued = 0;
+    auto queue_until = [&](int limit) {
+      while (k % ce != 0 && k < kmax && queued < limit) {
+        int n2 = std::min(std::min(S, ce - k % ce), kmax - k);
+        ens_sweeps<T>(e, false, k, n2, cur, other, other);
+        std::swap(cur, other);
+        k += n2;
+        ++queued;
+      }
+    };
+    if (nsw > 0) queue_until(kAhead);
+    nh_status ws = wait_seq(e->stream, &e->slot->seq, e->seq);
+    if (ws != NH_OK) return ws;
+    if (e->slot->nactive == 0) break;
+    // the rest of the cycle, over the members still active
+    double corners = 0.0;
+    for (int i = 0; i < L; ++i)
+      if (act[i]) corners += (double)e->live_corners[i];
+    int before = queued;
+    long pm = (k % ce != 0 && k < kmax) ? e->prof.open(e->stream, 4) : -1;
+    queue_until(1 << 30);
+    e->prof.close(e->stream, pm, queued - before,
+                  (double)(queued - before) * S * corners);
+  }
+  return NH_OK;
+}
+
+template <typename T>
+nh_status ens_stage(nh_ensemble* e, int idx) {
+  const int L = (int)e->live.size();
+  hipStream_t st = e->stream;
+  const dim3 B(nh::kBlock);
+  long pm = e->prof.open(st, 0);
+  hipLaunchKernelGGL((nh::k_fv_batch<T, false>), dim3(e->tot_fv), B, 0, st,
+                     (const nh::FvArgs<T>*)e->fv[idx], (const int*)e->pre_fv,
+                     L);
+  e->prof.close(st, pm, 1);
+  pm = e->prof.open(st, 1);
+  if (e->breaking_on) {
+    hipLaunchKernelGGL((nh::k_break_cells_batch<T, false>), dim3(e->tot_brc),
+                       B, 0, st, (const nh::BreakCellsArgs<T>*)e->brc[idx],
+                       (const int*)e->pre_brc, L);
+    hipLaunchKernelGGL((nh::k_break_corners_batch<T, false>),
+                       dim3(e->tot_brk), B, 0, st,
+                       (const nh::BreakCornersArgs<T>*)e->brk[idx],
+                       (const int*)e->pre_brk, L);
+  }
+  if (e->nh_on)
+    hipLaunchKernelGGL((nh::k_assemble2d_batch<T>), dim3(e->tot_asm), B, 0,
+                       st, (const nh::AssembleArgs<T>*)e->asmb[idx],
+                       (const int*)e->pre_asm, L);
+  e->prof.close(st, pm, (e->breaking_on ? 2 : 0) + (e->nh_on ? 1 : 0));
+  if (e->nh_on) {
+    pm = e->prof.open(st, 2);
+    nh_status s2 = ens_solve<T>(e, idx);
+    if (s2 != NH_OK) return s2;
+    e->prof.close(st, pm, 0);
+  }
+  pm = e->prof.open(st, 3);
+  if (idx == 1)
+    hipLaunchKernelGGL((nh::k_correct_batch<T, false, true>),
+                       dim3(e->tot_corr), B, 0, st,
+                       (const nh::CorrectArgs<T>*)e->corr[idx],
+                       (const int*)e->pre_corr, L,
+                       (const nh::SweepArgs<T>*)e->sweep,
+                       (const nh::EnsMember*)e->dmem_live);
+  else
+    hipLaunchKernelGGL((nh::k_correct_batch<T, false, false>),
+                       dim3(e->tot_corr), B, 0, st,
+                       (const nh::CorrectArgs<T>*)e->corr[idx],
+                       (const int*)e->pre_corr, L,
+                       (const nh::SweepArgs<T>*)e->sweep,
+                       (const nh::EnsMember*)e->dmem_live);
+  e->prof.close(st, pm, 1);
+  return NH_OK;
+}
+
+template <typename T>
+nh_status ens_step(nh_ensemble* e) {
+  nh_status st = ens_stage<T>(e, 0);
+  if (st != NH_OK) return st;
+  st = ens_stage<T>(e, 1);
+  if (st != NH_OK) return st;
+  long pm = e->prof.open(e->stream, 3);
+  hipLaunchKernelGGL(nh::k_finalize_dt_batch, dim3(e->live.size()),
+                     dim3(nh::kBlock), 0, e->stream,
+                     (const nh::FinalizeArgs*)e->fin);
+  e->prof.close(e->stream, pm, 1);
+  return NH_OK;
+}
+
+// Statistics of every live member; a member whose state failed leaves the
+// batch (its status is kept in member_status).
+nh_status ens_sync(nh_ensemble* e) {
+  HIP_TRY(hipStreamSynchronize(e->stream));
+  std::vector<nh::EnsMember> rec(e->live.size());
+  if (!rec.empty())
+    HIP_TRY(hipMemcpy(rec.data(), e->dmem_live,
+                      rec.size() * sizeof(nh::EnsMember),
+                      hipMemcpyDeviceToHost));
+  e->prof.flush();
+  nh_status worst = NH_OK;
+  std::vector<int> keep;
+  for (size_t i = 0; i < e->live.size(); ++i) {
+    const int id = e->live[i];
+    nh_solver* m = e->mem[id];
+    nh_status st = sync_stats(m);
+    m->st.sweeps[0] = rec[i].sweeps[0];
+    m->st.sweeps[1] = rec[i].sweeps[1];
+    m->st.measure = rec[i].measure;
+    m->st.sweeps_total = rec[i].sweeps_total;
+    m->st.solves_total = rec[i].solves_total;
+    if (st == NH_OK && rec[i].noconv > 0) {
+      m->st.last_status = NH_ENOCONV;
+    } else if (st == NH_OK) {
+      m->st.last_status = NH_OK;
+    }
+    if (st != NH_OK) {
+      e->failed[id] = 1;
+      e->member_status[id] = st;
+      if (worst == NH_OK) worst = st;
+    } else {
+      keep.push_back(id);
+    }
+  }
+  if (keep.size() != e->live.size()) {
+    // scatter the records, then rebuild the tables without the failed members
+    nh_status s2 = ens_gather(e, false);
+    if (s2 != NH_OK) return s2;
+    e->live = keep;
+    e->dirty = true;
+  }
+  return worst;
+}
+
+nh_status ens_check_member(const nh_ensemble* e, int k) {
+  if (!e) return fail(NH_EINVAL, "null ensemble");
+  if (k < 0 || k >= e->n) return fail(NH_EINVAL, "member index out of range");
+  return NH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nh_status nh_ensemble_create(int32_t n, const nh_grid* grids,
+                             const nh_params* params, void* hip_stream,
+                             nh_ensemble** out) {
+  if (!out) return fail(NH_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (n < 1 || !grids || !params) return fail(NH_EINVAL, "need n >= 1 members");
+  for (int k = 0; k < n; ++k) {
+    nh_status st = check_params(&grids[k], &params[k]);
+    if (st != NH_OK) return st;
+    if (grids[k].ny < 2) return fail(NH_EINVAL, "ensemble members must be 2D");
+    const nh_params& a = params[0];
+    const nh_params& b = params[k];
+    if (a.precision != b.precision || a.nh_on != b.nh_on ||
+        a.breaking_on != b.breaking_on ||
+        a.solve_max_iter != b.solve_max_iter ||
+        (a.check_every > 0 ? a.check_every : 1) !=
+            (b.check_every > 0 ? b.check_every : 1))
+      return fail(NH_EINVAL,
+                  "members must share precision, nh_on, breaking_on, "
+                  "solve_max_iter and check_every");
+  }
+  nh_ensemble* e = new nh_ensemble();
+  e->n = n;
+  e->fp32 = params[0].precision == NH_FP32;
+  e->nh_on = params[0].nh_on;
+  e->breaking_on = params[0].breaking_on;
+  e->kmax = params[0].solve_max_iter;
+  e->check_every = params[0].check_every > 0 ? params[0].check_every : 1;
+  if (hip_stream) {
+    e->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreate(&e->stream) != hipSuccess) {
+      delete e;
+      return fail(NH_EDEVICE, "hipStreamCreate failed");
+    }
+    e->own_stream = true;
+  }
+  e->failed.assign(n, 0);
+  e->member_status.assign(n, NH_OK);
+  for (int k = 0; k < n; ++k) {
+    nh_solver* m = nullptr;
+    nh_status st = nh_create(&grids[k], &params[k], e->stream, &m);
+    if (st != NH_OK) {
+      std::string msg = g_err;
+      nh_ensemble_destroy(e);
+      return fail(st, "member " + std::to_string(k) + ": " + msg);
+    }
+    e->mem.push_back(m);
+  }
+  size_t slot_bytes =
+      sizeof(EnsSlot) + (size_t)n * (sizeof(double) + sizeof(int));
+  if (hipMalloc((void**)&e->dmem, n * sizeof(nh::EnsMember)) != hipSuccess ||
+      hipMalloc((void**)&e->dmem_live, n * sizeof(nh::EnsMember)) !=
+          hipSuccess ||
+      hipHostMalloc((void**)&e->slot, slot_bytes,
+                    hipHostMallocMapped | hipHostMallocCoherent) !=
+          hipSuccess ||
+      hipHostGetDevicePointer((void**)&e->slot_dev, e->slot, 0) !=
+          hipSuccess) {
+    nh_ensemble_destroy(e);
+    return fail(NH_ENOMEM, "allocation of the ensemble records failed");
+  }
+  std::memset(e->slot, 0, slot_bytes);
+  e->E_host = slot_E(e->slot);
+  e->active_host = slot_active(e->slot, n);
+  std::vector<nh::EnsMember> rec(n);
+  for (int k = 0; k < n; ++k) {
+    std::memset(&rec[k], 0, sizeof(rec[k]));
+    rec[k].tol = params[k].solve_tol;
+  }
+  if (hipMemcpy(e->dmem, rec.data(), n * sizeof(nh::EnsMember),
+                hipMemcpyHostToDevice) != hipSuccess) {
+    nh_ensemble_destroy(e);
+    return fail(NH_EDEVICE, "upload of the ensemble records failed");
+  }
+  *out = e;
+  return NH_OK;
+}
+
+nh_status nh_ensemble_set_bathymetry(nh_ensemble* e, int32_t k,
+                                     const double* H) {
+  nh_status st = ens_check_member(e, k);
+  if (st != NH_OK) return st;
+  return nh_set_bathymetry(e->mem[k], H);
+}
+
+nh_status nh_ensemble_set_state(nh_ensemble* e, int32_t k, const double* h,
+                                const double* hu, const double* hv,
+                                const double* w, const double* p) {
+  nh_status st = ens_check_member(e, k);
+  if (st != NH_OK) return st;
+  // records of the live members back to their own slots first
+  if ((st = ens_gather(e, false)) != NH_OK) return st;
+  HIP_TRY(hipStreamSynchronize(e->stream));
+  st = nh_set_state(e->mem[k], h, hu, hv, w, p);
+  nh::EnsMember rec;
+  std::memset(&rec, 0, sizeof(rec));
+  rec.tol = e->mem[k]->par.solve_tol;
+  HIP_TRY(hipMemcpy(e->dmem + k, &rec, sizeof(rec), hipMemcpyHostToDevice));
+  e->failed[k] = st == NH_OK ? 0 : 1;
+  e->member_status[k] = st;
+  e->live.clear();
+  for (int i = 0; i < e->n; ++i)
+    if (!e->failed[i] && e->mem[i]->have_state) e->live.push_back(i);
+  e->dirty = true;
+  return st;
+}
+
+nh_status nh_ensemble_set_tile(nh_ensemble* e, int32_t k, int32_t bx,
+                               int32_t by) {
+  nh_status st = ens_check_member(e, k);
+  if (st != NH_OK) return st;
+  HIP_TRY(hipStreamSynchronize(e->stream));
+  st = set_member_tile(e->mem[k], bx, by);
+  e->dirty = true;
+  return st;
+}
+
+nh_status nh_ensemble_get_tile(const nh_ensemble* e, int32_t k, int32_t* bx,
+                               int32_t* by) {
+  nh_status st = ens_check_member(e, k);
+  if (st != NH_OK) return st;
+  if (bx) *bx = e->mem[k]->tbx;
+  if (by) *by = e->mem[k]->tby;
+  return NH_OK;
+}
+
+nh_status nh_ensemble_tune(nh_ensemble* e, int32_t reps) {
+  if (!e) return fail(NH_EINVAL, "null ensemble");
+  if (reps < 1) reps = 1;
+  HIP_TRY(hipStreamSynchronize(e->stream));
+  // one timing per distinct grid shape, on scratch data of that shape
+  std::vector<std::pair<std::pair<int, int>, std::pair<int, int>>> done;
+  hipEvent_t a = nullptr, b = nullptr;
+  HIP_TRY(hipEventCreate(&a));
+  if (hipEventCreate(&b) != hipSuccess) {
+    hipEventDestroy(a);
+    return fail(NH_EDEVICE, "hipEventCreate failed");
+  }
+  nh_status result = NH_OK;
+  for (int k = 0; k < e->n && result == NH_OK; ++k) {
+    nh_solver* m = e->mem[k];
+    std::pair<int, int> shape{m->grid.nx, m->grid.ny};
+    int bx = 0, by = 0;
+    for (auto& d : done)
+      if (d.first == shape) {
+        bx = d.second.first;
+        by = d.second.second;
+      }
+    if (bx == 0) {
+      // scratch system: diag 1, neighbours 0.25, rhs 0; iterates 0
+      const size_t es = m->esize, nk = (size_t)m->ncorn;
+      void* scratch = nullptr;
+      size_t bytes = 6 * nk * es + 2 * nk * sizeof(double) +
+                     8192 * sizeof(double);
+      if (hipMalloc(&scratch, bytes) != hipSuccess) {
+        result = fail(NH_ENOMEM, "allocation of the tuning scratch failed");
+        break;
+      }
+      hipMemsetAsync(scratch, 0, bytes, e->stream);
+      char* c = static_cast<char*>(scratch);
+      nh::SweepArgs<double> a64{};
+      nh::SweepArgs<float> a32{};
+      auto fill = [&](int i, double v) {
+        if (e->fp32)
+          hipLaunchKernelGGL((nh::k_fill<float>), dim3(nblocks(nk)),
+                             dim3(nh::kBlock), 0, e->stream, (long)nk,
+                             (float)v, (float*)(c + i * nk * es));
+        else
+          hipLaunchKernelGGL((nh::k_fill<double>), dim3(nblocks(nk)),
+                             dim3(nh::kBlock), 0, e->stream, (long)nk, v,
+                             (double*)(c + i * nk * es));
+      };
+      fill(0, 1.0);
+      for (int i = 1; i < 5; ++i) fill(i, 0.25);
+      double best = 1e300;
+      for (const auto& t : kTiles) {
+        if (!tile_ok(t[0], t[1])) continue;
+        int ntx = (m->grid.nx + 1 + t[0] - 1) / t[0];
+        int nty = (m->grid.ny + 1 + t[1] - 1) / t[1];
+        if ((long)ntx * nty > 8192) continue;  // scratch measures
+        double* pbase = (double*)(c + 6 * nk * es);
+        auto setup = [&](auto& s) {
+          using TT = typename std::remove_pointer<decltype(s.diag)>::type;
+          using U = typename std::remove_const<TT>::type;
+          s.ncx = m->grid.nx + 1;
+          s.ncy = m->grid.ny + 1;
+          s.BX = t[0];
+          s.BY = t[1];
+          s.ntx = ntx;
+          s.ntiles = ntx * nty;
+          U* base = (U*)c;
+          s.diag = base;
+          s.cE = base + nk;
+          s.cW = base + 2 * nk;
+          s.cN = base + 3 * nk;
+          s.cS = base + 4 * nk;
+          s.rhs = base + 5 * nk;
+          s.p[0] = pbase;
+          s.p[1] = pbase + nk;
+          s.p[2] = pbase + nk;
+          s.omega = m->omega_dev;
+          s.nom = (int)m->omega.size();
+          s.part = pbase + 2 * nk;
+        };
+        nh::SweepLaunch Lc{0, 1, 2, 0, nh::kSweepS, 0};
+        float ms_min = 1e30f;
+        for (int r = 0; r <= reps; ++r) {
+          (void)hipEventRecord(a, e->stream);
+          if (e->fp32) {
+            setup(a32);
+            hipLaunchKernelGGL((nh::k_sweep_tb<float, nh::kSweepB,
+                                               nh::kSweepS, nh::kSweepM>),
+                               dim3(a32.nblocks()), dim3(nh::kSweepB),
+                               sweep_lds_bytes(t[0], t[1]), e->stream, a32,
+                               Lc);
+          } else {
+            setup(a64);
+            hipLaunchKernelGGL((nh::k_sweep_tb<double, nh::kSweepB,
+                                               nh::kSweepS, nh::kSweepM>),
+                               dim3(a64.nblocks()), dim3(nh::kSweepB),
+                               sweep_lds_bytes(t[0], t[1]), e->stream, a64,
+                               Lc);
+          }
+          (void)hipEventRecord(b, e->stream);
+          if (hipEventSynchronize(b) != hipSuccess) {
+            result = fail(NH_EDEVICE, "tuning launch failed");
+            break;
+          }
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, a, b);
+          if (r > 0) ms_min = std::min(ms_min, ms);  // first: warmup
+        }
+        if (result != NH_OK) break;
+        if (ms_min < best) {
+          best = ms_min;
+          bx = t[0];
+          by = t[1];
+        }
+      }
+      hipStreamSynchronize(e->stream);
+      hipFree(scratch);
+      if (result != NH_OK) break;
+      done.push_back({shape, {bx, by}});
+    }
+    if ((result = set_member_tile(m, bx, by)) != NH_OK) break;
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  e->dirty = true;
+  return result;
+}
+
+nh_status nh_ensemble_run(nh_ensemble* e, int64_t nsteps) {
+  if (!e) return fail(NH_EINVAL, "null ensemble");
+  if (nsteps < 0) return fail(NH_EINVAL, "nsteps < 0");
+  if (e->live.empty()) return fail(NH_ESTATE, "no member has a valid state");
+  for (int id : e->live)
+    if (!(e->mem[id]->st.dt_next > 0))
+      return fail(NH_ESTATE, "member " + std::to_string(id) +
+                                 ": dt is not positive");
+  nh_status st;
+  if (e->dirty) {
+    st = e->fp32 ? ens_build<float>(e) : ens_build<double>(e);
+    if (st != NH_OK) return st;
+  }
+  if ((st = ens_gather(e, true)) != NH_OK) return st;
+  const int64_t kStatusEvery = 64;
+  nh_status worst = NH_OK;
+  for (int64_t n = 0; n < nsteps; ++n) {
+    st = e->fp32 ? ens_step<float>(e) : ens_step<double>(e);
+    if (st != NH_OK) {
+      (void)ens_sync(e);
+      (void)ens_gather(e, false);
+      return st;
+    }
+    if ((n + 1) % kStatusEvery == 0 || n + 1 == nsteps) {
+      nh_status ss = ens_sync(e);
+      if (ss != NH_OK && worst == NH_OK) worst = ss;
+      if (e->live.empty()) break;
+      if (e->dirty) {
+        // failed members left: rebuild and continue with the rest
+        st = e->fp32 ? ens_build<float>(e) : ens_build<double>(e);
+        if (st != NH_OK) return st;
+        if ((st = ens_gather(e, true)) != NH_OK) return st;
+      }
+    }
+  }
+  if ((st = ens_gather(e, false)) != NH_OK) return st;
+  HIP_TRY(hipStreamSynchronize(e->stream));
+  if (worst != NH_OK) return fail(worst, "a member failed (see its stats)");
+  return NH_OK;
+}
+
+nh_status nh_ensemble_read_state(nh_ensemble* e, int32_t k, double* h,
+                                 double* hu, double* hv, double* w,
+                                 double* p) {
+  nh_status st = ens_check_member(e, k);
+  if (st != NH_OK) return st;
+  HIP_TRY(hipStreamSynchronize(e->stream));
+  nh::EnsMember rec;
+  HIP_TRY(hipMemcpy(&rec, e->dmem + k, sizeof(rec), hipMemcpyDeviceToHost));
+  e->mem[k]->pcur = rec.rot;
+  return nh_read_state(e->mem[k], h, hu, hv, w, p);
+}
+
+nh_status nh_ensemble_get_stats(const nh_ensemble* e, int32_t k,
+                                nh_stats* out) {
+  nh_status st = ens_check_member(e, k);
+  if (st != NH_OK) return st;
+  if (!out) return fail(NH_EINVAL, "null argument");
+  *out = e->mem[k]->st;
+  if (e->failed[k]) out->last_status = e->member_status[k];
+  return NH_OK;
+}
+
+nh_status nh_ensemble_profile(nh_ensemble* e, int32_t on) {
+  if (!e) return fail(NH_EINVAL, "null ensemble");
+  HIP_TRY(hipStreamSynchronize(e->stream));
+  e->prof.flush();
+  e->prof.on = on != 0;
+  if (e->prof.on) std::memset(&e->prof.pr, 0, sizeof(e->prof.pr));
+  return NH_OK;
+}
+
+nh_status nh_ensemble_get_profile(nh_ensemble* e, nh_profile_t* out) {
+  if (!e || !out) return fail(NH_EINVAL, "null argument");
+  HIP_TRY(hipStreamSynchronize(e->stream));
+  e->prof.flush();
+  *out = e->prof.pr;
+  return NH_OK;
+}
+
+void nh_ensemble_destroy(nh_ensemble* e) {
+  if (!e) return;
+  if (e->stream) hipStreamSynchronize(e->stream);
+  for (nh_solver* m : e->mem) nh_destroy(m);
+  if (e->table) hipFree(e->table);
+  if (e->dmem) hipFree(e->dmem);
+  if (e->dmem_live) hipFree(e->dmem_live);
+  if (e->slot) hipHostFree(e->slot);
+  e->prof.release();
+  if (e->own_stream) hipStreamDestroy(e->stream);
+  delete e;
+}
+
+}  // extern "C"

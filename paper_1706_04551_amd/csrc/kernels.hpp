@@ -970,11 +970,95 @@ __global__ void __launch_bounds__(kBlock)
 
 __global__ void k_zero_u64(unsigned long long* a) { *a = 0ull; }
 
+template <typename T>
+__global__ void k_fill(long n, T v, T* __restrict__ a) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
 template <typename Tdst, typename Tsrc>
 __global__ void k_convert(int n, const Tsrc* __restrict__ s,
                           Tdst* __restrict__ d) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) d[i] = (Tdst)s[i];
+}
+
+// -------------------------------------------------------------------------
+// ensemble control.  The members of an ensemble run their pressure solves in
+// lockstep cycles; each member leaves the cycles at its own convergence check
+// and its result then becomes its logical iterate 0.  These records are only
+// written by k_ens_begin and k_ens_check (one workgroup each).
+// -------------------------------------------------------------------------
+struct EnsMember {
+  int active;              // takes part in the running solve
+  int rot;                 // logical iterate buffer i is buffer (i + rot) % 3
+  int sweeps[2];           // sweeps of the last solve of each stage
+  int noconv;              // solves stopped by the sweep cap or a NaN measure
+  double tol;              // convergence tolerance of the member
+  double measure;          // measure at the end of the last solve
+  long long sweeps_total;  // since the state was set
+  long long solves_total;
+};
+
+__global__ void k_ens_begin(EnsMember* __restrict__ mem, int n) {
+  for (int g = threadIdx.x; g < n; g += blockDim.x) mem[g].active = 1;
+}
+
+// Convergence check of every active member (one wave per member): the max of
+// its per-tile measures of the iterate p^kc; a member stops when it is below
+// its tolerance, when kc reached the sweep cap or when it is not finite, and
+// its saved iterate p^kc (logical buffer `save`) becomes logical buffer 0.
+// The measures, the active flags and the number of members still active go
+// to mapped host memory, then the check's sequence number is released.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_ens_check(const SweepArgs<T>* __restrict__ as,
+                EnsMember* __restrict__ mem, int n, int kc, int kmax,
+                int save, int stage, double* __restrict__ E_host,
+                int* __restrict__ active_host, int* __restrict__ nactive_host,
+                long long* seq_slot, long long seq) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  int still = 0;
+  for (int g = wv; g < n; g += nw) {
+    if (!mem[g].active) continue;  // uniform over the wave
+    const double* part = as[g].part;
+    double v = 0.0;
+    for (int i = lane; i < as[g].ntiles; i += 64) {
+      double x = part[i];
+      v = (x > v || x != x) ? x : v;
+    }
+    v = wave_max(v);
+    if (lane == 0) {
+      EnsMember& m = mem[g];
+      const bool ok = v < m.tol;
+      const bool stop = ok || kc >= kmax || !(v == v) || isinf(v);
+      if (stop) {
+        m.active = 0;
+        m.rot = (m.rot + save) % 3;
+        m.sweeps[stage] = kc;
+        m.measure = v;
+        m.sweeps_total += kc;
+        m.solves_total += 1;
+        if (!ok) m.noconv += 1;
+      } else {
+        still += 1;
+      }
+      E_host[g] = v;
+      active_host[g] = stop ? 0 : 1;
+    }
+  }
+  __shared__ int cnt[kBlock / 64];
+  if (lane == 0) cnt[wv] = still;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int w = 0; w < nw; ++w) tot += cnt[w];
+    *nactive_host = tot;
+    __threadfence_system();
+    __hip_atomic_store(seq_slot, seq, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 // -------------------------------------------------------------------------
@@ -1048,28 +1132,41 @@ __global__ void __launch_bounds__(B)
   extern __shared__ double lds[];
   sweep_body<T, B, S, M>(a, L, (int)blockIdx.x, lds);
 }
-// batch: grids whose active flag is 0 (converged) are skipped
+// batch: members that are not active in the running solve are skipped; the
+// launch's buffer indices are logical and map to (index + rot) % 3 of each
+// member.  Every member's workgroup count is a multiple of 8, so the local
+// workgroup index keeps the XCD of the global one.
 template <typename T, int B, int S, int M>
 __global__ void __launch_bounds__(B)
     k_sweep_tb_batch(const SweepArgs<T>* __restrict__ as,
                      const int* __restrict__ pre, int ngrids,
-                     const int* __restrict__ active, SweepLaunch L) {
+                     const EnsMember* __restrict__ mem, SweepLaunch L) {
   extern __shared__ double lds[];
   int g = batch_grid(pre, ngrids, (int)blockIdx.x);
-  if (!active[g]) return;
-  sweep_body<T, B, S, M>(as[g], L, (int)blockIdx.x - pre[g], lds);
+  if (!mem[g].active) return;
+  const int r = mem[g].rot;
+  SweepLaunch Lg = L;
+  Lg.iin = (L.iin + r) % 3;
+  Lg.iout = (L.iout + r) % 3;
+  Lg.isave = (L.isave + r) % 3;
+  sweep_body<T, B, S, M>(as[g], Lg, (int)blockIdx.x - pre[g], lds);
 }
 
 template <typename T, bool ONE_D, bool COMBINE>
 __global__ void __launch_bounds__(kBlock) k_correct(CorrectArgs<T> a) {
   correct_body<T, ONE_D, COMBINE>(a, (int)blockIdx.x);
 }
+// batch: the pressure of member g is its logical iterate 0, buffer rot[g]
 template <typename T, bool ONE_D, bool COMBINE>
 __global__ void __launch_bounds__(kBlock)
     k_correct_batch(const CorrectArgs<T>* __restrict__ as,
-                    const int* __restrict__ pre, int ngrids) {
+                    const int* __restrict__ pre, int ngrids,
+                    const SweepArgs<T>* __restrict__ sw,
+                    const EnsMember* __restrict__ mem) {
   int g = batch_grid(pre, ngrids, (int)blockIdx.x);
-  correct_body<T, ONE_D, COMBINE>(as[g], (int)blockIdx.x - pre[g]);
+  CorrectArgs<T> a = as[g];
+  if (a.have_p) a.p = sw[g].p[mem[g].rot];
+  correct_body<T, ONE_D, COMBINE>(a, (int)blockIdx.x - pre[g]);
 }
 
 template <typename T, bool ONE_D>

@@ -17,6 +17,8 @@
 #include <algorithm>
 #include <cstring>
 #include <string>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "../../include/nhswe.h"
@@ -47,6 +49,76 @@ inline unsigned nblocks(long n) {
 struct HostSlot {
   long long seq;
   double E[1];
+};
+
+// Per-phase device timing: event pairs recorded on the stream and read
+// lazily at the next synchronisation, so that timing never stalls the device.
+struct ProfPool {
+  bool on = false;
+  struct Mark {
+    hipEvent_t a = nullptr, b = nullptr;
+    int kind = 0;         // 0 fv, 1 assembly, 2 solve, 3 correction, 4 sweeps
+    long long count = 0;  // launches
+    double work = 0.0;    // sweeps: corner-sweeps done by those launches
+  };
+  std::vector<Mark> marks;
+  size_t used = 0;
+  nh_profile_t pr{};
+
+  // open an interval of the given kind on the stream (or -1)
+  long open(hipStream_t st, int kind) {
+    if (!on) return -1;
+    if (used == marks.size()) {
+      Mark m;
+      if (hipEventCreate(&m.a) != hipSuccess) return -1;
+      if (hipEventCreate(&m.b) != hipSuccess) {
+        hipEventDestroy(m.a);
+        return -1;
+      }
+      marks.push_back(m);
+    }
+    Mark& m = marks[used];
+    m.kind = kind;
+    m.count = 0;
+    m.work = 0.0;
+    if (hipEventRecord(m.a, st) != hipSuccess) return -1;
+    return (long)used++;
+  }
+  void close(hipStream_t st, long id, long long count, double work = 0.0) {
+    if (id < 0) return;
+    marks[id].count = count;
+    marks[id].work = work;
+    (void)hipEventRecord(marks[id].b, st);
+  }
+  // accumulate every closed interval (the stream has been synchronised)
+  void flush() {
+    for (size_t i = 0; i < used; ++i) {
+      Mark& m = marks[i];
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, m.a, m.b) != hipSuccess) continue;
+      switch (m.kind) {
+        case 0: pr.fv_ms += ms; pr.fv_launches += m.count; break;
+        case 1: pr.assemble_ms += ms; pr.assemble_launches += m.count; break;
+        case 2: pr.solve_ms += ms; pr.solve_launches += m.count; break;
+        case 3: pr.correct_ms += ms; pr.correct_launches += m.count; break;
+        case 4:
+          pr.sweep_kernel_ms += ms;
+          pr.sweep_kernel_launches += m.count;
+          pr.sweep_kernel_sweeps += m.count * nh::kSweepS;
+          pr.sweep_kernel_corner_sweeps += m.work;
+          break;
+      }
+    }
+    used = 0;
+  }
+  void release() {
+    for (auto& m : marks) {
+      if (m.a) hipEventDestroy(m.a);
+      if (m.b) hipEventDestroy(m.b);
+    }
+    marks.clear();
+    used = 0;
+  }
 };
 
 }  // namespace
@@ -96,17 +168,7 @@ struct nh_solver {
   void* pcur_ptr() { return pbuf(pcur); }
   bool have_state = false, have_H = false;
   nh_stats st{};
-  // profiling: event pairs recorded on the stream and read lazily at the
-  // next synchronisation, so that timing never stalls the device
-  bool prof = false;
-  struct Mark {
-    hipEvent_t a = nullptr, b = nullptr;
-    int kind = 0;          // 0 fv, 1 assembly, 2 solve, 3 correction, 4 sweeps
-    long long count = 0;   // launches (sweeps: launches of 8 sweeps)
-  };
-  std::vector<Mark> marks;
-  size_t marks_used = 0;
-  nh_profile_t pr{};
+  ProfPool prof;
 
   std::vector<void*> allocs;
 };
@@ -152,63 +214,140 @@ nh_status download(nh_solver* s, double* dst, const void* src, long n) {
   return NH_OK;
 }
 
-// open a timing interval of the given kind on the stream (or -1)
-long prof_open(nh_solver* s, int kind) {
-  if (!s->prof) return -1;
-  if (s->marks_used == s->marks.size()) {
-    nh_solver::Mark m;
-    if (hipEventCreate(&m.a) != hipSuccess || hipEventCreate(&m.b) != hipSuccess)
-      return -1;
-    s->marks.push_back(m);
-  }
-  nh_solver::Mark& m = s->marks[s->marks_used];
-  m.kind = kind;
-  m.count = 0;
-  if (hipEventRecord(m.a, s->stream) != hipSuccess) return -1;
-  return (long)s->marks_used++;
-}
-
-void prof_close(nh_solver* s, long id, long long count) {
-  if (id < 0) return;
-  nh_solver::Mark& m = s->marks[id];
-  m.count = count;
-  (void)hipEventRecord(m.b, s->stream);
-}
-
-// accumulate every closed interval (the stream has been synchronised)
-void prof_flush(nh_solver* s) {
-  for (size_t i = 0; i < s->marks_used; ++i) {
-    nh_solver::Mark& m = s->marks[i];
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, m.a, m.b) != hipSuccess) continue;
-    switch (m.kind) {
-      case 0: s->pr.fv_ms += ms; s->pr.fv_launches += m.count; break;
-      case 1: s->pr.assemble_ms += ms; s->pr.assemble_launches += m.count; break;
-      case 2: s->pr.solve_ms += ms; s->pr.solve_launches += m.count; break;
-      case 3: s->pr.correct_ms += ms; s->pr.correct_launches += m.count; break;
-      case 4:
-        s->pr.sweep_kernel_ms += ms;
-        s->pr.sweep_kernel_launches += m.count;
-        s->pr.sweep_kernel_sweeps += m.count * nh::kSweepS;
-        break;
-    }
-  }
-  s->marks_used = 0;
-}
-
 // ---------------------------------------------------------------------------
 // typed launch helpers
 // ---------------------------------------------------------------------------
+// Pointers of one projection-correction stage: stage 0 maps U^n to U^(1)
+// (its h* is U^(1)'s depth, kept in hs), stage 1 maps U^(1) to U^(2) and
+// averages it with U^n in place.
+struct StagePlan {
+  void *Vh, *Vq1, *Vq2, *w_in;  // stage input
+  void* hs_cur;                 // h* of the stage
+  void *qa, *qb, *wst;          // discharges and w fed to the pressure system
+  void *oq1, *oq2, *w_out;      // stage output (stage 1: U^n in place)
+  bool combine;
+};
+
+StagePlan stage_plan(const nh_solver* s, int idx) {
+  StagePlan P;
+  if (idx == 0) {
+    P.Vh = s->h; P.Vq1 = s->q1; P.Vq2 = s->q2; P.w_in = s->w;
+    P.hs_cur = s->hs;
+    P.oq1 = s->q11; P.oq2 = s->q21; P.w_out = s->w1;
+  } else {
+    P.Vh = s->hs; P.Vq1 = s->q11; P.Vq2 = s->q21; P.w_in = s->w1;
+    P.hs_cur = s->h1;
+    P.oq1 = nullptr; P.oq2 = nullptr; P.w_out = s->w;
+  }
+  if (s->par.breaking_on) {
+    P.qa = s->q1b; P.qb = s->q2b; P.wst = s->ws;
+  } else {
+    P.qa = s->q1s; P.qb = s->q2s; P.wst = P.w_in;
+  }
+  P.combine = idx == 1;
+  return P;
+}
+
+// kernel arguments of one grid, shared by the single-grid launches and the
+// ensemble's batched launches
+template <typename T>
+struct Args {
+  static T* P(void* p) { return static_cast<T*>(p); }
+
+  static nh::FvArgs<T> fv(const nh_solver* s, const StagePlan& S) {
+    const auto& g = s->grid;
+    const auto& pr = s->par;
+    return nh::FvArgs<T>{g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g,
+                         (T)pr.delta, (T)pr.dry_eps, P(S.Vh), P(S.Vq1),
+                         P(S.Vq2), P(s->H), s->dt, P(S.hs_cur), P(s->q1s),
+                         P(s->q2s), s->clamped};
+  }
+  static nh::BreakCellsArgs<T> break_cells(const nh_solver* s,
+                                           const StagePlan& S) {
+    const auto& g = s->grid;
+    const auto& pr = s->par;
+    return nh::BreakCellsArgs<T>{g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g,
+                                 (T)pr.delta, (T)pr.dry_eps, (T)pr.b1,
+                                 P(S.hs_cur), P(s->q1s), P(s->q2s), P(s->H),
+                                 s->dt, P(s->q1b), P(s->q2b), P(s->rw)};
+  }
+  static nh::BreakCornersArgs<T> break_corners(const nh_solver* s,
+                                               const StagePlan& S) {
+    return nh::BreakCornersArgs<T>{s->grid.nx, s->grid.ny, (T)s->par.delta,
+                                   P(S.hs_cur), P(s->rw), s->dt, P(S.w_in),
+                                   P(s->ws)};
+  }
+  static nh::AssembleArgs<T> assemble(const nh_solver* s, const StagePlan& S) {
+    const auto& g = s->grid;
+    return nh::AssembleArgs<T>{g.nx, g.ny, (T)g.dx, (T)g.dy, P(S.hs_cur),
+                               P(S.qa), P(S.qb), P(s->H), P(S.wst), s->dt,
+                               P(s->cdiag), P(s->cE), P(s->cW), P(s->cN),
+                               P(s->cS), P(s->crhs)};
+  }
+  static nh::SweepArgs<T> sweep(const nh_solver* s) {
+    nh::SweepArgs<T> a;
+    a.ncx = s->grid.nx + 1;
+    a.ncy = s->grid.ny + 1;
+    a.BX = s->tbx;
+    a.BY = s->tby;
+    a.ntx = s->ntx;
+    a.ntiles = s->ntx * s->nty;
+    a.diag = P(s->cdiag);
+    a.cE = P(s->cE);
+    a.cW = P(s->cW);
+    a.cN = P(s->cN);
+    a.cS = P(s->cS);
+    a.rhs = P(s->crhs);
+    a.p[0] = (double*)s->pa;
+    a.p[1] = (double*)s->pb;
+    a.p[2] = (double*)s->pc;
+    a.omega = s->omega_dev;
+    a.nom = (int)s->omega.size();
+    a.part = s->part;
+    return a;
+  }
+  // p: the solved pressure (ignored when the system is hydrostatic)
+  static nh::CorrectArgs<T> correct(const nh_solver* s, const StagePlan& S,
+                                    const void* p) {
+    const auto& g = s->grid;
+    const auto& pr = s->par;
+    return nh::CorrectArgs<T>{g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g,
+                              (T)pr.delta, (T)pr.dry_eps,
+                              s->par.nh_on ? 1 : 0, P(S.hs_cur), P(S.qa),
+                              P(S.qb), P(s->H), P(S.wst),
+                              (const double*)(p ? p : s->pa), s->dt,
+                              P(S.oq1), P(S.oq2), P(S.w_out), P(s->h),
+                              P(s->q1), P(s->q2), s->lampart, s->flags};
+  }
+  static nh::LambdaArgs<T> lambda(const nh_solver* s) {
+    const auto& g = s->grid;
+    const auto& pr = s->par;
+    return nh::LambdaArgs<T>{g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g,
+                             (T)pr.delta, (T)pr.dry_eps, P(s->h), P(s->q1),
+                             P(s->q2), s->lampart};
+  }
+};
+
+// end of a step (with_stats) or of set_state: dt from the CFL measures
+inline nh::FinalizeArgs finalize_args(const nh_solver* s, bool with_stats) {
+  if (with_stats)
+    return nh::FinalizeArgs{s->par.cfl, s->par.fixed_dt, s->lampart,
+                            (int)nblocks(std::max(s->ncell, s->ncorn)), s->dt,
+                            s->flags, s->dstats};
+  return nh::FinalizeArgs{s->par.cfl, 0, s->lampart, (int)nblocks(s->ncell),
+                          s->dt, s->flags, nullptr};
+}
+
+inline size_t sweep_lds_bytes(int bx, int by) {
+  return 2 * sizeof(double) * (bx + 2 * nh::kSweepS) * (by + 2 * nh::kSweepS);
+}
+
 template <typename T>
 struct Launch {
   static T* P(void* p) { return static_cast<T*>(p); }
 
-  static void fv(nh_solver* s, void* h, void* q1, void* q2) {
-    const auto& g = s->grid;
-    const auto& pr = s->par;
-    nh::FvArgs<T> a{g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g, (T)pr.delta,
-                    (T)pr.dry_eps, P(h), P(q1), P(q2), P(s->H), s->dt,
-                    P(s->hs_cur), P(s->q1s), P(s->q2s), s->clamped};
+  static void fv(nh_solver* s, const StagePlan& S) {
+    auto a = Args<T>::fv(s, S);
     if (s->one_d)
       hipLaunchKernelGGL((nh::k_fv<T, true>), dim3(a.nblocks()),
                          dim3(nh::kBlock), 0, s->stream, a);
@@ -217,15 +356,9 @@ struct Launch {
                          dim3(nh::kBlock), 0, s->stream, a);
   }
 
-  static void breaking(nh_solver* s, void* w_in) {
-    const auto& g = s->grid;
-    const auto& pr = s->par;
-    nh::BreakCellsArgs<T> c{g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g,
-                            (T)pr.delta, (T)pr.dry_eps, (T)pr.b1,
-                            P(s->hs_cur), P(s->q1s), P(s->q2s), P(s->H),
-                            s->dt, P(s->q1b), P(s->q2b), P(s->rw)};
-    nh::BreakCornersArgs<T> k{g.nx, g.ny, (T)pr.delta, P(s->hs_cur),
-                              P(s->rw), s->dt, P(w_in), P(s->ws)};
+  static void breaking(nh_solver* s, const StagePlan& S) {
+    auto c = Args<T>::break_cells(s, S);
+    auto k = Args<T>::break_corners(s, S);
     if (s->one_d) {
       hipLaunchKernelGGL((nh::k_break_cells<T, true>), dim3(c.nblocks()),
                          dim3(nh::kBlock), 0, s->stream, c);
@@ -241,18 +374,15 @@ struct Launch {
     }
   }
 
-  static void assemble(nh_solver* s, void* q1, void* q2, void* wst) {
+  static void assemble(nh_solver* s, const StagePlan& S) {
     const auto& g = s->grid;
     if (s->one_d) {
       hipLaunchKernelGGL((nh::k_assemble1d<T>), dim3(nblocks(s->ncorn)),
                          dim3(nh::kBlock), 0, s->stream, g.nx, (T)g.dx,
-                         P(s->hs_cur), P(q1), P(s->H), P(wst), s->dt, P(s->cW),
-                         P(s->cdiag), P(s->cE), P(s->crhs));
+                         P(S.hs_cur), P(S.qa), P(s->H), P(S.wst), s->dt,
+                         P(s->cW), P(s->cdiag), P(s->cE), P(s->crhs));
     } else {
-      nh::AssembleArgs<T> a{g.nx, g.ny, (T)g.dx, (T)g.dy, P(s->hs_cur),
-                            P(q1), P(q2), P(s->H), P(wst), s->dt,
-                            P(s->cdiag), P(s->cE), P(s->cW), P(s->cN),
-                            P(s->cS), P(s->crhs)};
+      auto a = Args<T>::assemble(s, S);
       hipLaunchKernelGGL((nh::k_assemble2d<T>), dim3(a.nblocks()),
                          dim3(nh::kBlock), 0, s->stream, a);
     }
@@ -263,30 +393,12 @@ struct Launch {
   // goes to s->part per tile and the input iterate is saved to isave
   static void sweeps(nh_solver* s, bool check, int k0, int nsw, int iin,
                      int iout, int isave) {
-    nh::SweepArgs<T> a;
-    a.ncx = s->grid.nx + 1;
-    a.ncy = s->grid.ny + 1;
-    a.BX = s->tbx;
-    a.BY = s->tby;
-    a.ntx = s->ntx;
-    a.ntiles = s->ntx * s->nty;
-    a.diag = P(s->cdiag);
-    a.cE = P(s->cE);
-    a.cW = P(s->cW);
-    a.cN = P(s->cN);
-    a.cS = P(s->cS);
-    a.rhs = P(s->crhs);
-    for (int i = 0; i < 3; ++i) a.p[i] = (double*)s->pbuf(i);
-    a.omega = s->omega_dev;
-    a.nom = (int)s->omega.size();
-    a.part = s->part;
+    auto a = Args<T>::sweep(s);
     nh::SweepLaunch L{iin, iout, isave, k0, nsw, check ? 1 : 0};
-    size_t lds = 2 * sizeof(double) * (s->tbx + 2 * nh::kSweepS) *
-                 (s->tby + 2 * nh::kSweepS);
     hipLaunchKernelGGL((nh::k_sweep_tb<T, nh::kSweepB, nh::kSweepS,
                                          nh::kSweepM>),
-                       dim3(a.nblocks()), dim3(nh::kSweepB), lds, s->stream, a,
-                       L);
+                       dim3(a.nblocks()), dim3(nh::kSweepB),
+                       sweep_lds_bytes(s->tbx, s->tby), s->stream, a, L);
   }
 
   static void thomas(nh_solver* s, void* pout) {
@@ -296,32 +408,28 @@ struct Launch {
                        s->flags);
   }
 
-  template <bool COMBINE>
-  static void correct(nh_solver* s, int have_p, void* q1, void* q2, void* wst,
-                      void* p, void* oq1, void* oq2, void* w_out) {
-    const auto& g = s->grid;
-    const auto& pr = s->par;
-    nh::CorrectArgs<T> a{g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g, (T)pr.delta,
-                         (T)pr.dry_eps, have_p, P(s->hs_cur), P(q1), P(q2),
-                         P(s->H), P(wst), (const double*)p, s->dt, P(oq1),
-                         P(oq2), P(w_out), P(s->h), P(s->q1), P(s->q2),
-                         s->lampart, s->flags};
-    if (s->one_d)
-      hipLaunchKernelGGL((nh::k_correct<T, true, COMBINE>),
-                         dim3(a.nblocks(true)), dim3(nh::kBlock), 0,
-                         s->stream, a);
-    else
-      hipLaunchKernelGGL((nh::k_correct<T, false, COMBINE>),
-                         dim3(a.nblocks(false)), dim3(nh::kBlock), 0,
-                         s->stream, a);
+  static void correct(nh_solver* s, const StagePlan& S, const void* p) {
+    auto a = Args<T>::correct(s, S, p);
+    const unsigned nb = a.nblocks(s->one_d);
+    if (s->one_d) {
+      if (S.combine)
+        hipLaunchKernelGGL((nh::k_correct<T, true, true>), dim3(nb),
+                           dim3(nh::kBlock), 0, s->stream, a);
+      else
+        hipLaunchKernelGGL((nh::k_correct<T, true, false>), dim3(nb),
+                           dim3(nh::kBlock), 0, s->stream, a);
+    } else {
+      if (S.combine)
+        hipLaunchKernelGGL((nh::k_correct<T, false, true>), dim3(nb),
+                           dim3(nh::kBlock), 0, s->stream, a);
+      else
+        hipLaunchKernelGGL((nh::k_correct<T, false, false>), dim3(nb),
+                           dim3(nh::kBlock), 0, s->stream, a);
+    }
   }
 
   static void lambda(nh_solver* s) {
-    const auto& g = s->grid;
-    const auto& pr = s->par;
-    nh::LambdaArgs<T> a{g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g, (T)pr.delta,
-                        (T)pr.dry_eps, P(s->h), P(s->q1), P(s->q2),
-                        s->lampart};
+    auto a = Args<T>::lambda(s);
     if (s->one_d)
       hipLaunchKernelGGL((nh::k_lambda<T, true>), dim3(a.nblocks()),
                          dim3(nh::kBlock), 0, s->stream, a);
@@ -331,22 +439,29 @@ struct Launch {
   }
 };
 
-// Wait until the reduction kernel has published the measure of check number
-// s->seq in mapped host memory (spinning; the device keeps running the
-// launches queued behind it).  Stream errors end the wait.
-nh_status wait_measure(nh_solver* s, double* E) {
+// Spin until the device has released sequence number `want` into mapped host
+// memory; the stream is polled now and then so that a failed or drained
+// stream ends the wait with an error instead of a hang.
+nh_status wait_seq(hipStream_t stream, long long* seq_host, long long want) {
   long spins = 0;
-  while (__atomic_load_n(&s->slot->seq, __ATOMIC_ACQUIRE) != s->seq) {
+  while (__atomic_load_n(seq_host, __ATOMIC_ACQUIRE) != want) {
     if ((++spins & 1023) == 0) {
-      hipError_t q = hipStreamQuery(s->stream);
+      hipError_t q = hipStreamQuery(stream);
       if (q != hipSuccess && q != hipErrorNotReady)
         return fail(NH_EDEVICE, std::string("stream error while waiting: ") +
                                     hipGetErrorString(q));
-      if (q == hipSuccess &&
-          __atomic_load_n(&s->slot->seq, __ATOMIC_ACQUIRE) != s->seq)
+      if (q == hipSuccess && __atomic_load_n(seq_host, __ATOMIC_ACQUIRE) != want)
         return fail(NH_EDEVICE, "convergence measure was not published");
     }
   }
+  return NH_OK;
+}
+
+// the measure of the solver's check number s->seq (the device keeps running
+// the launches queued behind it)
+nh_status wait_measure(nh_solver* s, double* E) {
+  nh_status st = wait_seq(s->stream, &s->slot->seq, s->seq);
+  if (st != NH_OK) return st;
   *E = s->slot->E[0];
   return NH_OK;
 }
@@ -403,9 +518,10 @@ nh_status solve2d(nh_solver* s, int32_t* sweeps, double* measure) {
     }
     // the rest of the cycle: back-to-back sweep launches (timed as such)
     int before = queued;
-    long pm = (k % ce != 0 && k < kmax) ? prof_open(s, 4) : -1;
+    long pm = (k % ce != 0 && k < kmax) ? s->prof.open(s->stream, 4) : -1;
     queue_until(1 << 30);
-    prof_close(s, pm, queued - before);
+    s->prof.close(s->stream, pm, queued - before,
+                  (double)(queued - before) * nh::kSweepS * s->ncorn);
     (void)nsweeps_done;
   }
   s->solve_launches_last = launches;
@@ -415,31 +531,23 @@ nh_status solve2d(nh_solver* s, int32_t* sweeps, double* measure) {
 }
 
 template <typename T>
-nh_status stage(nh_solver* s, int idx, void* Vh, void* Vq1, void* Vq2,
-                void* w_in, void* oq1, void* oq2, void* w_out,
-                int32_t* sweeps, double* measure) {
-  const bool combine = idx == 1;
-  // h* of stage 1 is read as U^(1)'s depth by stage 2: two buffers
-  s->hs_cur = idx == 0 ? s->hs : s->h1;
-  long pm = prof_open(s, 0);
-  Launch<T>::fv(s, Vh, Vq1, Vq2);
-  prof_close(s, pm, 1);
-  void *qa = s->q1s, *qb = s->q2s, *wst = w_in;
-  pm = prof_open(s, 1);
-  if (s->par.breaking_on) {
-    Launch<T>::breaking(s, w_in);
-    qa = s->q1b;
-    qb = s->q2b;
-    wst = s->ws;
-  }
+nh_status stage(nh_solver* s, int idx, int32_t* sweeps, double* measure) {
+  const StagePlan S = stage_plan(s, idx);
+  s->hs_cur = S.hs_cur;
+  long pm = s->prof.open(s->stream, 0);
+  Launch<T>::fv(s, S);
+  s->prof.close(s->stream, pm, 1);
+  pm = s->prof.open(s->stream, 1);
+  if (s->par.breaking_on) Launch<T>::breaking(s, S);
+  if (s->par.nh_on) Launch<T>::assemble(s, S);
+  s->prof.close(s->stream, pm,
+                (s->par.breaking_on ? 2 : 0) + (s->par.nh_on ? 1 : 0));
   nh_status st = NH_OK;
   *sweeps = 0;
   *measure = 0.0;
-  void* p = nullptr;
-  if (s->par.nh_on) Launch<T>::assemble(s, qa, qb, wst);
-  prof_close(s, pm, (s->par.breaking_on ? 2 : 0) + (s->par.nh_on ? 1 : 0));
+  const void* p = nullptr;
   if (s->par.nh_on) {
-    pm = prof_open(s, 2);
+    pm = s->prof.open(s->stream, 2);
     if (s->one_d) {
       Launch<T>::thomas(s, s->pcur_ptr());
       s->solve_launches_last = 1;
@@ -447,20 +555,12 @@ nh_status stage(nh_solver* s, int idx, void* Vh, void* Vq1, void* Vq2,
       st = solve2d<T>(s, sweeps, measure);
       if (st != NH_OK && st != NH_ENOCONV) return st;
     }
-    prof_close(s, pm, s->solve_launches_last);
+    s->prof.close(s->stream, pm, s->solve_launches_last);
     p = s->pcur_ptr();
   }
-  int have_p = s->par.nh_on ? 1 : 0;
-  void* pp = p ? p : s->pa;
-  pm = prof_open(s, 3);
-  if (combine)
-    Launch<T>::template correct<true>(s, have_p, qa, qb, wst, pp, nullptr,
-                                      nullptr, w_out);
-  else
-    Launch<T>::template correct<false>(s, have_p, qa, qb, wst, pp, oq1, oq2,
-                                       w_out);
-  prof_close(s, pm, 1);
-  (void)Vh;
+  pm = s->prof.open(s->stream, 3);
+  Launch<T>::correct(s, S, p);
+  s->prof.close(s->stream, pm, 1);
   return st;
 }
 
@@ -479,7 +579,7 @@ nh_status sync_stats(nh_solver* s) {
   HIP_TRY(hipMemcpyAsync(&clamped, s->clamped, sizeof(double),
                          hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
-  prof_flush(s);
+  s->prof.flush();
   s->st.t = ds.t;
   s->st.dt_last = ds.dt_last;
   s->st.step = ds.step;
@@ -506,17 +606,13 @@ nh_status step_impl(nh_solver* s) {
   int32_t sw1 = 0, sw2 = 0;
   double m1 = 0.0, m2 = 0.0;
   // stage 1: U^n -> U^(1)  (h* of stage 1 in hs)
-  nh_status st = stage<T>(s, 0, s->h, s->q1, s->q2, s->w, s->q11, s->q21,
-                          s->w1, &sw1, &m1);
+  nh_status st = stage<T>(s, 0, &sw1, &m1);
   if (st != NH_OK && st != NH_ENOCONV) return st;
   // stage 2: U^(1) -> U^(2), averaged into U^n
-  nh_status st2 = stage<T>(s, 1, s->hs, s->q11, s->q21, s->w1, nullptr,
-                           nullptr, s->w, &sw2, &m2);
+  nh_status st2 = stage<T>(s, 1, &sw2, &m2);
   if (st2 != NH_OK && st2 != NH_ENOCONV) return st2;
   if (st == NH_OK) st = st2;
-  nh::FinalizeArgs fa{s->par.cfl, s->par.fixed_dt, s->lampart,
-                      (int)nblocks(std::max(s->ncell, s->ncorn)), s->dt,
-                      s->flags, s->dstats};
+  nh::FinalizeArgs fa = finalize_args(s, true);
   hipLaunchKernelGGL(nh::k_finalize_dt, dim3(1), dim3(nh::kBlock), 0,
                      s->stream, fa);
   s->st.sweeps[0] = sw1;
@@ -730,8 +826,7 @@ nh_status nh_set_state(nh_solver* s, const double* h, const double* hu,
       Launch<float>::lambda(s);
     else
       Launch<double>::lambda(s);
-    nh::FinalizeArgs fa{s->par.cfl, 0, s->lampart, (int)nblocks(s->ncell),
-                        s->dt, s->flags, nullptr};
+    nh::FinalizeArgs fa = finalize_args(s, false);
     hipLaunchKernelGGL(nh::k_finalize_dt, dim3(1), dim3(nh::kBlock), 0,
                        s->stream, fa);
     HIP_TRY(hipMemcpyAsync(&dt0, s->dt, sizeof(double), hipMemcpyDeviceToHost,
@@ -818,17 +913,17 @@ nh_status nh_get_stats(const nh_solver* s, nh_stats* out) {
 nh_status nh_profile(nh_solver* s, int32_t on) {
   if (!s) return fail(NH_EINVAL, "null solver");
   if (s->stream) HIP_TRY(hipStreamSynchronize(s->stream));
-  prof_flush(s);
-  s->prof = on != 0;
-  if (s->prof) std::memset(&s->pr, 0, sizeof(s->pr));
+  s->prof.flush();
+  s->prof.on = on != 0;
+  if (s->prof.on) std::memset(&s->prof.pr, 0, sizeof(s->prof.pr));
   return NH_OK;
 }
 
 nh_status nh_get_profile(nh_solver* s, nh_profile_t* out) {
   if (!s || !out) return fail(NH_EINVAL, "null argument");
   HIP_TRY(hipStreamSynchronize(s->stream));
-  prof_flush(s);
-  *out = s->pr;
+  s->prof.flush();
+  *out = s->prof.pr;
   return NH_OK;
 }
 
@@ -837,12 +932,12 @@ void nh_destroy(nh_solver* s) {
   if (s->stream) hipStreamSynchronize(s->stream);
   for (void* p : s->allocs) hipFree(p);
   if (s->slot) hipHostFree(s->slot);
-  for (auto& m : s->marks) {
-    if (m.a) hipEventDestroy(m.a);
-    if (m.b) hipEventDestroy(m.b);
-  }
+  s->prof.release();
   if (s->own_stream) hipStreamDestroy(s->stream);
   delete s;
 }
 
 }  // extern "C"
+
+// ensembles of grids (nh_ensemble_*), built on the pieces above
+#include "ensemble_impl.hpp"

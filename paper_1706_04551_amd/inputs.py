@@ -13,6 +13,7 @@ have the shapes of its workloads):
       hump (circular dam-break / conical-island shapes of Sections 7.6-7.7).
   c3  2D 2048x2048 plane beach with an incoming solitary wave, breaking on
       (Section 7.4 shape).
+  c4  ensemble of 64 c2-like basins of uneven sides 128-1024, FP32 bulk.
 Cell centres sit at ((i+1/2) dx, (j+1/2) dy).  Arrays are [ny][nx], float64.
 
 CFL: the 1D channel uses 0.9.  The 2D workloads use 0.7: with the 2D time
@@ -249,6 +250,39 @@ def case_c3(n: int = 2048, steps: int = 4000) -> Case:
     c.check_every = 64
     del x_shore
     return c
+
+
+C4_SIDES = (128, 256, 512, 768, 1024)
+
+
+def case_c4_member(k: int, seed: int = SEED_C4, sides=C4_SIDES,
+                   steps: int = 500, precision: str = "f32") -> Case:
+    """Scenario k of the ensemble workload, drawn from its own generator
+    (seed + k): side n uniform over `sides`, the island basin of c2 at that
+    side (dx = 1 m), a Gaussian source of amplitude U[0.1, 1] m and radius
+    20 m on wet water.  FP32 bulk unless precision says otherwise."""
+    rng = np.random.default_rng(seed + k)
+    n = int(sides[int(rng.integers(len(sides)))])
+    amp = float(rng.uniform(0.1, 1.0))
+    basin_seed = int(rng.integers(1 << 31))
+    H, h0 = island_basin(n, 1.0, basin_seed, hump_amp=amp, hump_radius=20.0)
+    z = np.zeros_like(h0)
+    f32 = precision == "f32"
+    c = Case(f"c4-{k}", n, n, 1.0, 1.0, H, h0, z, z.copy(), steps,
+             precision=precision, solve_tol=1e-5 if f32 else 1e-10,
+             dry_eps=1e-5 if f32 else 1e-10, cfl=CFL_2D)
+    rho = jacobi_radius_bound(float(h0.max()), c.dx, c.dy)
+    c.omega = srj_schedule(rho, 64)
+    c.check_every = 64
+    return c
+
+
+def case_c4(members: int = 64, seed: int = SEED_C4, sides=C4_SIDES,
+            steps: int = 500, precision: str = "f32") -> list:
+    """Ensemble workload: `members` independent scenarios (case_c4_member),
+    64 by default, of uneven sizes (expected total about 25.4 M cells)."""
+    return [case_c4_member(k, seed, sides, steps, precision)
+            for k in range(members)]
 
 
 def lake_at_rest(n: int = 64, dx: float = 1.0, seed: int = SEED_C2,

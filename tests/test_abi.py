@@ -58,3 +58,25 @@ def test_invalid_arguments_are_rejected_without_a_device():
                        ctypes.byref(out)) == -1
     assert b"multiple" in L.nh_last_error()
     assert L.nh_step(None, None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_ensemble_arguments_are_checked_without_a_device():
+    from paper_1706_04551_amd import binding as B
+    L = B.lib()
+    out = ctypes.c_void_p()
+
+    def params(prec=0):
+        return B.NhParams(9.81, 0.7, 1e-5, 1e-10, prec, 1, 0, 0.15, 0.5, 100,
+                          1, 1e-10, None, 0, 0, 0.0)
+    G = (B.NhGrid * 2)(B.NhGrid(10, 10, 1.0, 1.0), B.NhGrid(12, 12, 1.0, 1.0))
+    P = (B.NhParams * 2)(params(0), params(1))
+    assert L.nh_ensemble_create(2, G, P, None, ctypes.byref(out)) == -1
+    assert b"share" in L.nh_last_error()
+    P = (B.NhParams * 2)(params(0), params(0))
+    G1 = (B.NhGrid * 2)(B.NhGrid(10, 10, 1.0, 1.0), B.NhGrid(12, 1, 1.0, 1.0))
+    assert L.nh_ensemble_create(2, G1, P, None, ctypes.byref(out)) == -1
+    assert b"2D" in L.nh_last_error()
+    assert L.nh_ensemble_create(0, G, P, None, ctypes.byref(out)) == -1
+    assert L.nh_ensemble_run(None, 1) == -1
+    assert L.nh_ensemble_set_tile(None, 0, 24, 24) == -1

@@ -1,0 +1,193 @@
+"""Ensembles (many grids advanced by the same launches) on the GPU.
+
+Each member must compute exactly what a single-grid solve of its case
+computes -- the batched kernels run the single-grid arithmetic -- so the
+comparison with single-grid solves is bitwise; the comparison with the FP64
+oracle uses the usual normwise bars (1e-9 FP64, 1e-4 FP32 on h and hu).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle, Params
+from paper_1706_04551_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("h", "hu", "hv", "w", "p")
+SMALL = (64, 97, 80, 130)   # uneven sides, ragged tiles for every candidate
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def small_cases(precision, sides=SMALL):
+    return [I.case_c4_member(k, sides=(n,), precision=precision)
+            for k, n in enumerate(sides)]
+
+
+def ensemble(cases):
+    from paper_1706_04551_amd import Ensemble
+    return Ensemble.from_cases(cases)
+
+
+def single(case, steps):
+    from paper_1706_04551_amd import Solver
+    s = Solver.from_case(case)
+    s.run(steps)
+    out, st = s.state(), s.stats()
+    s.close()
+    return out, st
+
+
+def maxrel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_members_match_single_grid_solves_bitwise(precision):
+    cases = small_cases(precision)
+    steps = 12
+    say(f"[ensemble] {len(cases)} members {SMALL} {precision} steps={steps}")
+    e = ensemble(cases)
+    e.run(steps)
+    for k, c in enumerate(cases):
+        g, gs = e.state(k), e.stats(k)
+        r, rs = single(c, steps)
+        for f in FIELDS:
+            assert np.array_equal(g[f], r[f]), (k, f, maxrel(g[f], r[f]))
+        for key in ("t", "dt", "step", "sweeps1", "sweeps2", "sweeps_total",
+                    "solves", "measure"):
+            assert gs[key] == rs[key], (k, key, gs[key], rs[key])
+    e.close()
+
+
+def test_tile_shapes_do_not_change_results():
+    cases = small_cases("f64")
+    steps = 6
+    a = ensemble(cases)
+    a.run(steps)
+    b = ensemble(cases)
+    tiles = [(16, 16), (64, 8), (40, 16), (28, 28)]
+    for k, t in enumerate(tiles):
+        b.set_tile(k, *t)
+        assert b.tile(k) == t
+    b.run(steps)
+    for k in range(len(cases)):
+        sa, sb = a.state(k), b.state(k)
+        for f in FIELDS:
+            assert np.array_equal(sa[f], sb[f]), (k, f)
+    a.close()
+    b.close()
+
+
+def test_tuner_picks_a_valid_tile_and_keeps_results():
+    cases = small_cases("f32", sides=(64, 130, 64))
+    steps = 4
+    a = ensemble(cases)
+    a.tune(2)
+    for k in range(len(cases)):
+        bx, by = a.tile(k)
+        assert bx >= 4 and by >= 4 and (bx + 16) * (by + 16) <= 2048
+    assert a.tile(0) == a.tile(2)           # one choice per grid shape
+    a.run(steps)
+    b = ensemble(cases)
+    b.run(steps)
+    for k in range(len(cases)):
+        for f in FIELDS:
+            assert np.array_equal(a.state(k)[f], b.state(k)[f]), (k, f)
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-9), ("f32", 1e-4)])
+def test_members_match_the_oracle(precision, tol):
+    cases = small_cases(precision, sides=(64, 97, 80))
+    steps = 10
+    e = ensemble(cases)
+    e.run(steps)
+    for k, c in enumerate(cases):
+        say(f"[ensemble-oracle] member {k} {c.nx}x{c.ny} {precision}")
+        o = Oracle(Params(**c.param_dict()))
+        o.set_bathymetry(c.H)
+        o.set_state(c.h, c.hu, c.hv)
+        assert o.run(steps) == 0
+        r = o.state()
+        g = e.state(k)
+        scale = max(np.abs(r["hu"]).max(), np.abs(r["hv"]).max())
+        assert maxrel(g["h"], r["h"]) <= tol
+        assert np.abs(g["hu"] - r["hu"]).max() / scale <= tol
+        if precision == "f64":
+            assert np.abs(g["hv"] - r["hv"]).max() / scale <= tol
+            assert abs(e.stats(k)["t"] - o.stats()["t"]) <= 1e-9 * o.stats()["t"]
+    e.close()
+
+
+def test_members_without_a_valid_state_are_left_out():
+    from paper_1706_04551_amd import NhError
+    cases = small_cases("f64", sides=(64, 80, 64))
+    from paper_1706_04551_amd import Ensemble
+    grids, params = [], []
+    for c in cases:
+        kw = c.param_dict()
+        grids.append((kw.pop("nx"), kw.pop("ny"), kw.pop("dx"), kw.pop("dy")))
+        kw["precision"] = c.precision
+        params.append(kw)
+    e = Ensemble(grids, params)
+    for k, c in enumerate(cases):
+        e.set_bathymetry(k, c.H)
+    e.set_state(0, cases[0].h, cases[0].hu, cases[0].hv)
+    dry = np.zeros_like(cases[1].h)
+    with pytest.raises(NhError):
+        e.set_state(1, dry, dry, dry)    # no wet cell: no CFL time step
+    # member 2 never gets a state
+    e.run(5)
+    r, _ = single(cases[0], 5)
+    assert np.array_equal(e.state(0)["h"], r["h"])
+    assert e.stats(1)["step"] == 0 and e.stats(2)["step"] == 0
+    # a member can join later
+    e.set_state(2, cases[2].h, cases[2].hu, cases[2].hv)
+    e.run(5)
+    r2, _ = single(cases[2], 5)
+    assert np.array_equal(e.state(2)["h"], r2["h"])
+    assert e.stats(0)["step"] == 10
+    e.close()
+
+
+def test_full_ensemble_workload_short_run():
+    """The 64-member workload at full size in the launch configuration of the
+    benchmark (tuned tiles): members sampled against single-grid solves
+    (bitwise) and the smallest one against the oracle; mass of every member
+    conserved."""
+    cases = I.case_c4()
+    steps = 3
+    say(f"[c4] {len(cases)} members, {sum(c.nx * c.ny for c in cases)} cells")
+    e = ensemble(cases)
+    e.tune(2)
+    e.run(steps)
+    small = min(range(len(cases)), key=lambda k: cases[k].nx)
+    big = max(range(len(cases)), key=lambda k: cases[k].nx)
+    for k in (small, big):
+        say(f"[c4] member {k} {cases[k].nx}^2 vs single grid")
+        r, rs = single(cases[k], steps)
+        g = e.state(k)
+        for f in FIELDS:
+            assert np.array_equal(g[f], r[f]), (k, f)
+    c = cases[small]
+    o = Oracle(Params(**c.param_dict()))
+    o.set_bathymetry(c.H)
+    o.set_state(c.h, c.hu, c.hv)
+    assert o.run(steps) == 0
+    r = o.state()
+    g = e.state(small)
+    assert maxrel(g["h"], r["h"]) <= 1e-4
+    for k, c in enumerate(cases):
+        st = e.stats(k)
+        assert st["step"] == steps and st["status"] in (0, -4)
+        m0 = float(np.sum(c.h, dtype=np.float64))
+        m1 = float(np.sum(e.state(k)["h"], dtype=np.float64))
+        assert abs(m1 - m0 - st["clamped"]) <= 1e-5 * m0, k
+    e.close()
