@@ -213,7 +213,7 @@ def case_c2(n: int = 512, steps: int = 1000, precision: str = "f64",
     (fully wet)."""
     H, h0 = island_basin(n, 1.0, seed, island=island)
     z = np.zeros_like(h0)
-    tol = 1e-10 if precision == "f64" else 1e-5
+    tol = 1e-10 if precision == "f64" else 1e-6
     c = Case("c2" if island else "c2-wet", n, n, 1.0, 1.0, H, h0, z,
              z.copy(), steps,
              precision=precision, solve_tol=tol, cfl=CFL_2D,
@@ -243,7 +243,7 @@ def case_c3(n: int = 2048, steps: int = 4000) -> Case:
     h = np.tile(hx, (n, 1))
     hu = np.tile(qx, (n, 1))
     c = Case("c3", n, n, dx, dx, H, h, hu, np.zeros_like(h), steps,
-             breaking_on=1, precision="f32", solve_tol=1e-5, dry_eps=1e-5,
+             breaking_on=1, precision="f32", solve_tol=1e-6, dry_eps=1e-5,
              cfl=CFL_2D)
     rho = jacobi_radius_bound(float(h.max()), dx, dx)
     c.omega = srj_schedule(rho, 64)
@@ -269,7 +269,7 @@ def case_c4_member(k: int, seed: int = SEED_C4, sides=C4_SIDES,
     z = np.zeros_like(h0)
     f32 = precision == "f32"
     c = Case(f"c4-{k}", n, n, 1.0, 1.0, H, h0, z, z.copy(), steps,
-             precision=precision, solve_tol=1e-5 if f32 else 1e-10,
+             precision=precision, solve_tol=1e-6 if f32 else 1e-10,
              dry_eps=1e-5 if f32 else 1e-10, cfl=CFL_2D)
     rho = jacobi_radius_bound(float(h0.max()), c.dx, c.dy)
     c.omega = srj_schedule(rho, 64)
