@@ -228,10 +228,12 @@ nh_status ens_solve(nh_ensemble* e, int stage) {
     int nsw = k >= kmax ? 0 : std::min(std::min(S, ce), kmax - k);
     ens_sweeps<T>(e, true, k, nsw, cur, out, save);
     ++e->seq;
-    hipLaunchKernelGGL((nh::k_ens_check<T>), dim3(1), dim3(nh::kBlock), 0,
+    hipLaunchKernelGGL((nh::k_ens_check<T>), dim3(L), dim3(nh::kBlock), 0,
                        e->stream, (const nh::SweepArgs<T>*)e->sweep,
-                       e->dmem_live, L, kc, kmax, save, stage,
-                       slot_E(e->slot_dev), slot_active(e->slot_dev, e->n),
+                       e->dmem_live, kc, kmax, save, stage,
+                       slot_E(e->slot_dev), slot_active(e->slot_dev, e->n));
+    hipLaunchKernelGGL(nh::k_ens_publish, dim3(1), dim3(nh::kBlock), 0,
+                       e->stream, (const nh::EnsMember*)e->dmem_live, L,
                        &e->slot_dev->nactive, &e->slot_dev->seq, e->seq);
     if (nsw > 0) {
       cur = out;

@@ -629,6 +629,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a,
   const int x0 = tx * BX - S, y0 = ty * BY - S;
   double* P0 = lds;
   double* P1 = lds + R;
+  // FP32 bulk: the update is formed with fused multiply-adds and the
+  // reciprocal of the diagonal, in FP64 (FP64 bulk keeps the operation order
+  // of the plain statement)
+  constexpr bool kFused = sizeof(T) == 4;
   // outside the domain: diag 1, everything else 0 (the iterate stays 0)
   double dg[M], ce[M], cw[M], cn[M], cs[M], cr[M];
   int rx[M], ry[M];
@@ -660,6 +664,11 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a,
       P0[idx] = pv;
     }
   }
+  double rdg[M];
+  if constexpr (kFused) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) rdg[m] = 1.0 / dg[m];
+  }
   __syncthreads();
   double e = 0.0;
   const int iters = nsw > 0 ? nsw : 1;
@@ -673,18 +682,30 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a,
       if (x > t && x < RW - 1 - t && y > t && y < RH - 1 - t) {
         const int idx = (int)threadIdx.x + B * m;
         const double pc = src[idx];
-        double Ap = dg[m] * pc;
-        Ap += ce[m] * src[idx + 1];
-        Ap += cw[m] * src[idx - 1];
-        Ap += cn[m] * src[idx + RW];
-        Ap += cs[m] * src[idx - RW];
-        const double r = cr[m] - Ap;
-        const double rd = r / dg[m];
+        double rd, pn;
+        if constexpr (kFused) {
+          double Ap = dg[m] * pc;
+          Ap = fma(ce[m], src[idx + 1], Ap);
+          Ap = fma(cw[m], src[idx - 1], Ap);
+          Ap = fma(cn[m], src[idx + RW], Ap);
+          Ap = fma(cs[m], src[idx - RW], Ap);
+          rd = (cr[m] - Ap) * rdg[m];
+          pn = fma(om, rd, pc);
+        } else {
+          double Ap = dg[m] * pc;
+          Ap += ce[m] * src[idx + 1];
+          Ap += cw[m] * src[idx - 1];
+          Ap += cn[m] * src[idx + RW];
+          Ap += cs[m] * src[idx - RW];
+          const double r = cr[m] - Ap;
+          rd = r / dg[m];
+          pn = pc + om * rd;
+        }
         if (t == 0 && check && x >= S && x < S + BX && y >= S && y < S + BY) {
           double ar = fabs(rd);
           e = (ar > e || ar != ar) ? ar : e;
         }
-        if (nsw > 0) dst[idx] = pc + om * rd;
+        if (nsw > 0) dst[idx] = pn;
       }
     }
     __syncthreads();
@@ -1004,56 +1025,65 @@ __global__ void k_ens_begin(EnsMember* __restrict__ mem, int n) {
   for (int g = threadIdx.x; g < n; g += blockDim.x) mem[g].active = 1;
 }
 
-// Convergence check of every active member (one wave per member): the max of
-// its per-tile measures of the iterate p^kc; a member stops when it is below
-// its tolerance, when kc reached the sweep cap or when it is not finite, and
-// its saved iterate p^kc (logical buffer `save`) becomes logical buffer 0.
-// The measures, the active flags and the number of members still active go
-// to mapped host memory, then the check's sequence number is released.
+// Convergence check of every active member, one workgroup per member: the
+// max of its per-tile measures of the iterate p^kc; a member stops when it
+// is below its tolerance, when kc reached the sweep cap or when it is not
+// finite, and its saved iterate p^kc (logical buffer `save`) becomes logical
+// buffer 0.  The measure and the active flag go to mapped host memory.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_ens_check(const SweepArgs<T>* __restrict__ as,
-                EnsMember* __restrict__ mem, int n, int kc, int kmax,
-                int save, int stage, double* __restrict__ E_host,
-                int* __restrict__ active_host, int* __restrict__ nactive_host,
-                long long* seq_slot, long long seq) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int nw = blockDim.x >> 6;
-  int still = 0;
-  for (int g = wv; g < n; g += nw) {
-    if (!mem[g].active) continue;  // uniform over the wave
-    const double* part = as[g].part;
-    double v = 0.0;
-    for (int i = lane; i < as[g].ntiles; i += 64) {
-      double x = part[i];
-      v = (x > v || x != x) ? x : v;
-    }
-    v = wave_max(v);
-    if (lane == 0) {
-      EnsMember& m = mem[g];
-      const bool ok = v < m.tol;
-      const bool stop = ok || kc >= kmax || !(v == v) || isinf(v);
-      if (stop) {
-        m.active = 0;
-        m.rot = (m.rot + save) % 3;
-        m.sweeps[stage] = kc;
-        m.measure = v;
-        m.sweeps_total += kc;
-        m.solves_total += 1;
-        if (!ok) m.noconv += 1;
-      } else {
-        still += 1;
-      }
-      E_host[g] = v;
-      active_host[g] = stop ? 0 : 1;
-    }
+                EnsMember* __restrict__ mem, int kc, int kmax, int save,
+                int stage, double* __restrict__ E_host,
+                int* __restrict__ active_host) {
+  const int g = blockIdx.x;
+  if (!mem[g].active) return;  // uniform over the workgroup
+  const double* part = as[g].part;
+  const int nt = as[g].ntiles;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+    double x = part[i];
+    v = (x > v || x != x) ? x : v;
   }
+  __shared__ double wmax[kBlock / 64];
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  v = wmax[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+    v = (wmax[w] > v || wmax[w] != wmax[w]) ? wmax[w] : v;
+  EnsMember& m = mem[g];
+  const bool ok = v < m.tol;
+  const bool stop = ok || kc >= kmax || !(v == v) || isinf(v);
+  if (stop) {
+    m.active = 0;
+    m.rot = (m.rot + save) % 3;
+    m.sweeps[stage] = kc;
+    m.measure = v;
+    m.sweeps_total += kc;
+    m.solves_total += 1;
+    if (!ok) m.noconv += 1;
+  }
+  E_host[g] = v;
+  active_host[g] = stop ? 0 : 1;
+}
+
+// After k_ens_check: the number of members still active goes to mapped host
+// memory, then the check's sequence number (release at system scope).
+__global__ void __launch_bounds__(kBlock)
+    k_ens_publish(const EnsMember* __restrict__ mem, int n,
+                  int* __restrict__ nactive_host, long long* seq_slot,
+                  long long seq) {
+  int c = 0;
+  for (int g = threadIdx.x; g < n; g += blockDim.x) c += mem[g].active;
   __shared__ int cnt[kBlock / 64];
-  if (lane == 0) cnt[wv] = still;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+  if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = c;
   __syncthreads();
   if (threadIdx.x == 0) {
     int tot = 0;
-    for (int w = 0; w < nw; ++w) tot += cnt[w];
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += cnt[w];
     *nactive_host = tot;
     __threadfence_system();
     __hip_atomic_store(seq_slot, seq, __ATOMIC_RELEASE,
