@@ -232,66 +232,81 @@ struct FvArgs {
   __host__ __device__ int nblocks() const { return (nx * ny + kBlock - 1) / kBlock; }
 };
 
+// loader of mirrored cells from the bulk arrays (walls by mirror images)
+template <typename T, bool ONE_D>
+struct CellLoader {
+  const T *h, *q1, *q2, *H;
+  int nx, ny;
+  __device__ __forceinline__ Cell<T> operator()(int i, int j) const {
+    return load_cell(h, q1, q2, H, i, j, nx, ny, ONE_D);
+  }
+};
+
+// The finite-volume update of cell (i, j) (eq. 20-22, 30): the values
+// h - dt (fx/dx + fy/dy), q1 - ..., q2 - ... before the positivity clamp.
+// `ld(i, j)` returns the mirrored cell; V is the arithmetic type.  `parts`
+// selects the x (1) and y (2) flux sums; a skipped part contributes zero.
+template <typename V, bool ONE_D, typename LD>
+__device__ __forceinline__ void fv_cell(const LD& ld, int i, int j, V dx, V dy,
+                                        V g, V delta, V dry_eps, V dt,
+                                        int parts, V out[3]) {
+  Prim<V> P[5];
+  Face<V> Lm, Rm, L0, R0, Lp, Rp;
+  V Dm_e[3], Dp_e[3], Dm_w[3], Dp_w[3], I[3];
+  Cell<V> c0 = ld(i, j);
+  V fx[3] = {V(0), V(0), V(0)}, fy[3] = {V(0), V(0), V(0)};
+  if (parts & 1) {
+#pragma unroll
+    for (int s = 0; s < 5; ++s)
+      P[s] = prim(s == 2 ? c0 : ld(i - 2 + s, j), true, delta, ONE_D);
+    reconstruct(P[0], P[1], P[2], dry_eps, Lm, Rm);
+    reconstruct(P[1], P[2], P[3], dry_eps, L0, R0);
+    reconstruct(P[2], P[3], P[4], dry_eps, Lp, Rp);
+    pvm(R0, Lp, g, dry_eps, Dm_e, Dp_e);
+    pvm(Rm, L0, g, dry_eps, Dm_w, Dp_w);
+    interior(L0, R0, c0.h, g, I);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) fx[m] = (Dm_e[m] + Dp_w[m]) + I[m];
+  }
+  if (!ONE_D && (parts & 2)) {
+#pragma unroll
+    for (int s = 0; s < 5; ++s)
+      P[s] = prim(s == 2 ? c0 : ld(i, j - 2 + s), false, delta, false);
+    reconstruct(P[0], P[1], P[2], dry_eps, Lm, Rm);
+    reconstruct(P[1], P[2], P[3], dry_eps, L0, R0);
+    reconstruct(P[2], P[3], P[4], dry_eps, Lp, Rp);
+    pvm(R0, Lp, g, dry_eps, Dm_e, Dp_e);
+    pvm(Rm, L0, g, dry_eps, Dm_w, Dp_w);
+    interior(L0, R0, c0.h, g, I);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) fy[m] = (Dm_e[m] + Dp_w[m]) + I[m];
+  }
+  if (ONE_D) {
+    out[0] = c0.h - dt * (fx[0] / dx);
+    out[1] = c0.q1 - dt * (fx[1] / dx);
+    out[2] = V(0);
+  } else {
+    out[0] = c0.h - dt * (fx[0] / dx + fy[0] / dy);
+    out[1] = c0.q1 - dt * (fx[1] / dx + fy[2] / dy);
+    out[2] = c0.q2 - dt * (fx[2] / dx + fy[1] / dy);
+  }
+}
+
 template <typename T, bool ONE_D>
 __device__ __forceinline__ void fv_body(const FvArgs<T>& a, int bid) {
   const int n = bid * kBlock + (int)threadIdx.x;
   const int nx = a.nx, ny = a.ny;
-  const T dx = a.dx, dy = a.dy, g = a.g, delta = a.delta, dry_eps = a.dry_eps;
-  const T* __restrict__ h = a.h;
-  const T* __restrict__ q1 = a.q1;
-  const T* __restrict__ q2 = a.q2;
-  const T* __restrict__ H = a.H;
-  int ncell = nx * ny;
+  const T dry_eps = a.dry_eps;
   double clamp_local = 0.0;
-  if (n < ncell) {
+  if (n < nx * ny) {
     int i = n % nx, j = n / nx;
     T dt = (T)(*a.dtp);
-    Prim<T> P[5];
-    Cell<T> c0;
-#pragma unroll
-    for (int s = 0; s < 5; ++s) {
-      Cell<T> c = load_cell(h, q1, q2, H, i - 2 + s, j, nx, ny, ONE_D);
-      if (s == 2) c0 = c;
-      P[s] = prim(c, true, delta, ONE_D);
-    }
-    Face<T> Lm, Rm, L0, R0, Lp, Rp;
-    reconstruct(P[0], P[1], P[2], dry_eps, Lm, Rm);
-    reconstruct(P[1], P[2], P[3], dry_eps, L0, R0);
-    reconstruct(P[2], P[3], P[4], dry_eps, Lp, Rp);
-    T Dm_e[3], Dp_e[3], Dm_w[3], Dp_w[3], I[3];
-    pvm(R0, Lp, g, dry_eps, Dm_e, Dp_e);
-    pvm(Rm, L0, g, dry_eps, Dm_w, Dp_w);
-    interior(L0, R0, c0.h, g, I);
-    T fx[3], fy[3] = {T(0), T(0), T(0)};
-#pragma unroll
-    for (int m = 0; m < 3; ++m) fx[m] = (Dm_e[m] + Dp_w[m]) + I[m];
-    if (!ONE_D) {
-#pragma unroll
-      for (int s = 0; s < 5; ++s) {
-        Cell<T> c = load_cell(h, q1, q2, H, i, j - 2 + s, nx, ny, false);
-        P[s] = prim(c, false, delta, false);
-      }
-      reconstruct(P[0], P[1], P[2], dry_eps, Lm, Rm);
-      reconstruct(P[1], P[2], P[3], dry_eps, L0, R0);
-      reconstruct(P[2], P[3], P[4], dry_eps, Lp, Rp);
-      pvm(R0, Lp, g, dry_eps, Dm_e, Dp_e);
-      pvm(Rm, L0, g, dry_eps, Dm_w, Dp_w);
-      interior(L0, R0, c0.h, g, I);
-#pragma unroll
-      for (int m = 0; m < 3; ++m) fy[m] = (Dm_e[m] + Dp_w[m]) + I[m];
-    }
-    T hs, qa, qb;
-    if (ONE_D) {
-      hs = c0.h - dt * (fx[0] / dx);
-      qa = c0.q1 - dt * (fx[1] / dx);
-      qb = T(0);
-    } else {
-      hs = c0.h - dt * (fx[0] / dx + fy[0] / dy);
-      qa = c0.q1 - dt * (fx[1] / dx + fy[2] / dy);
-      qb = c0.q2 - dt * (fx[2] / dx + fy[1] / dy);
-    }
+    CellLoader<T, ONE_D> ld{a.h, a.q1, a.q2, a.H, nx, ny};
+    T out[3];
+    fv_cell<T, ONE_D>(ld, i, j, a.dx, a.dy, a.g, a.delta, dry_eps, dt, 3, out);
+    T hs = out[0], qa = out[1], qb = out[2];
     if (hs < T(0)) {
-      clamp_local = -(double)hs * (double)dx * (ONE_D ? 1.0 : (double)dy);
+      clamp_local = -(double)hs * (double)a.dx * (ONE_D ? 1.0 : (double)a.dy);
       hs = T(0);
     }
     if (hs <= dry_eps) {
@@ -425,69 +440,83 @@ struct AssembleArgs {
   __host__ __device__ int nblocks() const { return ((nx + 1) * (ny + 1) + kBlock - 1) / kBlock; }
 };
 
+// The five-point row and right-hand side at corner (k, l) from the mirrored
+// cells of `ld`; wc = w* at the corner.  Out: diag, cE, cW, cN, cS, rhs.
+template <typename V, typename LD>
+__device__ __forceinline__ void assemble_row(const LD& ld, int k, int l, int nx,
+                                             int ny, V dx, V dy, V wc, V dt,
+                                             V row[6]) {
+  const int ci[4] = {k - 1, k, k - 1, k};  // SW, SE, NW, NE
+  const int cj[4] = {l - 1, l - 1, l, l};
+  V hh[4], zz[4], XX[4], YY[4], a1[4], a2[4];  // a1, a2: q1, q2 of the cells
+  auto zeta = [&](int i, int j) {
+    Cell<V> c = ld(i, j);
+    return c.h - V(2) * c.H;
+  };
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    Cell<V> c = ld(ci[s], cj[s]);
+    hh[s] = c.h;
+    a1[s] = c.q1;
+    a2[s] = c.q2;
+    zz[s] = c.h - V(2) * c.H;
+    XX[s] = (zeta(ci[s] + 1, cj[s]) - zeta(ci[s] - 1, cj[s])) / V(2);
+    YY[s] = (zeta(ci[s], cj[s] + 1) - zeta(ci[s], cj[s] - 1)) / V(2);
+  }
+  const int SW = 0, SE = 1, NW = 2, NE = 3;
+  V hc = V(0.25) * (hh[SW] + hh[SE] + hh[NW] + hh[NE]);
+  V hE = V(0.5) * (hh[SE] + hh[NE]), hW = V(0.5) * (hh[SW] + hh[NW]);
+  V hN = V(0.5) * (hh[NW] + hh[NE]), hS = V(0.5) * (hh[SW] + hh[SE]);
+  V XE = V(0.5) * (XX[SE] + XX[NE]), XW = V(0.5) * (XX[SW] + XX[NW]);
+  V YN = V(0.5) * (YY[NW] + YY[NE]), YS = V(0.5) * (YY[SW] + YY[SE]);
+  V sx = V(0.5) * (zz[SE] + zz[NE]) - V(0.5) * (zz[SW] + zz[NW]);
+  V sy = V(0.5) * (zz[NW] + zz[NE]) - V(0.5) * (zz[SW] + zz[SE]);
+  V q1E = V(0.5) * (a1[SE] + a1[NE]), q1W = V(0.5) * (a1[SW] + a1[NW]);
+  V q2N = V(0.5) * (a2[NW] + a2[NE]), q2S = V(0.5) * (a2[SW] + a2[SE]);
+  V dx2 = dx * dx, dy2 = dy * dy;
+  V d = V(16) +
+        ((V(2) * hc + sx) * (XW + V(2) * hW) -
+         (V(2) * hc - sx) * (XE - V(2) * hE)) / dx2 +
+        ((V(2) * hc + sy) * (YS + V(2) * hS) -
+         (V(2) * hc - sy) * (YN - V(2) * hN)) / dy2;
+  V e = -(V(2) * hc - sx) * (XE + V(2) * hE) / dx2;
+  V wv = (V(2) * hc + sx) * (XW - V(2) * hW) / dx2;
+  V nn = -(V(2) * hc - sy) * (YN + V(2) * hN) / dy2;
+  V ss = (V(2) * hc + sy) * (YS - V(2) * hS) / dy2;
+  V Bs = ((V(2) * hc - sx) * q1E - (V(2) * hc + sx) * q1W) / dx +
+         ((V(2) * hc - sy) * q2N - (V(2) * hc + sy) * q2S) / dy +
+         V(4) * hc * wc;
+  V r = -(V(4) / dt) * Bs;
+  if (k == 0) { e = e + wv; wv = V(0); }
+  if (k == nx) { wv = wv + e; e = V(0); }
+  if (l == 0) { nn = nn + ss; ss = V(0); }
+  if (l == ny) { ss = ss + nn; nn = V(0); }
+  row[0] = d;
+  row[1] = e;
+  row[2] = wv;
+  row[3] = nn;
+  row[4] = ss;
+  row[5] = r;
+}
+
 template <typename T>
 __device__ __forceinline__ void assemble2d_body(const AssembleArgs<T>& a,
                                                 int bid) {
   const int nx = a.nx, ny = a.ny;
-  const T dx = a.dx, dy = a.dy;
-  const T* __restrict__ h = a.h;
-  const T* __restrict__ q1 = a.q1;
-  const T* __restrict__ q2 = a.q2;
-  const T* __restrict__ H = a.H;
   int ncx = nx + 1, ncy = ny + 1;
   const int n = bid * kBlock + (int)threadIdx.x;
   if (n >= ncx * ncy) return;
   int k = n % ncx, l = n / ncx;
   T dt = (T)(*a.dtp);
-  const int ci[4] = {k - 1, k, k - 1, k};  // SW, SE, NW, NE
-  const int cj[4] = {l - 1, l - 1, l, l};
-  T hh[4], zz[4], XX[4], YY[4], a1[4], a2[4];  // a1, a2: q1, q2 of the cells
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    Cell<T> c = load_cell(h, q1, q2, H, ci[s], cj[s], nx, ny, false);
-    hh[s] = c.h;
-    a1[s] = c.q1;
-    a2[s] = c.q2;
-    zz[s] = c.h - T(2) * c.H;
-    XX[s] = (zeta_at(h, H, ci[s] + 1, cj[s], nx, ny) -
-             zeta_at(h, H, ci[s] - 1, cj[s], nx, ny)) / T(2);
-    YY[s] = (zeta_at(h, H, ci[s], cj[s] + 1, nx, ny) -
-             zeta_at(h, H, ci[s], cj[s] - 1, nx, ny)) / T(2);
-  }
-  const int SW = 0, SE = 1, NW = 2, NE = 3;
-  T hc = T(0.25) * (hh[SW] + hh[SE] + hh[NW] + hh[NE]);
-  T hE = T(0.5) * (hh[SE] + hh[NE]), hW = T(0.5) * (hh[SW] + hh[NW]);
-  T hN = T(0.5) * (hh[NW] + hh[NE]), hS = T(0.5) * (hh[SW] + hh[SE]);
-  T XE = T(0.5) * (XX[SE] + XX[NE]), XW = T(0.5) * (XX[SW] + XX[NW]);
-  T YN = T(0.5) * (YY[NW] + YY[NE]), YS = T(0.5) * (YY[SW] + YY[SE]);
-  T sx = T(0.5) * (zz[SE] + zz[NE]) - T(0.5) * (zz[SW] + zz[NW]);
-  T sy = T(0.5) * (zz[NW] + zz[NE]) - T(0.5) * (zz[SW] + zz[SE]);
-  T q1E = T(0.5) * (a1[SE] + a1[NE]), q1W = T(0.5) * (a1[SW] + a1[NW]);
-  T q2N = T(0.5) * (a2[NW] + a2[NE]), q2S = T(0.5) * (a2[SW] + a2[SE]);
-  T dx2 = dx * dx, dy2 = dy * dy;
-  T d = T(16) +
-        ((T(2) * hc + sx) * (XW + T(2) * hW) -
-         (T(2) * hc - sx) * (XE - T(2) * hE)) / dx2 +
-        ((T(2) * hc + sy) * (YS + T(2) * hS) -
-         (T(2) * hc - sy) * (YN - T(2) * hN)) / dy2;
-  T e = -(T(2) * hc - sx) * (XE + T(2) * hE) / dx2;
-  T wv = (T(2) * hc + sx) * (XW - T(2) * hW) / dx2;
-  T nn = -(T(2) * hc - sy) * (YN + T(2) * hN) / dy2;
-  T ss = (T(2) * hc + sy) * (YS - T(2) * hS) / dy2;
-  T Bs = ((T(2) * hc - sx) * q1E - (T(2) * hc + sx) * q1W) / dx +
-         ((T(2) * hc - sy) * q2N - (T(2) * hc + sy) * q2S) / dy +
-         T(4) * hc * a.w[n];
-  T r = -(T(4) / dt) * Bs;
-  if (k == 0) { e = e + wv; wv = T(0); }
-  if (k == nx) { wv = wv + e; e = T(0); }
-  if (l == 0) { nn = nn + ss; ss = T(0); }
-  if (l == ny) { ss = ss + nn; nn = T(0); }
-  a.diag[n] = d;
-  a.cE[n] = e;
-  a.cW[n] = wv;
-  a.cN[n] = nn;
-  a.cS[n] = ss;
-  a.rhs[n] = r;
+  CellLoader<T, false> ld{a.h, a.q1, a.q2, a.H, nx, ny};
+  T row[6];
+  assemble_row<T>(ld, k, l, nx, ny, a.dx, a.dy, a.w[n], dt, row);
+  a.diag[n] = row[0];
+  a.cE[n] = row[1];
+  a.cW[n] = row[2];
+  a.cN[n] = row[3];
+  a.cS[n] = row[4];
+  a.rhs[n] = row[5];
 }
 
 // 1D: eq. (43) coefficients, rows scaled by dx^2, with the right-hand side
@@ -761,6 +790,69 @@ struct CorrectArgs {
   }
 };
 
+// Correction of the discharges of cell (i, j) (eq. 26-27 in 1D, eq. 36 in
+// 2D) given its stage discharges qa, qb (in/out); `ld` gives the mirrored
+// stage cells (h*, H) and `pl(k, l)` the corner pressures.
+template <typename V, bool ONE_D, typename LD, typename PL>
+__device__ __forceinline__ void correct_cell(const LD& ld, const PL& pl, int i,
+                                             int j, V dx, V dy, V dt, V dry_eps,
+                                             V& qa, V& qb) {
+  auto zeta = [&](int ii, int jj) {
+    Cell<V> c = ld(ii, jj);
+    return c.h - V(2) * c.H;
+  };
+  V hc = ld(i, j).h;
+  V zx = (zeta(i + 1, j) - zeta(i - 1, j)) / (V(2) * dx);
+  if (ONE_D) {
+    V pR = pl(i + 1, 0), pL = pl(i, 0);
+    V Tn = -V(0.5) * (hc * ((pR - pL) / dx) + (V(0.5) * (pR + pL)) * zx);
+    qa = qa + dt * Tn;
+    qb = V(0);
+  } else {
+    V zy = (zeta(i, j + 1) - zeta(i, j - 1)) / (V(2) * dy);
+    V pSW = pl(i, j), pSE = pl(i + 1, j);
+    V pNW = pl(i, j + 1), pNE = pl(i + 1, j + 1);
+    V TN = -V(0.5) * hc * (pNE - pNW) / dx -
+           V(0.5) * (V(0.5) * (pNE + pNW)) * zx;
+    V TS = -V(0.5) * hc * (pSE - pSW) / dx -
+           V(0.5) * (V(0.5) * (pSE + pSW)) * zx;
+    V TE = -V(0.5) * hc * (pNE - pSE) / dy -
+           V(0.5) * (V(0.5) * (pNE + pSE)) * zy;
+    V TW = -V(0.5) * hc * (pNW - pSW) / dy -
+           V(0.5) * (V(0.5) * (pNW + pSW)) * zy;
+    qa = qa + dt * (V(0.5) * (TN + TS));
+    qb = qb + dt * (V(0.5) * (TE + TW));
+  }
+  if (hc <= dry_eps) {
+    qa = V(0);
+    qb = V(0);
+  }
+}
+
+// w = w* + dt p / h_c at corner (k, l) with the desingularised division
+// (Section 4.5); h_c is the mean of the (mirrored) cells around the corner.
+template <typename V, bool ONE_D, typename LD>
+__device__ __forceinline__ V correct_corner(const LD& ld, int k, int l, V ws,
+                                            V pc, V dt, V delta) {
+  V hc;
+  if (ONE_D)
+    hc = V(0.5) * (ld(k - 1, 0).h + ld(k, 0).h);
+  else
+    hc = V(0.25) * (ld(k - 1, l - 1).h + ld(k, l - 1).h + ld(k - 1, l).h +
+                    ld(k, l).h);
+  return ws + dt * desing(hc, pc, delta);
+}
+
+// corner pressures of the FP64 iterate, read in the bulk type
+template <typename T>
+struct PLoader {
+  const double* p;
+  int ncx;
+  __device__ __forceinline__ T operator()(int k, int l) const {
+    return (T)p[l * ncx + k];
+  }
+};
+
 template <typename T, bool ONE_D, bool COMBINE>
 __device__ __forceinline__ void correct_body(const CorrectArgs<T>& a,
                                              int bid) {
@@ -773,39 +865,13 @@ __device__ __forceinline__ void correct_body(const CorrectArgs<T>& a,
   const int ncx = nx + 1, ncy = ONE_D ? 1 : ny + 1;
   const T dt = (T)(*a.dtp);
   double lam_local = 0.0;
+  CellLoader<T, ONE_D> ld{hs, a.q1s, a.q2s, H, nx, ONE_D ? 1 : ny};
+  PLoader<T> pl{p, ncx};
   if (n < nx * ny) {
     int i = n % nx, j = n / nx;
     T hc = hs[n];
     T qa = a.q1s[n], qb = ONE_D ? T(0) : a.q2s[n];
-    if (have_p) {
-      T zx = (zeta_at(hs, H, i + 1, j, nx, ONE_D ? 1 : ny) -
-              zeta_at(hs, H, i - 1, j, nx, ONE_D ? 1 : ny)) / (T(2) * dx);
-      if (ONE_D) {
-        T pR = (T)p[i + 1], pL = (T)p[i];
-        T Tn = -T(0.5) * (hc * ((pR - pL) / dx) + (T(0.5) * (pR + pL)) * zx);
-        qa = qa + dt * Tn;
-        qb = T(0);
-      } else {
-        T zy = (zeta_at(hs, H, i, j + 1, nx, ny) -
-                zeta_at(hs, H, i, j - 1, nx, ny)) / (T(2) * dy);
-        T pSW = (T)p[j * ncx + i], pSE = (T)p[j * ncx + i + 1];
-        T pNW = (T)p[(j + 1) * ncx + i], pNE = (T)p[(j + 1) * ncx + i + 1];
-        T TN = -T(0.5) * hc * (pNE - pNW) / dx -
-               T(0.5) * (T(0.5) * (pNE + pNW)) * zx;
-        T TS = -T(0.5) * hc * (pSE - pSW) / dx -
-               T(0.5) * (T(0.5) * (pSE + pSW)) * zx;
-        T TE = -T(0.5) * hc * (pNE - pSE) / dy -
-               T(0.5) * (T(0.5) * (pNE + pSE)) * zy;
-        T TW = -T(0.5) * hc * (pNW - pSW) / dy -
-               T(0.5) * (T(0.5) * (pNW + pSW)) * zy;
-        qa = qa + dt * (T(0.5) * (TN + TS));
-        qb = qb + dt * (T(0.5) * (TE + TW));
-      }
-      if (hc <= dry_eps) {
-        qa = T(0);
-        qb = T(0);
-      }
-    }
+    if (have_p) correct_cell<T, ONE_D>(ld, pl, i, j, dx, dy, dt, dry_eps, qa, qb);
     if (!COMBINE) {
       a.oq1[n] = qa;
       if (!ONE_D) a.oq2[n] = qb;
@@ -834,18 +900,8 @@ __device__ __forceinline__ void correct_body(const CorrectArgs<T>& a,
   if (n < ncx * ncy) {
     int k = n % ncx, l = n / ncx;
     T wv = a.ws[n];
-    if (have_p) {
-      T hc;
-      if (ONE_D) {
-        hc = T(0.5) * (hs[mirror(k - 1, nx)] + hs[mirror(k, nx)]);
-      } else {
-        int im = mirror(k - 1, nx), ip = mirror(k, nx);
-        int jm = mirror(l - 1, ny), jp = mirror(l, ny);
-        hc = T(0.25) * (hs[jm * nx + im] + hs[jm * nx + ip] +
-                        hs[jp * nx + im] + hs[jp * nx + ip]);
-      }
-      wv = wv + dt * desing(hc, (T)p[n], delta);
-    }
+    if (have_p)
+      wv = correct_corner<T, ONE_D>(ld, k, l, wv, (T)p[n], dt, delta);
     if (COMBINE)
       a.w_out[n] = T(0.5) * (a.w_out[n] + wv);
     else
