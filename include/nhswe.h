@@ -154,6 +154,36 @@ nh_status nh_get_profile(nh_solver *s, nh_profile_t *out);
 
 void nh_destroy(nh_solver *s);
 
+/* ---- Adjoint -------------------------------------------------------------
+ * Gradient of the gauge misfit
+ *   J = 1/2 sum_{n=1..nsteps} sum_g (h^n_{gauge g} - target[n-1][g])^2
+ * of a run of nsteps steps from the solver's current state, by the adjoint
+ * (reverse) of the discrete time step: the transposed Jacobians of the
+ * finite-volume update (eq. 20-22, 30), of the correction (eq. 36, 41) and of
+ * the pressure system (eq. 37-41), whose solve is done with the transposed
+ * five-point rows and the same relaxation schedule (eq. 32); every limiter,
+ * speed and wet/dry decision is the forward run's.  The forward run is
+ * checkpointed every ckpt_every steps and each segment is run again, with its
+ * stage pressures recorded, before the adjoint goes back through it.
+ *
+ * Requires a 2D grid, a fixed time step (fixed_dt = 1) and breaking_on = 0.
+ * gauges[ngauges]: flat cell indices j*nx + i; target[nsteps][ngauges] FP64.
+ * adj_tol: a transposed solve stops when its measure of eq. (32) is below
+ * adj_tol * max_c |pbar_c / diag_c| (pbar: its right-hand side).
+ * Outputs (host, FP64, cells [ny][nx], each nullable except J): J; dJ/dh0,
+ * dJ/dhu0, dJ/dhv0 w.r.t. the initial state at fixed bathymetry; dJ/dH w.r.t.
+ * the bathymetry at fixed initial state.  For h0 = H + eta0 the gradient
+ * w.r.t. eta0 is dJ/dh0 and that w.r.t. H at fixed eta0 is dJ/dH + dJ/dh0.
+ * On return the solver holds the state after the nsteps forward steps.
+ * Device memory: (nsteps/ckpt_every + 1) checkpoints and ckpt_every recorded
+ * steps (3 cell and 1 corner arrays in the bulk type plus 2 FP64 corner
+ * arrays each), kept for the next call with the same sizes. */
+nh_status nh_adjoint_run(nh_solver *s, int64_t nsteps, int32_t ngauges,
+                         const int32_t *gauges, const double *target,
+                         int32_t ckpt_every, double adj_tol, double *J,
+                         double *dJ_dh0, double *dJ_dhu0, double *dJ_dhv0,
+                         double *dJ_dH);
+
 /* ---- Ensembles -----------------------------------------------------------
  * n independent 2D grids ("members", e.g. scenarios of one basin or of
  * different basins) advanced together on one stream.  Each phase of a time

@@ -84,6 +84,8 @@ def lib():
         L.nh_destroy.argtypes = [vp]
         L.nh_destroy.restype = None
         i32 = C.c_int32
+        L.nh_adjoint_run.argtypes = [vp, C.c_int64, i32, C.POINTER(i32), _DP,
+                                     i32, C.c_double, _DP, _DP, _DP, _DP, _DP]
         L.nh_ensemble_create.argtypes = [i32, C.POINTER(NhGrid),
                                          C.POINTER(NhParams), vp,
                                          C.POINTER(vp)]
@@ -105,7 +107,7 @@ def lib():
         L.nh_version.restype = C.c_char_p
         for f in ("nh_create", "nh_set_bathymetry", "nh_set_state", "nh_step",
                   "nh_run", "nh_read_state", "nh_get_stats", "nh_profile",
-                  "nh_get_profile", "nh_ensemble_create",
+                  "nh_get_profile", "nh_adjoint_run", "nh_ensemble_create",
                   "nh_ensemble_set_bathymetry", "nh_ensemble_set_state",
                   "nh_ensemble_set_tile", "nh_ensemble_get_tile",
                   "nh_ensemble_tune", "nh_ensemble_run",
@@ -239,6 +241,26 @@ class Solver:
 
     def profile(self, on: bool = True):
         _check(lib().nh_profile(self._h, 1 if on else 0), "nh_profile")
+
+    def adjoint(self, nsteps: int, gauges, target, ckpt_every: int = 100,
+                adj_tol: float = 1e-8) -> dict:
+        """Misfit J of nsteps steps from the current state against
+        target[nsteps][ngauges] at the gauge cells (flat indices), and its
+        gradients (nh_adjoint_run): dh0, dhu0, dhv0 w.r.t. the initial state,
+        dH w.r.t. the bathymetry at fixed initial state."""
+        g = np.ascontiguousarray(np.asarray(gauges, dtype=np.int32).ravel())
+        t = np.ascontiguousarray(np.asarray(target, dtype=np.float64))
+        if t.shape != (int(nsteps), g.size):
+            raise ValueError("target must be [nsteps, ngauges]")
+        J = C.c_double(0.0)
+        out = {k: np.zeros(self.shape) for k in ("dh0", "dhu0", "dhv0", "dH")}
+        _check(lib().nh_adjoint_run(
+            self._h, int(nsteps), int(g.size),
+            g.ctypes.data_as(C.POINTER(C.c_int32)), _ptr(t), int(ckpt_every),
+            float(adj_tol), C.byref(J), _ptr(out["dh0"]), _ptr(out["dhu0"]),
+            _ptr(out["dhv0"]), _ptr(out["dH"])), "nh_adjoint_run")
+        out["J"] = J.value
+        return out
 
     def get_profile(self) -> dict:
         p = NhProfile()

@@ -23,6 +23,7 @@
 
 #include "../../include/nhswe.h"
 #include "kernels.hpp"
+#include "adjoint.hpp"
 
 namespace {
 
@@ -123,6 +124,9 @@ struct ProfPool {
 
 }  // namespace
 
+struct AdjWork;
+void adj_release(AdjWork* w);  // adjoint work space (adjoint_impl.hpp)
+
 struct nh_solver {
   nh_grid grid{};
   nh_params par{};
@@ -169,6 +173,11 @@ struct nh_solver {
   bool have_state = false, have_H = false;
   nh_stats st{};
   ProfPool prof;
+  // recording of a forward run for the adjoint: the pressure of each stage
+  // is copied here after its solve when set
+  double* tape_p[2] = {nullptr, nullptr};
+  struct AdjWork* adj = nullptr;
+  int64_t adj_sweeps_last = 0;  // transposed-solve sweeps of the last run
 
   std::vector<void*> allocs;
 };
@@ -248,6 +257,19 @@ StagePlan stage_plan(const nh_solver* s, int idx) {
   return P;
 }
 
+// A five-point system on the corners of the grid and the three buffers of
+// its relaxation iterate: the solver's own pressure system, or the transposed
+// system of the adjoint.
+struct SysView {
+  void *diag, *cE, *cW, *cN, *cS, *rhs;
+  double* p[3];
+};
+
+inline SysView forward_system(const nh_solver* s) {
+  return SysView{s->cdiag, s->cE, s->cW, s->cN, s->cS, s->crhs,
+                 {(double*)s->pa, (double*)s->pb, (double*)s->pc}};
+}
+
 // kernel arguments of one grid, shared by the single-grid launches and the
 // ensemble's batched launches
 template <typename T>
@@ -285,6 +307,9 @@ struct Args {
                                P(s->cS), P(s->crhs)};
   }
   static nh::SweepArgs<T> sweep(const nh_solver* s) {
+    return sweep(s, forward_system(s));
+  }
+  static nh::SweepArgs<T> sweep(const nh_solver* s, const SysView& V) {
     nh::SweepArgs<T> a;
     a.ncx = s->grid.nx + 1;
     a.ncy = s->grid.ny + 1;
@@ -292,15 +317,15 @@ struct Args {
     a.BY = s->tby;
     a.ntx = s->ntx;
     a.ntiles = s->ntx * s->nty;
-    a.diag = P(s->cdiag);
-    a.cE = P(s->cE);
-    a.cW = P(s->cW);
-    a.cN = P(s->cN);
-    a.cS = P(s->cS);
-    a.rhs = P(s->crhs);
-    a.p[0] = (double*)s->pa;
-    a.p[1] = (double*)s->pb;
-    a.p[2] = (double*)s->pc;
+    a.diag = P(V.diag);
+    a.cE = P(V.cE);
+    a.cW = P(V.cW);
+    a.cN = P(V.cN);
+    a.cS = P(V.cS);
+    a.rhs = P(V.rhs);
+    a.p[0] = V.p[0];
+    a.p[1] = V.p[1];
+    a.p[2] = V.p[2];
     a.omega = s->omega_dev;
     a.nom = (int)s->omega.size();
     a.part = s->part;
@@ -391,9 +416,9 @@ struct Launch {
   // nsw <= kSweepS relaxation sweeps starting at sweep index k0 from buffer
   // iin into iout; with check the convergence measure of the input iterate
   // goes to s->part per tile and the input iterate is saved to isave
-  static void sweeps(nh_solver* s, bool check, int k0, int nsw, int iin,
-                     int iout, int isave) {
-    auto a = Args<T>::sweep(s);
+  static void sweeps(nh_solver* s, const SysView& V, bool check, int k0,
+                     int nsw, int iin, int iout, int isave) {
+    auto a = Args<T>::sweep(s, V);
     nh::SweepLaunch L{iin, iout, isave, k0, nsw, check ? 1 : 0};
     hipLaunchKernelGGL((nh::k_sweep_tb<T, nh::kSweepB, nh::kSweepS,
                                          nh::kSweepM>),
@@ -466,14 +491,18 @@ nh_status wait_measure(nh_solver* s, double* E) {
   return NH_OK;
 }
 
+// Relaxation solve of the system V from its iterate in buffer `pcur` (which
+// receives the buffer of the result): cycles of check_every sweeps, the
+// measure of eq. (32) taken at each cycle start, stop below `tol`.
 template <typename T>
-nh_status solve2d(nh_solver* s, int32_t* sweeps, double* measure) {
+nh_status solve2d(nh_solver* s, const SysView& V, int& pcur, double tol,
+                  int32_t* sweeps, double* measure) {
   const int ce = s->par.check_every > 0 ? s->par.check_every : 1;
   const int kmax = s->par.solve_max_iter;
   const int S = nh::kSweepS;
   const int kAhead = 1;  // launches queued before waiting for a measure
   int k = 0;             // sweep index of the iterate in buffer `cur`
-  int cur = s->pcur;
+  int cur = pcur;
   double E = 0.0;
   nh_status st = NH_OK;
   int launches = 0, nsweeps_done = 0;
@@ -481,7 +510,7 @@ nh_status solve2d(nh_solver* s, int32_t* sweeps, double* measure) {
     const int save = (cur + 2) % 3, out = (cur + 1) % 3;
     const int kc = k;
     int nsw = k >= kmax ? 0 : std::min(std::min(S, ce), kmax - k);
-    Launch<T>::sweeps(s, true, k, nsw, cur, out, save);
+    Launch<T>::sweeps(s, V, true, k, nsw, cur, out, save);
     ++s->seq;
     hipLaunchKernelGGL(nh::k_reduce_measure, dim3(1), dim3(nh::kBlock), 0,
                        s->stream, (const double* const*)s->part_list,
@@ -499,7 +528,7 @@ nh_status solve2d(nh_solver* s, int32_t* sweeps, double* measure) {
     auto queue_until = [&](int limit) {
       while (k % ce != 0 && k < kmax && queued < limit) {
         int n2 = std::min(std::min(S, ce - k % ce), kmax - k);
-        Launch<T>::sweeps(s, false, k, n2, cur, other, other);
+        Launch<T>::sweeps(s, V, false, k, n2, cur, other, other);
         std::swap(cur, other);
         k += n2;
         nsweeps_done += n2;
@@ -510,9 +539,9 @@ nh_status solve2d(nh_solver* s, int32_t* sweeps, double* measure) {
     if (nsw > 0) queue_until(kAhead);
     nh_status ws = wait_measure(s, &E);
     if (ws != NH_OK) return ws;
-    if (E < s->par.solve_tol || kc >= kmax) {
-      if (!(E < s->par.solve_tol)) st = NH_ENOCONV;
-      s->pcur = save;            // p^kc, saved by the check launch
+    if (E < tol || kc >= kmax) {
+      if (!(E < tol)) st = NH_ENOCONV;
+      pcur = save;               // p^kc, saved by the check launch
       k = kc;
       break;
     }
@@ -552,11 +581,15 @@ nh_status stage(nh_solver* s, int idx, int32_t* sweeps, double* measure) {
       Launch<T>::thomas(s, s->pcur_ptr());
       s->solve_launches_last = 1;
     } else {
-      st = solve2d<T>(s, sweeps, measure);
+      st = solve2d<T>(s, forward_system(s), s->pcur, s->par.solve_tol, sweeps,
+                      measure);
       if (st != NH_OK && st != NH_ENOCONV) return st;
     }
     s->prof.close(s->stream, pm, s->solve_launches_last);
     p = s->pcur_ptr();
+    if (s->tape_p[idx])
+      hipMemcpyAsync(s->tape_p[idx], p, s->ncorn * sizeof(double),
+                     hipMemcpyDeviceToDevice, s->stream);
   }
   pm = s->prof.open(s->stream, 3);
   Launch<T>::correct(s, S, p);
@@ -933,6 +966,7 @@ void nh_destroy(nh_solver* s) {
   for (void* p : s->allocs) hipFree(p);
   if (s->slot) hipHostFree(s->slot);
   s->prof.release();
+  adj_release(s->adj);
   if (s->own_stream) hipStreamDestroy(s->stream);
   delete s;
 }
@@ -941,3 +975,5 @@ void nh_destroy(nh_solver* s) {
 
 // ensembles of grids (nh_ensemble_*), built on the pieces above
 #include "ensemble_impl.hpp"
+// gradients by the adjoint time step (nh_adjoint_run)
+#include "adjoint_impl.hpp"

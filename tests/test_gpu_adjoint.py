@@ -1,0 +1,134 @@
+"""Adjoint of the time stepper on the GPU (nh_adjoint_run) vs the
+differentiable FP64 oracle (oracle/nh_torch.py: reverse-mode derivatives of
+the literal scheme with a dense pressure solve).
+
+Bars: FP64, normwise 1e-7 on the gradients and 1e-10 on J (both sides solve
+the pressure systems iteratively or directly to ~1e-13); FP32 bulk, 2e-3
+(single-precision state and Jacobian entries).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import nh_torch as NT
+from paper_1706_04551_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def problem(nx=12, ny=10, dx=2.0, dy=2.0, steps=8, seed=4, width2=8.0):
+    """Seeded wet basin, an off-lattice Gaussian surface bump of squared
+    width width2 (cells^2), four gauges and a seeded gauge record."""
+    rng = np.random.default_rng(seed)
+    H, _, _, _ = I.random_wet_state(rng, nx, ny, dx, dy, depth=(3.0, 8.0))
+    x = (np.arange(nx) + 0.5)[None, :] * dx / 2.0
+    y = (np.arange(ny) + 0.5)[:, None] * dy / 2.0
+    eta0 = 0.3 * np.exp(-((x - 0.53 * nx) ** 2 + (y - 0.47 * ny) ** 2) /
+                        width2)
+    gauges = rng.choice(nx * ny, size=4, replace=False)
+    target = (0.01 * rng.standard_normal((steps, gauges.size)) +
+              (H + eta0).reshape(-1)[gauges][None, :])
+    return dict(nx=nx, ny=ny, dx=dx, dy=dy, dt=0.05, steps=steps, H=H,
+                eta0=eta0, gauges=gauges, target=target)
+
+
+def solver_for(P, precision="f64"):
+    from paper_1706_04551_amd import Solver
+    s = Solver(P["nx"], P["ny"], P["dx"], P["dy"], precision=precision,
+               cfl=0.7, fixed_dt=1, dt_fixed=P["dt"],
+               solve_tol=1e-13 if precision == "f64" else 1e-7,
+               dry_eps=1e-10 if precision == "f64" else 1e-5,
+               solve_max_iter=400000, check_every=8)
+    s.set_bathymetry(P["H"])
+    z = np.zeros_like(P["H"])
+    s.set_state(np.maximum(P["H"] + P["eta0"], 0.0), z, z)
+    return s
+
+
+def gpu_gradient(P, precision="f64", ckpt=100, adj_tol=1e-12):
+    s = solver_for(P, precision)
+    r = s.adjoint(P["steps"], P["gauges"], P["target"], ckpt_every=ckpt,
+                  adj_tol=adj_tol)
+    st = s.state()
+    s.close()
+    return r, st
+
+
+def oracle_gradient(P):
+    TP = NT.TorchParams(P["nx"], P["ny"], P["dx"], P["dy"], P["dt"])
+    return NT.gradient(TP, P["eta0"], P["H"], P["gauges"], P["target"],
+                       P["steps"])
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.mark.parametrize("shape", [(12, 10, 8), (21, 17, 10)])
+def test_fp64_gradient_matches_the_oracle(shape):
+    nx, ny, steps = shape
+    P = problem(nx, ny, steps=steps)
+    say(f"[adjoint] {nx}x{ny} steps={steps} f64")
+    r, _ = gpu_gradient(P, "f64", ckpt=3)
+    J, ge, gb = oracle_gradient(P)
+    assert abs(r["J"] - J) <= 1e-10 * J
+    e_eta = rel(r["dh0"], ge)
+    e_H = rel(r["dH"] + r["dh0"], gb)
+    say(f"  J {r['J']:.6e} vs {J:.6e}; d/deta0 {e_eta:.2e}; d/dH {e_H:.2e}")
+    assert e_eta <= 1e-7 and e_H <= 1e-7
+
+
+def test_fp32_gradient_close_to_the_oracle():
+    # A broad bump: the limiters of an FP32 run decide on differences of the
+    # surface that must stand above FP32 rounding of h - H (~5e-7 m on 8 m);
+    # where the surface is flatter than that, the FP32 run takes other
+    # limiter branches than the FP64 one and its derivative differs there.
+    P = problem(21, 17, steps=10, width2=60.0)
+    say("[adjoint] 21x17 steps=10 f32")
+    r, _ = gpu_gradient(P, "f32", ckpt=4, adj_tol=1e-7)
+    J, ge, gb = oracle_gradient(P)
+    e_eta = rel(r["dh0"], ge)
+    e_H = rel(r["dH"] + r["dh0"], gb)
+    say(f"  J {r['J']:.6e} vs {J:.6e}; d/deta0 {e_eta:.2e}; d/dH {e_H:.2e}")
+    assert abs(r["J"] - J) <= 1e-4 * J
+    assert e_eta <= 2e-3 and e_H <= 2e-3
+
+
+def test_checkpoint_interval_does_not_change_anything():
+    P = problem(12, 10, steps=8)
+    a, sa = gpu_gradient(P, "f64", ckpt=1)
+    b, sb = gpu_gradient(P, "f64", ckpt=3)
+    c, sc = gpu_gradient(P, "f64", ckpt=8)
+    for k in ("dh0", "dhu0", "dhv0", "dH"):
+        assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k]), k
+    assert a["J"] == b["J"] == c["J"]
+    # the solver ends at the state after the forward steps
+    s = solver_for(P)
+    s.run(P["steps"])
+    ref = s.state()
+    s.close()
+    for k in ("h", "hu", "hv", "w"):
+        assert np.array_equal(sa[k], ref[k]) and np.array_equal(sb[k], ref[k]), k
+
+
+def test_autograd_function_gives_the_library_gradient():
+    import torch
+    from paper_1706_04551_amd.autograd import AdjointRun
+    P = problem(12, 10, steps=6)
+    s = solver_for(P)
+    eta0 = torch.tensor(P["eta0"], requires_grad=True)
+    H = torch.tensor(P["H"], requires_grad=True)
+    J = AdjointRun.apply(eta0, H, s, P["gauges"], P["target"], P["steps"], 2,
+                         1e-12)
+    (2.0 * J).backward()
+    r, _ = gpu_gradient(P, "f64", ckpt=2)
+    assert float(J) == r["J"]
+    assert np.array_equal(eta0.grad.numpy(), 2.0 * r["dh0"])
+    assert np.array_equal(H.grad.numpy(), 2.0 * (r["dH"] + r["dh0"]))
+    s.close()
