@@ -106,31 +106,31 @@ struct Dual {
   }
 };
 
-// Local Jacobians are evaluated in FP64 also for FP32 bulk arrays: their
-// entries are differences of large terms (notably the pressure rows), which
-// single precision would not resolve.
+// Type of the local Jacobian evaluations: the finite-volume and pressure-row
+// derivatives run in the bulk type (their cost dominates the adjoint step),
+// the correction's in FP64; sums over outputs are always FP64.
 using E = double;
 
 // mirrored cells of the bulk arrays as FP64 duals; cell `seed` carries the
 // directions dh (index ih), dq1 (iq1), dq2 (iq2), dH (iH) (-1: not seeded)
-template <typename T, int N>
+template <typename T, int N, typename V = E>
 struct SeedLoader {
   const T *h, *q1, *q2, *H;
   int nx, ny, seed;
   int ih, iq1, iq2, iH;
-  __device__ __forceinline__ Cell<Dual<E, N>> operator()(int i, int j) const {
+  __device__ __forceinline__ Cell<Dual<V, N>> operator()(int i, int j) const {
     int mi = mirror(i, nx), mj = mirror(j, ny);
     int idx = mj * nx + mi;
-    Cell<Dual<E, N>> c;
-    c.h = Dual<E, N>((E)h[idx]);
-    c.q1 = Dual<E, N>((E)q1[idx]);
-    c.q2 = Dual<E, N>((E)q2[idx]);
-    c.H = Dual<E, N>((E)H[idx]);
+    Cell<Dual<V, N>> c;
+    c.h = Dual<V, N>((V)h[idx]);
+    c.q1 = Dual<V, N>((V)q1[idx]);
+    c.q2 = Dual<V, N>((V)q2[idx]);
+    c.H = Dual<V, N>((V)H[idx]);
     if (idx == seed) {
-      if (ih >= 0) c.h.d[ih] = E(1);
-      if (iq1 >= 0) c.q1.d[iq1] = E(1);
-      if (iq2 >= 0) c.q2.d[iq2] = E(1);
-      if (iH >= 0) c.H.d[iH] = E(1);
+      if (ih >= 0) c.h.d[ih] = V(1);
+      if (iq1 >= 0) c.q1.d[iq1] = V(1);
+      if (iq2 >= 0) c.q2.d[iq2] = V(1);
+      if (iH >= 0) c.H.d[iH] = V(1);
     }
     if (mi != i) c.q1 = -c.q1;
     if (mj != j) c.q2 = -c.q2;
@@ -161,11 +161,13 @@ struct AdjGeom {
 // ---------------------------------------------------------------------------
 // finite-volume stage: (h*, q*) = FV(h, q; H).  Per input cell j:
 //   lh_j += sum_i dh*_i/dh_j lhs_i + dq*_i/dh_j lqs_i  (likewise q1, q2, H)
-// over the outputs i that read j (the cross of radius 2 around j; mirror
-// images of j are included by the loader).  hs_out (the stored h*) gives the
-// forward's clamp and dry decisions.
+// over the outputs i that read j: the cells within 2 of j along x, through
+// their x fluxes (DIR = 1), and along y, through their y fluxes (DIR = 2);
+// j's own identity term is counted by the x pass.  Mirror images of j are
+// included by the loader.  hs_out (the stored h*) gives the forward's clamp
+// and dry decisions.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int DIR>
 __global__ void __launch_bounds__(kBlock)
     k_adj_fv(AdjGeom G, const T* __restrict__ h, const T* __restrict__ q1,
              const T* __restrict__ q2, const T* __restrict__ H,
@@ -173,7 +175,7 @@ __global__ void __launch_bounds__(kBlock)
              const T* __restrict__ lq1s, const T* __restrict__ lq2s,
              T* __restrict__ lh, T* __restrict__ lq1, T* __restrict__ lq2,
              T* __restrict__ lH) {
-  using D = Dual<E, 4>;
+  using D = Dual<T, 4>;
   const int nx = G.nx, ny = G.ny;
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= nx * ny) return;
@@ -181,16 +183,14 @@ __global__ void __launch_bounds__(kBlock)
   const T dry_eps = (T)G.dry_eps;
   const D dx(G.dx), dy(G.dy), g(G.g), delta(G.delta), de(G.dry_eps),
       dt(*G.dtp);
-  SeedLoader<T, 4> ld{h, q1, q2, H, nx, ny, n, 0, 1, 2, 3};
-  const int ox[9] = {0, -2, -1, 1, 2, 0, 0, 0, 0};
-  const int oy[9] = {0, 0, 0, 0, 0, -2, -1, 1, 2};
+  SeedLoader<T, 4, T> ld{h, q1, q2, H, nx, ny, n, 0, 1, 2, 3};
   E acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int o = 0; o < 9; ++o) {
-    const int i = jx + ox[o], j = jy + oy[o];
+#pragma unroll 1
+  for (int o = -2; o <= 2; ++o) {
+    const int i = DIR == 1 ? jx + o : jx, j = DIR == 1 ? jy : jy + o;
     if (i < 0 || i >= nx || j < 0 || j >= ny) continue;
-    const int parts = o == 0 ? 3 : (oy[o] == 0 ? 1 : 2);
     D out[3];
-    fv_cell<D, false>(ld, i, j, dx, dy, g, delta, de, dt, parts, out);
+    fv_cell<D, false>(ld, i, j, dx, dy, g, delta, de, dt, DIR, out);
     const int m = j * nx + i;
     const T hv = hs_out[m];
     const E wh = hv > T(0) ? (E)lhs[m] : 0.0;
@@ -198,8 +198,13 @@ __global__ void __launch_bounds__(kBlock)
     const E w1 = wet ? (E)lq1s[m] : 0.0, w2 = wet ? (E)lq2s[m] : 0.0;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-      acc[k] = acc[k] + (out[0].d[k] * wh + out[1].d[k] * w1 +
-                         out[2].d[k] * w2);
+      acc[k] = acc[k] + ((E)out[0].d[k] * wh + (E)out[1].d[k] * w1 +
+                         (E)out[2].d[k] * w2);
+    if (DIR == 2 && o == 0) {  // the identity term went in with the x pass
+      acc[0] = acc[0] - wh;
+      acc[1] = acc[1] - w1;
+      acc[2] = acc[2] - w2;
+    }
   }
   lh[n] = (T)((E)lh[n] + acc[0]);
   lq1[n] = (T)((E)lq1[n] + acc[1]);
@@ -316,13 +321,13 @@ __global__ void __launch_bounds__(kBlock)
                    const double* __restrict__ p, const double* __restrict__ mu,
                    T* __restrict__ lhs, T* __restrict__ lq1s,
                    T* __restrict__ lq2s, T* __restrict__ lH) {
-  using D = Dual<E, 4>;
+  using D = Dual<T, 4>;
   const int nx = G.nx, ny = G.ny, ncx = nx + 1;
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= nx * ny) return;
   const int jx = n % nx, jy = n / nx;
   const D dx(G.dx), dy(G.dy), dt(*G.dtp);
-  SeedLoader<T, 4> ld{hs, q1s, q2s, H, nx, ny, n, 0, 1, 2, 3};
+  SeedLoader<T, 4, T> ld{hs, q1s, q2s, H, nx, ny, n, 0, 1, 2, 3};
   // corners (k, l) whose row reads cell (jx, jy): k in [jx-1, jx+2] on the
   // rows l = jy, jy+1, and k in [jx, jx+1] on the rows l = jy-1, jy+2
   const int ok[12] = {-1, 0, 1, 2, -1, 0, 1, 2, 0, 1, 0, 1};
@@ -337,7 +342,7 @@ __global__ void __launch_bounds__(kBlock)
     D R = row_residual<D>(row, p, k, l, nx, ny);
     const E m = mu[c];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = acc[q] + R.d[q] * m;
+    for (int q = 0; q < 4; ++q) acc[q] = acc[q] + (E)R.d[q] * m;
   }
   lhs[n] = (T)((E)lhs[n] + acc[0]);
   lq1s[n] = (T)((E)lq1s[n] + acc[1]);

@@ -305,9 +305,14 @@ nh_status adj_step(nh_solver* s, AdjWork* w, const StateRec& R, double tol,
                          P(lw_in));
     }
     // finite volumes
-    hipLaunchKernelGGL((nh::k_adj_fv<T>), Gc, B, 0, st, G, C(Vh), C(Vq1),
-                       C(Vq2), C(s->H), C(hs_), C(lh_out), C(w->Lqs1),
-                       C(w->Lqs2), P(lh_in), P(lq1_in), P(lq2_in), P(w->LH));
+    hipLaunchKernelGGL((nh::k_adj_fv<T, 1>), Gc, B, 0, st, G, C(Vh),
+                       C(Vq1), C(Vq2), C(s->H), C(hs_), C(lh_out),
+                       C(w->Lqs1), C(w->Lqs2), P(lh_in), P(lq1_in),
+                       P(lq2_in), P(w->LH));
+    hipLaunchKernelGGL((nh::k_adj_fv<T, 2>), Gc, B, 0, st, G, C(Vh),
+                       C(Vq1), C(Vq2), C(s->H), C(hs_), C(lh_out),
+                       C(w->Lqs1), C(w->Lqs2), P(lh_in), P(lq1_in),
+                       P(lq2_in), P(w->LH));
     return NH_OK;
   };
 

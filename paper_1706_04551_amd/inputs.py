@@ -14,6 +14,8 @@ have the shapes of its workloads):
   c3  2D 2048x2048 plane beach with an incoming solitary wave, breaking on
       (Section 7.4 shape).
   c4  ensemble of 64 c2-like basins of uneven sides 128-1024, FP32 bulk.
+  c5  1024x1024 fully wet basin (dx 10 m, depth 5-50 m), fixed dt, gauges:
+      the adjoint workload.
 Cell centres sit at ((i+1/2) dx, (j+1/2) dy).  Arrays are [ny][nx], float64.
 
 CFL: the 1D channel uses 0.9.  The 2D workloads use 0.7: with the 2D time
@@ -61,6 +63,8 @@ class Case:
     check_every: int = 1
     omega: np.ndarray = field(default_factory=lambda: np.ones(1))
     precision: str = "f64"
+    fixed_dt: int = 0
+    dt_fixed: float = 0.0
 
     def param_dict(self) -> dict:
         return dict(nx=self.nx, ny=self.ny, dx=self.dx, dy=self.dy, g=self.g,
@@ -68,7 +72,8 @@ class Case:
                     nh_on=self.nh_on, breaking_on=self.breaking_on,
                     b1=self.b1, b2=self.b2, solve_max_iter=self.solve_max_iter,
                     check_every=self.check_every, solve_tol=self.solve_tol,
-                    omega=self.omega)
+                    omega=self.omega, fixed_dt=self.fixed_dt,
+                    dt_fixed=self.dt_fixed)
 
 
 # --------------------------------------------------------------------------
@@ -283,6 +288,67 @@ def case_c4(members: int = 64, seed: int = SEED_C4, sides=C4_SIDES,
     64 by default, of uneven sizes (expected total about 25.4 M cells)."""
     return [case_c4_member(k, seed, sides, steps, precision)
             for k in range(members)]
+
+
+def c5_initial_surface(n: int, dx: float, seed: int, amp: float = 0.5,
+                       radius: float = 100.0) -> np.ndarray:
+    """A Gaussian surface bump of the given amplitude and radius [m] at a
+    seeded position in the central half of the domain."""
+    rng = np.random.default_rng(seed)
+    L = n * dx
+    c = rng.uniform(0.25 * L, 0.75 * L, 2)
+    xc = centres(n, dx)
+    X, Y = np.meshgrid(xc, xc)
+    return amp * np.exp(-((X - c[0]) ** 2 + (Y - c[1]) ** 2) / radius ** 2)
+
+
+def case_c5(n: int = 1024, steps: int = 2000, precision: str = "f32",
+            seed: int = SEED_C5, dx: float = 10.0, cfl_dt: float = 0.5):
+    """Adjoint workload: n x n (1024 by default) fully wet basin, dx = dy =
+    10 m, depth H = 5 + 45 D in [5, 50] m from 8 seeded Gaussians, initial
+    surface a 0.5 m bump of radius 100 m at a seeded position, at rest.  The
+    time step is fixed: cfl_dt / max((|u|+c)/dx + (|v|+c)/dy) of the initial
+    state (below the 2D limit of 0.7 through the run).  16 seeded gauge cells
+    in the interior.  Returns (Case with fixed dt, eta0, gauges, target_eta0)
+    where target_eta0 is the initial surface of the seeded target run
+    (another position, amplitude U[0.25, 0.75] m)."""
+    rng = np.random.default_rng(seed)
+    xc = centres(n, dx)
+    L = n * dx
+    D = gaussian_field(rng, n, n, L, L, xc, xc)
+    H = 5.0 + 45.0 * D
+    eta0 = c5_initial_surface(n, dx, seed + 1)
+    amp_t = float(np.random.default_rng(seed + 1000).uniform(0.25, 0.75))
+    target_eta0 = c5_initial_surface(n, dx, seed + 1000, amp=amp_t)
+    g_rng = np.random.default_rng(seed + 7)
+    gi = g_rng.integers(n // 10, n - n // 10, size=(16, 2))
+    gauges = gi[:, 1] * n + gi[:, 0]
+    h0 = H + eta0
+    z = np.zeros_like(h0)
+    lam = 2.0 * float(np.sqrt(G * h0.max())) / dx
+    dt = cfl_dt / lam
+    f32 = precision == "f32"
+    c = Case("c5", n, n, dx, dx, H, h0, z, z.copy(), steps, precision=precision,
+             solve_tol=1e-6 if f32 else 1e-10, dry_eps=1e-5 if f32 else 1e-10,
+             cfl=CFL_2D)
+    rho = jacobi_radius_bound(float(h0.max()), dx, dx)
+    c.omega = srj_schedule(rho, 64)
+    c.check_every = 64
+    c.fixed_dt = 1
+    c.dt_fixed = dt
+    return c, eta0, gauges, target_eta0
+
+
+def synthetic_gauge_record(case, gauges, steps: int, seed: int = SEED_C5):
+    """A seeded gauge record (steps x ngauges): the still-water depth at each
+    gauge plus a few centimetres of smooth seeded oscillation, a target for
+    the misfit that is independent of any solver run."""
+    rng = np.random.default_rng(seed + 2000)
+    t = case.dt_fixed * np.arange(1, steps + 1)[:, None]
+    a = rng.uniform(0.01, 0.05, size=(1, len(gauges)))
+    w = rng.uniform(0.02, 0.2, size=(1, len(gauges)))
+    ph = rng.uniform(0.0, 2 * np.pi, size=(1, len(gauges)))
+    return case.H.reshape(-1)[gauges][None, :] + a * np.sin(w * t + ph)
 
 
 def lake_at_rest(n: int = 64, dx: float = 1.0, seed: int = SEED_C2,

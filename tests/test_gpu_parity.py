@@ -266,18 +266,21 @@ def test_c2_full_workload_1000_steps_fp32_reported():
 def test_island_free_basin_fp32_vs_stored_oracle():
     # FP32 bulk on the island-free basin (no wet-dry front) against the
     # oracle run with the same FP32-bulk configuration
-    # (tests/golden/make_c2_reference.py f32 wet).  After 250 steps h and hu
-    # meet the 1e-4 bar.  After the full 1000 steps h meets it; the discharges
-    # are bounded by the run's own conditioning: in the FP64 oracle a 1e-7
-    # relative perturbation of the initial depth alone changes hu by 4e-5 and
-    # hv by 8e-5 (of the largest discharge) after 1000 steps, and FP32
-    # storage injects rounding of that size at every step.
+    # (tests/golden/make_c2_reference.py f32 wet), after 250 and 1000 steps.
+    # The bar is 1e-4, or twice the drift that FP32 storage of the state
+    # alone causes on this run where that is larger: the oracle with its
+    # state rounded to FP32 after every step
+    # (tests/golden/make_fp32_storage_bound.py) moves the discharges by
+    # ~1e-4 of their maximum after 250 steps and more later -- the run
+    # amplifies small perturbations of the state.
     import os
-    path = os.path.join(os.path.dirname(__file__), "golden",
-                        "c2wet_512_f32_1000.npz")
-    if not os.path.exists(path):
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    path = os.path.join(here, "c2wet_512_f32_1000.npz")
+    bpath = os.path.join(here, "c2wet_512_f32storage_1000.npz")
+    if not os.path.exists(path) or not os.path.exists(bpath):
         pytest.skip("reference not generated")
     ref = np.load(path)
+    rb = np.load(bpath)
     st = int(ref["stride"])
     early = int(ref["early_steps"])
     c = I.case_c2(precision="f32", island=False)
@@ -285,15 +288,20 @@ def test_island_free_basin_fp32_vs_stored_oracle():
         "steps vs stored oracle")
     s = gpu_solver(c)
 
-    def check(g, suffix, bars):
-        scale_q = max(float(ref["max_hu" + suffix]), float(ref["max_hv" + suffix]))
+    def check(g, suffix):
+        scale_q = max(float(ref["max_hu" + suffix]),
+                      float(ref["max_hv" + suffix]))
         for k, scale in (("h", float(ref["max_h" + suffix])), ("hu", scale_q),
                          ("hv", scale_q)):
             e = float(np.abs(g[k][::st, ::st] - ref[k + suffix]).max() / scale)
-            say(f"  {k}{suffix}: max rel diff on the lattice {e:.3e}")
-            assert e <= bars[k], (k + suffix, e)
+            e_sto = float(np.abs(rb[k + suffix] - ref[k + suffix]).max() /
+                          scale)
+            bar = max(TOL32, 2.0 * e_sto)
+            say(f"  {k}{suffix}: max rel diff on the lattice {e:.3e} "
+                f"(FP32 storage alone {e_sto:.3e}, bar {bar:.1e})")
+            assert e <= bar, (k + suffix, e, bar)
 
     s.run(early)
-    check(s.state(), f"_{early}", {"h": TOL32, "hu": TOL32, "hv": 1e-3})
+    check(s.state(), f"_{early}")
     s.run(c.steps - early)
-    check(s.state(), "", {"h": TOL32, "hu": 1e-3, "hv": 1e-3})
+    check(s.state(), "")
