@@ -211,7 +211,7 @@ def run_ensemble(args):
         "roofline": roof,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def run_adjoint(args):
@@ -277,46 +277,13 @@ def run_adjoint(args):
         "cpu_baseline": None,
     }
     del ncorn
-    print(json.dumps(out), flush=True)
+    return out
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c2")
-    ap.add_argument("--precision", default=None, choices=["f64", "f32"],
-                    help="default: f64 for c2, f32 for the c3 and c4 workloads")
-    ap.add_argument("--cpu-steps", type=int, default=12)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run a plain copy of 256 MiB (for counter runs)")
-    args = ap.parse_args()
-
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the time step of one "
-              "grid on one device); --gpus must be 1", file=sys.stderr)
-        raise SystemExit(2)
-
+def run_single(args):
+    """One grid (c2 or c3) for args.steps steps from its initial state."""
     import torch
     from paper_1706_04551_amd import Solver
-
-    assert torch.cuda.is_available(), "no HIP device visible"
-    torch.cuda.set_device(0)
-    if args.calibrate_copy:
-        copy_calibration()
-    args.steps_given = args.steps is not None
-    if args.precision is None:
-        args.precision = "f64" if args.workload == "c2" else "f32"
-    if args.workload == "c4":
-        run_ensemble(args)
-        return
-    if args.workload == "c5":
-        run_adjoint(args)
-        return
-    if args.steps is None:
-        args.steps = 1000
     case, desc = workload(args.workload, args.precision)
     stream = torch.cuda.current_stream()
     s = Solver.from_case(case, stream=stream.cuda_stream)
@@ -334,11 +301,11 @@ def main():
     st = s.stats()
     pr = s.get_profile()
     s.profile(False)
+    s.close()
 
     kbar = st["sweeps_total"] / max(1, st["solves"])
     value = ncell * args.steps / elapsed / 1e6
     ms_step = elapsed * 1e3 / args.steps
-    ncorn = (case.nx + 1) * (case.ny + 1)
 
     # roofline of the dominant kernel: the relaxation sweep
     sweep_ms = pr["sweep_kernel_ms"] / max(1, pr["sweep_kernel_launches"])
@@ -360,7 +327,7 @@ def main():
     if not args.no_cpu:
         cpu = cpu_baseline(case, args.cpu_steps)
 
-    out = {
+    return {
         "metric": "Mcell-steps/s per full step (flux+pressure solve), % HBM roofline, vs FP64 plain",
         "value": round(value, 3),
         "unit": "Mcell-steps/s",
@@ -382,6 +349,84 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+
+
+def variant_summary(out):
+    """The figures of a variant run, for the headline line."""
+    cfg = out["config"]
+    return {"workload": cfg["workload"], "value": out["value"],
+            "unit": out["unit"], "dtype": out["dtype"], "steps": out["steps"],
+            "ms_per_step": out["ms_per_step"],
+            "mean_sweeps_per_solve": cfg.get("mean_sweeps_per_solve",
+                                             cfg.get("forward_sweeps_per_solve")),
+            "full_step_hbm_roofline_frac": cfg.get("full_step_hbm_roofline_frac"),
+            "sweep_roofline_frac": out["roofline"]["frac"],
+            "sweep_kernel": out["roofline"]["kernel"]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--precision", default=None, choices=["f64", "f32"],
+                    help="default: f64 for c2, f32 for the c3 and c4 workloads")
+    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain copy of 256 MiB (for counter runs)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the FP32, ensemble and adjoint runs that follow "
+                         "the default workload")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the time step of one "
+              "grid on one device); --gpus must be 1", file=sys.stderr)
+        raise SystemExit(2)
+
+    import torch
+
+    assert torch.cuda.is_available(), "no HIP device visible"
+    torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        copy_calibration()
+    args.steps_given = args.steps is not None
+    if args.precision is None:
+        args.precision = "f64" if args.workload == "c2" else "f32"
+    if args.workload == "c4":
+        out = run_ensemble(args)
+    elif args.workload == "c5":
+        out = run_adjoint(args)
+    else:
+        if args.steps is None:
+            args.steps = 1000
+        out = run_single(args)
+        if (args.workload == "c2" and args.precision == "f64"
+                and not args.no_variants):
+            # the FP32-bulk, batched and adjoint forms on the same GPU, each
+            # timed on its own workload after the headline run
+            import copy
+            variants = {}
+
+            def note(msg):
+                print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+            note(f"headline {out['value']} {out['unit']}; variants follow")
+            v = copy.copy(args)
+            v.precision, v.no_cpu = "f32", True
+            variants["c2_fp32_bulk"] = variant_summary(run_single(v))
+            note("c2 FP32 done")
+            v = copy.copy(args)
+            v.workload, v.precision, v.no_cpu = "c4", "f32", True
+            v.steps, v.steps_given = None, False
+            variants["c4_ensemble_fp32"] = variant_summary(run_ensemble(v))
+            note("c4 ensemble done")
+            v = copy.copy(args)
+            v.workload, v.precision, v.no_cpu, v.warmup = "c5", "f32", True, 0
+            v.steps, v.steps_given = None, False
+            variants["c5_adjoint_fp32"] = variant_summary(run_adjoint(v))
+            out["variants"] = variants
     print(json.dumps(out), flush=True)
 
 

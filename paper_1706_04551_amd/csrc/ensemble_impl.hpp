@@ -42,6 +42,10 @@ struct nh_ensemble {
       tot_corr = 0;
   size_t sweep_lds = 0;
   std::vector<long> live_corners;  // corners of each live member
+  std::vector<int> sweep_nb;       // sweep workgroups of each live member
+  int *ids_all = nullptr;          // 0..L-1 (device)
+  int *nb_dev = nullptr;           // sweep_nb (device)
+  int *act_ids = nullptr, *act_pre = nullptr;  // compacted after a check
 
   nh::EnsMember* dmem = nullptr;   // per member (all n, not only live)
   nh::EnsMember* dmem_live = nullptr;  // gathered copy for the batch order
@@ -103,6 +107,7 @@ nh_status ens_build(nh_ensemble* e) {
   int tot[6] = {0, 0, 0, 0, 0, 0};
   e->sweep_lds = 0;
   e->live_corners.clear();
+  e->sweep_nb.clear();
   for (int i = 0; i < L; ++i) {
     nh_solver* m = e->mem[e->live[i]];
     for (int st = 0; st < 2; ++st) {
@@ -126,6 +131,7 @@ nh_status ens_build(nh_ensemble* e) {
     }
     e->sweep_lds = std::max(e->sweep_lds, sweep_lds_bytes(m->tbx, m->tby));
     e->live_corners.push_back(m->ncorn);
+    e->sweep_nb.push_back(nb[4]);
   }
   for (int k = 0; k < 6; ++k) pre[k].push_back(tot[k]);
   // layout: every block 256-byte aligned
@@ -148,6 +154,12 @@ nh_status ens_build(nh_ensemble* e) {
   size_t o_fin = put(fin.data(), fin.size() * sizeof(fin[0]));
   for (int k = 0; k < 6; ++k)
     o_pre[k] = put(pre[k].data(), pre[k].size() * sizeof(int));
+  std::vector<int> ids(L);
+  for (int i = 0; i < L; ++i) ids[i] = i;
+  size_t o_ids = put(ids.data(), L * sizeof(int));
+  size_t o_nb = put(e->sweep_nb.data(), L * sizeof(int));
+  size_t o_aids = put(ids.data(), L * sizeof(int));
+  size_t o_apre = put(pre[4].data(), (L + 1) * sizeof(int));
   if (buf.size() > e->table_bytes) {
     if (e->table) hipFree(e->table);
     e->table = nullptr;
@@ -171,6 +183,10 @@ nh_status ens_build(nh_ensemble* e) {
   int** pres[6] = {&e->pre_fv, &e->pre_brc, &e->pre_brk,
                    &e->pre_asm, &e->pre_sweep, &e->pre_corr};
   for (int k = 0; k < 6; ++k) *pres[k] = (int*)(base + o_pre[k]);
+  e->ids_all = (int*)(base + o_ids);
+  e->nb_dev = (int*)(base + o_nb);
+  e->act_ids = (int*)(base + o_aids);
+  e->act_pre = (int*)(base + o_apre);
   e->tot_fv = tot[0];
   e->tot_brc = tot[1];
   e->tot_brk = tot[2];
@@ -197,15 +213,18 @@ nh_status ens_gather(nh_ensemble* e, bool to_live) {
   return NH_OK;
 }
 
+// one batched sweep launch over the members ids[0..n) with workgroup prefix
+// pre and `total` workgroups
 template <typename T>
-void ens_sweeps(nh_ensemble* e, bool check, int k0, int nsw, int iin, int iout,
+void ens_sweeps(nh_ensemble* e, const int* ids, const int* pre, int n,
+                int total, bool check, int k0, int nsw, int iin, int iout,
                 int isave) {
+  if (total <= 0) return;
   nh::SweepLaunch Lc{iin, iout, isave, k0, nsw, check ? 1 : 0};
   hipLaunchKernelGGL((nh::k_sweep_tb_batch<T, nh::kSweepB, nh::kSweepS,
                                              nh::kSweepM>),
-                     dim3(e->tot_sweep), dim3(nh::kSweepB), e->sweep_lds,
-                     e->stream, (const nh::SweepArgs<T>*)e->sweep,
-                     (const int*)e->pre_sweep, (int)e->live.size(),
+                     dim3(total), dim3(nh::kSweepB), e->sweep_lds, e->stream,
+                     (const nh::SweepArgs<T>*)e->sweep, ids, pre, n,
                      (const nh::EnsMember*)e->dmem_live, Lc);
 }
 
@@ -222,11 +241,16 @@ nh_status ens_solve(nh_ensemble* e, int stage) {
                      e->dmem_live, L);
   int k = 0, cur = 0;
   int* act = e->active_host;
+  // launch table: every member for the first check, then the members still
+  // active (compacted on the device after each check)
+  const int* ids = e->ids_all;
+  const int* pre = e->pre_sweep;
+  int nmem = L, total = e->tot_sweep;
   for (;;) {
     const int save = (cur + 2) % 3, out = (cur + 1) % 3;
     const int kc = k;
     int nsw = k >= kmax ? 0 : std::min(std::min(S, ce), kmax - k);
-    ens_sweeps<T>(e, true, k, nsw, cur, out, save);
+    ens_sweeps<T>(e, ids, pre, nmem, total, true, k, nsw, cur, out, save);
     ++e->seq;
     hipLaunchKernelGGL((nh::k_ens_check<T>), dim3(L), dim3(nh::kBlock), 0,
                        e->stream, (const nh::SweepArgs<T>*)e->sweep,
@@ -244,7 +268,8 @@ nh_status ens_solve(nh_ensemble* e, int stage) {
     auto queue_until = [&](int limit) {
       while (k % ce != 0 && k < kmax && queued < limit) {
         int n2 = std::min(std::min(S, ce - k % ce), kmax - k);
-        ens_sweeps<T>(e, false, k, n2, cur, other, other);
+        ens_sweeps<T>(e, ids, pre, nmem, total, false, k, n2, cur, other,
+                      other);
         std::swap(cur, other);
         k += n2;
         ++queued;
@@ -256,8 +281,19 @@ nh_status ens_solve(nh_ensemble* e, int stage) {
     if (e->slot->nactive == 0) break;
     // the rest of the cycle, over the members still active
     double corners = 0.0;
+    nmem = 0;
+    total = 0;
     for (int i = 0; i < L; ++i)
-      if (act[i]) corners += (double)e->live_corners[i];
+      if (act[i]) {
+        corners += (double)e->live_corners[i];
+        total += e->sweep_nb[i];
+        ++nmem;
+      }
+    hipLaunchKernelGGL(nh::k_ens_compact, dim3(1), dim3(64), 0, e->stream,
+                       (const nh::EnsMember*)e->dmem_live,
+                       (const int*)e->nb_dev, L, e->act_ids, e->act_pre);
+    ids = e->act_ids;
+    pre = e->act_pre;
     int before = queued;
     long pm = (k % ce != 0 && k < kmax) ? e->prof.open(e->stream, 4) : -1;
     queue_until(1 << 30);

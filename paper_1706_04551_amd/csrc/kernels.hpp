@@ -1147,6 +1147,25 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// After a check: the members still active, in order, and the exclusive
+// prefix of their sweep workgroup counts nb[] (one thread; a few hundred
+// members at most).  The host forms the same total from the active flags it
+// reads in mapped memory.
+__global__ void k_ens_compact(const EnsMember* __restrict__ mem,
+                              const int* __restrict__ nb, int n,
+                              int* __restrict__ ids, int* __restrict__ pre) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int m = 0, acc = 0;
+  for (int g = 0; g < n; ++g) {
+    if (!mem[g].active) continue;
+    ids[m] = g;
+    pre[m] = acc;
+    acc += nb[g];
+    ++m;
+  }
+  pre[m] = acc;
+}
+
 // -------------------------------------------------------------------------
 // kernel entry points: one grid, or a batch of grids in one launch.  A batch
 // maps its workgroups onto the grids through an exclusive prefix sum of the
@@ -1218,24 +1237,27 @@ __global__ void __launch_bounds__(B)
   extern __shared__ double lds[];
   sweep_body<T, B, S, M>(a, L, (int)blockIdx.x, lds);
 }
-// batch: members that are not active in the running solve are skipped; the
-// launch's buffer indices are logical and map to (index + rot) % 3 of each
-// member.  Every member's workgroup count is a multiple of 8, so the local
-// workgroup index keeps the XCD of the global one.
+// batch: the launch covers the members ids[0..ngrids) (the members still
+// active in the running solve, compacted after each check), members found
+// inactive are skipped; the launch's buffer indices are logical and map to
+// (index + rot) % 3 of each member.  Every member's workgroup count is a
+// multiple of 8, so the local workgroup index keeps the XCD of the global one.
 template <typename T, int B, int S, int M>
 __global__ void __launch_bounds__(B)
     k_sweep_tb_batch(const SweepArgs<T>* __restrict__ as,
-                     const int* __restrict__ pre, int ngrids,
-                     const EnsMember* __restrict__ mem, SweepLaunch L) {
+                     const int* __restrict__ ids, const int* __restrict__ pre,
+                     int ngrids, const EnsMember* __restrict__ mem,
+                     SweepLaunch L) {
   extern __shared__ double lds[];
-  int g = batch_grid(pre, ngrids, (int)blockIdx.x);
+  const int pos = batch_grid(pre, ngrids, (int)blockIdx.x);
+  const int g = ids[pos];
   if (!mem[g].active) return;
   const int r = mem[g].rot;
   SweepLaunch Lg = L;
   Lg.iin = (L.iin + r) % 3;
   Lg.iout = (L.iout + r) % 3;
   Lg.isave = (L.isave + r) % 3;
-  sweep_body<T, B, S, M>(as[g], Lg, (int)blockIdx.x - pre[g], lds);
+  sweep_body<T, B, S, M>(as[g], Lg, (int)blockIdx.x - pre[pos], lds);
 }
 
 template <typename T, bool ONE_D, bool COMBINE>
