@@ -77,10 +77,12 @@ struct Dual {
     for (int k = 0; k < N; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) / b.v;
     return r;
   }
+  // at 0 (a dry face) the derivative is taken as 0: the forward run treats
+  // such a face as dry, and its speeds do not move to first order
   friend __device__ __forceinline__ Dual sqrt(const Dual& a) {
     Dual r;
     r.v = sqrt(a.v);
-    const T s = T(0.5) / r.v;
+    const T s = r.v > T(0) ? T(0.5) / r.v : T(0);
 #pragma unroll
     for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * s;
     return r;

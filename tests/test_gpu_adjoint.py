@@ -177,3 +177,85 @@ def test_full_size_gradient_against_central_differences():
             f"rel {abs(fd - ad) / abs(ad):.2e}")
         assert abs(fd - ad) <= 1e-4 * abs(ad)
     s.close()
+
+
+def test_hydrostatic_adjoint_matches_the_oracle():
+    """nh_on = 0: the adjoint of the finite-volume scheme alone."""
+    from paper_1706_04551_amd import Solver
+    P = problem(15, 12, steps=8)
+    s = Solver(P["nx"], P["ny"], P["dx"], P["dy"], cfl=0.7, fixed_dt=1,
+               dt_fixed=P["dt"], nh_on=0)
+    s.set_bathymetry(P["H"])
+    z = np.zeros_like(P["H"])
+    s.set_state(P["H"] + P["eta0"], z, z)
+    r = s.adjoint(P["steps"], P["gauges"], P["target"], ckpt_every=3,
+                  adj_tol=1e-12)
+    s.close()
+    TP = NT.TorchParams(P["nx"], P["ny"], P["dx"], P["dy"], P["dt"],
+                        nh_on=False)
+    J, ge, gb = NT.gradient(TP, P["eta0"], P["H"], P["gauges"], P["target"],
+                            P["steps"])
+    assert abs(r["J"] - J) <= 1e-12 * J
+    assert rel(r["dh0"], ge) <= 1e-10 and rel(r["dH"] + r["dh0"], gb) <= 1e-10
+
+
+def test_adjoint_with_dry_land_is_finite_and_checkpoint_invariant():
+    """The island basin: dry cells, wet/dry faces (the derivative at a dry
+    face is that of the forward's dry branch)."""
+    from paper_1706_04551_amd import Solver
+    H, h = I.island_basin(64, 1.0, 7, hump_amp=0.5)
+    z = np.zeros_like(h)
+    rng = np.random.default_rng(3)
+    wet = np.flatnonzero(h.reshape(-1) > 1.0)
+    gauges = rng.choice(wet, size=5, replace=False)
+    # (the oracle runs this small, steep basin stably for ~8 steps at this dt;
+    # beyond, its non-dominant rows make the relaxation diverge)
+    steps = 6
+    target = h.reshape(-1)[gauges][None, :] + 0.01 * rng.standard_normal(
+        (steps, 5))
+    # the workloads' relaxation schedule: plain Jacobi need not converge
+    # where rows lose diagonal dominance next to the island
+    om = I.srj_schedule(I.jacobi_radius_bound(float(h.max()), 1.0, 1.0), 64)
+    out = []
+    for ckpt in (4, 6):
+        s = Solver(64, 64, 1.0, 1.0, cfl=0.7, fixed_dt=1, dt_fixed=0.02,
+                   solve_tol=1e-12, solve_max_iter=400000, check_every=64,
+                   omega=om)
+        s.set_bathymetry(H)
+        s.set_state(h, z, z)
+        out.append(s.adjoint(steps, gauges, target, ckpt_every=ckpt,
+                             adj_tol=1e-10))
+        s.close()
+    for k in ("dh0", "dhu0", "dhv0", "dH"):
+        assert np.isfinite(out[0][k]).all(), k
+        assert np.array_equal(out[0][k], out[1][k]), k
+    assert np.abs(out[0]["dh0"]).max() > 0
+
+
+def test_adjoint_rejects_what_it_does_not_cover():
+    from paper_1706_04551_amd import NhError, Solver
+    P = problem(12, 10, steps=4)
+    g, t = P["gauges"], P["target"]
+    z = np.zeros_like(P["H"])
+
+    def make(**kw):
+        s = Solver(P["nx"], P["ny"], P["dx"], P["dy"], cfl=0.7, **kw)
+        s.set_bathymetry(P["H"])
+        s.set_state(P["H"] + P["eta0"], z, z)
+        return s
+    s = make()                                    # CFL time step
+    with pytest.raises(NhError):
+        s.adjoint(4, g, t)
+    s.close()
+    s = make(fixed_dt=1, dt_fixed=0.05, breaking_on=1)
+    with pytest.raises(NhError):
+        s.adjoint(4, g, t)
+    s.close()
+    s = make(fixed_dt=1, dt_fixed=0.05)
+    with pytest.raises(NhError):
+        s.adjoint(4, np.array([0, P["nx"] * P["ny"]]), t[:, :2])
+    with pytest.raises(NhError):
+        s.adjoint(4, g, t, ckpt_every=0)
+    r = s.adjoint(4, g, t, ckpt_every=2)          # still usable afterwards
+    assert np.isfinite(r["J"])
+    s.close()

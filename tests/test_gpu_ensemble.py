@@ -191,3 +191,19 @@ def test_full_ensemble_workload_short_run():
         m1 = float(np.sum(e.state(k)["h"], dtype=np.float64))
         assert abs(m1 - m0 - st["clamped"]) <= 1e-5 * m0, k
     e.close()
+
+
+def test_ensemble_with_breaking_matches_single_grid_solves():
+    """The breaking terms in batches: every member with breaking on."""
+    cases = small_cases("f64", sides=(64, 80))
+    for c in cases:
+        c.breaking_on = 1
+    steps = 8
+    e = ensemble(cases)
+    e.run(steps)
+    for k, c in enumerate(cases):
+        r, _ = single(c, steps)
+        g = e.state(k)
+        for f in FIELDS:
+            assert np.array_equal(g[f], r[f]), (k, f)
+    e.close()
