@@ -220,7 +220,8 @@ void ens_sweeps(nh_ensemble* e, const int* ids, const int* pre, int n,
                 int total, bool check, int k0, int nsw, int iin, int iout,
                 int isave) {
   if (total <= 0) return;
-  nh::SweepLaunch Lc{iin, iout, isave, k0, nsw, check ? 1 : 0};
+  nh::SweepLaunch Lc{iin, iout, isave, k0, nsw, check ? 1 : 0,
+                     0, nullptr, nullptr, 0};
   hipLaunchKernelGGL((nh::k_sweep_tb_batch<T, nh::kSweepB, nh::kSweepS,
                                              nh::kSweepM>),
                      dim3(total), dim3(nh::kSweepB), e->sweep_lds, e->stream,
@@ -626,7 +627,7 @@ nh_status nh_ensemble_tune(nh_ensemble* e, int32_t reps) {
           s.nom = (int)m->omega.size();
           s.part = pbase + 2 * nk;
         };
-        nh::SweepLaunch Lc{0, 1, 2, 0, nh::kSweepS, 0};
+        nh::SweepLaunch Lc{0, 1, 2, 0, nh::kSweepS, 0, 0, nullptr, nullptr, 0};
         float ms_min = 1e30f;
         for (int r = 0; r <= reps; ++r) {
           (void)hipEventRecord(a, e->stream);

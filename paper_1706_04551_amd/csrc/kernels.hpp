@@ -632,6 +632,13 @@ struct SweepArgs {
 struct SweepLaunch {
   int iin, iout, isave;  // buffers read, written, saved (check launch)
   int k0, nsw, check;
+  // single grid: the launch after a check carries one extra workgroup that
+  // reduces the check's per-tile measures (complete at the kernel boundary)
+  // into E_host and then releases seq into seq_slot (mapped host memory)
+  int reduce;
+  double* E_host;
+  long long* seq_slot;
+  long long seq;
 };
 
 template <typename T, int B, int S, int M>
@@ -1235,6 +1242,27 @@ template <typename T, int B, int S, int M>
 __global__ void __launch_bounds__(B)
     k_sweep_tb(SweepArgs<T> a, SweepLaunch L) {
   extern __shared__ double lds[];
+  if (L.reduce && (int)blockIdx.x == a.nblocks()) {
+    __shared__ double wmax[B / 64];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < a.ntiles; i += B) {
+      double x = a.part[i];
+      v = (x > v || x != x) ? x : v;
+    }
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double m = wmax[0];
+      for (int w = 1; w < B / 64; ++w)
+        m = (wmax[w] > m || wmax[w] != wmax[w]) ? wmax[w] : m;
+      *L.E_host = m;
+      __threadfence_system();
+      __hip_atomic_store(L.seq_slot, L.seq, __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    return;
+  }
   sweep_body<T, B, S, M>(a, L, (int)blockIdx.x, lds);
 }
 // batch: the launch covers the members ids[0..ngrids) (the members still

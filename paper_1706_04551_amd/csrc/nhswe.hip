@@ -416,14 +416,20 @@ struct Launch {
   // nsw <= kSweepS relaxation sweeps starting at sweep index k0 from buffer
   // iin into iout; with check the convergence measure of the input iterate
   // goes to s->part per tile and the input iterate is saved to isave
+  // with reduce_seq > 0 the launch also publishes the measure of the
+  // preceding check launch under that sequence number
   static void sweeps(nh_solver* s, const SysView& V, bool check, int k0,
-                     int nsw, int iin, int iout, int isave) {
+                     int nsw, int iin, int iout, int isave,
+                     long long reduce_seq = 0) {
     auto a = Args<T>::sweep(s, V);
-    nh::SweepLaunch L{iin, iout, isave, k0, nsw, check ? 1 : 0};
+    nh::SweepLaunch L{iin,        iout, isave, k0, nsw, check ? 1 : 0,
+                      reduce_seq > 0 ? 1 : 0, s->E_dev, &s->slot_dev->seq,
+                      reduce_seq};
     hipLaunchKernelGGL((nh::k_sweep_tb<T, nh::kSweepB, nh::kSweepS,
                                          nh::kSweepM>),
-                       dim3(a.nblocks()), dim3(nh::kSweepB),
-                       sweep_lds_bytes(s->tbx, s->tby), s->stream, a, L);
+                       dim3(a.nblocks() + (reduce_seq > 0 ? 1 : 0)),
+                       dim3(nh::kSweepB), sweep_lds_bytes(s->tbx, s->tby),
+                       s->stream, a, L);
   }
 
   static void thomas(nh_solver* s, void* pout) {
@@ -512,10 +518,6 @@ nh_status solve2d(nh_solver* s, const SysView& V, int& pcur, double tol,
     int nsw = k >= kmax ? 0 : std::min(std::min(S, ce), kmax - k);
     Launch<T>::sweeps(s, V, true, k, nsw, cur, out, save);
     ++s->seq;
-    hipLaunchKernelGGL(nh::k_reduce_measure, dim3(1), dim3(nh::kBlock), 0,
-                       s->stream, (const double* const*)s->part_list,
-                       (const int*)s->ntiles_list, 1, s->E_dev,
-                       &s->slot_dev->seq, s->seq);
     launches += 1;
     if (nsw > 0) {
       cur = out;                 // ping-pong between cur and (save's peer)
@@ -523,12 +525,15 @@ nh_status solve2d(nh_solver* s, const SysView& V, int& pcur, double tol,
       nsweeps_done += nsw;
     }
     int other = 3 - cur - save;  // the buffer that is neither cur nor save
-    // queue the rest of the cycle, the first kAhead launches before waiting
+    // queue the rest of the cycle, the first kAhead launches before waiting;
+    // the first of them also publishes the check's measure
     int queued = 0;
+    long long pending = s->seq;
     auto queue_until = [&](int limit) {
       while (k % ce != 0 && k < kmax && queued < limit) {
         int n2 = std::min(std::min(S, ce - k % ce), kmax - k);
-        Launch<T>::sweeps(s, V, false, k, n2, cur, other, other);
+        Launch<T>::sweeps(s, V, false, k, n2, cur, other, other, pending);
+        pending = 0;
         std::swap(cur, other);
         k += n2;
         nsweeps_done += n2;
@@ -537,6 +542,11 @@ nh_status solve2d(nh_solver* s, const SysView& V, int& pcur, double tol,
       }
     };
     if (nsw > 0) queue_until(kAhead);
+    if (pending)  // no launch follows the check in this cycle
+      hipLaunchKernelGGL(nh::k_reduce_measure, dim3(1), dim3(nh::kBlock), 0,
+                         s->stream, (const double* const*)s->part_list,
+                         (const int*)s->ntiles_list, 1, s->E_dev,
+                         &s->slot_dev->seq, s->seq);
     nh_status ws = wait_measure(s, &E);
     if (ws != NH_OK) return ws;
     if (E < tol || kc >= kmax) {
