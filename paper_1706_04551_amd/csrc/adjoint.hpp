@@ -69,12 +69,15 @@ struct Dual {
     for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
     return r;
   }
+  // the value is the forward's quotient (its branches see the same numbers);
+  // the derivatives use one reciprocal
   friend __device__ __forceinline__ Dual operator/(const Dual& a,
                                                   const Dual& b) {
     Dual r;
     r.v = a.v / b.v;
+    const T inv = T(1) / b.v;
 #pragma unroll
-    for (int k = 0; k < N; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) / b.v;
+    for (int k = 0; k < N; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * inv;
     return r;
   }
   // at 0 (a dry face) the derivative is taken as 0: the forward run treats
