@@ -164,13 +164,17 @@ struct AdjGeom {
 };
 
 // ---------------------------------------------------------------------------
-// finite-volume stage: (h*, q*) = FV(h, q; H).  Per input cell j:
-//   lh_j += sum_i dh*_i/dh_j lhs_i + dq*_i/dh_j lqs_i  (likewise q1, q2, H)
-// over the outputs i that read j: the cells within 2 of j along x, through
-// their x fluxes (DIR = 1), and along y, through their y fluxes (DIR = 2);
-// j's own identity term is counted by the x pass.  Mirror images of j are
-// included by the loader.  hs_out (the stored h*) gives the forward's clamp
-// and dry decisions.
+// finite-volume stage: (h*, q*) = FV(h, q; H), one direction per pass
+// (DIR = 1: x, 2: y).  Along the direction a cell's flux sum is
+//   f_i = Dm(i | i+1) + Dp(i-1 | i) + I_i,   out_i = U_i - dt f_i / dx + ...,
+// with the edge fluctuations (eq. 18-19) of the reconstructed states of the
+// two cells beside the edge (eq. 21) and the volume term I_i (eq. 22, 30).
+// Per input cell j the pass slides along j's line over the cells j-2..j+2:
+// their reconstructions, the 4 edges that read j and the 3 volume terms that
+// read j, each once, on 4-direction dual numbers (dh, dq1, dq2, dH of j), and
+//   lh_j += sum over those pieces of d(piece)/d(j) * (-dt/dx) * lambda(out),
+// likewise q1, q2, H; the x pass adds j's own identity term.  hs_out (the
+// stored h*) gives the forward's clamp and dry decisions.
 // ---------------------------------------------------------------------------
 template <typename T, int DIR>
 __global__ void __launch_bounds__(kBlock)
@@ -181,35 +185,77 @@ __global__ void __launch_bounds__(kBlock)
              T* __restrict__ lh, T* __restrict__ lq1, T* __restrict__ lq2,
              T* __restrict__ lH) {
   using D = Dual<T, 4>;
+  constexpr bool XD = DIR == 1;
   const int nx = G.nx, ny = G.ny;
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= nx * ny) return;
   const int jx = n % nx, jy = n / nx;
+  const int len = XD ? nx : ny, j0 = XD ? jx : jy;
   const T dry_eps = (T)G.dry_eps;
-  const D dx(G.dx), dy(G.dy), g(G.g), delta(G.delta), de(G.dry_eps),
-      dt(*G.dtp);
+  const D g(G.g), delta(G.delta), de(G.dry_eps);
+  const T dt = (T)(*G.dtp);
+  const E fac = -(E)dt / (E)(XD ? (T)G.dx : (T)G.dy);
   SeedLoader<T, 4, T> ld{h, q1, q2, H, nx, ny, n, 0, 1, 2, 3};
-  E acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
-  for (int o = -2; o <= 2; ++o) {
-    const int i = DIR == 1 ? jx + o : jx, j = DIR == 1 ? jy : jy + o;
-    if (i < 0 || i >= nx || j < 0 || j >= ny) continue;
-    D out[3];
-    fv_cell<D, false>(ld, i, j, dx, dy, g, delta, de, dt, DIR, out);
-    const int m = j * nx + i;
+  auto prim_at = [&](int c) {
+    return prim(XD ? ld(c, jy) : ld(jx, c), XD, delta, false);
+  };
+  // adjoint weights of the direction's flux components (h, normal, tangent)
+  // of cell c along the line
+  auto weights = [&](int c, E w[3]) {
+    const int m = XD ? jy * nx + c : c * nx + jx;
     const T hv = hs_out[m];
     const E wh = hv > T(0) ? (E)lhs[m] : 0.0;
     const bool wet = hv > dry_eps;
     const E w1 = wet ? (E)lq1s[m] : 0.0, w2 = wet ? (E)lq2s[m] : 0.0;
+    w[0] = fac * wh;
+    w[1] = fac * (XD ? w1 : w2);
+    w[2] = fac * (XD ? w2 : w1);
+  };
+  E acc[4] = {0.0, 0.0, 0.0, 0.0};
+  auto add = [&](const D f[3], const E w[3]) {
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-      acc[k] = acc[k] + ((E)out[0].d[k] * wh + (E)out[1].d[k] * w1 +
-                         (E)out[2].d[k] * w2);
-    if (DIR == 2 && o == 0) {  // the identity term went in with the x pass
-      acc[0] = acc[0] - wh;
-      acc[1] = acc[1] - w1;
-      acc[2] = acc[2] - w2;
+      acc[k] = acc[k] + ((E)f[0].d[k] * w[0] + (E)f[1].d[k] * w[1] +
+                         (E)f[2].d[k] * w[2]);
+  };
+  if (XD) {  // d out_j / d U_j contains the identity once
+    const T hv = hs_out[n];
+    const bool wet = hv > dry_eps;
+    acc[0] = hv > T(0) ? (E)lhs[n] : 0.0;
+    acc[1] = wet ? (E)lq1s[n] : 0.0;
+    acc[2] = wet ? (E)lq2s[n] : 0.0;
+  }
+  Prim<D> Pm = prim_at(j0 - 3), P0 = prim_at(j0 - 2);
+  Face<D> Rprev;
+#pragma unroll 1
+  for (int c = j0 - 2; c <= j0 + 2; ++c) {
+    const Prim<D> Pp = prim_at(c + 1);
+    Face<D> Lc, Rc;
+    reconstruct(Pm, P0, Pp, de, Lc, Rc);
+    const bool in_prev = c - 1 >= 0 && c - 1 < len, in_c = c >= 0 && c < len;
+    if (c > j0 - 2 && (in_prev || in_c)) {  // edge (c-1 | c)
+      D Dm[3], Dp[3];
+      pvm(Rprev, Lc, g, de, Dm, Dp);
+      E w[3];
+      if (in_prev) {
+        weights(c - 1, w);
+        add(Dm, w);
+      }
+      if (in_c) {
+        weights(c, w);
+        add(Dp, w);
+      }
     }
+    if (c >= j0 - 1 && c <= j0 + 1 && in_c) {  // volume term of cell c
+      D I[3];
+      interior(Lc, Rc, P0.h, g, I);
+      E w[3];
+      weights(c, w);
+      add(I, w);
+    }
+    Rprev = Rc;
+    Pm = P0;
+    P0 = Pp;
   }
   lh[n] = (T)((E)lh[n] + acc[0]);
   lq1[n] = (T)((E)lq1[n] + acc[1]);
