@@ -305,3 +305,64 @@ def test_island_free_basin_fp32_vs_stored_oracle():
     check(s.state(), f"_{early}")
     s.run(c.steps - early)
     check(s.state(), "")
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_c3_full_size_beach_vs_1d_oracle(precision):
+    """The 2048^2 plane beach (breaking on, wet-dry front) at full size over
+    its 4000 steps.  Its data are y-invariant, and a y-invariant 2D run
+    equals the 1D run (pinned in the oracle), so the 1D oracle checks every
+    row of the 2D run.  Both runs use one fixed dt, 0.5 of the 2D limit of
+    the initial state (the 1D oracle would take another dt from its own CFL
+    condition).  Bars: in FP64 1e-9 (the 2D relaxation stops at its
+    tolerance, the 1D solve is direct); in FP32 bulk 1e-4, or twice the
+    drift that FP32 storage of the state alone causes on this run where that
+    is larger (the 1D oracle with its state rounded to FP32 after every
+    step: ~1e-4 in hu after 4000 steps)."""
+    c = I.case_c3()
+    if precision == "f64":
+        c.precision, c.solve_tol, c.dry_eps = "f64", 1e-10, 1e-10
+    hmax = float(c.h.max())
+    umax = float(np.abs(c.hu / np.maximum(c.h, 1e-6)).max())
+    cel = math.sqrt(9.81 * hmax)
+    dt = 0.5 / ((umax + cel) / c.dx + cel / c.dy)
+    say(f"[case] c3 2048x2048 {precision} fixed dt {dt:.5f}, 4000 steps")
+    s = gpu_solver(c, fixed_dt=1, dt_fixed=dt)
+    kw = c.param_dict()
+    kw.update(nx=c.nx, ny=1, fixed_dt=1, dt_fixed=dt)
+    o = Oracle(Params(**kw))
+    o.set_bathymetry(c.H[:1])
+    o.set_state(c.h[:1], c.hu[:1], c.hv[:1])
+    if precision == "f32":   # the 1D oracle with FP32 storage of its state
+        ob = Oracle(Params(**kw))
+        ob.set_bathymetry(c.H[:1])
+        ob.set_state(c.h[:1], c.hu[:1], c.hv[:1])
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)  # noqa: E731
+    m0 = float(np.sum(c.h, dtype=np.float64))
+    done = 0
+    for n in (500, 3500):
+        s.run(n)
+        assert o.run(n) == 0
+        if precision == "f32":
+            for _ in range(n):
+                assert ob.step() == 0
+                rb = ob.state()
+                ob.set_state(f32(rb["h"]), f32(rb["hu"]), None, f32(rb["w"]),
+                             rb["p"])
+            rb = ob.state()
+        done += n
+        g, r = s.state(), o.state()
+        for k in ("h", "hu"):
+            e = np.abs(g[k] - r[k][0:1]).max() / np.abs(r[k]).max()
+            bar = 1e-9
+            if precision == "f32":
+                drift = np.abs(rb[k] - r[k]).max() / np.abs(r[k]).max()
+                bar = max(TOL32, 2.0 * drift)
+            say(f"  {done} steps {k}: every row vs the 1D oracle {e:.2e} "
+                f"(bar {bar:.1e})")
+            assert e <= bar, (done, k, e, bar)
+        say(f"  {done} steps: max|hv| {np.abs(g['hv']).max():.1e}")
+    st = s.stats()
+    m1 = float(np.sum(g["h"], dtype=np.float64))
+    assert abs(m1 - m0 - st["clamped"] / (c.dx * c.dy)) <= 1e-5 * m0
+    s.close()
