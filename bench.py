@@ -196,12 +196,14 @@ def run_ensemble(args):
         "steps": steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.precision, "data": "synthetic",
-        "config": {"workload": (f"ensemble of {len(cases)} island basins, sides "
+        "config": {"workload": (f"ensemble of {len(cases)} basins (dry island on sides >= 256), sides "
                                 f"128-1024 (dx=1m), {ncell} cells, "
                                 f"{args.precision.upper()} bulk, Jacobi+SRJ(64) "
                                 f"tol={cases[0].solve_tol:g}, tuned tiles"),
                    "cells": ncell, "members": len(cases), "steps": steps,
                    "mean_sweeps_per_solve": round(kbar, 2),
+                   "members_failed": sum(1 for s in stats if s["status"] != 0),
+                   "min_sim_time_s": round(min(s["t"] for s in stats), 3),
                    "full_step_hbm_roofline_frac": round(
                        full_bytes / elapsed / (HBM_PEAK_GBS * 1e9), 4),
                    "tiles": tiles,
@@ -361,7 +363,9 @@ def variant_summary(out):
                                              cfg.get("forward_sweeps_per_solve")),
             "full_step_hbm_roofline_frac": cfg.get("full_step_hbm_roofline_frac"),
             "sweep_roofline_frac": out["roofline"]["frac"],
-            "sweep_kernel": out["roofline"]["kernel"]}
+            "sweep_kernel": out["roofline"]["kernel"],
+            **{k: cfg[k] for k in ("members_failed", "min_sim_time_s")
+               if k in cfg}}
 
 
 def main():

@@ -177,12 +177,14 @@ def case_c1(steps: int = 300) -> Case:
 
 
 def island_basin(n: int, dx: float, seed: int, hump_amp: float = 0.5,
-                 hump_radius: float = 20.0, island: bool = True):
+                 hump_radius: float = 20.0, island: bool = True,
+                 min_sep: float | None = None):
     """Square basin (n x n cells, spacing dx): depth H = 20 - 18 D in [2, 20] m
     from 8 seeded Gaussians, minus an island Gaussian of height 24 m and width
     30 m (H <= 0 is dry land), and a Gaussian hump of the given amplitude on a
-    wet point (depth >= 10 m) at least 100 m from the island.  Returns
-    (H, h0); the water is at rest."""
+    wet point (depth >= 10 m) at least min_sep from the island centre
+    (default: 100 m, or 0.3 of the side on smaller basins).  Returns (H, h0);
+    the water is at rest."""
     rng = np.random.default_rng(seed)
     L = n * dx
     xc = centres(n, dx)
@@ -195,11 +197,12 @@ def island_basin(n: int, dx: float, seed: int, hump_amp: float = 0.5,
                               (2.0 * 30.0 ** 2))
     if hump_amp == 0.0:
         return H, np.where(H > 0.0, H, 0.0)
+    sep = min(100.0, 0.3 * L) if min_sep is None else min_sep
     for _ in range(10000):
         ce = rng.uniform(0.1 * L, 0.9 * L, 2)
         i = min(int(ce[0] / dx), n - 1)
         j = min(int(ce[1] / dx), n - 1)
-        far = math.hypot(ce[0] - ci[0], ce[1] - ci[1]) >= min(100.0, 0.3 * L)
+        far = math.hypot(ce[0] - ci[0], ce[1] - ci[1]) >= sep
         if H[j, i] >= 10.0 and (far or not island):
             break
     else:
@@ -261,17 +264,40 @@ def case_c3(n: int = 2048, steps: int = 4000) -> Case:
 C4_SIDES = (128, 256, 512, 768, 1024)
 
 
+C4_SOURCE_SEP = 100.0   # m between the source and the island centre
+
+
+def c4_has_island(n: int, dx: float = 1.0) -> bool:
+    """Whether a basin of side n keeps the source C4_SOURCE_SEP from the
+    island wherever the island falls: the island centre lies in
+    [0.25 L, 0.75 L]^2 and the source in [0.1 L, 0.9 L]^2, so the farthest
+    source point is at least 0.4 sqrt(2) L away."""
+    return 0.4 * math.sqrt(2.0) * n * dx >= C4_SOURCE_SEP
+
+
 def case_c4_member(k: int, seed: int = SEED_C4, sides=C4_SIDES,
-                   steps: int = 500, precision: str = "f32") -> Case:
+                   steps: int = 500, precision: str = "f32",
+                   island: bool | None = None) -> Case:
     """Scenario k of the ensemble workload, drawn from its own generator
-    (seed + k): side n uniform over `sides`, the island basin of c2 at that
-    side (dx = 1 m), a Gaussian source of amplitude U[0.1, 1] m and radius
-    20 m on wet water.  FP32 bulk unless precision says otherwise."""
+    (seed + k): side n uniform over `sides`, the basin of c2 at that side
+    (dx = 1 m), a Gaussian source of amplitude U[0.1, 1] m and radius 20 m
+    on wet water at least 100 m from the island centre.  Sides too small for
+    that separation (c4_has_island) get the basin without the island: a
+    source of up to 1 m next to the island's near-vertical flanks drives
+    thin films on the dry slope to velocities that collapse the time step,
+    in the FP64 oracle as on the GPU.  island=True/False overrides the rule
+    (the separation then falls back to 0.3 of the side).  FP32 bulk unless
+    precision says otherwise."""
     rng = np.random.default_rng(seed + k)
     n = int(sides[int(rng.integers(len(sides)))])
     amp = float(rng.uniform(0.1, 1.0))
     basin_seed = int(rng.integers(1 << 31))
-    H, h0 = island_basin(n, 1.0, basin_seed, hump_amp=amp, hump_radius=20.0)
+    if island is None:
+        isl, sep = c4_has_island(n), C4_SOURCE_SEP
+    else:
+        isl, sep = island, None
+    H, h0 = island_basin(n, 1.0, basin_seed, hump_amp=amp, hump_radius=20.0,
+                         island=isl, min_sep=sep)
     z = np.zeros_like(h0)
     f32 = precision == "f32"
     c = Case(f"c4-{k}", n, n, 1.0, 1.0, H, h0, z, z.copy(), steps,
