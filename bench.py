@@ -343,6 +343,7 @@ def run_single(args):
         "dtype": args.precision,
         "data": "synthetic",
         "config": {"workload": desc, "cells": ncell, "steps": args.steps,
+                   "sim_time_s": round(st["t"], 4),
                    "mean_sweeps_per_solve": round(kbar, 2),
                    "full_step_hbm_roofline_frac": round(step_roof_frac, 4),
                    "phase_ms": {k: round(pr[k], 2) for k in
