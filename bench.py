@@ -34,6 +34,19 @@ ALG_BYTES_SWEEP = {"f64": 40, "f32": 20}   # per corner per sweep (matrix-free
                                            # minimum: r p, h, H, rhs; w p)
 
 
+# The timed runs time only the back-to-back sweep batch of one relaxation
+# cycle in PROFILE_SAMPLE (HIP events on the solver's stream); timing every
+# phase stalls the queue at each event pair and costs ~13 % of a step, so the
+# phase split comes from a separate run of PHASE_STEPS steps.
+PROFILE_SAMPLE = 8
+PHASE_STEPS = 100
+PHASES = ("fv_ms", "assemble_ms", "solve_ms", "correct_ms")
+
+
+def phase_split(pr, steps):
+    return {"steps": steps, **{k: round(pr[k], 2) for k in PHASES}}
+
+
 def alg_bytes_per_cell_step(kbar: float, prec: str) -> float:
     """Compulsory bytes per cell-step with ideal stencil reuse:
     flux stages 56 + 88, assembly 2 x 48, corrections 2 x 72, sweeps
@@ -156,7 +169,7 @@ def run_ensemble(args):
     for k, c in enumerate(cases):
         e.set_state(k, c.h, c.hu, c.hv)
     torch.cuda.synchronize()
-    e.profile(True)
+    e.profile(PROFILE_SAMPLE)
     t0 = time.perf_counter()
     e.run(steps)
     torch.cuda.synchronize()
@@ -181,6 +194,13 @@ def run_ensemble(args):
     tiles = {}
     for k, c in enumerate(cases):
         tiles[str(c.nx)] = "x".join(map(str, e.tile(k)))
+    nph = min(steps, PHASE_STEPS // 2)
+    for k, c in enumerate(cases):
+        e.set_state(k, c.h, c.hu, c.hv)
+    e.profile(True)
+    e.run(nph)
+    phases = phase_split(e.get_profile(), nph)
+    e.profile(False)
     e.close()
     roof = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -188,7 +208,8 @@ def run_ensemble(args):
             "traffic": measured_traffic("c4", args.precision),
             "kernel": "k_sweep_tb_batch",
             "avg_launch_us": round(sweep_ms * 1e3, 3),
-            "alg_bytes_per_launch": int(alg)}
+            "alg_bytes_per_launch": int(alg),
+            "timed_cycles": f"1 in {PROFILE_SAMPLE}"}
     cpu = None if args.no_cpu else ensemble_cpu_baseline(cases, 4, 4)
     out = {
         "metric": "Mcell-steps/s per full step (flux+pressure solve), % HBM roofline, vs FP64 plain",
@@ -207,9 +228,7 @@ def run_ensemble(args):
                    "full_step_hbm_roofline_frac": round(
                        full_bytes / elapsed / (HBM_PEAK_GBS * 1e9), 4),
                    "tiles": tiles,
-                   "phase_ms": {k: round(pr[k], 2) for k in
-                                ("fv_ms", "assemble_ms", "solve_ms",
-                                 "correct_ms")}},
+                   "phase_ms_profiled_run": phases},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -234,13 +253,19 @@ def run_adjoint(args):
         s.adjoint(steps, gauges, target, ckpt_every=ckpt, adj_tol=1e-6)
         s.set_state(c.h, c.hu, c.hv)
     torch.cuda.synchronize()
-    s.profile(True)
+    s.profile(PROFILE_SAMPLE)
     t0 = time.perf_counter()
     r = s.adjoint(steps, gauges, target, ckpt_every=ckpt, adj_tol=1e-6)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     pr = s.get_profile()
     st = s.stats()
+    s.profile(False)
+    nph = min(steps, 2 * PHASE_STEPS)
+    s.set_state(c.h, c.hu, c.hv)
+    s.profile(True)
+    s.adjoint(nph, gauges, target[:nph], ckpt_every=ckpt, adj_tol=1e-6)
+    phases = phase_split(s.get_profile(), nph)
     s.profile(False)
     s.close()
     ncell = c.nx * c.ny
@@ -255,7 +280,8 @@ def run_adjoint(args):
             "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
             "traffic": None, "kernel": "k_sweep_tb",
             "avg_launch_us": round(sweep_ms * 1e3, 3),
-            "alg_bytes_per_launch": int(alg)}
+            "alg_bytes_per_launch": int(alg),
+            "timed_cycles": f"1 in {PROFILE_SAMPLE}"}
     out = {
         "metric": "Mcell-steps/s per full step (flux+pressure solve), % HBM roofline, vs FP64 plain",
         "value": round(value, 3), "unit": "Mcell-steps/s", "n_gpus": 1,
@@ -272,9 +298,7 @@ def run_adjoint(args):
                    "cells": ncell, "J": r["J"],
                    "forward_sweeps_per_solve": round(
                        st["sweeps_total"] / max(1, st["solves"]), 2),
-                   "phase_ms": {k: round(pr[k], 2) for k in
-                                ("fv_ms", "assemble_ms", "solve_ms",
-                                 "correct_ms")}},
+                   "phase_ms_profiled_run": phases},
         "roofline": roof,
         "cpu_baseline": None,
     }
@@ -295,13 +319,19 @@ def run_single(args):
     s.run(args.warmup)
     s.set_state(case.h, case.hu, case.hv)
     torch.cuda.synchronize()
-    s.profile(True)
+    s.profile(PROFILE_SAMPLE)
     t0 = time.perf_counter()
     s.run(args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     st = s.stats()
     pr = s.get_profile()
+    s.profile(False)
+    nph = min(args.steps, PHASE_STEPS)
+    s.set_state(case.h, case.hu, case.hv)
+    s.profile(True)
+    s.run(nph)
+    phases = phase_split(s.get_profile(), nph)
     s.profile(False)
     s.close()
 
@@ -321,7 +351,8 @@ def run_single(args):
             "traffic": measured_traffic(args.workload, args.precision),
             "kernel": "k_sweep_tb", "avg_launch_us": round(sweep_ms * 1e3, 3),
             "sweeps_per_launch": round(sweeps_per_launch, 3),
-            "alg_bytes_per_launch": int(alg)}
+            "alg_bytes_per_launch": int(alg),
+            "timed_cycles": f"1 in {PROFILE_SAMPLE}"}
     full_step_bytes = alg_bytes_per_cell_step(kbar, args.precision) * ncell
     step_roof_frac = full_step_bytes / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9)
 
@@ -346,9 +377,7 @@ def run_single(args):
                    "sim_time_s": round(st["t"], 4),
                    "mean_sweeps_per_solve": round(kbar, 2),
                    "full_step_hbm_roofline_frac": round(step_roof_frac, 4),
-                   "phase_ms": {k: round(pr[k], 2) for k in
-                                ("fv_ms", "assemble_ms", "solve_ms",
-                                 "correct_ms")}},
+                   "phase_ms_profiled_run": phases},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -382,8 +411,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain copy of 256 MiB (for counter runs)")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip the FP32, ensemble and adjoint runs that follow "
-                         "the default workload")
+                    help="skip the FP32, beach, ensemble and adjoint runs that "
+                         "follow the default workload")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -422,6 +451,11 @@ def main():
             v.precision, v.no_cpu = "f32", True
             variants["c2_fp32_bulk"] = variant_summary(run_single(v))
             note("c2 FP32 done")
+            v = copy.copy(args)
+            v.workload, v.precision, v.no_cpu = "c3", "f32", True
+            v.steps = 4000          # the beach workload's full run
+            variants["c3_beach_fp32"] = variant_summary(run_single(v))
+            note("c3 beach done")
             v = copy.copy(args)
             v.workload, v.precision, v.no_cpu = "c4", "f32", True
             v.steps, v.steps_given = None, False

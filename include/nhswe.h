@@ -28,9 +28,10 @@
  * Corner (k, l) sits at x = k dx, y = l dy.  Walls bound the domain on every
  * side.
  *
- * Ownership.  The solver owns its device buffers.  Host arrays are always
- * owned by the caller and are copied in (set_*) or out (read_state); the
- * state stays in device memory between steps.
+ * Ownership.  The solver owns its device buffers, except those it borrows
+ * through nh_bind_device_buffers.  Host arrays are always owned by the caller
+ * and are copied in (set_*) or out (read_state); the state stays in device
+ * memory between steps.
  *
  * Errors.  Every call returns an nh_status; no exception crosses the ABI.
  * nh_last_error() returns a thread-local message for the last failing call.
@@ -135,6 +136,37 @@ nh_status nh_set_bathymetry(nh_solver *s, const double *H);
 nh_status nh_set_state(nh_solver *s, const double *h, const double *hu,
                        const double *hv, const double *w, const double *p);
 
+/* Device memory owned by the caller (for instance PyTorch tensors) that the
+ * solver borrows for the bathymetry and for the state U^n = (h, hu, hv) and
+ * w of the scheme (Section 5, eq. 31), so that inputs and results need no
+ * host copy.  Element type of the precision (double for NH_FP64, float for
+ * NH_FP32), contiguous, row-major: H, h, hu, hv cells [ny][nx]; w corners
+ * [ny+1][nx+1] ([nx+1] in 1D).  NULL = keep the current buffer. */
+typedef struct {
+  void *H;
+  void *h, *hu, *hv; /* hv: NULL in 1D */
+  void *w;           /* NULL: w = 0 */
+} nh_device_views;
+
+/* Bind device views (see nh_device_views).  Each given view replaces the
+ * solver's buffer for that array (a buffer the solver allocated is freed);
+ * from then on the solver reads and writes it in place on its stream, so
+ * after nh_step / nh_run it holds U^{n+1}, and nh_set_bathymetry,
+ * nh_set_state and nh_read_state copy into and out of it.  Binding adopts
+ * the contents: a bound H is the bathymetry (as nh_set_bathymetry); bound
+ * h, hu (and hv in 2D), which go together, are the state as nh_set_state
+ * would set it with that w (or w = 0, written into the current w buffer)
+ * and p = 0: statistics reset and the first dt computed.
+ * Ownership: the caller keeps the memory alive and leaves it untouched by
+ * other streams while the solver's stream works on it, until nh_destroy or a
+ * later bind of the same array.  Views are checked before anything changes:
+ * NH_EINVAL for a view that is not device memory of the solver's device
+ * (hipPointerGetAttributes), is misaligned, extends past its allocation,
+ * overlaps another view, or holds non-finite values, and for an incomplete
+ * state; NH_ENEGDEPTH for h < 0; NH_ESTATE for a state without bathymetry.
+ * Synchronises the solver's stream. */
+nh_status nh_bind_device_buffers(nh_solver *s, const nh_device_views *v);
+
 /* One time step.  dt_used (nullable) receives the step's dt. */
 nh_status nh_step(nh_solver *s, double *dt_used);
 
@@ -147,8 +179,11 @@ nh_status nh_read_state(nh_solver *s, double *h, double *hu, double *hv,
 
 nh_status nh_get_stats(const nh_solver *s, nh_stats *out);
 
-/* Turn per-phase event timing on (1) or off (0); turning it on clears the
- * accumulated times. */
+/* Event timing on the solver's stream: 0 off; 1 every phase and every
+ * back-to-back relaxation-sweep batch; n >= 2 only the sweep batch of one
+ * cycle in n (phase fields stay 0), which leaves the step's time almost
+ * untouched, whereas timing every phase adds ~13 % (each event pair stalls
+ * the queue).  Turning it on clears the accumulated times. */
 nh_status nh_profile(nh_solver *s, int32_t on);
 nh_status nh_get_profile(nh_solver *s, nh_profile_t *out);
 
@@ -237,7 +272,7 @@ nh_status nh_ensemble_read_state(nh_ensemble *e, int32_t member, double *h,
  * state was set reached solve_max_iter, else NH_OK. */
 nh_status nh_ensemble_get_stats(const nh_ensemble *e, int32_t member,
                                 nh_stats *out);
-/* Per-phase timing summed over all members (as nh_profile). */
+/* Per-phase timing summed over all members (modes as nh_profile). */
 nh_status nh_ensemble_profile(nh_ensemble *e, int32_t on);
 nh_status nh_ensemble_get_profile(nh_ensemble *e, nh_profile_t *out);
 void nh_ensemble_destroy(nh_ensemble *e);

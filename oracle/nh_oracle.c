@@ -582,7 +582,11 @@ static int thomas(int n, const double *a, const double *b, const double *c,
  * Relaxed Jacobi with a scheduled relaxation factor (Section 5, the
  * "Jacobi method combined with a scheduled relaxation"): sweep k replaces
  *   p <- p + omega_{k mod m} (rhs - A p) / diag
- * with all residuals taken from the previous iterate.  Every check_every
+ * with all residuals taken from the previous iterate.  Rounding, which the
+ * paper leaves open: A p is accumulated as diag p, then fused multiply-adds
+ * of the E, W, N, S neighbours in that order; the division by the diagonal
+ * is a product with its correctly rounded reciprocal 1/diag; the update is
+ * one fused multiply-add.  Every check_every
  * sweeps (cycle boundaries) the convergence measure
  *   E = max_c |(rhs - A p)_c / diag_c|,
  * i.e. the size of the plain Jacobi update of eq. (32), is evaluated on the
@@ -590,6 +594,9 @@ static int thomas(int n, const double *a, const double *b, const double *c,
  * or when solve_max_iter sweeps are reached.  Walls are already folded into
  * the coefficients, so neighbours outside the corner range carry zero weight.
  */
+/* compiled twice: with the FMA instruction where the CPU has it (fma() is
+ * then one instruction), else with the library's fma(); both are exact */
+__attribute__((target_clones("fma", "default")))
 static int jacobi_srj(ora_t *o, const double *diag, const double *cE,
                       const double *cW, const double *cN, const double *cS,
                       const double *rhs, double *p, int32_t *sweeps,
@@ -610,16 +617,16 @@ static int jacobi_srj(ora_t *o, const double *diag, const double *cE,
       for (int kk = 0; kk < ncx; ++kk) {
         int c = CX(o, kk, l);
         double Ap = diag[c] * p[c];
-        if (kk + 1 < ncx) Ap += cE[c] * p[CX(o, kk + 1, l)];
-        if (kk - 1 >= 0) Ap += cW[c] * p[CX(o, kk - 1, l)];
-        if (l + 1 < ncy) Ap += cN[c] * p[CX(o, kk, l + 1)];
-        if (l - 1 >= 0) Ap += cS[c] * p[CX(o, kk, l - 1)];
-        double r = rhs[c] - Ap;
+        if (kk + 1 < ncx) Ap = fma(cE[c], p[CX(o, kk + 1, l)], Ap);
+        if (kk - 1 >= 0) Ap = fma(cW[c], p[CX(o, kk - 1, l)], Ap);
+        if (l + 1 < ncy) Ap = fma(cN[c], p[CX(o, kk, l + 1)], Ap);
+        if (l - 1 >= 0) Ap = fma(cS[c], p[CX(o, kk, l - 1)], Ap);
+        double upd = (rhs[c] - Ap) * (1.0 / diag[c]);  /* plain Jacobi update */
         if (check) {
-          double e = fabs(r / diag[c]);
+          double e = fabs(upd);
           if (!(e <= E)) E = (e == e) ? e : INFINITY;
         }
-        pn[c] = p[c] + om * (r / diag[c]);
+        pn[c] = fma(om, upd, p[c]);
       }
     if (check && E < o->P.solve_tol) break;
     if (k >= kmax) {

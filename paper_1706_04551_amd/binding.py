@@ -38,6 +38,11 @@ class NhParams(C.Structure):
                 ("fixed_dt", C.c_int32), ("dt", C.c_double)]
 
 
+class NhDeviceViews(C.Structure):
+    _fields_ = [("H", C.c_void_p), ("h", C.c_void_p), ("hu", C.c_void_p),
+                ("hv", C.c_void_p), ("w", C.c_void_p)]
+
+
 class NhStats(C.Structure):
     _fields_ = [("t", C.c_double), ("dt_next", C.c_double),
                 ("dt_last", C.c_double), ("step", C.c_int64),
@@ -78,6 +83,7 @@ def lib():
         L.nh_step.argtypes = [vp, _DP]
         L.nh_run.argtypes = [vp, C.c_int64]
         L.nh_read_state.argtypes = [vp, _DP, _DP, _DP, _DP, _DP]
+        L.nh_bind_device_buffers.argtypes = [vp, C.POINTER(NhDeviceViews)]
         L.nh_get_stats.argtypes = [vp, C.POINTER(NhStats)]
         L.nh_profile.argtypes = [vp, C.c_int32]
         L.nh_get_profile.argtypes = [vp, C.POINTER(NhProfile)]
@@ -106,7 +112,7 @@ def lib():
         L.nh_last_error.restype = C.c_char_p
         L.nh_version.restype = C.c_char_p
         for f in ("nh_create", "nh_set_bathymetry", "nh_set_state", "nh_step",
-                  "nh_run", "nh_read_state", "nh_get_stats", "nh_profile",
+                  "nh_run", "nh_read_state", "nh_bind_device_buffers", "nh_get_stats", "nh_profile",
                   "nh_get_profile", "nh_adjoint_run", "nh_ensemble_create",
                   "nh_ensemble_set_bathymetry", "nh_ensemble_set_state",
                   "nh_ensemble_set_tile", "nh_ensemble_get_tile",
@@ -174,6 +180,8 @@ class Solver:
                                                          self.nx + 1)
         grid = NhGrid(self.nx, self.ny, float(dx), float(dy))
         par, self._omega = _params(**params)
+        self.precision = params.get("precision", "f64")
+        self._bound = {}
         h = C.c_void_p()
         st = lib().nh_create(C.byref(grid), C.byref(par),
                              C.c_void_p(stream) if stream else None,
@@ -194,14 +202,45 @@ class Solver:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().nh_destroy(self._h)
+            lib().nh_destroy(self._h)   # synchronises the solver's stream
             self._h = None
+        self._bound = {}                # then the borrowed tensors may go
 
     __del__ = close
 
     @property
     def shape(self):
         return (self.ny, self.nx)
+
+    def bind(self, H=None, h=None, hu=None, hv=None, w=None):
+        """Borrow device tensors for the bathymetry and the state
+        (nh_bind_device_buffers): contiguous, on the solver's device, of the
+        solver's precision (float64, or float32 in FP32 bulk), with the cell
+        count (H, h, hu, hv) or the corner count (w).  Bound h, hu (and hv in
+        2D) become the state; the solver then steps them in place on its
+        stream (create it on torch's current stream to keep torch's work on
+        the tensors in order).  The tensors stay referenced here."""
+        import torch
+        dtype = torch.float64 if self.precision == "f64" else torch.float32
+        ncell, ncorn = self.nx * self.ny, int(np.prod(self.cshape))
+        views, keep = NhDeviceViews(), {}
+        for name, t, n in (("H", H, ncell), ("h", h, ncell), ("hu", hu, ncell),
+                           ("hv", hv, ncell), ("w", w, ncorn)):
+            if t is None:
+                continue
+            if not isinstance(t, torch.Tensor) or not t.is_cuda:
+                raise TypeError(f"{name}: a device tensor is required")
+            if t.dtype != dtype:
+                raise TypeError(f"{name}: dtype {t.dtype}, the solver uses "
+                                f"{dtype}")
+            if not t.is_contiguous() or t.numel() != n:
+                raise ValueError(f"{name}: a contiguous tensor of {n} "
+                                 "elements is required")
+            setattr(views, name, t.data_ptr())
+            keep[name] = t
+        _check(lib().nh_bind_device_buffers(self._h, C.byref(views)),
+               "nh_bind_device_buffers")
+        self._bound.update(keep)
 
     def set_bathymetry(self, H):
         H = _f64(H, self.shape)
@@ -239,8 +278,10 @@ class Solver:
         _check(lib().nh_get_stats(self._h, C.byref(s)), "nh_get_stats")
         return _stats_dict(s)
 
-    def profile(self, on: bool = True):
-        _check(lib().nh_profile(self._h, 1 if on else 0), "nh_profile")
+    def profile(self, on=True):
+        """nh_profile: False/0 off, True/1 every phase, n >= 2 only the sweep
+        batch of one relaxation cycle in n (low overhead)."""
+        _check(lib().nh_profile(self._h, int(on)), "nh_profile")
 
     def adjoint(self, nsteps: int, gauges, target, ckpt_every: int = 100,
                 adj_tol: float = 1e-8) -> dict:
@@ -368,8 +409,9 @@ class Ensemble:
                "nh_ensemble_get_stats")
         return _stats_dict(s)
 
-    def profile(self, on: bool = True):
-        _check(lib().nh_ensemble_profile(self._h, 1 if on else 0),
+    def profile(self, on=True):
+        """As Solver.profile, summed over the members."""
+        _check(lib().nh_ensemble_profile(self._h, int(on)),
                "nh_ensemble_profile")
 
     def get_profile(self) -> dict:

@@ -742,7 +742,9 @@ nh_status nh_ensemble_profile(nh_ensemble* e, int32_t on) {
   if (!e) return fail(NH_EINVAL, "null ensemble");
   HIP_TRY(hipStreamSynchronize(e->stream));
   e->prof.flush();
-  e->prof.on = on != 0;
+  e->prof.on = on > 0;
+  e->prof.sample = on > 1 ? on : 1;
+  e->prof.nbatch = 0;
   if (e->prof.on) std::memset(&e->prof.pr, 0, sizeof(e->prof.pr));
   return NH_OK;
 }

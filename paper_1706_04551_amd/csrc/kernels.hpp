@@ -665,10 +665,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a,
   const int x0 = tx * BX - S, y0 = ty * BY - S;
   double* P0 = lds;
   double* P1 = lds + R;
-  // FP32 bulk: the update is formed with fused multiply-adds and the
-  // reciprocal of the diagonal, in FP64 (FP64 bulk keeps the operation order
-  // of the plain statement)
-  constexpr bool kFused = sizeof(T) == 4;
+  // the update in FP64 (also for FP32 coefficients): A p as diag p plus fused
+  // multiply-adds of the E, W, N, S neighbours in that order, a product with
+  // the correctly rounded reciprocal of the diagonal, and a fused update --
+  // the operation order of the oracle, so that FP64 iterates agree bit for bit
   // outside the domain: diag 1, everything else 0 (the iterate stays 0)
   double dg[M], ce[M], cw[M], cn[M], cs[M], cr[M];
   int rx[M], ry[M];
@@ -701,10 +701,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a,
     }
   }
   double rdg[M];
-  if constexpr (kFused) {
 #pragma unroll
-    for (int m = 0; m < M; ++m) rdg[m] = 1.0 / dg[m];
-  }
+  for (int m = 0; m < M; ++m) rdg[m] = 1.0 / dg[m];
   __syncthreads();
   double e = 0.0;
   const int iters = nsw > 0 ? nsw : 1;
@@ -718,25 +716,13 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a,
       if (x > t && x < RW - 1 - t && y > t && y < RH - 1 - t) {
         const int idx = (int)threadIdx.x + B * m;
         const double pc = src[idx];
-        double rd, pn;
-        if constexpr (kFused) {
-          double Ap = dg[m] * pc;
-          Ap = fma(ce[m], src[idx + 1], Ap);
-          Ap = fma(cw[m], src[idx - 1], Ap);
-          Ap = fma(cn[m], src[idx + RW], Ap);
-          Ap = fma(cs[m], src[idx - RW], Ap);
-          rd = (cr[m] - Ap) * rdg[m];
-          pn = fma(om, rd, pc);
-        } else {
-          double Ap = dg[m] * pc;
-          Ap += ce[m] * src[idx + 1];
-          Ap += cw[m] * src[idx - 1];
-          Ap += cn[m] * src[idx + RW];
-          Ap += cs[m] * src[idx - RW];
-          const double r = cr[m] - Ap;
-          rd = r / dg[m];
-          pn = pc + om * rd;
-        }
+        double Ap = dg[m] * pc;
+        Ap = fma(ce[m], src[idx + 1], Ap);
+        Ap = fma(cw[m], src[idx - 1], Ap);
+        Ap = fma(cn[m], src[idx + RW], Ap);
+        Ap = fma(cs[m], src[idx - RW], Ap);
+        const double rd = (cr[m] - Ap) * rdg[m];
+        const double pn = fma(om, rd, pc);
         if (t == 0 && check && x >= S && x < S + BX && y >= S && y < S + BY) {
           double ar = fabs(rd);
           e = (ar > e || ar != ar) ? ar : e;
@@ -1058,6 +1044,26 @@ template <typename T>
 __global__ void k_fill(long n, T v, T* __restrict__ a) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = v;
+}
+
+// check of an array handed in as device memory: a non-finite element sets
+// bit nf of *flags, a negative one (when neg != 0) bit neg; one atomic per
+// workgroup
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_check_values(long n, const T* __restrict__ a, int nf, int neg,
+                   int* __restrict__ flags) {
+  const long i = (long)blockIdx.x * kBlock + threadIdx.x;
+  int bad_nf = 0, bad_neg = 0;
+  if (i < n) {
+    const double v = (double)a[i];
+    bad_nf = !isfinite(v);
+    bad_neg = neg != 0 && v < 0.0;
+  }
+  bad_nf = __syncthreads_or(bad_nf);
+  bad_neg = __syncthreads_or(bad_neg);
+  if (threadIdx.x == 0 && (bad_nf || bad_neg))
+    atomicOr(flags, (bad_nf ? nf : 0) | (bad_neg ? neg : 0));
 }
 
 template <typename Tdst, typename Tsrc>

@@ -56,6 +56,11 @@ struct HostSlot {
 // lazily at the next synchronisation, so that timing never stalls the device.
 struct ProfPool {
   bool on = false;
+  // 1: every phase and every back-to-back sweep batch; n >= 2: only the
+  // sweep batch of one cycle in n (each event pair stalls the queue for a
+  // few microseconds, ~13 % of a step when every phase is timed)
+  int sample = 1;
+  long long nbatch = 0;
   struct Mark {
     hipEvent_t a = nullptr, b = nullptr;
     int kind = 0;         // 0 fv, 1 assembly, 2 solve, 3 correction, 4 sweeps
@@ -69,6 +74,7 @@ struct ProfPool {
   // open an interval of the given kind on the stream (or -1)
   long open(hipStream_t st, int kind) {
     if (!on) return -1;
+    if (sample > 1 && (kind != 4 || (nbatch++ % sample) != 0)) return -1;
     if (used == marks.size()) {
       Mark m;
       if (hipEventCreate(&m.a) != hipSuccess) return -1;
@@ -136,6 +142,7 @@ struct nh_solver {
   size_t esize = 8;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  int device = 0;          // HIP device current at nh_create
   long ncell = 0, ncorn = 0;
 
   // device buffers (element type double or float, see esize)
@@ -697,6 +704,93 @@ nh_status check_params(const nh_grid* g, const nh_params* p) {
   return NH_OK;
 }
 
+// with U^n (h, q1, q2, w) in place on the device: p from the host array (or
+// 0), statistics reset, dt from the CFL condition (or the fixed dt)
+nh_status adopt_state(nh_solver* s, const double* p) {
+  s->pcur = 0;
+  if (p) {
+    HIP_TRY(hipMemcpyAsync(s->pa, p, s->ncorn * sizeof(double),
+                           hipMemcpyHostToDevice, s->stream));
+  } else {
+    HIP_TRY(hipMemsetAsync(s->pa, 0, s->ncorn * sizeof(double), s->stream));
+  }
+  HIP_TRY(hipMemsetAsync(s->flags, 0, sizeof(int), s->stream));
+  HIP_TRY(hipMemsetAsync(s->clamped, 0, sizeof(double), s->stream));
+  HIP_TRY(hipMemsetAsync(s->dstats, 0, sizeof(nh::DevStats), s->stream));
+  double dt0 = 0.0;
+  if (s->par.fixed_dt) {
+    dt0 = s->par.dt;
+    HIP_TRY(hipMemcpyAsync(s->dt, &dt0, sizeof(double), hipMemcpyHostToDevice,
+                           s->stream));
+  } else {
+    if (s->fp32)
+      Launch<float>::lambda(s);
+    else
+      Launch<double>::lambda(s);
+    nh::FinalizeArgs fa = finalize_args(s, false);
+    hipLaunchKernelGGL(nh::k_finalize_dt, dim3(1), dim3(nh::kBlock), 0,
+                       s->stream, fa);
+    HIP_TRY(hipMemcpyAsync(&dt0, s->dt, sizeof(double), hipMemcpyDeviceToHost,
+                           s->stream));
+  }
+  int flags = 0;
+  HIP_TRY(hipMemcpyAsync(&flags, s->flags, sizeof(int), hipMemcpyDeviceToHost,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(hipMemsetAsync(s->flags, 0, sizeof(int), s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  std::memset(&s->st, 0, sizeof(s->st));
+  s->st.dt_next = dt0;
+  if (flags & 4) {
+    s->have_state = false;
+    return fail(NH_ESTATE, "no wet cell: the CFL time step is undefined");
+  }
+  s->have_state = true;
+  return NH_OK;
+}
+
+// a view handed to nh_bind_device_buffers: device memory of the solver's
+// device, aligned to the element size, with n elements inside its allocation
+nh_status check_view(const nh_solver* s, const void* p, long n) {
+  if (reinterpret_cast<uintptr_t>(p) % s->esize != 0)
+    return fail(NH_EINVAL, "device view not aligned to the element size");
+  hipPointerAttribute_t at{};
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(NH_EINVAL, "view is not device memory");
+  }
+  if (at.type != hipMemoryTypeDevice || at.device != s->device)
+    return fail(NH_EINVAL, "view is not device memory of the solver's device");
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return fail(NH_EINVAL, "view is not inside a device allocation");
+  }
+  const char* b = static_cast<const char*>(base);
+  const char* q = static_cast<const char*>(p);
+  if (q < b || q + (size_t)n * s->esize > b + size)
+    return fail(NH_EINVAL, "view extends past the end of its allocation");
+  return NH_OK;
+}
+
+// frees a buffer the solver allocated itself (borrowed ones are left alone)
+void release_own(nh_solver* s, void* p) {
+  auto it = std::find(s->allocs.begin(), s->allocs.end(), p);
+  if (it != s->allocs.end()) {
+    (void)hipFree(p);
+    s->allocs.erase(it);
+  }
+}
+
+template <typename T>
+void check_values(nh_solver* s, const void* a, long n, int nf, int neg) {
+  hipLaunchKernelGGL((nh::k_check_values<T>), dim3(nblocks(n)),
+                     dim3(nh::kBlock), 0, s->stream, n,
+                     static_cast<const T*>(a), nf, neg, s->flags);
+}
+
 }  // namespace
 
 extern "C" {
@@ -731,6 +825,11 @@ nh_status nh_create(const nh_grid* grid, const nh_params* params,
       return fail(NH_EDEVICE, "hipStreamCreate failed");
     }
     s->own_stream = true;
+  }
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    if (s->own_stream) hipStreamDestroy(s->stream);
+    delete s;
+    return fail(NH_EDEVICE, "hipGetDevice failed");
   }
   s->ncell = (long)grid->nx * grid->ny;
   s->ncorn = (long)(grid->nx + 1) * (s->one_d ? 1 : grid->ny + 1);
@@ -849,46 +948,74 @@ nh_status nh_set_state(nh_solver* s, const double* h, const double* hu,
   } else {
     HIP_TRY(hipMemsetAsync(s->w, 0, s->ncorn * s->esize, s->stream));
   }
-  s->pcur = 0;
-  if (p) {
-    HIP_TRY(hipMemcpyAsync(s->pa, p, s->ncorn * sizeof(double),
-                           hipMemcpyHostToDevice, s->stream));
-  } else {
-    HIP_TRY(hipMemsetAsync(s->pa, 0, s->ncorn * sizeof(double), s->stream));
+  return adopt_state(s, p);
+}
+
+nh_status nh_bind_device_buffers(nh_solver* s, const nh_device_views* v) {
+  if (!s || !v) return fail(NH_EINVAL, "null argument");
+  const bool state = v->h || v->hu || v->hv || v->w;
+  if (!v->H && !state) return fail(NH_EINVAL, "no view given");
+  if (s->one_d && v->hv) return fail(NH_EINVAL, "hv is not used in 1D");
+  if (state && (!v->h || !v->hu || (!s->one_d && !v->hv)))
+    return fail(NH_EINVAL, "h and hu (and hv in 2D) are bound together");
+  if (state && !v->H && !s->have_H)
+    return fail(NH_ESTATE, "set or bind the bathymetry first");
+  const void* views[5] = {v->H, v->h, v->hu, v->hv, v->w};
+  const long counts[5] = {s->ncell, s->ncell, s->ncell, s->ncell, s->ncorn};
+  for (int i = 0; i < 5; ++i) {
+    if (!views[i]) continue;
+    nh_status st = check_view(s, views[i], counts[i]);
+    if (st != NH_OK) return st;
+    const char* a = static_cast<const char*>(views[i]);
+    for (int j = 0; j < i; ++j) {
+      if (!views[j]) continue;
+      const char* b = static_cast<const char*>(views[j]);
+      if (a < b + counts[j] * s->esize && b < a + counts[i] * s->esize)
+        return fail(NH_EINVAL, "bound views overlap");
+    }
   }
+  // no queued work may still use the buffers about to be replaced, and the
+  // contents are checked before anything is adopted
+  HIP_TRY(hipStreamSynchronize(s->stream));
   HIP_TRY(hipMemsetAsync(s->flags, 0, sizeof(int), s->stream));
-  HIP_TRY(hipMemsetAsync(s->clamped, 0, sizeof(double), s->stream));
-  HIP_TRY(hipMemsetAsync(s->dstats, 0, sizeof(nh::DevStats), s->stream));
-  double dt0 = 0.0;
-  if (s->par.fixed_dt) {
-    dt0 = s->par.dt;
-    HIP_TRY(hipMemcpyAsync(s->dt, &dt0, sizeof(double), hipMemcpyHostToDevice,
-                           s->stream));
-  } else {
+  for (int i = 0; i < 5; ++i) {
+    if (!views[i]) continue;
+    const int neg = i == 1 ? 16 : 0;  // depth >= 0
     if (s->fp32)
-      Launch<float>::lambda(s);
+      check_values<float>(s, views[i], counts[i], 8, neg);
     else
-      Launch<double>::lambda(s);
-    nh::FinalizeArgs fa = finalize_args(s, false);
-    hipLaunchKernelGGL(nh::k_finalize_dt, dim3(1), dim3(nh::kBlock), 0,
-                       s->stream, fa);
-    HIP_TRY(hipMemcpyAsync(&dt0, s->dt, sizeof(double), hipMemcpyDeviceToHost,
-                           s->stream));
+      check_values<double>(s, views[i], counts[i], 8, neg);
   }
   int flags = 0;
   HIP_TRY(hipMemcpyAsync(&flags, s->flags, sizeof(int), hipMemcpyDeviceToHost,
                          s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   HIP_TRY(hipMemsetAsync(s->flags, 0, sizeof(int), s->stream));
-  HIP_TRY(hipStreamSynchronize(s->stream));
-  std::memset(&s->st, 0, sizeof(s->st));
-  s->st.dt_next = dt0;
-  if (flags & 4) {
-    s->have_state = false;
-    return fail(NH_ESTATE, "no wet cell: the CFL time step is undefined");
+  if (flags & 8) return fail(NH_EINVAL, "non-finite values in a bound view");
+  if (flags & 16) return fail(NH_ENEGDEPTH, "negative depth in the bound h");
+  if (v->H) {
+    release_own(s, s->H);
+    s->H = v->H;
+    s->have_H = true;
   }
-  s->have_state = true;
-  return NH_OK;
+  if (!state) return NH_OK;
+  release_own(s, s->h);
+  s->h = v->h;
+  release_own(s, s->q1);
+  s->q1 = v->hu;
+  if (v->hv) {
+    release_own(s, s->q2);
+    s->q2 = v->hv;
+  } else {
+    HIP_TRY(hipMemsetAsync(s->q2, 0, s->ncell * s->esize, s->stream));
+  }
+  if (v->w) {
+    release_own(s, s->w);
+    s->w = v->w;
+  } else {
+    HIP_TRY(hipMemsetAsync(s->w, 0, s->ncorn * s->esize, s->stream));
+  }
+  return adopt_state(s, nullptr);
 }
 
 nh_status nh_step(nh_solver* s, double* dt_used) {
@@ -957,7 +1084,9 @@ nh_status nh_profile(nh_solver* s, int32_t on) {
   if (!s) return fail(NH_EINVAL, "null solver");
   if (s->stream) HIP_TRY(hipStreamSynchronize(s->stream));
   s->prof.flush();
-  s->prof.on = on != 0;
+  s->prof.on = on > 0;
+  s->prof.sample = on > 1 ? on : 1;
+  s->prof.nbatch = 0;
   if (s->prof.on) std::memset(&s->prof.pr, 0, sizeof(s->prof.pr));
   return NH_OK;
 }

@@ -58,6 +58,7 @@ def test_invalid_arguments_are_rejected_without_a_device():
                        ctypes.byref(out)) == -1
     assert b"multiple" in L.nh_last_error()
     assert L.nh_step(None, None) == -1
+    assert L.nh_bind_device_buffers(None, None) == -1
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")

@@ -91,6 +91,9 @@ def test_c2_geometry_fp64_small():
     g, r, gs, os_ = compare(c, 20, TOL64, fields=("h", "hu", "hv", "w", "p"))
     assert gs["sweeps_total"] == os_["sweeps_total"]
     assert gs["t"] == pytest.approx(os_["t"], rel=1e-12)
+    # the FP64 kernels round every operation as the oracle does
+    for k in ("h", "hu", "hv", "w", "p"):
+        assert np.array_equal(g[k], r[k]), k
 
 
 def test_ragged_wet_fp64_several_tiles():
@@ -231,7 +234,9 @@ def _run_vs_golden(prec, steps_check_t_rel):
     for k, scale in (("h", float(ref["max_h"])), ("hu", scale_q),
                      ("hv", scale_q)):
         errs[k] = float(np.abs(g[k][::st, ::st] - ref[k]).max() / scale)
-        say(f"  {k}: max rel diff on the lattice {errs[k]:.3e}")
+        same = np.array_equal(g[k][::st, ::st], ref[k])
+        say(f"  {k}: max rel diff on the lattice {errs[k]:.3e}"
+            f"{' (bitwise equal)' if same else ''}")
     say(f"  mean sweeps per solve: gpu {gs['sweeps_total'] / gs['solves']:.1f}"
         f" oracle {int(ref['sweeps_total']) / int(ref['solves']):.1f}")
     return errs, gs, ref
@@ -366,3 +371,24 @@ def test_c3_full_size_beach_vs_1d_oracle(precision):
     m1 = float(np.sum(g["h"], dtype=np.float64))
     assert abs(m1 - m0 - st["clamped"] / (c.dx * c.dy)) <= 1e-5 * m0
     s.close()
+
+
+def test_profiling_modes_do_not_change_results():
+    # events on the solver's stream (every phase, or the sweep batch of one
+    # relaxation cycle in n) only observe the run
+    c = I.case_c2(n=96)
+    out = {}
+    for mode in (0, 1, 8):
+        s = gpu_solver(c)
+        s.profile(mode)
+        s.run(10)
+        out[mode] = (s.state(), s.get_profile())
+        s.close()
+    for mode in (1, 8):
+        for k in ("h", "hu", "hv", "w", "p"):
+            assert np.array_equal(out[0][0][k], out[mode][0][k]), (mode, k)
+    full, sampled = out[1][1], out[8][1]
+    assert full["fv_ms"] > 0 and full["solve_ms"] > 0
+    assert sampled["fv_ms"] == 0 and sampled["solve_ms"] == 0
+    assert 0 < sampled["sweep_kernel_launches"] < full["sweep_kernel_launches"]
+    assert sampled["sweep_kernel_ms"] > 0
