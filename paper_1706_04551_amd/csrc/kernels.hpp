@@ -221,6 +221,10 @@ __device__ __forceinline__ double block_sum(double v) {
 // finite-volume stage: U* = V - dt (fluctuations + volume terms), eq. (20),
 // (30); positivity clamp and dry discharge.
 // -------------------------------------------------------------------------
+// 2D stages run on tiles of kFvTX x kFvTY cells, one thread per cell
+constexpr int kFvTX = 32, kFvTY = 8;
+static_assert(kFvTX * kFvTY == kBlock, "one thread per tile cell");
+
 template <typename T>
 struct FvArgs {
   int nx, ny;
@@ -229,7 +233,12 @@ struct FvArgs {
   const double* dtp;
   T *oh, *oq1, *oq2;
   double* clamped;
-  __host__ __device__ int nblocks() const { return (nx * ny + kBlock - 1) / kBlock; }
+  __host__ __device__ int tiles_x() const { return (nx + kFvTX - 1) / kFvTX; }
+  // 1D: one thread per cell; 2D: one workgroup per tile
+  __host__ __device__ int nblocks() const {
+    return ny == 1 ? (nx + kBlock - 1) / kBlock
+                   : tiles_x() * ((ny + kFvTY - 1) / kFvTY);
+  }
 };
 
 // loader of mirrored cells from the bulk arrays (walls by mirror images)
@@ -292,33 +301,160 @@ __device__ __forceinline__ void fv_cell(const LD& ld, int i, int j, V dx, V dy,
   }
 }
 
-template <typename T, bool ONE_D>
-__device__ __forceinline__ void fv_body(const FvArgs<T>& a, int bid) {
-  const int n = bid * kBlock + (int)threadIdx.x;
+// positivity clamp (mass added counted) and dry discharge of a stage cell
+template <typename T>
+__device__ __forceinline__ void fv_finish(T& hs, T& qa, T& qb, T dry_eps,
+                                          double dx, double dy,
+                                          double& clamp) {
+  if (hs < T(0)) {
+    clamp = -(double)hs * dx * dy;
+    hs = T(0);
+  }
+  if (hs <= dry_eps) {
+    qa = T(0);
+    qb = T(0);
+  }
+}
+
+// The 2D stage on a tile of kFvTX x kFvTY cells: the primitive values of the
+// tile and of a halo of 2 cells are formed once into LDS; each thread then
+// evaluates the east and north edges of its cell (the tile's first column
+// and row also get their west and south edges), and every edge's
+// fluctuations go to both of its cells.  Each cell sums them with its volume
+// terms exactly as fv_cell does, so the result is the same to the bit, with
+// one evaluation of each edge and of each cell's primitive values instead of
+// two and five.
+template <typename T>
+__device__ __forceinline__ void fv_tile_body(const FvArgs<T>& a, int bid) {
+  constexpr int TX = kFvTX, TY = kFvTY, RX = TX + 4, RY = TY + 4;
+  __shared__ T ph[RY][RX], pu[RY][RX], pv[RY][RX], pe[RY][RX];
+  // fluctuations of x-edge e of a tile row (e: west edge of column e) and of
+  // y-edge e of a tile column; m = to the cell below e, p = to the one above
+  __shared__ T xm[3][TY][TX + 1], xp[3][TY][TX + 1];
+  __shared__ T ym[3][TY + 1][TX], yp[3][TY + 1][TX];
   const int nx = a.nx, ny = a.ny;
-  const T dry_eps = a.dry_eps;
+  const int txs = a.tiles_x();
+  const int i0 = (bid % txs) * TX, j0 = (bid / txs) * TY;
+  const T g = a.g, delta = a.delta, dry_eps = a.dry_eps;
+  for (int r = (int)threadIdx.x; r < RX * RY; r += kBlock) {
+    const int rx = r % RX, ry = r / RX;
+    const int i = i0 - 2 + rx, j = j0 - 2 + ry;
+    T h = T(0), u = T(0), v = T(0), e = T(0);
+    if (i <= nx + 1 && j <= ny + 1) {  // the cells a grid cell's stencil reads
+      const Cell<T> c = load_cell(a.h, a.q1, a.q2, a.H, i, j, nx, ny, false);
+      h = c.h;
+      u = desing(c.h, c.q1, delta);
+      v = desing(c.h, c.q2, delta);
+      e = c.h - c.H;
+    }
+    ph[ry][rx] = h;
+    pu[ry][rx] = u;
+    pv[ry][rx] = v;
+    pe[ry][rx] = e;
+  }
+  __syncthreads();
+  auto px = [&](int rx, int ry) {  // along x: normal u, tangential v
+    Prim<T> p;
+    p.h = ph[ry][rx];
+    p.un = pu[ry][rx];
+    p.ut = pv[ry][rx];
+    p.eta = pe[ry][rx];
+    return p;
+  };
+  auto py = [&](int rx, int ry) {  // along y: normal v, tangential u
+    Prim<T> p;
+    p.h = ph[ry][rx];
+    p.un = pv[ry][rx];
+    p.ut = pu[ry][rx];
+    p.eta = pe[ry][rx];
+    return p;
+  };
+  // edge between region columns c and c + 1 of region row r (x), stored at
+  // tile edge index e of tile row (r - 2)
+  auto x_edge = [&](int c, int r, int e) {
+    Face<T> La, Ra, Lb, Rb;
+    reconstruct(px(c - 1, r), px(c, r), px(c + 1, r), dry_eps, La, Ra);
+    reconstruct(px(c, r), px(c + 1, r), px(c + 2, r), dry_eps, Lb, Rb);
+    T Dm[3], Dp[3];
+    pvm(Ra, Lb, g, dry_eps, Dm, Dp);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      xm[m][r - 2][e] = Dm[m];
+      xp[m][r - 2][e] = Dp[m];
+    }
+  };
+  auto y_edge = [&](int c, int r, int e) {
+    Face<T> La, Ra, Lb, Rb;
+    reconstruct(py(c, r - 1), py(c, r), py(c, r + 1), dry_eps, La, Ra);
+    reconstruct(py(c, r), py(c, r + 1), py(c, r + 2), dry_eps, Lb, Rb);
+    T Dm[3], Dp[3];
+    pvm(Ra, Lb, g, dry_eps, Dm, Dp);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      ym[m][e][c - 2] = Dm[m];
+      yp[m][e][c - 2] = Dp[m];
+    }
+  };
+  const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;
+  const int cx = tx + 2, cy = ty + 2;  // the thread's cell in the region
+  x_edge(cx, cy, tx + 1);              // east edge
+  y_edge(cx, cy, ty + 1);              // north edge
+  if ((int)threadIdx.x < TY)           // west edges of the tile's rows
+    x_edge(1, (int)threadIdx.x + 2, 0);
+  else if ((int)threadIdx.x >= 64 && (int)threadIdx.x < 64 + TX)
+    y_edge((int)threadIdx.x - 64 + 2, 1, 0);  // south edges of its columns
+  // the cell's own reconstructions for its volume terms
+  Face<T> Lx, Rx, Ly, Ry;
+  reconstruct(px(cx - 1, cy), px(cx, cy), px(cx + 1, cy), dry_eps, Lx, Rx);
+  reconstruct(py(cx, cy - 1), py(cx, cy), py(cx, cy + 1), dry_eps, Ly, Ry);
+  __syncthreads();
+  const int i = i0 + tx, j = j0 + ty;
   double clamp_local = 0.0;
-  if (n < nx * ny) {
-    int i = n % nx, j = n / nx;
-    T dt = (T)(*a.dtp);
-    CellLoader<T, ONE_D> ld{a.h, a.q1, a.q2, a.H, nx, ny};
-    T out[3];
-    fv_cell<T, ONE_D>(ld, i, j, a.dx, a.dy, a.g, a.delta, dry_eps, dt, 3, out);
-    T hs = out[0], qa = out[1], qb = out[2];
-    if (hs < T(0)) {
-      clamp_local = -(double)hs * (double)a.dx * (ONE_D ? 1.0 : (double)a.dy);
-      hs = T(0);
+  if (i < nx && j < ny) {
+    const int n = j * nx + i;
+    const T h0 = ph[cy][cx], q10 = a.q1[n], q20 = a.q2[n];
+    const T dt = (T)(*a.dtp);
+    T Ix[3], Iy[3], fx[3], fy[3];
+    interior(Lx, Rx, h0, g, Ix);
+    interior(Ly, Ry, h0, g, Iy);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      fx[m] = (xm[m][ty][tx + 1] + xp[m][ty][tx]) + Ix[m];
+      fy[m] = (ym[m][ty + 1][tx] + yp[m][ty][tx]) + Iy[m];
     }
-    if (hs <= dry_eps) {
-      qa = T(0);
-      qb = T(0);
-    }
+    T hs = h0 - dt * (fx[0] / a.dx + fy[0] / a.dy);
+    T qa = q10 - dt * (fx[1] / a.dx + fy[2] / a.dy);
+    T qb = q20 - dt * (fx[2] / a.dx + fy[1] / a.dy);
+    fv_finish(hs, qa, qb, dry_eps, (double)a.dx, (double)a.dy, clamp_local);
     a.oh[n] = hs;
     a.oq1[n] = qa;
-    if (!ONE_D) a.oq2[n] = qb;
+    a.oq2[n] = qb;
   }
   double s = block_sum(clamp_local);
   if (threadIdx.x == 0 && s > 0.0) atomicAdd(a.clamped, s);
+}
+
+template <typename T, bool ONE_D>
+__device__ __forceinline__ void fv_body(const FvArgs<T>& a, int bid) {
+  if constexpr (!ONE_D) {
+    fv_tile_body<T>(a, bid);
+  } else {
+    const int n = bid * kBlock + (int)threadIdx.x;
+    double clamp_local = 0.0;
+    if (n < a.nx) {
+      T dt = (T)(*a.dtp);
+      CellLoader<T, true> ld{a.h, a.q1, a.q2, a.H, a.nx, 1};
+      T out[3];
+      fv_cell<T, true>(ld, n, 0, a.dx, a.dy, a.g, a.delta, a.dry_eps, dt, 3,
+                       out);
+      T hs = out[0], qa = out[1], qb = out[2];
+      fv_finish(hs, qa, qb, a.dry_eps, (double)a.dx, 1.0, clamp_local);
+      a.oh[n] = hs;
+      a.oq1[n] = qa;
+    }
+    double s = block_sum(clamp_local);
+    if (threadIdx.x == 0 && s > 0.0) atomicAdd(a.clamped, s);
+  }
 }
 
 // -------------------------------------------------------------------------
