@@ -123,6 +123,9 @@ def test_members_match_the_oracle(precision, tol):
         if precision == "f64":
             assert np.abs(g["hv"] - r["hv"]).max() / scale <= tol
             assert abs(e.stats(k)["t"] - o.stats()["t"]) <= 1e-9 * o.stats()["t"]
+            # FP64 members round every operation as the oracle does
+            for f in FIELDS:
+                assert np.array_equal(g[f], r[f]), (k, f)
     e.close()
 
 

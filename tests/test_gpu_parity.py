@@ -239,7 +239,7 @@ def _run_vs_golden(prec, steps_check_t_rel):
             f"{' (bitwise equal)' if same else ''}")
     say(f"  mean sweeps per solve: gpu {gs['sweeps_total'] / gs['solves']:.1f}"
         f" oracle {int(ref['sweeps_total']) / int(ref['solves']):.1f}")
-    return errs, gs, ref
+    return errs, gs, ref, g
 
 
 def test_c2_full_workload_1000_steps_fp64_vs_stored_oracle():
@@ -249,10 +249,16 @@ def test_c2_full_workload_1000_steps_fp64_vs_stored_oracle():
     # oracle's full-field maxima).  The run is sensitive to round-off once the
     # flooding front on the island sets the CFL step, so this holds only
     # because the FP64 kernels repeat the oracle's operations exactly.
-    errs, gs, ref = _run_vs_golden("f64", 1e-9)
+    errs, gs, ref, g = _run_vs_golden("f64", 1e-9)
     assert gs["t"] == pytest.approx(float(ref["t"]), rel=1e-9)
     for k, e in errs.items():
         assert e <= TOL64, (k, e)
+    # and to the bit: the FP64 kernels round every operation as the oracle
+    assert gs["t"] == float(ref["t"])
+    assert gs["sweeps_total"] == int(ref["sweeps_total"])
+    st = int(ref["stride"])
+    for k in ("h", "hu", "hv"):
+        assert np.array_equal(g[k][::st, ::st], ref[k]), k
 
 
 def test_c2_full_workload_1000_steps_fp32_reported():
@@ -263,7 +269,7 @@ def test_c2_full_workload_1000_steps_fp32_reported():
     # full 1000 steps of this workload; the difference is reported and only
     # bounded here.  The FP32 bar is checked on the early steps of this
     # workload and over 1000 steps of the island-free basin.
-    errs, gs, ref = _run_vs_golden("f32", None)
+    errs, gs, ref, _ = _run_vs_golden("f32", None)
     for k, e in errs.items():
         assert np.isfinite(e) and e <= 0.1, (k, e)
 
