@@ -1,0 +1,26 @@
+"""bench.py's command line on a machine without a GPU: more than one GPU is
+refused with a message before anything touches a device."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"),
+                        "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_help_lists_the_modes():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"),
+                        "--help"], capture_output=True, text=True,
+                       timeout=120, cwd=ROOT)
+    assert r.returncode == 0
+    for opt in ("--workload", "--precision", "--steps", "--warmup",
+                "--solve-tol", "--no-variants"):
+        assert opt in r.stdout
