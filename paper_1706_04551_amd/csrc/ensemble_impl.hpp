@@ -22,6 +22,7 @@ struct EnsSlot {
 struct nh_ensemble {
   int n = 0;
   bool fp32 = false;
+  int sweep_m = nh::kSweepM;   // region points per thread of the batched sweep
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int nh_on = 1, breaking_on = 0, kmax = 0, check_every = 1;
@@ -65,20 +66,25 @@ int* slot_active(EnsSlot* s, int n) {
   return reinterpret_cast<int*>(slot_E(s) + n);
 }
 
-// candidate sweep tiles (corners); every region (BX+2S)(BY+2S) fits the
-// workgroup's kSweepB * kSweepM points
+// candidate sweep tiles (corners); a tile fits when its region
+// (BX+2S)(BY+2S) fits the workgroup's kSweepB * sweep_m points.  FP32-bulk
+// ensembles sweep with 3 region points per thread, so that large members
+// can take the larger tiles (FP64 keeps 2: its 3-point kernel loses half
+// its occupancy)
 constexpr int kTiles[][2] = {{24, 24}, {28, 28}, {32, 24}, {40, 16},
-                             {48, 16}, {64, 8},  {16, 16}};
+                             {48, 16}, {64, 8},  {16, 16}, {32, 32},
+                             {36, 28}, {40, 24}};
 
-bool tile_ok(int bx, int by) {
+bool tile_ok(int bx, int by, int points) {
   return bx >= 4 && by >= 4 &&
          (bx + 2 * nh::kSweepS) * (by + 2 * nh::kSweepS) <=
-             nh::kSweepB * nh::kSweepM;
+             nh::kSweepB * points;
 }
 
 // (re)allocate the per-tile measures for the member's tile shape
 nh_status set_member_tile(nh_solver* m, int bx, int by) {
-  if (!tile_ok(bx, by)) return fail(NH_EINVAL, "tile does not fit the workgroup");
+  if (!tile_ok(bx, by, m->sweep_m))
+    return fail(NH_EINVAL, "tile does not fit the workgroup");
   int ntx = (m->grid.nx + 1 + bx - 1) / bx;
   int nty = (m->grid.ny + 1 + by - 1) / by;
   if ((long)ntx * nty > (long)m->ntx * m->nty) {
@@ -222,11 +228,18 @@ void ens_sweeps(nh_ensemble* e, const int* ids, const int* pre, int n,
   if (total <= 0) return;
   nh::SweepLaunch Lc{iin, iout, isave, k0, nsw, check ? 1 : 0,
                      0, nullptr, nullptr, 0};
-  hipLaunchKernelGGL((nh::k_sweep_tb_batch<T, nh::kSweepB, nh::kSweepS,
-                                             nh::kSweepM>),
-                     dim3(total), dim3(nh::kSweepB), e->sweep_lds, e->stream,
-                     (const nh::SweepArgs<T>*)e->sweep, ids, pre, n,
-                     (const nh::EnsMember*)e->dmem_live, Lc);
+  const auto* as = (const nh::SweepArgs<T>*)e->sweep;
+  const auto* mem = (const nh::EnsMember*)e->dmem_live;
+  if (e->sweep_m == nh::kSweepMBig)
+    hipLaunchKernelGGL((nh::k_sweep_tb_batch<T, nh::kSweepB, nh::kSweepS,
+                                               nh::kSweepMBig>),
+                       dim3(total), dim3(nh::kSweepB), e->sweep_lds,
+                       e->stream, as, ids, pre, n, mem, Lc);
+  else
+    hipLaunchKernelGGL((nh::k_sweep_tb_batch<T, nh::kSweepB, nh::kSweepS,
+                                               nh::kSweepM>),
+                       dim3(total), dim3(nh::kSweepB), e->sweep_lds,
+                       e->stream, as, ids, pre, n, mem, Lc);
 }
 
 // Lockstep solve of every live member (the same cycle structure as the
@@ -446,6 +459,7 @@ nh_status nh_ensemble_create(int32_t n, const nh_grid* grids,
   nh_ensemble* e = new nh_ensemble();
   e->n = n;
   e->fp32 = params[0].precision == NH_FP32;
+  e->sweep_m = e->fp32 ? nh::kSweepMBig : nh::kSweepM;
   e->nh_on = params[0].nh_on;
   e->breaking_on = params[0].breaking_on;
   e->kmax = params[0].solve_max_iter;
@@ -469,6 +483,7 @@ nh_status nh_ensemble_create(int32_t n, const nh_grid* grids,
       nh_ensemble_destroy(e);
       return fail(st, "member " + std::to_string(k) + ": " + msg);
     }
+    m->sweep_m = e->sweep_m;  // members are swept by the batched kernel
     e->mem.push_back(m);
   }
   size_t slot_bytes =
@@ -599,7 +614,7 @@ nh_status nh_ensemble_tune(nh_ensemble* e, int32_t reps) {
       for (int i = 1; i < 5; ++i) fill(i, 0.25);
       double best = 1e300;
       for (const auto& t : kTiles) {
-        if (!tile_ok(t[0], t[1])) continue;
+        if (!tile_ok(t[0], t[1], e->sweep_m)) continue;
         int ntx = (m->grid.nx + 1 + t[0] - 1) / t[0];
         int nty = (m->grid.ny + 1 + t[1] - 1) / t[1];
         if ((long)ntx * nty > 8192) continue;  // scratch measures
@@ -634,10 +649,10 @@ nh_status nh_ensemble_tune(nh_ensemble* e, int32_t reps) {
           if (e->fp32) {
             setup(a32);
             hipLaunchKernelGGL((nh::k_sweep_tb<float, nh::kSweepB,
-                                               nh::kSweepS, nh::kSweepM>),
+                                               nh::kSweepS, nh::kSweepMBig>),
                                dim3(a32.nblocks()), dim3(nh::kSweepB),
                                sweep_lds_bytes(t[0], t[1]), e->stream, a32,
-                               Lc);
+                               Lc);  // FP32 ensembles sweep with 3 points
           } else {
             setup(a64);
             hipLaunchKernelGGL((nh::k_sweep_tb<double, nh::kSweepB,

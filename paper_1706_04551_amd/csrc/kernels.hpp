@@ -751,6 +751,7 @@ constexpr int kSweepB = 1024;  // threads per workgroup (16 waves)
 constexpr int kSweepS = 8;     // sweeps per launch (= halo width)
 constexpr int kSweepM = 2;     // region points per thread:
                                // (BX+2S)(BY+2S) <= kSweepB * kSweepM
+constexpr int kSweepMBig = 3;  // large grids and ensembles: bigger tiles
 
 // per-grid arguments of the sweep kernel
 template <typename T>
@@ -806,13 +807,15 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a,
   // the correctly rounded reciprocal of the diagonal, and a fused update --
   // the operation order of the oracle, so that FP64 iterates agree bit for bit
   // outside the domain: diag 1, everything else 0 (the iterate stays 0)
-  double dg[M], ce[M], cw[M], cn[M], cs[M], cr[M];
+  // the row coefficients stay in registers in their storage type and are
+  // widened to FP64 for the update (the same values either way)
+  T dg[M], ce[M], cw[M], cn[M], cs[M], cr[M];
   int rx[M], ry[M];
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     int idx = (int)threadIdx.x + B * m;
-    ce[m] = cw[m] = cn[m] = cs[m] = cr[m] = 0.0;
-    dg[m] = 1.0;
+    ce[m] = cw[m] = cn[m] = cs[m] = cr[m] = T(0);
+    dg[m] = T(1);
     rx[m] = -1;
     ry[m] = -1;
     if (idx < R) {
@@ -826,19 +829,19 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a,
         if (check && rx[m] >= S && rx[m] < S + BX && ry[m] >= S &&
             ry[m] < S + BY)
           psave[g] = pv;
-        dg[m] = (double)dgl[g];
-        ce[m] = (double)cE[g];
-        cw[m] = (double)cW[g];
-        cn[m] = (double)cN[g];
-        cs[m] = (double)cS[g];
-        cr[m] = (double)rhs[g];
+        dg[m] = dgl[g];
+        ce[m] = cE[g];
+        cw[m] = cW[g];
+        cn[m] = cN[g];
+        cs[m] = cS[g];
+        cr[m] = rhs[g];
       }
       P0[idx] = pv;
     }
   }
   double rdg[M];
 #pragma unroll
-  for (int m = 0; m < M; ++m) rdg[m] = 1.0 / dg[m];
+  for (int m = 0; m < M; ++m) rdg[m] = 1.0 / (double)dg[m];
   __syncthreads();
   double e = 0.0;
   const int iters = nsw > 0 ? nsw : 1;
@@ -852,12 +855,22 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a,
       if (x > t && x < RW - 1 - t && y > t && y < RH - 1 - t) {
         const int idx = (int)threadIdx.x + B * m;
         const double pc = src[idx];
-        double Ap = dg[m] * pc;
-        Ap = fma(ce[m], src[idx + 1], Ap);
-        Ap = fma(cw[m], src[idx - 1], Ap);
-        Ap = fma(cn[m], src[idx + RW], Ap);
-        Ap = fma(cs[m], src[idx - RW], Ap);
-        const double rd = (cr[m] - Ap) * rdg[m];
+        T cd = dg[m], c1 = ce[m], c2 = cw[m], c3 = cn[m], c4 = cs[m],
+          c5 = cr[m];
+        if constexpr (sizeof(T) == 4 && M >= 3) {
+          // opaque to loop-invariant code motion: the widening stays here
+          // and the floats, not their FP64 copies, live across the sweeps
+          // (with 3 points per thread this keeps the kernel within 64
+          // registers, i.e. two 1024-thread workgroups per CU)
+          asm volatile("" : "+v"(cd), "+v"(c1), "+v"(c2), "+v"(c3), "+v"(c4),
+                       "+v"(c5));
+        }
+        double Ap = (double)cd * pc;
+        Ap = fma((double)c1, src[idx + 1], Ap);
+        Ap = fma((double)c2, src[idx - 1], Ap);
+        Ap = fma((double)c3, src[idx + RW], Ap);
+        Ap = fma((double)c4, src[idx - RW], Ap);
+        const double rd = ((double)c5 - Ap) * rdg[m];
         const double pn = fma(om, rd, pc);
         if (t == 0 && check && x >= S && x < S + BX && y >= S && y < S + BY) {
           double ar = fabs(rd);

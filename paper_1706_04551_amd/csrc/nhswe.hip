@@ -172,6 +172,7 @@ struct nh_solver {
   int solve_launches_last = 0;
   double* omega_dev = nullptr;
   int tbx = 32, tby = 32, ntx = 1, nty = 1;  // sweep tiles
+  int sweep_m = nh::kSweepM;  // region points per thread of the sweep
   double* clamped = nullptr;
   int* flags = nullptr;
   // host mirrors
@@ -432,11 +433,16 @@ struct Launch {
     nh::SweepLaunch L{iin,        iout, isave, k0, nsw, check ? 1 : 0,
                       reduce_seq > 0 ? 1 : 0, s->E_dev, &s->slot_dev->seq,
                       reduce_seq};
-    hipLaunchKernelGGL((nh::k_sweep_tb<T, nh::kSweepB, nh::kSweepS,
-                                         nh::kSweepM>),
-                       dim3(a.nblocks() + (reduce_seq > 0 ? 1 : 0)),
-                       dim3(nh::kSweepB), sweep_lds_bytes(s->tbx, s->tby),
-                       s->stream, a, L);
+    const dim3 grid(a.nblocks() + (reduce_seq > 0 ? 1 : 0));
+    const size_t lds = sweep_lds_bytes(s->tbx, s->tby);
+    if (s->sweep_m == nh::kSweepMBig)
+      hipLaunchKernelGGL((nh::k_sweep_tb<T, nh::kSweepB, nh::kSweepS,
+                                           nh::kSweepMBig>),
+                         grid, dim3(nh::kSweepB), lds, s->stream, a, L);
+    else
+      hipLaunchKernelGGL((nh::k_sweep_tb<T, nh::kSweepB, nh::kSweepS,
+                                           nh::kSweepM>),
+                         grid, dim3(nh::kSweepB), lds, s->stream, a, L);
   }
 
   static void thomas(nh_solver* s, void* pout) {
@@ -870,14 +876,24 @@ nh_status nh_create(const nh_grid* grid, const nh_params* params,
     nh_destroy(s);
     return fail(NH_EDEVICE, "copy of the relaxation schedule failed");
   }
-  // sweep tiles: 24 x 24 corners with a halo of kSweepS (measured best of
-  // the tile/halo/workgroup shapes tried on gfx950 for 513^2 corners); the
-  // region must fit kSweepB * kSweepM points (checked here, assumed by the
-  // kernel)
+  // sweep tiles: 24 x 24 corners with a halo of kSweepS and 2 region points
+  // per thread (measured best of the tile/halo/workgroup shapes tried on
+  // gfx950 for 513^2 corners); FP32-bulk grids of more than 1024 such tiles
+  // take 32 x 32 tiles with 3 points per thread (fewer halo re-reads; in
+  // FP64 the 3-point kernel needs more than 64 registers and loses half its
+  // occupancy).  The region must fit kSweepB * sweep_m points (checked here,
+  // assumed by the kernel).
   s->tbx = 24;
   s->tby = 24;
+  s->sweep_m = nh::kSweepM;
+  if (!s->one_d && s->fp32 &&
+      (long)((grid->nx + 24) / 24) * ((grid->ny + 24) / 24) > 1024) {
+    s->tbx = 32;
+    s->tby = 32;
+    s->sweep_m = nh::kSweepMBig;
+  }
   if ((s->tbx + 2 * nh::kSweepS) * (s->tby + 2 * nh::kSweepS) >
-      nh::kSweepB * nh::kSweepM) {
+      nh::kSweepB * s->sweep_m) {
     nh_destroy(s);
     return fail(NH_EINVAL, "sweep tile does not fit the workgroup");
   }

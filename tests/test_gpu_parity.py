@@ -398,3 +398,39 @@ def test_profiling_modes_do_not_change_results():
     assert sampled["fv_ms"] == 0 and sampled["solve_ms"] == 0
     assert 0 < sampled["sweep_kernel_launches"] < full["sweep_kernel_launches"]
     assert sampled["sweep_kernel_ms"] > 0
+
+
+def test_large_grid_fp64():
+    # a grid of more than 1024 sweep tiles in FP64: equal to the oracle's
+    # state to the bit
+    c = I.case_c2(n=800)
+    steps = 3
+    say(f"[case] c2 geometry 800x800 FP64, {steps} steps")
+    g, r, gs, os_ = compare(c, steps, TOL64, fields=("h", "hu", "hv", "w", "p"))
+    assert gs["sweeps_total"] == os_["sweeps_total"]
+    for k in ("h", "hu", "hv", "w", "p"):
+        assert np.array_equal(g[k], r[k]), k
+
+
+def test_large_grid_fp32_sweep_configuration():
+    # FP32 bulk on more than 1024 tiles of 24 x 24 corners: the solver sweeps
+    # 32 x 32 tiles with 3 region points per thread.  The per-point
+    # arithmetic is that of every other tile shape, so the state equals the
+    # same case swept on 24 x 24 tiles (an ensemble of one with its tile
+    # set) to the bit, and the oracle within the FP32 bar
+    from paper_1706_04551_amd import Ensemble
+    c = I.case_c2(n=800, precision="f32")
+    steps = 3
+    say(f"[case] c2 geometry 800x800 FP32, {steps} steps, 32x32 vs 24x24 tiles")
+    s = gpu_solver(c)
+    s.run(steps)
+    g = s.state()
+    s.close()
+    e = Ensemble.from_cases([c])
+    e.set_tile(0, 24, 24)
+    e.run(steps)
+    r = e.state(0)
+    e.close()
+    for k in ("h", "hu", "hv", "w", "p"):
+        assert np.array_equal(g[k], r[k]), k
+    compare(c, steps, TOL32, fields=("h", "hu"))
