@@ -249,9 +249,11 @@ nh_status nh_ensemble_set_state(nh_ensemble *e, int32_t member,
                                 const double *h, const double *hu,
                                 const double *hv, const double *w,
                                 const double *p);
-/* Sweep tile of a member, bx x by corners per workgroup, with
- * (bx + 16)(by + 16) <= 2048 and bx, by >= 4.  The tile changes only the
- * speed, never the result.  Default 24 x 24. */
+/* Sweep tile of a member, bx x by corners per workgroup, with bx, by >= 4
+ * and (bx + 16)(by + 16) <= 2048 in an FP64 ensemble, <= 3072 in an FP32
+ * ensemble (3 region points per thread of a 1024-thread workgroup).  The tile
+ * changes only the speed, never the result.  Default: 24 x 24, or 32 x 32 for
+ * an FP32 member of more than 1024 such tiles. */
 nh_status nh_ensemble_set_tile(nh_ensemble *e, int32_t member, int32_t bx,
                                int32_t by);
 nh_status nh_ensemble_get_tile(const nh_ensemble *e, int32_t member,
