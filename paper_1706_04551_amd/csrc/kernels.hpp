@@ -205,7 +205,7 @@ __device__ __forceinline__ void block_max_to(double v,
 }
 
 __device__ __forceinline__ double block_sum(double v) {
-  __shared__ double part[kBlock / 64];
+  __shared__ double part[1024 / 64];  // any workgroup size
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
