@@ -1,13 +1,15 @@
 // adjoint.hpp -- device code of the adjoint (reverse) time step.
 //
 // The adjoint of one projection-correction stage is assembled from local
-// transposed Jacobian products.  Each local Jacobian is evaluated exactly by
-// running the forward formulas of kernels.hpp (fv_cell, assemble_row,
+// transposed Jacobian products.  The flux and correction Jacobians are
+// evaluated exactly by running the forward formulas of kernels.hpp (fv_cell,
 // correct_cell, correct_corner) on forward-mode dual numbers, seeded at one
 // input; every branch (limiter, HLL speeds, wet/dry tests, clamps) takes the
-// decision of the forward values.  The products are gathered: one thread per
-// input cell or corner visits every output that reads it, so no two threads
-// add into the same place and the result does not depend on scheduling.
+// decision of the forward values.  The pressure rows, polynomials without
+// branches, are differentiated in reverse by hand (k_adj_row_bars).  The
+// products are gathered: one thread per input cell or corner visits every
+// output that reads it, so no two threads add into the same place and the
+// result does not depend on scheduling.
 //
 // Pressure: the stage solves A(U) p = rhs(U).  With A^T mu = pbar (pbar the
 // adjoint of p), the adjoint of U gains mu^T d(rhs - A p)/dU at fixed p.
@@ -169,13 +171,224 @@ struct AdjGeom {
 //   f_i = Dm(i | i+1) + Dp(i-1 | i) + I_i,   out_i = U_i - dt f_i / dx + ...,
 // with the edge fluctuations (eq. 18-19) of the reconstructed states of the
 // two cells beside the edge (eq. 21) and the volume term I_i (eq. 22, 30).
-// Per input cell j the pass slides along j's line over the cells j-2..j+2:
-// their reconstructions, the 4 edges that read j and the 3 volume terms that
-// read j, each once, on 4-direction dual numbers (dh, dq1, dq2, dH of j), and
-//   lh_j += sum over those pieces of d(piece)/d(j) * (-dt/dx) * lambda(out),
-// likewise q1, q2, H; the x pass adds j's own identity term.  hs_out (the
-// stored h*) gives the forward's clamp and dry decisions.
+// Reverse mode, gathered: the thread of input cell j slides along j's line
+// over the edges and volume terms whose reconstructions read j, and carries
+// the adjoint weights of their output cells back through them (the forward
+// values, hence every branch, are those of the forward formulas):
+//   edge and volume term -> cotangents of the two faces of each cell,
+//   faces -> primitive values (h, un, ut, eta) of the 3 cells of the
+//   reconstruction, primitives -> (h, q1, q2, H) of j.
+// Next to a wall the mirrored ghost positions of j are carried too (their
+// normal discharge is -q of j).  The x pass adds j's own identity term;
+// hs_out (the stored h*) gives the forward's clamp and dry decisions.
+// Derivative conventions: sqrt' = 0 at 0, |x|' = 1 at 0.
 // ---------------------------------------------------------------------------
+template <typename V>
+struct FaceBar {
+  V h, qn, qt, un, ut, eta;
+};
+
+template <typename V>
+__device__ __forceinline__ void zero(FaceBar<V>& b) {
+  b.h = b.qn = b.qt = b.un = b.ut = b.eta = V(0);
+}
+
+// cotangent of the primitive values of one cell
+template <typename V>
+struct PrimBar {
+  V h, un, ut, eta;
+};
+
+template <typename V>
+__device__ __forceinline__ V dsqrt(V r) {  // d sqrt(x)/dx at sqrt(x) = r
+  return r > V(0) ? V(0.5) / r : V(0);
+}
+
+template <typename V>
+__device__ __forceinline__ V dabs(V x) {
+  return x < V(0) ? V(-1) : V(1);
+}
+
+// adds wL . d Dm + wR . d Dp (eq. 18-19, the forward pvm) to the faces'
+// cotangents
+template <typename T>
+__device__ __forceinline__ void pvm_rev(const Face<T>& L, const Face<T>& R,
+                                        T g, T dry_eps, const T wL[3],
+                                        const T wR[3], FaceBar<T>& bL,
+                                        FaceBar<T>& bR) {
+  if (L.h <= dry_eps && R.h <= dry_eps) return;
+  const T he = T(0.5) * (L.h + R.h);
+  const T sL = sqrt(L.h), sR = sqrt(R.h);
+  const T den = sL + sR;
+  const T ue = (L.un * sL + R.un * sR) / den;
+  const T ce = sqrt(g * he);
+  const T cL = sqrt(g * L.h), cR = sqrt(g * R.h);
+  const T SLa = ue - ce, SLb = L.un - cL;
+  const T SRa = ue + ce, SRb = R.un + cR;
+  const bool slA = SLa < SLb, srA = SRa > SRb;  // tmin, tmax picks
+  const T SL = slA ? SLa : SLb, SR = srA ? SRa : SRb;
+  if (!(SR - SL > T(0))) return;
+  const T D = SR - SL;
+  const T aSL = fabs(SL), aSR = fabs(SR);
+  const T a0 = (SR * aSL - SL * aSR) / D;
+  const T a1 = (aSR - aSL) / D;
+  T deta = R.eta - L.eta;
+  bool eta_on = true;
+  if (R.h <= dry_eps && L.eta < -R.H) eta_on = false;
+  if (L.h <= dry_eps && R.eta < -L.H) eta_on = false;
+  if (!eta_on) deta = T(0);
+  T Rv[3], dU[3];
+  Rv[0] = R.qn - L.qn;
+  Rv[1] = (R.qn * R.un - L.qn * L.un) + g * he * deta;
+  Rv[2] = R.qn * R.ut - L.qn * L.ut;
+  dU[0] = deta;
+  dU[1] = R.qn - L.qn;
+  dU[2] = R.qt - L.qt;
+  // S = sum_m Dm_m wL_m + Dp_m wR_m
+  //   = 1/2 sum_m Rv_m (wL + wR)_m + a1 Rv_m (wR - wL)_m + a0 dU_m (wR - wL)_m
+  T Rvb[3], dUb[3], a0b = T(0), a1b = T(0);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const T sw = wL[m] + wR[m], dw = wR[m] - wL[m];
+    Rvb[m] = T(0.5) * (sw + a1 * dw);
+    dUb[m] = T(0.5) * a0 * dw;
+    a1b = a1b + T(0.5) * Rv[m] * dw;
+    a0b = a0b + T(0.5) * dU[m] * dw;
+  }
+  T heb = Rvb[1] * g * deta, detab = Rvb[1] * g * he + dUb[0];
+  bR.qn = bR.qn + Rvb[0] + Rvb[1] * R.un + Rvb[2] * R.ut + dUb[1];
+  bL.qn = bL.qn - Rvb[0] - Rvb[1] * L.un - Rvb[2] * L.ut - dUb[1];
+  bR.un = bR.un + Rvb[1] * R.qn;
+  bL.un = bL.un - Rvb[1] * L.qn;
+  bR.ut = bR.ut + Rvb[2] * R.qn;
+  bL.ut = bL.ut - Rvb[2] * L.qn;
+  bR.qt = bR.qt + dUb[2];
+  bL.qt = bL.qt - dUb[2];
+  if (eta_on) {
+    bR.eta = bR.eta + detab;
+    bL.eta = bL.eta - detab;
+  }
+  // a0, a1 of the speeds
+  const T gL = dabs(SL), gR = dabs(SR);
+  const T SRbar = (a0b * (aSL - SL * gR - a0) + a1b * (gR - a1)) / D;
+  const T SLbar = (a0b * (SR * gL - aSR + a0) + a1b * (a1 - gL)) / D;
+  T ueb = T(0), ceb = T(0);
+  if (slA) {
+    ueb = ueb + SLbar;
+    ceb = ceb - SLbar;
+  } else {
+    bL.un = bL.un + SLbar;
+    bL.h = bL.h - SLbar * g * dsqrt(cL);
+  }
+  if (srA) {
+    ueb = ueb + SRbar;
+    ceb = ceb + SRbar;
+  } else {
+    bR.un = bR.un + SRbar;
+    bR.h = bR.h + SRbar * g * dsqrt(cR);
+  }
+  heb = heb + ceb * g * dsqrt(ce);
+  bL.un = bL.un + ueb * sL / den;
+  bR.un = bR.un + ueb * sR / den;
+  bL.h = bL.h + ueb * (L.un - ue) / den * dsqrt(sL) + T(0.5) * heb;
+  bR.h = bR.h + ueb * (R.un - ue) / den * dsqrt(sR) + T(0.5) * heb;
+}
+
+// adds w . d I (the forward interior) to the faces' cotangents and to h0's
+template <typename T>
+__device__ __forceinline__ void interior_rev(const Face<T>& L,
+                                             const Face<T>& R, T h0, T g,
+                                             const T w[3], FaceBar<T>& bL,
+                                             FaceBar<T>& bR, T& h0b) {
+  bR.qn = bR.qn + w[0] + w[1] * R.un + w[2] * R.ut;
+  bL.qn = bL.qn - w[0] - w[1] * L.un - w[2] * L.ut;
+  bR.un = bR.un + w[1] * R.qn;
+  bL.un = bL.un - w[1] * L.qn;
+  bR.ut = bR.ut + w[2] * R.qn;
+  bL.ut = bL.ut - w[2] * L.qn;
+  h0b = h0b + w[1] * g * (R.eta - L.eta);
+  bR.eta = bR.eta + w[1] * g * h0;
+  bL.eta = bL.eta - w[1] * g * h0;
+}
+
+// which argument the forward minmod returned: 1 = a, 2 = b, 0 = neither
+template <typename T>
+__device__ __forceinline__ int minmod_pick(T a, T b) {
+  if (a > T(0) && b > T(0)) return a < b ? 1 : 2;
+  if (a < T(0) && b < T(0)) return a > b ? 1 : 2;
+  return 0;
+}
+
+// reverse of reconstruct(m, c, p): face cotangents -> the cotangents of the
+// primitive values of m, c, p (added)
+template <typename T>
+__device__ __forceinline__ void reconstruct_rev(
+    const Prim<T>& m, const Prim<T>& c, const Prim<T>& p, T dry_eps,
+    const Face<T>& L, const Face<T>& R, FaceBar<T> bL, FaceBar<T> bR,
+    PrimBar<T>& bm, PrimBar<T>& bc, PrimBar<T>& bp) {
+  // qn = h un, qt = h ut on each face
+  bR.h = bR.h + bR.qn * R.un + bR.qt * R.ut;
+  bR.un = bR.un + bR.qn * R.h;
+  bR.ut = bR.ut + bR.qt * R.h;
+  bL.h = bL.h + bL.qn * L.un + bL.qt * L.ut;
+  bL.un = bL.un + bL.qn * L.h;
+  bL.ut = bL.ut + bL.qt * L.h;
+  // R = c + s/2, L = c - s/2 for each of h, eta, un, ut
+  bc.h = bc.h + bR.h + bL.h;
+  bc.eta = bc.eta + bR.eta + bL.eta;
+  bc.un = bc.un + bR.un + bL.un;
+  bc.ut = bc.ut + bR.ut + bL.ut;
+  // slope = p - c (pick 1) or c - m (pick 2) or 0
+  auto slope = [&](T sb, T pv, T cv, T mv, T& pb, T& cb, T& mb) {
+    const int k = minmod_pick(pv - cv, cv - mv);
+    pb = pb + (k == 1 ? sb : T(0));
+    cb = cb + (k == 1 ? -sb : (k == 2 ? sb : T(0)));
+    mb = mb + (k == 2 ? -sb : T(0));
+  };
+  slope(T(0.5) * (bR.h - bL.h), p.h, c.h, m.h, bp.h, bc.h, bm.h);
+  if (m.h > dry_eps && c.h > dry_eps && p.h > dry_eps) {
+    slope(T(0.5) * (bR.eta - bL.eta), p.eta, c.eta, m.eta, bp.eta, bc.eta,
+          bm.eta);
+    slope(T(0.5) * (bR.un - bL.un), p.un, c.un, m.un, bp.un, bc.un, bm.un);
+    slope(T(0.5) * (bR.ut - bL.ut), p.ut, c.ut, m.ut, bp.ut, bc.ut, bm.ut);
+  }
+}
+
+// partial derivatives of desing(h, q) (the forward formula's branch)
+template <typename T>
+__device__ __forceinline__ void desing_partials(T h, T q, T delta, T& dh,
+                                                T& dq) {
+  const T h4 = h * h * h * h;
+  const T d4 = delta * delta * delta * delta;
+  const bool big = h4 > d4;
+  const T D4 = h4 + (big ? h4 : d4);
+  const T s = sqrt(D4);
+  const T f = sqrt(T(2)) * h * q / s;
+  const T dD4 = (big ? T(8) : T(4)) * h * h * h;
+  dq = sqrt(T(2)) * h / s;
+  dh = sqrt(T(2)) * q / s - T(0.5) * f * dD4 / D4;
+}
+
+template <typename T>
+__device__ __forceinline__ void add_bar(PrimBar<T>& t, const PrimBar<T>& b) {
+  t.h = t.h + b.h;
+  t.un = t.un + b.un;
+  t.ut = t.ut + b.ut;
+  t.eta = t.eta + b.eta;
+}
+
+// adds b to the accumulators of the line positions it belongs to: j itself
+// (b0) and its mirrored ghosts gl, gh (bl, bh; equal to j0 when absent)
+template <typename T>
+__device__ __forceinline__ void to_positions(int pos, const PrimBar<T>& b,
+                                             int j0, int gl, int gh,
+                                             PrimBar<T>& b0, PrimBar<T>& bl,
+                                             PrimBar<T>& bh) {
+  if (pos == j0) add_bar(b0, b);
+  if (gl != j0 && pos == gl) add_bar(bl, b);
+  if (gh != j0 && pos == gh) add_bar(bh, b);
+}
+
 template <typename T, int DIR>
 __global__ void __launch_bounds__(kBlock)
     k_adj_fv(AdjGeom G, const T* __restrict__ h, const T* __restrict__ q1,
@@ -184,83 +397,110 @@ __global__ void __launch_bounds__(kBlock)
              const T* __restrict__ lq1s, const T* __restrict__ lq2s,
              T* __restrict__ lh, T* __restrict__ lq1, T* __restrict__ lq2,
              T* __restrict__ lH) {
-  using D = Dual<T, 4>;
   constexpr bool XD = DIR == 1;
   const int nx = G.nx, ny = G.ny;
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= nx * ny) return;
   const int jx = n % nx, jy = n / nx;
   const int len = XD ? nx : ny, j0 = XD ? jx : jy;
-  const T dry_eps = (T)G.dry_eps;
-  const D g(G.g), delta(G.delta), de(G.dry_eps);
+  const T dry_eps = (T)G.dry_eps, g = (T)G.g, delta = (T)G.delta;
   const T dt = (T)(*G.dtp);
-  const E fac = -(E)dt / (E)(XD ? (T)G.dx : (T)G.dy);
-  SeedLoader<T, 4, T> ld{h, q1, q2, H, nx, ny, n, 0, 1, 2, 3};
+  const T fac = -dt / (XD ? (T)G.dx : (T)G.dy);
+  // positions beyond one reflection (reached only on lines of 2 or 3 cells)
+  // feed no cotangent; they are clamped to stay inside the grid
   auto prim_at = [&](int c) {
-    return prim(XD ? ld(c, jy) : ld(jx, c), XD, delta, false);
+    c = min(max(c, -len), 2 * len - 1);
+    return prim(XD ? load_cell(h, q1, q2, H, c, jy, nx, ny, false)
+                   : load_cell(h, q1, q2, H, jx, c, nx, ny, false),
+                XD, delta, false);
   };
   // adjoint weights of the direction's flux components (h, normal, tangent)
-  // of cell c along the line
-  auto weights = [&](int c, E w[3]) {
+  // of cell c along the line; zero outside the grid
+  auto weights = [&](int c, T w[3]) {
+    w[0] = w[1] = w[2] = T(0);
+    if (c < 0 || c >= len) return;
     const int m = XD ? jy * nx + c : c * nx + jx;
     const T hv = hs_out[m];
-    const E wh = hv > T(0) ? (E)lhs[m] : 0.0;
     const bool wet = hv > dry_eps;
-    const E w1 = wet ? (E)lq1s[m] : 0.0, w2 = wet ? (E)lq2s[m] : 0.0;
-    w[0] = fac * wh;
-    w[1] = fac * (XD ? w1 : w2);
-    w[2] = fac * (XD ? w2 : w1);
+    w[0] = hv > T(0) ? fac * lhs[m] : T(0);
+    const T w1 = wet ? fac * lq1s[m] : T(0), w2 = wet ? fac * lq2s[m] : T(0);
+    w[1] = XD ? w1 : w2;
+    w[2] = XD ? w2 : w1;
   };
-  E acc[4] = {0.0, 0.0, 0.0, 0.0};
-  auto add = [&](const D f[3], const E w[3]) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      acc[k] = acc[k] + ((E)f[0].d[k] * w[0] + (E)f[1].d[k] * w[1] +
-                         (E)f[2].d[k] * w[2]);
-  };
+  // positions whose primitive values are j's: j itself and the ghosts
+  // mirrored onto it (-1 - j at the low wall, 2 len - 1 - j at the high one)
+  const int gl = j0 <= 1 ? -1 - j0 : j0;
+  const int gh = j0 >= len - 2 ? 2 * len - 1 - j0 : j0;
+  const int lo = max(min(gl, j0) - 1, -1), hi = min(max(gh, j0) + 1, len);
+  PrimBar<T> b0{T(0), T(0), T(0), T(0)}, bl = b0, bh = b0;
+  Prim<T> Pm2 = prim_at(lo - 3), Pm = prim_at(lo - 2), P0 = prim_at(lo - 1);
+  Face<T> Lprev, Rprev;
+  FaceBar<T> bLprev, bRprev;
+  zero(bLprev);
+  zero(bRprev);
+  T h0bprev = T(0);
+#pragma unroll 1
+  for (int c = lo - 1; c <= hi + 1; ++c) {
+    const Prim<T> Pp = prim_at(c + 1);
+    Face<T> Lc, Rc;
+    reconstruct(Pm, P0, Pp, dry_eps, Lc, Rc);
+    FaceBar<T> bLc, bRc;
+    zero(bLc);
+    zero(bRc);
+    T h0b = T(0);
+    if (c >= lo && c >= 0 && c <= len) {  // edge (c-1 | c)
+      T wl[3], wr[3];
+      weights(c - 1, wl);
+      weights(c, wr);
+      pvm_rev(Rprev, Lc, g, dry_eps, wl, wr, bRprev, bLc);
+    }
+    if (c >= lo && c <= hi && c >= 0 && c < len) {  // volume term of c
+      T w[3];
+      weights(c, w);
+      interior_rev(Lc, Rc, P0.h, g, w, bLc, bRc, h0b);
+    }
+    if (c - 1 >= lo && c - 1 <= hi) {  // reconstruction of c-1 is complete
+      PrimBar<T> bm{T(0), T(0), T(0), T(0)}, bc = bm, bp = bm;
+      bc.h = h0bprev;
+      reconstruct_rev(Pm2, Pm, P0, dry_eps, Lprev, Rprev, bLprev, bRprev, bm,
+                      bc, bp);
+      to_positions(c - 2, bm, j0, gl, gh, b0, bl, bh);
+      to_positions(c - 1, bc, j0, gl, gh, b0, bl, bh);
+      to_positions(c, bp, j0, gl, gh, b0, bl, bh);
+    }
+    Pm2 = Pm;
+    Pm = P0;
+    P0 = Pp;
+    Lprev = Lc;
+    Rprev = Rc;
+    bLprev = bLc;
+    bRprev = bRc;
+    h0bprev = h0b;
+  }
+  // a ghost's normal velocity is desing(h, -qn) = -desing(h, qn)
+  PrimBar<T> b = b0;
+  bl.un = -bl.un;
+  bh.un = -bh.un;
+  if (gl != j0) add_bar(b, bl);
+  if (gh != j0) add_bar(b, bh);
+  // primitives of j: un = desing(h, qn), ut = desing(h, qt), eta = h - H
+  const T hj = h[n], qn = XD ? q1[n] : q2[n], qt = XD ? q2[n] : q1[n];
+  T dhn, dqn, dht, dqt;
+  desing_partials(hj, qn, delta, dhn, dqn);
+  desing_partials(hj, qt, delta, dht, dqt);
+  E ah = (E)b.h + (E)b.eta + (E)(dhn * b.un) + (E)(dht * b.ut);
+  E an = (E)(dqn * b.un), at = (E)(dqt * b.ut);
   if (XD) {  // d out_j / d U_j contains the identity once
     const T hv = hs_out[n];
     const bool wet = hv > dry_eps;
-    acc[0] = hv > T(0) ? (E)lhs[n] : 0.0;
-    acc[1] = wet ? (E)lq1s[n] : 0.0;
-    acc[2] = wet ? (E)lq2s[n] : 0.0;
+    ah = ah + (hv > T(0) ? (E)lhs[n] : 0.0);
+    an = an + (wet ? (E)lq1s[n] : 0.0);
+    at = at + (wet ? (E)lq2s[n] : 0.0);
   }
-  Prim<D> Pm = prim_at(j0 - 3), P0 = prim_at(j0 - 2);
-  Face<D> Rprev;
-#pragma unroll 1
-  for (int c = j0 - 2; c <= j0 + 2; ++c) {
-    const Prim<D> Pp = prim_at(c + 1);
-    Face<D> Lc, Rc;
-    reconstruct(Pm, P0, Pp, de, Lc, Rc);
-    const bool in_prev = c - 1 >= 0 && c - 1 < len, in_c = c >= 0 && c < len;
-    if (c > j0 - 2 && (in_prev || in_c)) {  // edge (c-1 | c)
-      D Dm[3], Dp[3];
-      pvm(Rprev, Lc, g, de, Dm, Dp);
-      E w[3];
-      if (in_prev) {
-        weights(c - 1, w);
-        add(Dm, w);
-      }
-      if (in_c) {
-        weights(c, w);
-        add(Dp, w);
-      }
-    }
-    if (c >= j0 - 1 && c <= j0 + 1 && in_c) {  // volume term of cell c
-      D I[3];
-      interior(Lc, Rc, P0.h, g, I);
-      E w[3];
-      weights(c, w);
-      add(I, w);
-    }
-    Rprev = Rc;
-    Pm = P0;
-    P0 = Pp;
-  }
-  lh[n] = (T)((E)lh[n] + acc[0]);
-  lq1[n] = (T)((E)lq1[n] + acc[1]);
-  lq2[n] = (T)((E)lq2[n] + acc[2]);
-  lH[n] = (T)((E)lH[n] + acc[3]);
+  lh[n] = (T)((E)lh[n] + ah);
+  lq1[n] = (T)((E)lq1[n] + (XD ? an : at));
+  lq2[n] = (T)((E)lq2[n] + (XD ? at : an));
+  lH[n] = (T)((E)lH[n] - (E)b.eta);
 }
 
 // ---------------------------------------------------------------------------
@@ -348,79 +588,200 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ---------------------------------------------------------------------------
-// pressure system.  R_c(U) = rhs_c - (A p)_c at fixed p.  Per cell j:
-//   lhs_j += sum_c mu_c dR_c/dh*_j over the 12 corners whose row reads j,
-// likewise q1*, q2*, H; per corner: lw_c += mu_c dR_c/dw*_c.
+// pressure system.  R_c(U) = rhs_c - (A p)_c at fixed p; the adjoint of U
+// gains sum_c mu_c dR_c/dU.  Every row is a polynomial in the cells it reads
+// (closed-form 5-point coefficients, eq. 43 in 2D), so it is differentiated
+// in reverse: one pass per corner carries mu_c back to the 15 pair averages
+// of the row (kRowBars, below), and one pass per cell gathers them.
+//   corner pass: hc = (h_SW + h_SE + h_NW + h_NE)/4; hE, hW, hN, hS and
+//     XE, XW, YN, YS the side averages of h and of the central zeta
+//     differences X, Y (zeta = h - 2H); sx, sy the zeta differences across
+//     the corner; q1E, q1W, q2N, q2S the side averages of the discharges.
+//   cell pass: cell j sits at one of the 4 positions of each corner around
+//     it, and the X, Y of its neighbours read its zeta; at the walls the
+//     mirrored ghost positions fold onto j (discharge sign flipped across).
+// dR_c/dw_c goes straight to lw_c in the corner pass.
 // ---------------------------------------------------------------------------
-template <typename V>
-__device__ __forceinline__ V row_residual(const V row[6], const double* p,
-                                          int k, int l, int nx, int ny) {
-  const int ncx = nx + 1, c = l * ncx + k;
-  V Ap = row[0] * V(p[c]);
-  if (k < nx) Ap = Ap + row[1] * V(p[c + 1]);
-  if (k > 0) Ap = Ap + row[2] * V(p[c - 1]);
-  if (l < ny) Ap = Ap + row[3] * V(p[c + ncx]);
-  if (l > 0) Ap = Ap + row[4] * V(p[c - ncx]);
-  return row[5] - Ap;
-}
+enum RowBar {
+  kBhc, kBhE, kBhW, kBhN, kBhS, kBXE, kBXW, kBYN, kBYS, kBsx, kBsy,
+  kBq1E, kBq1W, kBq2N, kBq2S, kRowBars
+};
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-    k_adj_assemble(AdjGeom G, const T* __restrict__ hs,
+    k_adj_row_bars(AdjGeom G, const T* __restrict__ hs,
                    const T* __restrict__ q1s, const T* __restrict__ q2s,
                    const T* __restrict__ H, const T* __restrict__ ws,
                    const double* __restrict__ p, const double* __restrict__ mu,
-                   T* __restrict__ lhs, T* __restrict__ lq1s,
-                   T* __restrict__ lq2s, T* __restrict__ lH) {
-  using D = Dual<T, 4>;
+                   double* __restrict__ rb, T* __restrict__ lw) {
   const int nx = G.nx, ny = G.ny, ncx = nx + 1;
-  const int n = blockIdx.x * kBlock + threadIdx.x;
-  if (n >= nx * ny) return;
-  const int jx = n % nx, jy = n / nx;
-  const D dx(G.dx), dy(G.dy), dt(*G.dtp);
-  SeedLoader<T, 4, T> ld{hs, q1s, q2s, H, nx, ny, n, 0, 1, 2, 3};
-  // corners (k, l) whose row reads cell (jx, jy): k in [jx-1, jx+2] on the
-  // rows l = jy, jy+1, and k in [jx, jx+1] on the rows l = jy-1, jy+2
-  const int ok[12] = {-1, 0, 1, 2, -1, 0, 1, 2, 0, 1, 0, 1};
-  const int ol[12] = {0, 0, 0, 0, 1, 1, 1, 1, -1, -1, 2, 2};
-  E acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int o = 0; o < 12; ++o) {
-    const int k = jx + ok[o], l = jy + ol[o];
-    if (k < 0 || k > nx || l < 0 || l > ny) continue;
-    const int c = l * ncx + k;
-    D row[6];
-    assemble_row<D>(ld, k, l, nx, ny, dx, dy, D(ws[c]), dt, row);
-    D R = row_residual<D>(row, p, k, l, nx, ny);
-    const E m = mu[c];
+  const long ncorn = (long)ncx * (ny + 1);
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= ncorn) return;
+  const int k = c % ncx, l = c / ncx;
+  auto zeta = [&](int i, int j) {
+    const int m = mirror(j, ny) * nx + mirror(i, nx);
+    return (E)hs[m] - E(2) * (E)H[m];
+  };
+  // SW, SE, NW, NE cells of the corner (mirrored; discharges flip sign
+  // across the wall they are mirrored over)
+  E hh[4], zz[4], XX[4], YY[4], a1[4], a2[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = acc[q] + (E)R.d[q] * m;
+  for (int s = 0; s < 4; ++s) {
+    const int i = k - 1 + (s & 1), j = l - 1 + (s >> 1);
+    const int mi = mirror(i, nx), mj = mirror(j, ny), m = mj * nx + mi;
+    hh[s] = (E)hs[m];
+    zz[s] = hh[s] - E(2) * (E)H[m];
+    a1[s] = mi != i ? -(E)q1s[m] : (E)q1s[m];
+    a2[s] = mj != j ? -(E)q2s[m] : (E)q2s[m];
+    XX[s] = (zeta(i + 1, j) - zeta(i - 1, j)) / E(2);
+    YY[s] = (zeta(i, j + 1) - zeta(i, j - 1)) / E(2);
   }
-  lhs[n] = (T)((E)lhs[n] + acc[0]);
-  lq1s[n] = (T)((E)lq1s[n] + acc[1]);
-  lq2s[n] = (T)((E)lq2s[n] + acc[2]);
-  lH[n] = (T)((E)lH[n] + acc[3]);
+  const int SW = 0, SE = 1, NW = 2, NE = 3;
+  const E hc = E(0.25) * (hh[SW] + hh[SE] + hh[NW] + hh[NE]);
+  const E hE = E(0.5) * (hh[SE] + hh[NE]), hW = E(0.5) * (hh[SW] + hh[NW]);
+  const E hN = E(0.5) * (hh[NW] + hh[NE]), hS = E(0.5) * (hh[SW] + hh[SE]);
+  const E XE = E(0.5) * (XX[SE] + XX[NE]), XW = E(0.5) * (XX[SW] + XX[NW]);
+  const E YN = E(0.5) * (YY[NW] + YY[NE]), YS = E(0.5) * (YY[SW] + YY[SE]);
+  const E sx = E(0.5) * (zz[SE] + zz[NE]) - E(0.5) * (zz[SW] + zz[NW]);
+  const E sy = E(0.5) * (zz[NW] + zz[NE]) - E(0.5) * (zz[SW] + zz[SE]);
+  const E q1E = E(0.5) * (a1[SE] + a1[NE]), q1W = E(0.5) * (a1[SW] + a1[NW]);
+  const E q2N = E(0.5) * (a2[NW] + a2[NE]), q2S = E(0.5) * (a2[SW] + a2[SE]);
+  const E dx = G.dx, dy = G.dy, dx2 = dx * dx, dy2 = dy * dy;
+  const E Ap = E(2) * hc + sx, Am = E(2) * hc - sx;  // x factors of the row
+  const E Bp = E(2) * hc + sy, Bm = E(2) * hc - sy;  // y factors
+  // neighbour pressures the folded row multiplies: at a wall the outward
+  // coefficient is added to the inward one
+  const E p0 = p[c];
+  const E PE = k < nx ? p[c + 1] : p[c - 1], PW = k > 0 ? p[c - 1] : p[c + 1];
+  const E PN = l < ny ? p[c + ncx] : p[c - ncx];
+  const E PS = l > 0 ? p[c - ncx] : p[c + ncx];
+  // R = rhs - (d p0 + e PE + w PW + n PN + s PS), rhs = -(4/dt) Bs
+  const E m = mu[c];
+  const E db = -m * p0, eb = -m * PE, wb = -m * PW, nb = -m * PN,
+          sb = -m * PS;
+  const E Bsb = -(E(4) / *G.dtp) * m;
+  const E Apb = (db * (XW + E(2) * hW) + wb * (XW - E(2) * hW)) / dx2 -
+                Bsb * q1W / dx;
+  const E Amb = -(db * (XE - E(2) * hE) + eb * (XE + E(2) * hE)) / dx2 +
+                Bsb * q1E / dx;
+  const E Bpb = (db * (YS + E(2) * hS) + sb * (YS - E(2) * hS)) / dy2 -
+                Bsb * q2S / dy;
+  const E Bmb = -(db * (YN - E(2) * hN) + nb * (YN + E(2) * hN)) / dy2 +
+                Bsb * q2N / dy;
+  const E wc = (E)ws[c];
+  double* o = rb + c;
+  o[kBhc * ncorn] = E(2) * (Apb + Amb + Bpb + Bmb) + E(4) * wc * Bsb;
+  o[kBhE * ncorn] = E(2) * Am * (db - eb) / dx2;
+  o[kBhW * ncorn] = E(2) * Ap * (db - wb) / dx2;
+  o[kBhN * ncorn] = E(2) * Bm * (db - nb) / dy2;
+  o[kBhS * ncorn] = E(2) * Bp * (db - sb) / dy2;
+  o[kBXE * ncorn] = -Am * (db + eb) / dx2;
+  o[kBXW * ncorn] = Ap * (db + wb) / dx2;
+  o[kBYN * ncorn] = -Bm * (db + nb) / dy2;
+  o[kBYS * ncorn] = Bp * (db + sb) / dy2;
+  o[kBsx * ncorn] = Apb - Amb;
+  o[kBsy * ncorn] = Bpb - Bmb;
+  o[kBq1E * ncorn] = Bsb * Am / dx;
+  o[kBq1W * ncorn] = -Bsb * Ap / dx;
+  o[kBq2N * ncorn] = Bsb * Bm / dy;
+  o[kBq2S * ncorn] = -Bsb * Bp / dy;
+  lw[c] = (T)((E)lw[c] + E(4) * hc * Bsb);
+}
+
+// the positions a in [lo, hi] with mirror(a, n) == j (n >= 2, so one
+// reflection covers [-2, n + 1]); returns their count
+__device__ __forceinline__ int mirror_preimages(int j, int lo, int hi, int n,
+                                                int a[3]) {
+  int cnt = 0;
+  const int cand[3] = {j, -1 - j, 2 * n - 1 - j};
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+    if (cand[t] >= lo && cand[t] <= hi) a[cnt++] = cand[t];
+  return cnt;
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-    k_adj_assemble_w(AdjGeom G, const T* __restrict__ hs,
-                     const T* __restrict__ q1s, const T* __restrict__ q2s,
-                     const T* __restrict__ H, const T* __restrict__ ws,
-                     const double* __restrict__ p,
-                     const double* __restrict__ mu, T* __restrict__ lw) {
-  using D = Dual<E, 1>;
+    k_adj_row_gather(AdjGeom G, const double* __restrict__ rb,
+                     T* __restrict__ lhs, T* __restrict__ lq1s,
+                     T* __restrict__ lq2s, T* __restrict__ lH) {
   const int nx = G.nx, ny = G.ny, ncx = nx + 1;
-  const int c = blockIdx.x * kBlock + threadIdx.x;
-  if (c >= ncx * (ny + 1)) return;
-  const int k = c % ncx, l = c / ncx;
-  const D dx(G.dx), dy(G.dy), dt(*G.dtp);
-  SeedLoader<T, 1> ld{hs, q1s, q2s, H, nx, ny, -1, -1, -1, -1, -1};
-  D wc(ws[c]);
-  wc.d[0] = E(1);
-  D row[6];
-  assemble_row<D>(ld, k, l, nx, ny, dx, dy, wc, dt, row);
-  D R = row_residual<D>(row, p, k, l, nx, ny);
-  lw[c] = (T)((E)lw[c] + R.d[0] * mu[c]);
+  const long ncorn = (long)ncx * (ny + 1);
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= nx * ny) return;
+  const int jx = n % nx, jy = n / nx;
+  auto bar = [&](int q, int k, int l) { return rb[q * ncorn + l * ncx + k]; };
+  // sums over the corners around the (unmirrored) cell position (u, v):
+  // the corner at (u, .) has the cell on its east side, at (u + 1, .) west;
+  // at (., v) north, at (., v + 1) south
+  auto xsum = [&](int u, int v) {  // X of the position, one half per side
+    E s = 0.0;
+    for (int dk = 0; dk < 2; ++dk)
+      for (int dl = 0; dl < 2; ++dl) {
+        const int k = u + dk, l = v + dl;
+        if (k < 0 || k > nx || l < 0 || l > ny) continue;
+        s = s + E(0.5) * bar(dk == 0 ? kBXE : kBXW, k, l);
+      }
+    return s;
+  };
+  auto ysum = [&](int u, int v) {
+    E s = 0.0;
+    for (int dk = 0; dk < 2; ++dk)
+      for (int dl = 0; dl < 2; ++dl) {
+        const int k = u + dk, l = v + dl;
+        if (k < 0 || k > nx || l < 0 || l > ny) continue;
+        s = s + E(0.5) * bar(dl == 0 ? kBYN : kBYS, k, l);
+      }
+    return s;
+  };
+  int cx[3], cy[3];
+  const int ncxs = mirror_preimages(jx, -1, nx, nx, cx);
+  const int ncys = mirror_preimages(jy, -1, ny, ny, cy);
+  E ah = 0.0, aq1 = 0.0, aq2 = 0.0, az = 0.0;
+  // the cell at a corner position: its h, zeta and discharges
+  for (int a = 0; a < ncxs; ++a)
+    for (int b = 0; b < ncys; ++b) {
+      const int u = cx[a], v = cy[b];
+      E hb = 0.0, zb = 0.0, q1b = 0.0, q2b = 0.0;
+      for (int dk = 0; dk < 2; ++dk)
+        for (int dl = 0; dl < 2; ++dl) {
+          const int k = u + dk, l = v + dl;
+          if (k < 0 || k > nx || l < 0 || l > ny) continue;
+          const bool east = dk == 0, north = dl == 0;
+          hb = hb + (E(0.25) * bar(kBhc, k, l) +
+                     E(0.5) * bar(east ? kBhE : kBhW, k, l) +
+                     E(0.5) * bar(north ? kBhN : kBhS, k, l));
+          zb = zb + E(0.5) * (east ? bar(kBsx, k, l) : -bar(kBsx, k, l)) +
+               E(0.5) * (north ? bar(kBsy, k, l) : -bar(kBsy, k, l));
+          q1b = q1b + E(0.5) * bar(east ? kBq1E : kBq1W, k, l);
+          q2b = q2b + E(0.5) * bar(north ? kBq2N : kBq2S, k, l);
+        }
+      ah = ah + hb;
+      az = az + zb;
+      aq1 = u != jx ? aq1 - q1b : aq1 + q1b;
+      aq2 = v != jy ? aq2 - q2b : aq2 + q2b;
+    }
+  // the cell's zeta in the central differences X, Y of the positions
+  // beside it: X(u) = (zeta(u + 1) - zeta(u - 1)) / 2
+  int t[3];
+  int nt = mirror_preimages(jx, 0, nx + 1, nx, t);
+  for (int a = 0; a < nt; ++a)
+    for (int b = 0; b < ncys; ++b) az = az + E(0.5) * xsum(t[a] - 1, cy[b]);
+  nt = mirror_preimages(jx, -2, nx - 1, nx, t);
+  for (int a = 0; a < nt; ++a)
+    for (int b = 0; b < ncys; ++b) az = az - E(0.5) * xsum(t[a] + 1, cy[b]);
+  nt = mirror_preimages(jy, 0, ny + 1, ny, t);
+  for (int b = 0; b < nt; ++b)
+    for (int a = 0; a < ncxs; ++a) az = az + E(0.5) * ysum(cx[a], t[b] - 1);
+  nt = mirror_preimages(jy, -2, ny - 1, ny, t);
+  for (int b = 0; b < nt; ++b)
+    for (int a = 0; a < ncxs; ++a) az = az - E(0.5) * ysum(cx[a], t[b] + 1);
+  // zeta = h - 2H
+  lhs[n] = (T)((E)lhs[n] + ah + az);
+  lq1s[n] = (T)((E)lq1s[n] + aq1);
+  lq2s[n] = (T)((E)lq2s[n] + aq2);
+  lH[n] = (T)((E)lH[n] - E(2) * az);
 }
 
 // rows of A^T: (A^T mu)_c = diag_c mu_c + cW_{c+1} mu_{c+1} + cE_{c-1} mu_{c-1}

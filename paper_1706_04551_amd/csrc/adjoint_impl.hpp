@@ -23,6 +23,7 @@ struct AdjWork {
   void *Lqs1 = nullptr, *Lqs2 = nullptr, *pbar = nullptr;
   void *tE = nullptr, *tW = nullptr, *tN = nullptr, *tS = nullptr;
   double* mu[2][3] = {};
+  double* rowbar = nullptr;  // kRowBars planes of corner cotangents (FP64)
   int mucur[2] = {0, 0};
   // tape of one segment and the checkpoints
   void* tape = nullptr;      // ce x (h, q1, q2, w) bulk + ce x (p1, p2) FP64
@@ -83,6 +84,8 @@ nh_status adj_prepare(nh_solver* s, int64_t nsteps, int ce, int ng) {
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 3; ++b)
       if ((r = adj_alloc(w, (void**)&w->mu[a][b], kd, st)) != NH_OK) return r;
+  if ((r = adj_alloc(w, (void**)&w->rowbar, nh::kRowBars * kd, st)) != NH_OK)
+    return r;
   if ((r = adj_alloc(w, &w->tape, (size_t)ce * rec_bytes(s, 2), st)) !=
           NH_OK ||
       (r = adj_alloc(w, &w->ckpt, (size_t)(nck + 1) * rec_bytes(s, 1), st)) !=
@@ -290,12 +293,12 @@ nh_status adj_step(nh_solver* s, AdjWork* w, const StateRec& R, double tol,
       if (r != NH_OK) return r;
       *sweeps_total += sw;
       const double* mu = w->mu[idx][w->mucur[idx]];
-      hipLaunchKernelGGL((nh::k_adj_assemble<T>), Gc, B, 0, st, G, C(hs_),
+      hipLaunchKernelGGL((nh::k_adj_row_bars<T>), Gk, B, 0, st, G, C(hs_),
                          C(q1s_), C(q2s_), C(s->H), C(w_in), p, mu,
-                         P(lh_out), P(w->Lqs1), P(w->Lqs2), P(w->LH));
-      hipLaunchKernelGGL((nh::k_adj_assemble_w<T>), Gk, B, 0, st, G, C(hs_),
-                         C(q1s_), C(q2s_), C(s->H), C(w_in), p, mu,
-                         P(lw_in));
+                         w->rowbar, P(lw_in));
+      hipLaunchKernelGGL((nh::k_adj_row_gather<T>), Gc, B, 0, st, G,
+                         w->rowbar, P(lh_out), P(w->Lqs1), P(w->Lqs2),
+                         P(w->LH));
     } else {
       hipLaunchKernelGGL((nh::k_copy<T>), Gc, B, 0, st, nc, C(lq1_out),
                          P(w->Lqs1));
