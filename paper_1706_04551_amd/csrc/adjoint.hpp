@@ -1,15 +1,15 @@
 // adjoint.hpp -- device code of the adjoint (reverse) time step.
 //
 // The adjoint of one projection-correction stage is assembled from local
-// transposed Jacobian products.  The flux and correction Jacobians are
-// evaluated exactly by running the forward formulas of kernels.hpp (fv_cell,
-// correct_cell, correct_corner) on forward-mode dual numbers, seeded at one
-// input; every branch (limiter, HLL speeds, wet/dry tests, clamps) takes the
-// decision of the forward values.  The pressure rows, polynomials without
-// branches, are differentiated in reverse by hand (k_adj_row_bars).  The
-// products are gathered: one thread per input cell or corner visits every
-// output that reads it, so no two threads add into the same place and the
-// result does not depend on scheduling.
+// transposed Jacobian products, each written out in reverse mode from the
+// forward formulas of kernels.hpp: the flux (prim, reconstruct, pvm,
+// interior), the pressure rows (assemble_row) and the correction
+// (correct_cell, correct_corner).  The forward values are recomputed with
+// those very functions where a branch depends on them, so every branch
+// (limiter, HLL speeds, wet/dry tests, clamps) takes the forward's decision.
+// The products are gathered: one thread per input cell or corner visits
+// every output that reads it, so no two threads add into the same place and
+// the result does not depend on scheduling.
 //
 // Pressure: the stage solves A(U) p = rhs(U).  With A^T mu = pbar (pbar the
 // adjoint of p), the adjoint of U gains mu^T d(rhs - A p)/dU at fixed p.
@@ -18,146 +18,10 @@
 
 namespace nh {
 
-// value and N directional derivatives
-template <typename T, int N>
-struct Dual {
-  T v;
-  T d[N];
-  __device__ __forceinline__ Dual() : v(T(0)) {
-#pragma unroll
-    for (int k = 0; k < N; ++k) d[k] = T(0);
-  }
-  __device__ __forceinline__ Dual(double x) : v((T)x) {
-#pragma unroll
-    for (int k = 0; k < N; ++k) d[k] = T(0);
-  }
-  __device__ __forceinline__ Dual(float x) : v((T)x) {
-#pragma unroll
-    for (int k = 0; k < N; ++k) d[k] = T(0);
-  }
-  __device__ __forceinline__ Dual(int x) : v((T)x) {
-#pragma unroll
-    for (int k = 0; k < N; ++k) d[k] = T(0);
-  }
-
-  friend __device__ __forceinline__ Dual operator+(const Dual& a,
-                                                  const Dual& b) {
-    Dual r;
-    r.v = a.v + b.v;
-#pragma unroll
-    for (int k = 0; k < N; ++k) r.d[k] = a.d[k] + b.d[k];
-    return r;
-  }
-  friend __device__ __forceinline__ Dual operator-(const Dual& a,
-                                                  const Dual& b) {
-    Dual r;
-    r.v = a.v - b.v;
-#pragma unroll
-    for (int k = 0; k < N; ++k) r.d[k] = a.d[k] - b.d[k];
-    return r;
-  }
-  friend __device__ __forceinline__ Dual operator-(const Dual& a) {
-    Dual r;
-    r.v = -a.v;
-#pragma unroll
-    for (int k = 0; k < N; ++k) r.d[k] = -a.d[k];
-    return r;
-  }
-  friend __device__ __forceinline__ Dual operator*(const Dual& a,
-                                                  const Dual& b) {
-    Dual r;
-    r.v = a.v * b.v;
-#pragma unroll
-    for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
-    return r;
-  }
-  // the value is the forward's quotient (its branches see the same numbers);
-  // the derivatives use one reciprocal
-  friend __device__ __forceinline__ Dual operator/(const Dual& a,
-                                                  const Dual& b) {
-    Dual r;
-    r.v = a.v / b.v;
-    const T inv = T(1) / b.v;
-#pragma unroll
-    for (int k = 0; k < N; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * inv;
-    return r;
-  }
-  // at 0 (a dry face) the derivative is taken as 0: the forward run treats
-  // such a face as dry, and its speeds do not move to first order
-  friend __device__ __forceinline__ Dual sqrt(const Dual& a) {
-    Dual r;
-    r.v = sqrt(a.v);
-    const T s = r.v > T(0) ? T(0.5) / r.v : T(0);
-#pragma unroll
-    for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * s;
-    return r;
-  }
-  friend __device__ __forceinline__ Dual fabs(const Dual& a) {
-    return a.v < T(0) ? -a : a;
-  }
-  friend __device__ __forceinline__ bool operator<(const Dual& a,
-                                                  const Dual& b) {
-    return a.v < b.v;
-  }
-  friend __device__ __forceinline__ bool operator>(const Dual& a,
-                                                  const Dual& b) {
-    return a.v > b.v;
-  }
-  friend __device__ __forceinline__ bool operator<=(const Dual& a,
-                                                   const Dual& b) {
-    return a.v <= b.v;
-  }
-  friend __device__ __forceinline__ bool operator>=(const Dual& a,
-                                                   const Dual& b) {
-    return a.v >= b.v;
-  }
-};
-
-// Type of the local Jacobian evaluations: the finite-volume and pressure-row
-// derivatives run in the bulk type (their cost dominates the adjoint step),
-// the correction's in FP64; sums over outputs are always FP64.
+// Sums over outputs are FP64.  The flux cotangents are formed in the bulk
+// type (their arithmetic dominates), those of the rows and the correction
+// in FP64.
 using E = double;
-
-// mirrored cells of the bulk arrays as FP64 duals; cell `seed` carries the
-// directions dh (index ih), dq1 (iq1), dq2 (iq2), dH (iH) (-1: not seeded)
-template <typename T, int N, typename V = E>
-struct SeedLoader {
-  const T *h, *q1, *q2, *H;
-  int nx, ny, seed;
-  int ih, iq1, iq2, iH;
-  __device__ __forceinline__ Cell<Dual<V, N>> operator()(int i, int j) const {
-    int mi = mirror(i, nx), mj = mirror(j, ny);
-    int idx = mj * nx + mi;
-    Cell<Dual<V, N>> c;
-    c.h = Dual<V, N>((V)h[idx]);
-    c.q1 = Dual<V, N>((V)q1[idx]);
-    c.q2 = Dual<V, N>((V)q2[idx]);
-    c.H = Dual<V, N>((V)H[idx]);
-    if (idx == seed) {
-      if (ih >= 0) c.h.d[ih] = V(1);
-      if (iq1 >= 0) c.q1.d[iq1] = V(1);
-      if (iq2 >= 0) c.q2.d[iq2] = V(1);
-      if (iH >= 0) c.H.d[iH] = V(1);
-    }
-    if (mi != i) c.q1 = -c.q1;
-    if (mj != j) c.q2 = -c.q2;
-    return c;
-  }
-};
-
-// corner pressures as FP64 duals (rounded to the bulk type first, as the
-// forward correction reads them); corner `seed` carries direction 0
-template <typename T, int N>
-struct SeedPLoader {
-  const double* p;
-  int ncx, seed;
-  __device__ __forceinline__ Dual<E, N> operator()(int k, int l) const {
-    int idx = l * ncx + k;
-    Dual<E, N> v((E)(T)p[idx]);
-    if (idx == seed) v.d[0] = E(1);
-    return v;
-  }
-};
 
 struct AdjGeom {
   int nx, ny;
@@ -505,83 +369,170 @@ __global__ void __launch_bounds__(kBlock)
 
 // ---------------------------------------------------------------------------
 // correction (eq. 36, 41).  q = q* + dt T(p; h*, H) (zero where dry),
-// w = w_in + dt p / h_c.
-//   k_adj_correct_p: pbar_c = sum over the cells i around corner c of
-//     dq_i/dp_c lq_i + dw_c/dp_c lw_c                       (one per corner)
-//   k_adj_correct_h: lhs_j += dq_i/dh*_j lq_i + dw_c/dh*_j lw_c, lH_j alike,
-//     over the cells i in {j, its 4 neighbours} and the corners of j; and
-//     lqs_j = lq_j where wet (0 where dry)                    (one per cell)
+// w = w_in + dt desing(h_c, p) at the corners.  Per cell i with the corner
+// pressures pSW, pSE, pNW, pNE and zx, zy the central differences of
+// zeta = h* - 2H (eq. 36):
+//   q1 += dt/2 (TN + TS),  TN + TS = -hc/(2dx) (pNE - pNW + pSE - pSW)
+//                                    - zx/4 (pNE + pNW + pSE + pSW),
+//   q2 += dt/2 (TE + TW),  TE + TW = -hc/(2dy) (pNE - pSE + pNW - pSW)
+//                                    - zy/4 (same sum).
+// Both are linear in p and in (hc, zx, zy), so their adjoints are written
+// out: with a = dt/2 lq1_i, b = dt/2 lq2_i (0 where dry),
+//   k_adj_correct_p: pbar_c = sum over the cells around c of
+//     a (+-hc/(2dx) - zx/4) + b (+-hc/(2dy) - zy/4)    (+ west/south of c)
+//     + dt lw_c d desing/dp                              (one per corner)
+//   k_adj_correct_h: lhs_j += the hc, zeta (through the zx, zy of the cells
+//     beside j, mirrored at walls) and corner-mean (w) terms, lH_j -= 2 x
+//     the zeta terms; lqs_j = lq_j where wet             (one per cell)
 // ---------------------------------------------------------------------------
+
+// the positions a in [lo, hi] with mirror(a, n) == j (n >= 2, so one
+// reflection covers [-2, n + 1]); returns their count
+__device__ __forceinline__ int mirror_preimages(int j, int lo, int hi, int n,
+                                                int a[3]) {
+  int cnt = 0;
+  const int cand[3] = {j, -1 - j, 2 * n - 1 - j};
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+    if (cand[t] >= lo && cand[t] <= hi) a[cnt++] = cand[t];
+  return cnt;
+}
+
+// per cell of the correction: a, b (dt/2 times the adjoint of q1, q2; zero
+// where dry), hc and the zeta differences zx, zy (undivided by 2dx, 2dy)
+template <typename T>
+struct CorrCell {
+  E a, b, hc, zx, zy;
+};
+
+template <typename T>
+__device__ __forceinline__ CorrCell<T> corr_cell(const AdjGeom& G,
+                                                 const T* __restrict__ hs,
+                                                 const T* __restrict__ H,
+                                                 const T* __restrict__ lq1,
+                                                 const T* __restrict__ lq2,
+                                                 E dt, int i, int j) {
+  const int nx = G.nx, ny = G.ny, m = j * nx + i;
+  auto zeta = [&](int ii, int jj) {
+    const int q = mirror(jj, ny) * nx + mirror(ii, nx);
+    return (E)hs[q] - E(2) * (E)H[q];
+  };
+  CorrCell<T> c;
+  c.hc = (E)hs[m];
+  const bool wet = !(hs[m] <= (T)G.dry_eps);
+  c.a = wet ? E(0.5) * dt * (E)lq1[m] : 0.0;
+  c.b = wet ? E(0.5) * dt * (E)lq2[m] : 0.0;
+  c.zx = zeta(i + 1, j) - zeta(i - 1, j);
+  c.zy = zeta(i, j + 1) - zeta(i, j - 1);
+  return c;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_adj_correct_p(AdjGeom G, const T* __restrict__ hs,
-                    const T* __restrict__ H, const T* __restrict__ q1s,
-                    const T* __restrict__ q2s, const T* __restrict__ ws,
-                    const double* __restrict__ p, const T* __restrict__ lq1,
-                    const T* __restrict__ lq2, const T* __restrict__ lw,
-                    T* __restrict__ pbar) {
-  using D = Dual<E, 1>;
+                    const T* __restrict__ H, const double* __restrict__ p,
+                    const T* __restrict__ lq1, const T* __restrict__ lq2,
+                    const T* __restrict__ lw, T* __restrict__ pbar) {
   const int nx = G.nx, ny = G.ny, ncx = nx + 1;
   const int c = blockIdx.x * kBlock + threadIdx.x;
   if (c >= ncx * (ny + 1)) return;
   const int k = c % ncx, l = c / ncx;
-  const D dx(G.dx), dy(G.dy), de(G.dry_eps), delta(G.delta), dt(*G.dtp);
-  SeedLoader<T, 1> ld{hs, q1s, q2s, H, nx, ny, -1, -1, -1, -1, -1};
-  SeedPLoader<T, 1> pl{p, ncx, c};
+  const E dx = G.dx, dy = G.dy, dt = *G.dtp;
   E acc = 0.0;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int i = k - 1 + (s & 1), j = l - 1 + (s >> 1);
     if (i < 0 || i >= nx || j < 0 || j >= ny) continue;
-    const int m = j * nx + i;
-    D qa(q1s[m]), qb(q2s[m]);
-    correct_cell<D, false>(ld, pl, i, j, dx, dy, dt, de, qa, qb);
-    acc = acc + (qa.d[0] * (E)lq1[m] + qb.d[0] * (E)lq2[m]);
+    const CorrCell<T> q = corr_cell<T>(G, hs, H, lq1, lq2, dt, i, j);
+    // the corner is east of cell i for s & 1 == 0 (k = i + 1), north for
+    // s >> 1 == 0 (l = j + 1)
+    const E sx = (s & 1) ? E(1) : E(-1), sy = (s >> 1) ? E(1) : E(-1);
+    acc = acc + q.a * (sx * q.hc / (E(2) * dx) - q.zx / (E(8) * dx)) +
+          q.b * (sy * q.hc / (E(2) * dy) - q.zy / (E(8) * dy));
   }
-  D wv = correct_corner<D, false>(ld, k, l, D(ws[c]), pl(k, l), dt, delta);
-  acc = acc + wv.d[0] * (E)lw[c];
+  // w_c = w_in + dt desing(mean of the corner's cells, p_c)
+  auto hcell = [&](int i, int j) {
+    return (E)hs[mirror(j, ny) * nx + mirror(i, nx)];
+  };
+  const E hm = E(0.25) * (hcell(k - 1, l - 1) + hcell(k, l - 1) +
+                          hcell(k - 1, l) + hcell(k, l));
+  E dh, dq;
+  desing_partials<E>(hm, (E)(T)p[c], (E)G.delta, dh, dq);
+  acc = acc + dt * dq * (E)lw[c];
   pbar[c] = (T)acc;
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_adj_correct_h(AdjGeom G, const T* __restrict__ hs,
-                    const T* __restrict__ H, const T* __restrict__ q1s,
-                    const T* __restrict__ q2s, const T* __restrict__ ws,
-                    const double* __restrict__ p, const T* __restrict__ lq1,
-                    const T* __restrict__ lq2, const T* __restrict__ lw,
-                    T* __restrict__ lhs, T* __restrict__ lH,
-                    T* __restrict__ lq1s, T* __restrict__ lq2s) {
-  using D = Dual<E, 2>;
+                    const T* __restrict__ H, const double* __restrict__ p,
+                    const T* __restrict__ lq1, const T* __restrict__ lq2,
+                    const T* __restrict__ lw, T* __restrict__ lhs,
+                    T* __restrict__ lH, T* __restrict__ lq1s,
+                    T* __restrict__ lq2s) {
   const int nx = G.nx, ny = G.ny, ncx = nx + 1;
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= nx * ny) return;
   const int jx = n % nx, jy = n / nx;
-  const D dx(G.dx), dy(G.dy), de(G.dry_eps), delta(G.delta), dt(*G.dtp);
-  SeedLoader<T, 2> ld{hs, q1s, q2s, H, nx, ny, n, 0, -1, -1, 1};
-  SeedPLoader<T, 2> pl{p, ncx, -1};
-  E ah = 0.0, aH = 0.0;
-  const int ox[5] = {0, -1, 1, 0, 0};
-  const int oy[5] = {0, 0, 0, -1, 1};
-#pragma unroll
-  for (int o = 0; o < 5; ++o) {
-    const int i = jx + ox[o], j = jy + oy[o];
-    if (i < 0 || i >= nx || j < 0 || j >= ny) continue;
-    const int m = j * nx + i;
-    D qa(q1s[m]), qb(q2s[m]);
-    correct_cell<D, false>(ld, pl, i, j, dx, dy, dt, de, qa, qb);
-    ah = ah + (qa.d[0] * (E)lq1[m] + qb.d[0] * (E)lq2[m]);
-    aH = aH + (qa.d[1] * (E)lq1[m] + qb.d[1] * (E)lq2[m]);
+  const E dx = G.dx, dy = G.dy, dt = *G.dtp;
+  auto pc = [&](int k, int l) { return (E)(T)p[l * ncx + k]; };
+  E ah = 0.0, az = 0.0;
+  {  // hc of cell j itself
+    const CorrCell<T> q = corr_cell<T>(G, hs, H, lq1, lq2, dt, jx, jy);
+    const E pSW = pc(jx, jy), pSE = pc(jx + 1, jy);
+    const E pNW = pc(jx, jy + 1), pNE = pc(jx + 1, jy + 1);
+    ah = ah - q.a * ((pNE - pNW) + (pSE - pSW)) / (E(2) * dx) -
+         q.b * ((pNE - pSE) + (pNW - pSW)) / (E(2) * dy);
   }
+  // zeta of j in zx of the cells i with mirror(i +- 1) == jx (same row),
+  // and in zy of the cells with mirror(i +- 1) == jy (same column):
+  // d(TN + TS)/d zx = -(sum of the cell's corner pressures) / (4 2dx)
+  auto psum = [&](int i, int j) {
+    return pc(i, j) + pc(i + 1, j) + pc(i, j + 1) + pc(i + 1, j + 1);
+  };
+  int t[3];
+  int nt = mirror_preimages(jx, 1, nx, nx, t);  // i + 1 reads j
+  for (int u = 0; u < nt; ++u) {
+    const int i = t[u] - 1;
+    const CorrCell<T> q = corr_cell<T>(G, hs, H, lq1, lq2, dt, i, jy);
+    az = az - q.a * psum(i, jy) / (E(8) * dx);
+  }
+  nt = mirror_preimages(jx, -1, nx - 2, nx, t);  // i - 1 reads j
+  for (int u = 0; u < nt; ++u) {
+    const int i = t[u] + 1;
+    const CorrCell<T> q = corr_cell<T>(G, hs, H, lq1, lq2, dt, i, jy);
+    az = az + q.a * psum(i, jy) / (E(8) * dx);
+  }
+  nt = mirror_preimages(jy, 1, ny, ny, t);
+  for (int u = 0; u < nt; ++u) {
+    const int j = t[u] - 1;
+    const CorrCell<T> q = corr_cell<T>(G, hs, H, lq1, lq2, dt, jx, j);
+    az = az - q.b * psum(jx, j) / (E(8) * dy);
+  }
+  nt = mirror_preimages(jy, -1, ny - 2, ny, t);
+  for (int u = 0; u < nt; ++u) {
+    const int j = t[u] + 1;
+    const CorrCell<T> q = corr_cell<T>(G, hs, H, lq1, lq2, dt, jx, j);
+    az = az + q.b * psum(jx, j) / (E(8) * dy);
+  }
+  // corner means: j is 1 or 2 (at a wall) of the 4 mirrored cells per axis
+  auto hcell = [&](int i, int j) {
+    return (E)hs[mirror(j, ny) * nx + mirror(i, nx)];
+  };
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int k = jx + (s & 1), l = jy + (s >> 1);
-    const int c = l * ncx + k;
-    D wv = correct_corner<D, false>(ld, k, l, D(ws[c]), pl(k, l), dt, delta);
-    ah = ah + wv.d[0] * (E)lw[c];
+    const int mx = (mirror(k - 1, nx) == jx) + (mirror(k, nx) == jx);
+    const int my = (mirror(l - 1, ny) == jy) + (mirror(l, ny) == jy);
+    const E hm = E(0.25) * (hcell(k - 1, l - 1) + hcell(k, l - 1) +
+                            hcell(k - 1, l) + hcell(k, l));
+    E dh, dq;
+    desing_partials<E>(hm, pc(k, l), (E)G.delta, dh, dq);
+    ah = ah + E(0.25) * E(mx * my) * dt * dh * (E)lw[l * ncx + k];
   }
-  lhs[n] = (T)((E)lhs[n] + ah);
-  lH[n] = (T)((E)lH[n] + aH);
+  // zeta = h - 2H
+  lhs[n] = (T)((E)lhs[n] + ah + az);
+  lH[n] = (T)((E)lH[n] - E(2) * az);
   const bool wet = hs[n] > (T)G.dry_eps;
   lq1s[n] = wet ? lq1[n] : T(0);
   lq2s[n] = wet ? lq2[n] : T(0);
@@ -687,18 +638,6 @@ __global__ void __launch_bounds__(kBlock)
   o[kBq2N * ncorn] = Bsb * Bm / dy;
   o[kBq2S * ncorn] = -Bsb * Bp / dy;
   lw[c] = (T)((E)lw[c] + E(4) * hc * Bsb);
-}
-
-// the positions a in [lo, hi] with mirror(a, n) == j (n >= 2, so one
-// reflection covers [-2, n + 1]); returns their count
-__device__ __forceinline__ int mirror_preimages(int j, int lo, int hi, int n,
-                                                int a[3]) {
-  int cnt = 0;
-  const int cand[3] = {j, -1 - j, 2 * n - 1 - j};
-#pragma unroll
-  for (int t = 0; t < 3; ++t)
-    if (cand[t] >= lo && cand[t] <= hi) a[cnt++] = cand[t];
-  return cnt;
 }
 
 template <typename T>

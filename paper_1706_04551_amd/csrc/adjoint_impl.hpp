@@ -274,12 +274,11 @@ nh_status adj_step(nh_solver* s, AdjWork* w, const StateRec& R, double tol,
     if (pr.nh_on) {
       // correction
       hipLaunchKernelGGL((nh::k_adj_correct_p<T>), Gk, B, 0, st, G, C(hs_),
-                         C(s->H), C(q1s_), C(q2s_), C(w_in), p, C(lq1_out),
-                         C(lq2_out), C(lw_out), P(w->pbar));
+                         C(s->H), p, C(lq1_out), C(lq2_out), C(lw_out),
+                         P(w->pbar));
       hipLaunchKernelGGL((nh::k_adj_correct_h<T>), Gc, B, 0, st, G, C(hs_),
-                         C(s->H), C(q1s_), C(q2s_), C(w_in), p, C(lq1_out),
-                         C(lq2_out), C(lw_out), P(lh_out), P(w->LH),
-                         P(w->Lqs1), P(w->Lqs2));
+                         C(s->H), p, C(lq1_out), C(lq2_out), C(lw_out),
+                         P(lh_out), P(w->LH), P(w->Lqs1), P(w->Lqs2));
       hipLaunchKernelGGL((nh::k_axpy1<T>), Gk, B, 0, st, nk, C(lw_out),
                          P(lw_in));
       // pressure system of the stage, transposed solve, its adjoint
