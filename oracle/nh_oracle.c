@@ -798,6 +798,31 @@ static void assemble_g(ora_t *o, const double *h, const double *q1,
   }
 }
 
+/* Manning friction (the law of Section 2: tau = g h n^2 u |u| / h^(4/3)),
+ * discretised semi-implicitly as Sections 3-4 state, in this reading: on the
+ * finite-volume result of each stage, in every wet cell,
+ *   q <- q / (1 + dt g n^2 |u| / h^(4/3)),
+ * i.e. q_t = -g n^2 |u| q / h^(4/3) with q implicit and |u|, h explicit; |u|
+ * from the desingularised velocities of that result (Section 4.5). */
+static void friction_g(ora_t *o, double *hs, double *q1s, double *q2s,
+                       double dt) {
+  const double n = o->P.manning;
+  if (!(n > 0.0)) return;
+  const double gn2 = o->P.g * n * n;
+  for (int j = 0; j < (o->is1d ? 1 : o->ny); ++j)
+    for (int i = 0; i < o->nx; ++i) {
+      const int c = IX(o, i, j);
+      const double h = hs[c];
+      if (h <= o->P.dry_eps) continue;
+      const double u = ora_desing_velocity(h, q1s[c], o->P.delta);
+      const double v =
+          o->is1d ? 0.0 : ora_desing_velocity(h, q2s[c], o->P.delta);
+      const double den = 1.0 + dt * gn2 * sqrt(u * u + v * v) / (h * cbrt(h));
+      q1s[c] = q1s[c] / den;
+      if (!o->is1d) q2s[c] = q2s[c] / den;
+    }
+}
+
 /* Stage: V (ghosted, filled) + corner w_in, warm start p -> outputs. */
 static int stage_g(ora_t *o, const double *Vh, const double *Vq1,
                    const double *Vq2, const double *w_in, double *p, double dt,
@@ -809,6 +834,7 @@ static int stage_g(ora_t *o, const double *Vh, const double *Vq1,
   memset(q1s, 0, sizeof(double) * N);
   memset(q2s, 0, sizeof(double) * N);
   fv_stage_g(o, Vh, Vq1, Vq2, dt, hs, q1s, q2s, &o->clamped_total);
+  friction_g(o, hs, q1s, q2s, dt);
   fill_ghosts(o, hs, 1.0, 1.0);
   fill_ghosts(o, q1s, -1.0, 1.0);
   fill_ghosts(o, q2s, 1.0, -1.0);
@@ -911,6 +937,7 @@ ora_t *ora_create(const ora_params *pp, const double *omega, int32_t n_omega) {
   /* mirror ghosts need at least two interior cells per direction */
   if (!pp || pp->nx < 2 || pp->ny < 1 || !(pp->dx > 0) || !(pp->dy > 0))
     return NULL;
+  if (!(pp->manning >= 0.0) || isinf(pp->manning)) return NULL;
   ora_t *o = (ora_t *)calloc(1, sizeof(ora_t));
   o->P = *pp;
   o->is1d = pp->ny == 1;

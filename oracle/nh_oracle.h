@@ -39,6 +39,8 @@ typedef struct ora_params {
   double solve_tol;        /* stop when max |D^-1 (rhs - A p)| < solve_tol */
   int32_t fixed_dt;        /* 1: use dt_fixed for every step */
   double dt_fixed;
+  double manning;          /* Gauckler-Manning n of the friction law of
+                              Section 2 [s m^-1/3]; 0: no friction */
 } ora_params;
 
 /* status codes */
