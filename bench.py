@@ -317,6 +317,9 @@ def run_single(args):
         desc = re.sub(r"tol=[0-9.e+-]+", f"tol={case.solve_tol:g}", desc)
         if "tol=" not in desc:
             desc += f", tol={case.solve_tol:g}"
+    if getattr(args, "manning", None):
+        case.manning = args.manning
+        desc += f", Manning n={case.manning:g}"
     stream = torch.cuda.current_stream()
     s = Solver.from_case(case, stream=stream.cuda_stream)
     ncell = case.nx * case.ny
@@ -415,6 +418,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--solve-tol", type=float, default=None,
                     help="override the workload's stop tolerance (eq. 32)")
+    ap.add_argument("--manning", type=float, default=None,
+                    help="Gauckler-Manning n of the friction law (default 0)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain copy of 256 MiB (for counter runs)")
@@ -463,6 +468,10 @@ def main():
             v.no_cpu, v.solve_tol = True, 1e-5   # the paper's tightest (Table 2)
             variants["c2_fp64_eps1e-5"] = variant_summary(run_single(v))
             note("c2 FP64 at eps 1e-5 done")
+            v = copy.copy(args)
+            v.no_cpu, v.manning = True, 0.012   # the paper's flume roughness
+            variants["c2_fp64_manning"] = variant_summary(run_single(v))
+            note("c2 FP64 with friction done")
             v = copy.copy(args)
             v.workload, v.precision, v.no_cpu = "c3", "f32", True
             v.steps = 4000          # the beach workload's full run

@@ -10,7 +10,8 @@
  *   - the second-order well-balanced PVM path-conservative finite-volume
  *     update of (h, hu, hv) with MUSCL-minmod reconstruction, desingularised
  *     velocities and the wet-dry treatment (Sections 4.1, 4.5, 5, eq. 16-22,30);
- *   - optionally the breaking terms of the eddy viscosity (Section 3, eq. 9-12);
+ *   - optionally the Manning friction of Section 2, semi-implicit, and the
+ *     breaking terms of the eddy viscosity (Section 3, eq. 9-12);
  *   - the compact finite-difference non-hydrostatic pressure system at the
  *     cell corners: assembly (eq. 28-29, 37-41, 43), solve (Thomas in 1D,
  *     scheduled-relaxation Jacobi in 2D, eq. 32) and the correction of the
@@ -91,6 +92,13 @@ typedef struct {
   int32_t n_omega;
   int32_t fixed_dt;    /* 1: every step uses dt below instead of the CFL */
   double dt;
+  double manning;      /* Gauckler-Manning n of the friction law of Section 2
+                          [s m^-1/3], >= 0; 0: no friction.  Applied
+                          semi-implicitly to each stage's finite-volume
+                          result in wet cells: q <- q / (1 + dt g n^2 |u| /
+                          h^(4/3)), |u| from the desingularised velocities.
+                          Ensemble members may differ in it; the adjoint
+                          needs 0 */
 } nh_params;
 
 typedef struct {
@@ -201,7 +209,8 @@ void nh_destroy(nh_solver *s);
  * checkpointed every ckpt_every steps and each segment is run again, with its
  * stage pressures recorded, before the adjoint goes back through it.
  *
- * Requires a 2D grid, a fixed time step (fixed_dt = 1) and breaking_on = 0.
+ * Requires a 2D grid, a fixed time step (fixed_dt = 1), breaking_on = 0 and
+ * manning = 0.
  * gauges[ngauges]: flat cell indices j*nx + i; target[nsteps][ngauges] FP64.
  * adj_tol: a transposed solve stops when its measure of eq. (32) is below
  * adj_tol * max_c |pbar_c / diag_c| (pbar: its right-hand side).

@@ -233,6 +233,7 @@ struct FvArgs {
   const double* dtp;
   T *oh, *oq1, *oq2;
   double* clamped;
+  T fric;  // g n^2 of the Manning friction law (Section 2); 0: none
   __host__ __device__ int tiles_x() const { return (nx + kFvTX - 1) / kFvTX; }
   // 1D: one thread per cell; 2D: one workgroup per tile
   __host__ __device__ int nblocks() const {
@@ -301,11 +302,16 @@ __device__ __forceinline__ void fv_cell(const LD& ld, int i, int j, V dx, V dy,
   }
 }
 
-// positivity clamp (mass added counted) and dry discharge of a stage cell
+// positivity clamp (mass added counted), dry cells without discharge, and
+// the Manning friction
+// discretised semi-implicitly (q implicit, |u| and h explicit) on the stage's
+// finite-volume result: q <- q / (1 + dt g n^2 |u| / h^(4/3)), |u| from the
+// desingularised velocities (Section 4.5)
 template <typename T>
 __device__ __forceinline__ void fv_finish(T& hs, T& qa, T& qb, T dry_eps,
                                           double dx, double dy,
-                                          double& clamp) {
+                                          double& clamp, T fric, T dt,
+                                          T delta) {
   if (hs < T(0)) {
     clamp = -(double)hs * dx * dy;
     hs = T(0);
@@ -313,6 +319,11 @@ __device__ __forceinline__ void fv_finish(T& hs, T& qa, T& qb, T dry_eps,
   if (hs <= dry_eps) {
     qa = T(0);
     qb = T(0);
+  } else if (fric > T(0)) {
+    const T u = desing(hs, qa, delta), v = desing(hs, qb, delta);
+    const T den = T(1) + dt * fric * sqrt(u * u + v * v) / (hs * cbrt(hs));
+    qa = qa / den;
+    qb = qb / den;
   }
 }
 
@@ -425,7 +436,8 @@ __device__ __forceinline__ void fv_tile_body(const FvArgs<T>& a, int bid) {
     T hs = h0 - dt * (fx[0] / a.dx + fy[0] / a.dy);
     T qa = q10 - dt * (fx[1] / a.dx + fy[2] / a.dy);
     T qb = q20 - dt * (fx[2] / a.dx + fy[1] / a.dy);
-    fv_finish(hs, qa, qb, dry_eps, (double)a.dx, (double)a.dy, clamp_local);
+    fv_finish(hs, qa, qb, dry_eps, (double)a.dx, (double)a.dy, clamp_local,
+              a.fric, dt, a.delta);
     a.oh[n] = hs;
     a.oq1[n] = qa;
     a.oq2[n] = qb;
@@ -448,7 +460,8 @@ __device__ __forceinline__ void fv_body(const FvArgs<T>& a, int bid) {
       fv_cell<T, true>(ld, n, 0, a.dx, a.dy, a.g, a.delta, a.dry_eps, dt, 3,
                        out);
       T hs = out[0], qa = out[1], qb = out[2];
-      fv_finish(hs, qa, qb, a.dry_eps, (double)a.dx, 1.0, clamp_local);
+      fv_finish(hs, qa, qb, a.dry_eps, (double)a.dx, 1.0, clamp_local, a.fric,
+                dt, a.delta);
       a.oh[n] = hs;
       a.oq1[n] = qa;
     }

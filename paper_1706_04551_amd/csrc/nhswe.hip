@@ -290,7 +290,8 @@ struct Args {
     return nh::FvArgs<T>{g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g,
                          (T)pr.delta, (T)pr.dry_eps, P(S.Vh), P(S.Vq1),
                          P(S.Vq2), P(s->H), s->dt, P(S.hs_cur), P(s->q1s),
-                         P(s->q2s), s->clamped};
+                         P(s->q2s), s->clamped,
+                         (T)(pr.g * pr.manning * pr.manning)};
   }
   static nh::BreakCellsArgs<T> break_cells(const nh_solver* s,
                                            const StagePlan& S) {
@@ -693,6 +694,8 @@ nh_status check_params(const nh_grid* g, const nh_params* p) {
     return fail(NH_EINVAL, "need g > 0 and 0 < cfl <= 1");
   if (!(p->delta > 0) || !(p->dry_eps >= 0))
     return fail(NH_EINVAL, "need delta > 0 and dry_eps >= 0");
+  if (!(p->manning >= 0) || !std::isfinite(p->manning))
+    return fail(NH_EINVAL, "need a finite manning >= 0");
   if (p->precision != NH_FP64 && p->precision != NH_FP32)
     return fail(NH_EINVAL, "precision must be NH_FP64 or NH_FP32");
   if (p->nh_on && g->ny > 1) {

@@ -251,6 +251,10 @@ def test_adjoint_rejects_what_it_does_not_cover():
     with pytest.raises(NhError):
         s.adjoint(4, g, t)
     s.close()
+    s = make(fixed_dt=1, dt_fixed=0.05, manning=0.02)   # friction
+    with pytest.raises(NhError):
+        s.adjoint(4, g, t)
+    s.close()
     s = make(fixed_dt=1, dt_fixed=0.05)
     with pytest.raises(NhError):
         s.adjoint(4, np.array([0, P["nx"] * P["ny"]]), t[:, :2])
