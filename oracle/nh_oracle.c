@@ -53,6 +53,9 @@ struct ora {
   /* work buffers */
   double *b[16];  /* ghosted cell buffers */
   double *c[16];  /* corner buffers */
+  /* relaxation zones (Section 4.4): weights and targets, NULL when off */
+  double *rm_cell, *rm_corn;               /* m of cells (ghosted), corners */
+  double *rt_h, *rt_q1, *rt_q2, *rt_w, *rt_p;
 };
 
 /* ------------------------------------------------------------------ */
@@ -880,6 +883,112 @@ static int stage_g(ora_t *o, const double *Vh, const double *Vq1,
  * (reading of "steps 1-4 repeated twice" in Section 6).  The next dt comes
  * from the CFL condition on U^{n+1}.
  */
+/* Generation/absorption zones of Section 4.4, on every wall with a width
+ * L > 0, in this reading: the zone holds the k + 1 cells nearest the wall,
+ * k the least natural number with k dx >= L; a cell at distance d from the
+ * zone's innermost cell (d = 0 .. k dx) gets m = sqrt(max(0, 1 - (d/L)^2)),
+ * so m = 1 at the inner edge and 0 at the wall cell (the paper states this
+ * for the right end; the left end mirrors it).  Cells outside every zone have
+ * m = 1; in 2D the weights of x and y multiply (each side relaxed in turn).
+ * A corner takes the mean of the two cells beside it per direction (mirrored
+ * at walls).  After each step: U <- m U + (1 - m) U*, w and p likewise with
+ * the corner weights. */
+/* the cell whose mirror image sits at index i (walls) */
+static int cell_mirror(int i, int n) {
+  return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i);
+}
+
+static void zone_weights(int n, double dx, double Llo, double Lhi, double *m) {
+  for (int i = 0; i < n; ++i) m[i] = 1.0;
+  const double L[2] = {Llo, Lhi};
+  for (int side = 0; side < 2; ++side) {
+    if (!(L[side] > 0.0)) continue;
+    int k = (int)ceil(L[side] / dx);
+    while (k > 0 && (k - 1) * dx >= L[side]) --k;  /* least k: k dx >= L */
+    for (int r = 0; r <= k && r < n; ++r) {        /* r: cells from inner */
+      const int i = side == 0 ? k - r : n - 1 - k + r;
+      if (i < 0 || i >= n) continue;
+      const double d = r * dx / L[side];
+      m[i] *= sqrt(dmax(0.0, 1.0 - d * d));
+    }
+  }
+}
+
+int ora_set_relaxation(ora_t *o, const double *widths, const double *h_t,
+                       const double *q1_t, const double *q2_t,
+                       const double *w_t, const double *p_t) {
+  if (!o || !widths) return ORA_EINVAL;
+  for (int s = 0; s < 4; ++s)
+    if (!(widths[s] >= 0.0) || isinf(widths[s])) return ORA_EINVAL;
+  const int N = o->gx * o->gy, nc = ncorners(o);
+  double **arrs[7] = {&o->rm_cell, &o->rm_corn, &o->rt_h, &o->rt_q1,
+                      &o->rt_q2,   &o->rt_w,    &o->rt_p};
+  for (int a = 0; a < 7; ++a) {
+    free(*arrs[a]);
+    *arrs[a] = NULL;
+  }
+  if (!(widths[0] > 0 || widths[1] > 0 ||
+        (!o->is1d && (widths[2] > 0 || widths[3] > 0))))
+    return ORA_OK;  /* no zone: off */
+  double *mx = (double *)malloc(sizeof(double) * o->nx);
+  double *my = (double *)malloc(sizeof(double) * (o->is1d ? 1 : o->ny));
+  zone_weights(o->nx, o->P.dx, widths[0], widths[1], mx);
+  if (o->is1d)
+    my[0] = 1.0;
+  else
+    zone_weights(o->ny, o->P.dy, widths[2], widths[3], my);
+  o->rm_cell = (double *)calloc(N, sizeof(double));
+  o->rm_corn = (double *)calloc(nc, sizeof(double));
+  o->rt_h = (double *)calloc(N, sizeof(double));
+  o->rt_q1 = (double *)calloc(N, sizeof(double));
+  o->rt_q2 = (double *)calloc(N, sizeof(double));
+  o->rt_w = (double *)calloc(nc, sizeof(double));
+  o->rt_p = (double *)calloc(nc, sizeof(double));
+  const int ny = o->is1d ? 1 : o->ny;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < o->nx; ++i) {
+      const int c = IX(o, i, j), f = j * o->nx + i;
+      o->rm_cell[c] = mx[i] * my[j];
+      /* still water by default: eta* = 0 (h* = H, none on land), q* = 0 */
+      o->rt_h[c] = h_t ? h_t[f] : dmax(o->H[c], 0.0);
+      o->rt_q1[c] = q1_t ? q1_t[f] : 0.0;
+      o->rt_q2[c] = q2_t ? q2_t[f] : 0.0;
+    }
+  for (int l = 0; l < o->ncy; ++l)
+    for (int k = 0; k < o->ncx; ++k) {
+      const int c = CX(o, k, l);
+      const double ax =
+          0.5 * (mx[cell_mirror(k - 1, o->nx)] + mx[cell_mirror(k, o->nx)]);
+      const double ay = o->is1d ? 1.0
+                                : 0.5 * (my[cell_mirror(l - 1, o->ny)] +
+                                         my[cell_mirror(l, o->ny)]);
+      o->rm_corn[c] = ax * ay;
+      o->rt_w[c] = w_t ? w_t[c] : 0.0;
+      o->rt_p[c] = p_t ? p_t[c] : 0.0;
+    }
+  free(mx);
+  free(my);
+  return ORA_OK;
+}
+
+static void relax_g(ora_t *o) {
+  if (!o->rm_cell) return;
+  const int ny = o->is1d ? 1 : o->ny;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < o->nx; ++i) {
+      const int c = IX(o, i, j);
+      const double m = o->rm_cell[c];
+      o->h[c] = m * o->h[c] + (1.0 - m) * o->rt_h[c];
+      o->q1[c] = m * o->q1[c] + (1.0 - m) * o->rt_q1[c];
+      o->q2[c] = m * o->q2[c] + (1.0 - m) * o->rt_q2[c];
+    }
+  for (int c = 0; c < ncorners(o); ++c) {
+    const double m = o->rm_corn[c];
+    o->w[c] = m * o->w[c] + (1.0 - m) * o->rt_w[c];
+    o->p[c] = m * o->p[c] + (1.0 - m) * o->rt_p[c];
+  }
+}
+
 int ora_step(ora_t *o) {
   int N = o->gx * o->gy, nc = ncorners(o);
   double dt = o->P.fixed_dt ? o->P.dt_fixed : o->dt;
@@ -903,6 +1012,7 @@ int ora_step(ora_t *o) {
     o->q2[n] = 0.5 * (o->q2[n] + q22[n]);
   }
   for (int c = 0; c < nc; ++c) o->w[c] = 0.5 * (o->w[c] + w2[c]);
+  relax_g(o);
   o->t += dt;
   o->dt_last = dt;
   o->step += 1;
@@ -984,6 +1094,13 @@ void ora_destroy(ora_t *o) {
     free(o->b[m]);
     free(o->c[m]);
   }
+  free(o->rm_cell);
+  free(o->rm_corn);
+  free(o->rt_h);
+  free(o->rt_q1);
+  free(o->rt_q2);
+  free(o->rt_w);
+  free(o->rt_p);
   free(o);
 }
 

@@ -76,6 +76,14 @@ int ora_fv_stage(ora_t *o, const double *h, const double *q1, const double *q2,
                  double dt, double *h_out, double *q1_out, double *q2_out,
                  double *clamped);
 /* Breaking terms (Section 3, eqs. 9-12, 28): q += dt*R_u, w += dt*R_w/h_c. */
+/* Generation/absorption zones of Section 4.4.  widths[4] = L of the west,
+ * east, south, north walls [m] (0: none; south/north ignored in 1D).
+ * Targets: h_t, q1_t, q2_t over the cells (row-major ny x nx), w_t, p_t over
+ * the corners; NULL gives still water (h* = max(H, 0), q* = w* = p* = 0).
+ * Call after ora_set_bathymetry.  All widths 0 switches the zones off. */
+int ora_set_relaxation(ora_t *o, const double *widths, const double *h_t,
+                       const double *q1_t, const double *q2_t,
+                       const double *w_t, const double *p_t);
 int ora_breaking(ora_t *o, const double *h, double *q1, double *q2, double *w,
                  double dt);
 /* Pressure system coefficients.  2D: 5-point closed form, rows scaled as

@@ -53,6 +53,7 @@ def lib():
         L.ora_set_state.argtypes = [C.c_void_p, _DP, _DP, _DP, _DP, _DP]
         L.ora_get_state.argtypes = [C.c_void_p, _DP, _DP, _DP, _DP, _DP]
         L.ora_step.argtypes = [C.c_void_p]
+        L.ora_set_relaxation.argtypes = [C.c_void_p] + [_DP] * 6
         L.ora_run.argtypes = [C.c_void_p, C.c_int64]
         L.ora_get_stats.argtypes = [C.c_void_p, _DP]
         L.ora_cfl_dt.restype = C.c_double
@@ -168,6 +169,17 @@ class Oracle:
         st = lib().ora_set_state(self._h, _p(h), _p(hu), _p(hv), _p(w), _p(p))
         if st != 0:
             raise ValueError(f"oracle set_state status {st}")
+
+    def set_relaxation(self, widths, h=None, hu=None, hv=None, w=None,
+                       p=None):
+        """Generation/absorption zones (Section 4.4): widths = (west, east,
+        south, north) in metres; targets default to still water."""
+        wd = _f64(np.asarray(widths, dtype=np.float64).ravel(), (4,))
+        self._relax = [wd] + [self._cells(a) for a in (h, hu, hv)] + \
+            [self._corn(a) for a in (w, p)]
+        st = lib().ora_set_relaxation(self._h, *[_p(a) for a in self._relax])
+        if st != 0:
+            raise ValueError(f"oracle set_relaxation status {st}")
 
     def step(self) -> int:
         return lib().ora_step(self._h)
