@@ -987,6 +987,10 @@ static void relax_g(ora_t *o) {
     o->w[c] = m * o->w[c] + (1.0 - m) * o->rt_w[c];
     o->p[c] = m * o->p[c] + (1.0 - m) * o->rt_p[c];
   }
+  /* the wall ghosts image the relaxed state */
+  fill_ghosts(o, o->h, 1.0, 1.0);
+  fill_ghosts(o, o->q1, -1.0, 1.0);
+  fill_ghosts(o, o->q2, 1.0, -1.0);
 }
 
 int ora_step(ora_t *o) {
