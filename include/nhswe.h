@@ -144,6 +144,26 @@ nh_status nh_set_bathymetry(nh_solver *s, const double *H);
 nh_status nh_set_state(nh_solver *s, const double *h, const double *hu,
                        const double *hv, const double *w, const double *p);
 
+/* Generation/absorption zones (Section 4.4): after every step the state in a
+ * zone is relaxed towards a target, U <- m U + (1 - m) U* in the cells, and
+ * w and p likewise at the corners.  widths[4]: zone widths L [m] at the
+ * west, east, south, north walls (0: no zone; south/north ignored in 1D).
+ * Along one direction, the k + 1 cells nearest a wall with a zone (k the
+ * least natural number with k dx >= L) get m = sqrt(max(0, 1 - (d/L)^2)),
+ * d the distance to the zone's innermost cell, so m = 1 at its inner edge
+ * and 0 at the wall cell; every other cell has m = 1.  In 2D the weights of
+ * x and y multiply; a corner takes, per direction, the mean of the two
+ * cells beside it (mirrored at a wall).  Targets, copied: h_t, q1_t, q2_t
+ * over the cells (row-major ny x nx, h_t >= 0), w_t, p_t over the corners;
+ * NULL gives still water (h* = max(H, 0), q* = w* = p* = 0: the absorbing
+ * zone), so call nh_set_bathymetry first.  All widths 0 switches the zones
+ * off.  NH_EINVAL for negative or non-finite widths or targets.  The
+ * adjoint refuses a solver with zones. */
+nh_status nh_set_relaxation(nh_solver *s, const double *widths,
+                            const double *h_t, const double *q1_t,
+                            const double *q2_t, const double *w_t,
+                            const double *p_t);
+
 /* Device memory owned by the caller (for instance PyTorch tensors) that the
  * solver borrows for the bathymetry and for the state U^n = (h, hu, hv) and
  * w of the scheme (Section 5, eq. 31), so that inputs and results need no
@@ -209,8 +229,8 @@ void nh_destroy(nh_solver *s);
  * checkpointed every ckpt_every steps and each segment is run again, with its
  * stage pressures recorded, before the adjoint goes back through it.
  *
- * Requires a 2D grid, a fixed time step (fixed_dt = 1), breaking_on = 0 and
- * manning = 0.
+ * Requires a 2D grid, a fixed time step (fixed_dt = 1), breaking_on = 0,
+ * manning = 0 and no relaxation zones.
  * gauges[ngauges]: flat cell indices j*nx + i; target[nsteps][ngauges] FP64.
  * adj_tol: a transposed solve stops when its measure of eq. (32) is below
  * adj_tol * max_c |pbar_c / diag_c| (pbar: its right-hand side).

@@ -80,6 +80,7 @@ def lib():
         L.nh_create.argtypes = [C.POINTER(NhGrid), C.POINTER(NhParams), vp,
                                 C.POINTER(vp)]
         L.nh_set_bathymetry.argtypes = [vp, _DP]
+        L.nh_set_relaxation.argtypes = [vp] + [_DP] * 6
         L.nh_set_state.argtypes = [vp, _DP, _DP, _DP, _DP, _DP]
         L.nh_step.argtypes = [vp, _DP]
         L.nh_run.argtypes = [vp, C.c_int64]
@@ -112,7 +113,8 @@ def lib():
         L.nh_ensemble_destroy.restype = None
         L.nh_last_error.restype = C.c_char_p
         L.nh_version.restype = C.c_char_p
-        for f in ("nh_create", "nh_set_bathymetry", "nh_set_state", "nh_step",
+        for f in ("nh_create", "nh_set_bathymetry", "nh_set_relaxation",
+                  "nh_set_state", "nh_step",
                   "nh_run", "nh_read_state", "nh_bind_device_buffers", "nh_get_stats", "nh_profile",
                   "nh_get_profile", "nh_adjoint_run", "nh_ensemble_create",
                   "nh_ensemble_set_bathymetry", "nh_ensemble_set_state",
@@ -247,6 +249,17 @@ class Solver:
     def set_bathymetry(self, H):
         H = _f64(H, self.shape)
         _check(lib().nh_set_bathymetry(self._h, _ptr(H)), "nh_set_bathymetry")
+
+    def set_relaxation(self, widths, h=None, hu=None, hv=None, w=None,
+                       p=None):
+        """Generation/absorption zones: widths (west, east, south, north)
+        in metres; targets default to still water (the absorbing zone)."""
+        wd = _f64(widths, (4,))
+        t = [_f64(a, self.shape) for a in (h, hu, hv)] + \
+            [_f64(a, self.cshape) for a in (w, p)]
+        _check(lib().nh_set_relaxation(self._h, _ptr(wd),
+                                       *[_ptr(a) for a in t]),
+               "nh_set_relaxation")
 
     def set_state(self, h, hu, hv=None, w=None, p=None):
         h, hu = _f64(h, self.shape), _f64(hu, self.shape)

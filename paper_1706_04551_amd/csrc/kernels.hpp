@@ -939,6 +939,10 @@ struct CorrectArgs {
   T *oq1, *oq2, *w_out, *h_n, *q1_n, *q2_n;
   double* lampart;
   int* flags;
+  // generation/absorption zones (Section 4.4), applied with the RK average:
+  // weights of the state and targets in the cells and at the corners (null:
+  // no zones)
+  const T *rm_c, *rt_h, *rt_q1, *rt_q2, *rm_k, *rt_w;
   __host__ __device__ int nblocks(bool one_d) const {
     int nc = nx * ny, nk = (nx + 1) * (one_d ? 1 : ny + 1);
     return ((nc > nk ? nc : nk) + kBlock - 1) / kBlock;
@@ -1034,6 +1038,12 @@ __device__ __forceinline__ void correct_body(const CorrectArgs<T>& a,
       T hn = T(0.5) * (a.h_n[n] + hc);
       T an = T(0.5) * (a.q1_n[n] + qa);
       T bn = ONE_D ? T(0) : T(0.5) * (a.q2_n[n] + qb);
+      if (a.rm_c) {  // U <- m U + (1 - m) U* in the zones
+        const T m = a.rm_c[n];
+        hn = m * hn + (T(1) - m) * a.rt_h[n];
+        an = m * an + (T(1) - m) * a.rt_q1[n];
+        if (!ONE_D) bn = m * bn + (T(1) - m) * a.rt_q2[n];
+      }
       a.h_n[n] = hn;
       a.q1_n[n] = an;
       if (!ONE_D) a.q2_n[n] = bn;
@@ -1057,10 +1067,16 @@ __device__ __forceinline__ void correct_body(const CorrectArgs<T>& a,
     T wv = a.ws[n];
     if (have_p)
       wv = correct_corner<T, ONE_D>(ld, k, l, wv, (T)p[n], dt, delta);
-    if (COMBINE)
-      a.w_out[n] = T(0.5) * (a.w_out[n] + wv);
-    else
+    if (COMBINE) {
+      T wn = T(0.5) * (a.w_out[n] + wv);
+      if (a.rm_k) {
+        const T m = a.rm_k[n];
+        wn = m * wn + (T(1) - m) * a.rt_w[n];
+      }
+      a.w_out[n] = wn;
+    } else {
       a.w_out[n] = wv;
+    }
   }
   if (COMBINE) {
     __shared__ double wmax[kBlock / 64];
@@ -1074,6 +1090,18 @@ __device__ __forceinline__ void correct_body(const CorrectArgs<T>& a,
       a.lampart[bid] = m;
     }
   }
+}
+
+// p <- m p + (1 - m) p* at the corners of the zones, after the step's
+// correction (other threads of the correction still read p)
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_relax_p(int n, double* __restrict__ p, const T* __restrict__ m,
+              const double* __restrict__ pt) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= n) return;
+  const double w = (double)m[c];
+  p[c] = w * p[c] + (1.0 - w) * pt[c];
 }
 
 // CFL measure of a state (used at set_state): per-block maxima of

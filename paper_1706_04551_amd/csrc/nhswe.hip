@@ -158,6 +158,11 @@ struct nh_solver {
        *cS = nullptr, *crhs = nullptr;
   double *thomas_cp = nullptr, *thomas_dp = nullptr;
   void *stage_buf = nullptr;   // FP64 staging for host copies
+  // generation/absorption zones: weights and targets (bulk type; p* FP64)
+  bool relax_on = false;
+  void *rm_c = nullptr, *rt_h = nullptr, *rt_q1 = nullptr, *rt_q2 = nullptr,
+       *rm_k = nullptr, *rt_w = nullptr;
+  double* rt_p = nullptr;
   // device scalars
   double* dt = nullptr;
   double* lampart = nullptr;             // per-block CFL measures
@@ -351,7 +356,11 @@ struct Args {
                               P(S.qb), P(s->H), P(S.wst),
                               (const double*)(p ? p : s->pa), s->dt,
                               P(S.oq1), P(S.oq2), P(S.w_out), P(s->h),
-                              P(s->q1), P(s->q2), s->lampart, s->flags};
+                              P(s->q1), P(s->q2), s->lampart, s->flags,
+                              s->relax_on ? P(s->rm_c) : nullptr, P(s->rt_h),
+                              P(s->rt_q1), P(s->rt_q2),
+                              s->relax_on ? P(s->rm_k) : nullptr,
+                              P(s->rt_w)};
   }
   static nh::LambdaArgs<T> lambda(const nh_solver* s) {
     const auto& g = s->grid;
@@ -617,6 +626,10 @@ nh_status stage(nh_solver* s, int idx, int32_t* sweeps, double* measure) {
   }
   pm = s->prof.open(s->stream, 3);
   Launch<T>::correct(s, S, p);
+  if (S.combine && s->relax_on && p)
+    hipLaunchKernelGGL((nh::k_relax_p<T>), dim3(nblocks(s->ncorn)),
+                       dim3(nh::kBlock), 0, s->stream, (int)s->ncorn,
+                       (double*)p, (const T*)s->rm_k, s->rt_p);
   s->prof.close(s->stream, pm, 1);
   return st;
 }
@@ -942,6 +955,109 @@ nh_status nh_set_bathymetry(nh_solver* s, const double* H) {
   nh_status st = upload(s, s->H, H, s->ncell);
   if (st == NH_OK) s->have_H = true;
   return st;
+}
+
+// weights of the generation/absorption zones along one direction of n cells
+// (low and high walls of widths Llo, Lhi): the k + 1 cells nearest a wall
+// with a zone, k the least natural number with k dx >= L, get
+// m = sqrt(max(0, 1 - (d/L)^2)), d the distance to the zone's innermost cell
+static void zone_profile(int n, double dx, double Llo, double Lhi,
+                         std::vector<double>& m) {
+  m.assign(n, 1.0);
+  const double L[2] = {Llo, Lhi};
+  for (int side = 0; side < 2; ++side) {
+    if (!(L[side] > 0.0)) continue;
+    long k = (long)std::ceil(L[side] / dx);
+    while (k > 0 && (double)(k - 1) * dx >= L[side]) --k;
+    for (long r = 0; r <= k; ++r) {
+      const long i = side == 0 ? k - r : n - 1 - k + r;
+      if (i < 0 || i >= n) continue;
+      const double d = (double)r * dx / L[side];
+      m[i] *= std::sqrt(std::max(0.0, 1.0 - d * d));
+    }
+  }
+}
+
+nh_status nh_set_relaxation(nh_solver* s, const double* widths,
+                            const double* h_t, const double* q1_t,
+                            const double* q2_t, const double* w_t,
+                            const double* p_t) {
+  if (!s || !widths) return fail(NH_EINVAL, "null argument");
+  for (int i = 0; i < 4; ++i)
+    if (!(widths[i] >= 0.0) || !std::isfinite(widths[i]))
+      return fail(NH_EINVAL, "zone widths must be finite and >= 0");
+  const bool on = widths[0] > 0 || widths[1] > 0 ||
+                  (!s->one_d && (widths[2] > 0 || widths[3] > 0));
+  s->relax_on = false;
+  if (!on) return NH_OK;
+  if (!h_t && !s->have_H) return fail(NH_ESTATE, "set the bathymetry first");
+  const int nx = s->grid.nx, ny = s->one_d ? 1 : s->grid.ny;
+  const int ncx = nx + 1, ncy = s->one_d ? 1 : ny + 1;
+  std::vector<double> mx, my;
+  zone_profile(nx, s->grid.dx, widths[0], widths[1], mx);
+  if (s->one_d)
+    my.assign(1, 1.0);
+  else
+    zone_profile(ny, s->grid.dy, widths[2], widths[3], my);
+  auto mir = [](int i, int n) {
+    return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i);
+  };
+  std::vector<double> mc(s->ncell), mk(s->ncorn), th(s->ncell), tq1(s->ncell),
+      tq2(s->ncell), tw(s->ncorn), tp(s->ncorn);
+  std::vector<double> Hh;
+  nh_status st;
+  if (!h_t) {  // still water: h* = max(H, 0)
+    Hh.resize(s->ncell);
+    if ((st = download(s, Hh.data(), s->H, s->ncell)) != NH_OK) return st;
+  }
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const long c = (long)j * nx + i;
+      mc[c] = mx[i] * my[j];
+      th[c] = h_t ? h_t[c] : std::max(Hh[c], 0.0);
+      tq1[c] = q1_t ? q1_t[c] : 0.0;
+      tq2[c] = q2_t ? q2_t[c] : 0.0;
+    }
+  for (int l = 0; l < ncy; ++l)
+    for (int k = 0; k < ncx; ++k) {
+      const long c = (long)l * ncx + k;
+      const double ax = 0.5 * (mx[mir(k - 1, nx)] + mx[mir(k, nx)]);
+      const double ay =
+          s->one_d ? 1.0 : 0.5 * (my[mir(l - 1, ny)] + my[mir(l, ny)]);
+      mk[c] = ax * ay;
+      tw[c] = w_t ? w_t[c] : 0.0;
+      tp[c] = p_t ? p_t[c] : 0.0;
+    }
+  for (long c = 0; c < s->ncell; ++c)
+    if (!std::isfinite(th[c]) || !std::isfinite(tq1[c]) ||
+        !std::isfinite(tq2[c]) || th[c] < 0.0)
+      return fail(NH_EINVAL, "targets must be finite, with h* >= 0");
+  for (long c = 0; c < s->ncorn; ++c)
+    if (!std::isfinite(tw[c]) || !std::isfinite(tp[c]))
+      return fail(NH_EINVAL, "targets must be finite");
+  if (!s->rm_c) {  // first use: the zone arrays, kept for the solver's life
+    void** cells[] = {&s->rm_c, &s->rt_h, &s->rt_q1, &s->rt_q2};
+    void** corners[] = {&s->rm_k, &s->rt_w};
+    for (auto a : cells)
+      if ((st = dalloc(s, a, s->ncell * s->esize)) != NH_OK) return st;
+    for (auto a : corners)
+      if ((st = dalloc(s, a, s->ncorn * s->esize)) != NH_OK) return st;
+    if ((st = dalloc(s, (void**)&s->rt_p, s->ncorn * sizeof(double))) !=
+        NH_OK)
+      return st;
+  }
+  if ((st = upload(s, s->rm_c, mc.data(), s->ncell)) != NH_OK ||
+      (st = upload(s, s->rt_h, th.data(), s->ncell)) != NH_OK ||
+      (st = upload(s, s->rt_q1, tq1.data(), s->ncell)) != NH_OK ||
+      (st = upload(s, s->rt_q2, tq2.data(), s->ncell)) != NH_OK ||
+      (st = upload(s, s->rm_k, mk.data(), s->ncorn)) != NH_OK ||
+      (st = upload(s, s->rt_w, tw.data(), s->ncorn)) != NH_OK)
+    return st;
+  HIP_TRY(hipMemcpyAsync(s->rt_p, tp.data(), s->ncorn * sizeof(double),
+                         hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->relax_on = true;
+  return NH_OK;
 }
 
 nh_status nh_set_state(nh_solver* s, const double* h, const double* hu,

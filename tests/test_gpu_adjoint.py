@@ -255,6 +255,11 @@ def test_adjoint_rejects_what_it_does_not_cover():
     with pytest.raises(NhError):
         s.adjoint(4, g, t)
     s.close()
+    s = make(fixed_dt=1, dt_fixed=0.05)                 # relaxation zones
+    s.set_relaxation((3.0, 0.0, 0.0, 0.0))
+    with pytest.raises(NhError):
+        s.adjoint(4, g, t)
+    s.close()
     s = make(fixed_dt=1, dt_fixed=0.05)
     with pytest.raises(NhError):
         s.adjoint(4, np.array([0, P["nx"] * P["ny"]]), t[:, :2])
