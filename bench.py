@@ -322,6 +322,10 @@ def run_single(args):
         desc += f", Manning n={case.manning:g}"
     stream = torch.cuda.current_stream()
     s = Solver.from_case(case, stream=stream.cuda_stream)
+    zones = getattr(args, "zones", None)
+    if zones:
+        s.set_relaxation((zones,) * 4)   # absorbing zones on every wall
+        desc += f", absorbing zones {zones:g} m"
     ncell = case.nx * case.ny
 
     # warmup, then reset to the initial state (uploads are outside the timing)
@@ -420,6 +424,9 @@ def main():
                     help="override the workload's stop tolerance (eq. 32)")
     ap.add_argument("--manning", type=float, default=None,
                     help="Gauckler-Manning n of the friction law (default 0)")
+    ap.add_argument("--zones", type=float, default=None,
+                    help="width [m] of absorbing relaxation zones on every "
+                         "wall (default none)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain copy of 256 MiB (for counter runs)")
@@ -472,6 +479,11 @@ def main():
             v.no_cpu, v.manning = True, 0.012   # the paper's flume roughness
             variants["c2_fp64_manning"] = variant_summary(run_single(v))
             note("c2 FP64 with friction done")
+            v = copy.copy(args)
+            v.no_cpu, v.zones = True, 32.0   # ~1.5 wavelengths of the hump
+            variants["c2_fp64_absorbing_zones"] = variant_summary(
+                run_single(v))
+            note("c2 FP64 with absorbing zones done")
             v = copy.copy(args)
             v.workload, v.precision, v.no_cpu = "c3", "f32", True
             v.steps = 4000          # the beach workload's full run
