@@ -104,17 +104,22 @@ static double desing_div(double num, double h, double delta) {
  * ghost -1 <-> cell 0, ghost -2 <-> cell 1, and likewise on the far side.
  * px / py = +1 (even) or -1 (odd) parity across x / y walls. */
 static void fill_ghosts(const ora_t *o, double *a, double px, double py) {
+  /* Outflow sides (Section 4.4, homogeneous Neumann): the ghosts take the
+   * value of the adjacent cell, with no change of sign. */
+  const int open = o->P.open_sides;
   int nx = o->nx, ny = o->ny;
   for (int j = 0; j < ny; ++j)
     for (int g = 1; g <= GH; ++g) {
-      a[IX(o, -g, j)] = px * a[IX(o, g - 1, j)];
-      a[IX(o, nx - 1 + g, j)] = px * a[IX(o, nx - g, j)];
+      a[IX(o, -g, j)] = (open & 1) ? a[IX(o, 0, j)] : px * a[IX(o, g - 1, j)];
+      a[IX(o, nx - 1 + g, j)] =
+          (open & 2) ? a[IX(o, nx - 1, j)] : px * a[IX(o, nx - g, j)];
     }
   if (o->is1d) return;
   for (int i = -GH; i < nx + GH; ++i)
     for (int g = 1; g <= GH; ++g) {
-      a[IX(o, i, -g)] = py * a[IX(o, i, g - 1)];
-      a[IX(o, i, ny - 1 + g)] = py * a[IX(o, i, ny - g)];
+      a[IX(o, i, -g)] = (open & 4) ? a[IX(o, i, 0)] : py * a[IX(o, i, g - 1)];
+      a[IX(o, i, ny - 1 + g)] =
+          (open & 8) ? a[IX(o, i, ny - 1)] : py * a[IX(o, i, ny - g)];
     }
 }
 
@@ -1052,6 +1057,7 @@ ora_t *ora_create(const ora_params *pp, const double *omega, int32_t n_omega) {
   if (!pp || pp->nx < 2 || pp->ny < 1 || !(pp->dx > 0) || !(pp->dy > 0))
     return NULL;
   if (!(pp->manning >= 0.0) || isinf(pp->manning)) return NULL;
+  if (pp->open_sides < 0 || pp->open_sides > 15) return NULL;
   ora_t *o = (ora_t *)calloc(1, sizeof(ora_t));
   o->P = *pp;
   o->is1d = pp->ny == 1;

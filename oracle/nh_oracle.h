@@ -41,6 +41,9 @@ typedef struct ora_params {
   double dt_fixed;
   double manning;          /* Gauckler-Manning n of the friction law of
                               Section 2 [s m^-1/3]; 0: no friction */
+  int32_t open_sides;      /* outflow sides of Section 4.4 (homogeneous
+                              Neumann ghosts), a bit each: 1 west, 2 east,
+                              4 south, 8 north; the others are walls */
 } ora_params;
 
 /* status codes */

@@ -32,7 +32,7 @@ class OraParams(C.Structure):
         ("solve_max_iter", C.c_int32), ("check_every", C.c_int32),
         ("solve_tol", C.c_double),
         ("fixed_dt", C.c_int32), ("dt_fixed", C.c_double),
-        ("manning", C.c_double),
+        ("manning", C.c_double), ("open_sides", C.c_int32),
     ]
 
 
@@ -114,6 +114,7 @@ class Params:
     fixed_dt: int = 0
     dt_fixed: float = 0.0
     manning: float = 0.0
+    open_sides: int = 0
     omega: np.ndarray = field(default_factory=lambda: np.ones(1))
 
     def c_struct(self) -> OraParams:
@@ -121,7 +122,7 @@ class Params:
                          self.delta, self.dry_eps, self.nh_on, self.breaking_on,
                          self.b1, self.b2, self.solve_max_iter,
                          self.check_every, self.solve_tol, self.fixed_dt,
-                         self.dt_fixed, self.manning)
+                         self.dt_fixed, self.manning, self.open_sides)
 
 
 class Oracle:
