@@ -99,6 +99,13 @@ typedef struct {
                           h^(4/3)), |u| from the desingularised velocities.
                           Ensemble members may differ in it; the adjoint
                           needs 0 */
+  int32_t open_sides;  /* outflow boundaries (Section 4.4), a bit per side:
+                          1 west (x = 0), 2 east, 4 south (y = 0), 8 north
+                          (south/north ignored in 1D).  An open side has
+                          homogeneous Neumann ghosts that copy the adjacent
+                          cell (h, H and both discharges); p is even across
+                          it, as at a wall.  Unset sides are walls.  The
+                          adjoint needs 0 */
 } nh_params;
 
 typedef struct {
@@ -230,7 +237,7 @@ void nh_destroy(nh_solver *s);
  * stage pressures recorded, before the adjoint goes back through it.
  *
  * Requires a 2D grid, a fixed time step (fixed_dt = 1), breaking_on = 0,
- * manning = 0 and no relaxation zones.
+ * manning = 0, open_sides = 0 and no relaxation zones.
  * gauges[ngauges]: flat cell indices j*nx + i; target[nsteps][ngauges] FP64.
  * adj_tol: a transposed solve stops when its measure of eq. (32) is below
  * adj_tol * max_c |pbar_c / diag_c| (pbar: its right-hand side).

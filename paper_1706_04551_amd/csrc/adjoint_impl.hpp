@@ -429,6 +429,8 @@ nh_status nh_adjoint_run(nh_solver* s, int64_t nsteps, int32_t ngauges,
     return fail(NH_EINVAL, "the adjoint does not cover friction");
   if (s->relax_on)
     return fail(NH_EINVAL, "the adjoint does not cover relaxation zones");
+  if (s->par.open_sides != 0)
+    return fail(NH_EINVAL, "the adjoint covers walls only");
   if (nsteps < 1 || ngauges < 1 || ckpt_every < 1)
     return fail(NH_EINVAL, "need nsteps, ngauges, ckpt_every >= 1");
   if (!(adj_tol > 0)) return fail(NH_EINVAL, "need adj_tol > 0");

@@ -25,6 +25,19 @@ __device__ __forceinline__ int mirror(int i, int n) {
   return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i);
 }
 
+// open (outflow) sides of a grid, a bit each: homogeneous Neumann ghosts
+// that copy the adjacent cell (Section 4.4); every other side is a wall
+constexpr int kOpenW = 1, kOpenE = 2, kOpenS = 4, kOpenN = 8;
+
+// the cell whose values position i of a line of n cells takes: its mirror
+// image at a wall, the end cell itself at an open end
+__device__ __forceinline__ int ghost_src(int i, int n, bool open_lo,
+                                         bool open_hi) {
+  if (i < 0) return open_lo ? 0 : -1 - i;
+  if (i >= n) return open_hi ? n - 1 : 2 * n - 1 - i;
+  return i;
+}
+
 template <typename T>
 __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
 template <typename T>
@@ -59,17 +72,18 @@ __device__ __forceinline__ Cell<T> load_cell(const T* __restrict__ h,
                                              const T* __restrict__ q2,
                                              const T* __restrict__ H, int i,
                                              int j, int nx, int ny,
-                                             bool one_d) {
-  int mi = mirror(i, nx);
-  int mj = one_d ? 0 : mirror(j, ny);
+                                             bool one_d, int open = 0) {
+  int mi = ghost_src(i, nx, open & kOpenW, open & kOpenE);
+  int mj = one_d ? 0 : ghost_src(j, ny, open & kOpenS, open & kOpenN);
   int idx = mj * nx + mi;
   Cell<T> c;
   c.h = h[idx];
   c.H = H[idx];
   c.q1 = q1[idx];
   c.q2 = one_d ? T(0) : q2[idx];
-  if (mi != i) c.q1 = -c.q1;
-  if (mj != j) c.q2 = -c.q2;
+  // the normal discharge is odd across a wall, even across an open end
+  if (mi != i && !(open & (i < 0 ? kOpenW : kOpenE))) c.q1 = -c.q1;
+  if (mj != j && !(open & (j < 0 ? kOpenS : kOpenN))) c.q2 = -c.q2;
   return c;
 }
 
@@ -234,6 +248,7 @@ struct FvArgs {
   T *oh, *oq1, *oq2;
   double* clamped;
   T fric;  // g n^2 of the Manning friction law (Section 2); 0: none
+  int open;  // open sides (kOpen*)
   __host__ __device__ int tiles_x() const { return (nx + kFvTX - 1) / kFvTX; }
   // 1D: one thread per cell; 2D: one workgroup per tile
   __host__ __device__ int nblocks() const {
@@ -247,8 +262,9 @@ template <typename T, bool ONE_D>
 struct CellLoader {
   const T *h, *q1, *q2, *H;
   int nx, ny;
+  int open = 0;  // open sides (kOpen*)
   __device__ __forceinline__ Cell<T> operator()(int i, int j) const {
-    return load_cell(h, q1, q2, H, i, j, nx, ny, ONE_D);
+    return load_cell(h, q1, q2, H, i, j, nx, ny, ONE_D, open);
   }
 };
 
@@ -352,7 +368,8 @@ __device__ __forceinline__ void fv_tile_body(const FvArgs<T>& a, int bid) {
     const int i = i0 - 2 + rx, j = j0 - 2 + ry;
     T h = T(0), u = T(0), v = T(0), e = T(0);
     if (i <= nx + 1 && j <= ny + 1) {  // the cells a grid cell's stencil reads
-      const Cell<T> c = load_cell(a.h, a.q1, a.q2, a.H, i, j, nx, ny, false);
+      const Cell<T> c =
+          load_cell(a.h, a.q1, a.q2, a.H, i, j, nx, ny, false, a.open);
       h = c.h;
       u = desing(c.h, c.q1, delta);
       v = desing(c.h, c.q2, delta);
@@ -455,7 +472,7 @@ __device__ __forceinline__ void fv_body(const FvArgs<T>& a, int bid) {
     double clamp_local = 0.0;
     if (n < a.nx) {
       T dt = (T)(*a.dtp);
-      CellLoader<T, true> ld{a.h, a.q1, a.q2, a.H, a.nx, 1};
+      CellLoader<T, true> ld{a.h, a.q1, a.q2, a.H, a.nx, 1, a.open};
       T out[3];
       fv_cell<T, true>(ld, n, 0, a.dx, a.dy, a.g, a.delta, a.dry_eps, dt, 3,
                        out);
@@ -481,6 +498,7 @@ struct BreakCellsArgs {
   const T *h, *q1, *q2, *H;
   const double* dtp;
   T *oq1, *oq2, *rw;
+  int open;  // open sides (kOpen*)
   __host__ __device__ int nblocks() const { return (nx * ny + kBlock - 1) / kBlock; }
 };
 
@@ -498,15 +516,15 @@ __device__ __forceinline__ void break_cells_body(const BreakCellsArgs<T>& a,
   if (n >= nx * ny) return;
   int i = n % nx, j = n / nx;
   T dt = (T)(*a.dtp);
-  Cell<T> e = load_cell(h, q1, q2, H, i + 1, j, nx, ny, ONE_D);
-  Cell<T> w = load_cell(h, q1, q2, H, i - 1, j, nx, ny, ONE_D);
+  Cell<T> e = load_cell(h, q1, q2, H, i + 1, j, nx, ny, ONE_D, a.open);
+  Cell<T> w = load_cell(h, q1, q2, H, i - 1, j, nx, ny, ONE_D, a.open);
   T divq = (e.q1 - w.q1) / (T(2) * dx);
   T divu = (desing(e.h, e.q1, delta) - desing(w.h, w.q1, delta)) / (T(2) * dx);
   T Hx = (e.H - w.H) / (T(2) * dx);
   T Hy = T(0);
   if (!ONE_D) {
-    Cell<T> nn = load_cell(h, q1, q2, H, i, j + 1, nx, ny, false);
-    Cell<T> ss = load_cell(h, q1, q2, H, i, j - 1, nx, ny, false);
+    Cell<T> nn = load_cell(h, q1, q2, H, i, j + 1, nx, ny, false, a.open);
+    Cell<T> ss = load_cell(h, q1, q2, H, i, j - 1, nx, ny, false, a.open);
     divq += (nn.q2 - ss.q2) / (T(2) * dy);
     divu += (desing(nn.h, nn.q2, delta) - desing(ss.h, ss.q2, delta)) /
             (T(2) * dy);
@@ -586,6 +604,7 @@ struct AssembleArgs {
   const T *h, *q1, *q2, *H, *w;
   const double* dtp;
   T *diag, *cE, *cW, *cN, *cS, *rhs;
+  int open;  // open sides (kOpen*)
   __host__ __device__ int nblocks() const { return ((nx + 1) * (ny + 1) + kBlock - 1) / kBlock; }
 };
 
@@ -657,7 +676,7 @@ __device__ __forceinline__ void assemble2d_body(const AssembleArgs<T>& a,
   if (n >= ncx * ncy) return;
   int k = n % ncx, l = n / ncx;
   T dt = (T)(*a.dtp);
-  CellLoader<T, false> ld{a.h, a.q1, a.q2, a.H, nx, ny};
+  CellLoader<T, false> ld{a.h, a.q1, a.q2, a.H, nx, ny, a.open};
   T row[6];
   assemble_row<T>(ld, k, l, nx, ny, a.dx, a.dy, a.w[n], dt, row);
   a.diag[n] = row[0];
@@ -676,17 +695,18 @@ __global__ void __launch_bounds__(kBlock)
                  const T* __restrict__ q, const T* __restrict__ H,
                  const T* __restrict__ w, const double* __restrict__ dtp,
                  T* __restrict__ a, T* __restrict__ b, T* __restrict__ c,
-                 T* __restrict__ rhs) {
+                 T* __restrict__ rhs, int open) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k > nx) return;
   T dt = (T)(*dtp);
+  const bool ow = open & kOpenW, oe = open & kOpenE;
   auto zeta = [&](int i) {
-    int m = mirror(i, nx);
+    int m = ghost_src(i, nx, ow, oe);
     return h[m] - T(2) * H[m];
   };
   auto qv = [&](int i) {
-    int m = mirror(i, nx);
-    return m != i ? -q[m] : q[m];
+    int m = ghost_src(i, nx, ow, oe);
+    return (m != i && !(i < 0 ? ow : oe)) ? -q[m] : q[m];
   };
   int Wi = mirror(k - 1, nx), Ei = mirror(k, nx);
   T hW = h[Wi], hE = h[Ei];
@@ -943,6 +963,7 @@ struct CorrectArgs {
   // weights of the state and targets in the cells and at the corners (null:
   // no zones)
   const T *rm_c, *rt_h, *rt_q1, *rt_q2, *rm_k, *rt_w;
+  int open;  // open sides (kOpen*)
   __host__ __device__ int nblocks(bool one_d) const {
     int nc = nx * ny, nk = (nx + 1) * (one_d ? 1 : ny + 1);
     return ((nc > nk ? nc : nk) + kBlock - 1) / kBlock;
@@ -1024,7 +1045,7 @@ __device__ __forceinline__ void correct_body(const CorrectArgs<T>& a,
   const int ncx = nx + 1, ncy = ONE_D ? 1 : ny + 1;
   const T dt = (T)(*a.dtp);
   double lam_local = 0.0;
-  CellLoader<T, ONE_D> ld{hs, a.q1s, a.q2s, H, nx, ONE_D ? 1 : ny};
+  CellLoader<T, ONE_D> ld{hs, a.q1s, a.q2s, H, nx, ONE_D ? 1 : ny, a.open};
   PLoader<T> pl{p, ncx};
   if (n < nx * ny) {
     int i = n % nx, j = n / nx;

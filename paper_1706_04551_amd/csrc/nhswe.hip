@@ -296,7 +296,7 @@ struct Args {
                          (T)pr.delta, (T)pr.dry_eps, P(S.Vh), P(S.Vq1),
                          P(S.Vq2), P(s->H), s->dt, P(S.hs_cur), P(s->q1s),
                          P(s->q2s), s->clamped,
-                         (T)(pr.g * pr.manning * pr.manning)};
+                         (T)(pr.g * pr.manning * pr.manning), pr.open_sides};
   }
   static nh::BreakCellsArgs<T> break_cells(const nh_solver* s,
                                            const StagePlan& S) {
@@ -305,7 +305,8 @@ struct Args {
     return nh::BreakCellsArgs<T>{g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g,
                                  (T)pr.delta, (T)pr.dry_eps, (T)pr.b1,
                                  P(S.hs_cur), P(s->q1s), P(s->q2s), P(s->H),
-                                 s->dt, P(s->q1b), P(s->q2b), P(s->rw)};
+                                 s->dt, P(s->q1b), P(s->q2b), P(s->rw),
+                                 pr.open_sides};
   }
   static nh::BreakCornersArgs<T> break_corners(const nh_solver* s,
                                                const StagePlan& S) {
@@ -318,7 +319,7 @@ struct Args {
     return nh::AssembleArgs<T>{g.nx, g.ny, (T)g.dx, (T)g.dy, P(S.hs_cur),
                                P(S.qa), P(S.qb), P(s->H), P(S.wst), s->dt,
                                P(s->cdiag), P(s->cE), P(s->cW), P(s->cN),
-                               P(s->cS), P(s->crhs)};
+                               P(s->cS), P(s->crhs), s->par.open_sides};
   }
   static nh::SweepArgs<T> sweep(const nh_solver* s) {
     return sweep(s, forward_system(s));
@@ -360,7 +361,7 @@ struct Args {
                               s->relax_on ? P(s->rm_c) : nullptr, P(s->rt_h),
                               P(s->rt_q1), P(s->rt_q2),
                               s->relax_on ? P(s->rm_k) : nullptr,
-                              P(s->rt_w)};
+                              P(s->rt_w), pr.open_sides};
   }
   static nh::LambdaArgs<T> lambda(const nh_solver* s) {
     const auto& g = s->grid;
@@ -423,7 +424,8 @@ struct Launch {
       hipLaunchKernelGGL((nh::k_assemble1d<T>), dim3(nblocks(s->ncorn)),
                          dim3(nh::kBlock), 0, s->stream, g.nx, (T)g.dx,
                          P(S.hs_cur), P(S.qa), P(s->H), P(S.wst), s->dt,
-                         P(s->cW), P(s->cdiag), P(s->cE), P(s->crhs));
+                         P(s->cW), P(s->cdiag), P(s->cE), P(s->crhs),
+                         s->par.open_sides);
     } else {
       auto a = Args<T>::assemble(s, S);
       hipLaunchKernelGGL((nh::k_assemble2d<T>), dim3(a.nblocks()),
@@ -709,6 +711,8 @@ nh_status check_params(const nh_grid* g, const nh_params* p) {
     return fail(NH_EINVAL, "need delta > 0 and dry_eps >= 0");
   if (!(p->manning >= 0) || !std::isfinite(p->manning))
     return fail(NH_EINVAL, "need a finite manning >= 0");
+  if (p->open_sides < 0 || p->open_sides > 15)
+    return fail(NH_EINVAL, "open_sides is a mask of 4 bits");
   if (p->precision != NH_FP64 && p->precision != NH_FP32)
     return fail(NH_EINVAL, "precision must be NH_FP64 or NH_FP32");
   if (p->nh_on && g->ny > 1) {

@@ -66,6 +66,7 @@ class Case:
     fixed_dt: int = 0
     dt_fixed: float = 0.0
     manning: float = 0.0    # Gauckler-Manning n (0: no friction)
+    open_sides: int = 0     # outflow sides: 1 west, 2 east, 4 south, 8 north
 
     def param_dict(self) -> dict:
         return dict(nx=self.nx, ny=self.ny, dx=self.dx, dy=self.dy, g=self.g,
@@ -74,7 +75,8 @@ class Case:
                     b1=self.b1, b2=self.b2, solve_max_iter=self.solve_max_iter,
                     check_every=self.check_every, solve_tol=self.solve_tol,
                     omega=self.omega, fixed_dt=self.fixed_dt,
-                    dt_fixed=self.dt_fixed, manning=self.manning)
+                    dt_fixed=self.dt_fixed, manning=self.manning,
+                    open_sides=self.open_sides)
 
 
 # --------------------------------------------------------------------------

@@ -260,6 +260,10 @@ def test_adjoint_rejects_what_it_does_not_cover():
     with pytest.raises(NhError):
         s.adjoint(4, g, t)
     s.close()
+    s = make(fixed_dt=1, dt_fixed=0.05, open_sides=2)   # an outflow side
+    with pytest.raises(NhError):
+        s.adjoint(4, g, t)
+    s.close()
     s = make(fixed_dt=1, dt_fixed=0.05)
     with pytest.raises(NhError):
         s.adjoint(4, np.array([0, P["nx"] * P["ny"]]), t[:, :2])

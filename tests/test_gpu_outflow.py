@@ -1,0 +1,101 @@
+"""Outflow boundaries (homogeneous Neumann ghosts, Section 4.4) on the GPU
+against the FP64 oracle, whose outflow is pinned (a uniform current passes
+open ends unchanged; a wave leaves; a lake at rest stays at rest), in single
+grids and ensembles.  FP64 is compared to the bit, FP32 to 1e-4 on h and the
+discharges, as for the other parity tests.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle, Params
+from paper_1706_04551_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-4
+FIELDS = ("h", "hu", "hv", "w", "p")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def normwise(g, r, k):
+    scale = np.abs(r[k]).max()
+    if k in ("hu", "hv"):
+        scale = max(np.abs(r["hu"]).max(), np.abs(r["hv"]).max())
+    return float(np.abs(g[k] - r[k]).max() / max(scale, 1e-300))
+
+
+def gpu_state(case, steps):
+    from paper_1706_04551_amd import Solver
+    s = Solver.from_case(case)
+    s.run(steps)
+    out = s.state()
+    s.close()
+    return out
+
+
+def oracle_state(case, steps):
+    o = Oracle(Params(**case.param_dict()))
+    o.set_bathymetry(case.H)
+    o.set_state(case.h, case.hu, case.hv)
+    assert o.run(steps) == 0
+    return o.state()
+
+
+@pytest.mark.parametrize("open_sides", [15, 1 | 8])
+def test_open_basin_fp64_equals_the_oracle(open_sides):
+    c = I.case_c2(n=128)
+    c.open_sides = open_sides
+    say(f"[case] c2 128 f64 open_sides={open_sides}")
+    g, r = gpu_state(c, 60), oracle_state(c, 60)
+    for k in FIELDS:
+        say(f"  {k}: max rel diff {normwise(g, r, k):.3e}")
+        assert np.array_equal(g[k], r[k]), k
+
+
+def test_open_basin_fp32_close_to_the_oracle():
+    c = I.case_c2(n=128, precision="f32")
+    c.open_sides = 15
+    g, r = gpu_state(c, 60), oracle_state(c, 60)
+    for k in ("h", "hu", "hv"):
+        e = normwise(g, r, k)
+        say(f"  {k}: max rel diff {e:.3e}")
+        assert e <= TOL32, (k, e)
+
+
+def test_channel_wave_leaves_as_in_the_oracle():
+    c = I.case_c1()
+    c.open_sides = 2
+    g, r = gpu_state(c, 660), oracle_state(c, 660)
+    for k in ("h", "hu", "w", "p"):
+        assert np.array_equal(g[k], r[k]), k
+    assert g["h"].sum() < c.h.sum() - 0.8 * (c.h - c.H).sum()  # it left
+
+
+def test_ensemble_members_with_their_own_open_sides():
+    from paper_1706_04551_amd import Ensemble
+    cases = [I.case_c4_member(k, sides=(n,), precision="f64", island=True)
+             for k, n in enumerate((64, 80, 72))]
+    for c, op in zip(cases, (0, 15, 2 | 4)):
+        c.open_sides = op
+    steps = 10
+    e = Ensemble.from_cases(cases)
+    e.run(steps)
+    for k, c in enumerate(cases):
+        r = gpu_state(c, steps)
+        g = e.state(k)
+        for f in FIELDS:
+            assert np.array_equal(g[f], r[f]), (k, f)
+    e.close()
+
+
+def test_open_side_mask_is_checked():
+    from paper_1706_04551_amd import NhError, Solver
+    for op in (-1, 16):
+        with pytest.raises(NhError):
+            Solver(16, 16, 1.0, 1.0, open_sides=op)
