@@ -12,6 +12,8 @@
  *     velocities and the wet-dry treatment (Sections 4.1, 4.5, 5, eq. 16-22,30);
  *   - optionally the Manning friction of Section 2, semi-implicit, and the
  *     breaking terms of the eddy viscosity (Section 3, eq. 9-12);
+ *   - walls, or outflow sides, and optional generation/absorption zones
+ *     (Section 4.4);
  *   - the compact finite-difference non-hydrostatic pressure system at the
  *     cell corners: assembly (eq. 28-29, 37-41, 43), solve (Thomas in 1D,
  *     scheduled-relaxation Jacobi in 2D, eq. 32) and the correction of the
