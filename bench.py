@@ -97,8 +97,24 @@ def copy_calibration():
     torch.cuda.synchronize()
 
 
-def workload(name: str, prec: str):
+# runtimes to t = 1 s of the circular dam-break in the paper's Table 2 (FP64
+# CUDA on a GTX Titan Black), by (cells per side, eps of eq. 32)
+TABLE2_S = {(250, 1e-3): 0.64, (500, 1e-3): 5.79, (750, 1e-3): 17.33,
+            (1000, 1e-3): 40.47, (1250, 1e-3): 79.67, (1500, 1e-3): 136.12,
+            (250, 1e-4): 1.88, (500, 1e-4): 8.44, (750, 1e-4): 25.78,
+            (1000, 1e-4): 57.23, (1250, 1e-4): 143.19, (1500, 1e-4): 243.86,
+            (250, 1e-5): 3.47, (500, 1e-5): 33.54, (750, 1e-5): 99.58,
+            (1000, 1e-5): 198.91, (1250, 1e-5): 381.89, (1500, 1e-5): 662.51}
+
+
+def workload(name: str, prec: str, n=None, eps=None):
     from paper_1706_04551_amd import inputs
+    if name == "dambreak":
+        n, eps = n or 1000, eps or 1e-5
+        c = inputs.case_dambreak(n=n, eps=eps, precision=prec)
+        return c, (f"circular dam-break {n}x{n} on [-5,5]^2 (Section 7.7), "
+                   f"open sides, CFL 0.9, to t = 1 s, {prec.upper()}, "
+                   f"Jacobi+SRJ(64) tol={eps:g}")
     if name == "c2":
         c = inputs.case_c2(precision=prec)
         desc = (f"island basin 512x512 dx=1m, depth 2-20 m + dry island, "
@@ -311,7 +327,9 @@ def run_single(args):
     """One grid (c2 or c3) for args.steps steps from its initial state."""
     import torch
     from paper_1706_04551_amd import Solver
-    case, desc = workload(args.workload, args.precision)
+    case, desc = workload(args.workload, args.precision,
+                          getattr(args, "n", None),
+                          getattr(args, "solve_tol", None))
     if getattr(args, "solve_tol", None):
         case.solve_tol = args.solve_tol
         desc = re.sub(r"tol=[0-9.e+-]+", f"tol={case.solve_tol:g}", desc)
@@ -327,6 +345,14 @@ def run_single(args):
         s.set_relaxation((zones,) * 4)   # absorbing zones on every wall
         desc += f", absorbing zones {zones:g} m"
     ncell = case.nx * case.ny
+    t_end = None
+    if args.workload == "dambreak":   # as many steps as reach t = 1 s
+        t_end, k = 1.0, 0
+        while s.stats()["t"] < t_end:
+            s.run(1)
+            k += 1
+        args.steps = k
+        s.set_state(case.h, case.hu, case.hv)
 
     # warmup, then reset to the initial state (uploads are outside the timing)
     s.run(args.warmup)
@@ -390,7 +416,13 @@ def run_single(args):
                    "sim_time_s": round(st["t"], 4),
                    "mean_sweeps_per_solve": round(kbar, 2),
                    "full_step_hbm_roofline_frac": round(step_roof_frac, 4),
-                   "phase_ms_profiled_run": phases},
+                   "phase_ms_profiled_run": phases,
+                   **({} if t_end is None else {
+                       "time_to_t_end_s": round(elapsed, 4),
+                       "paper_table2_s": TABLE2_S.get(
+                           (case.nx, case.solve_tol)),
+                       "paper_hardware": "GTX Titan Black, FP64 CUDA "
+                                         "(context: other hardware)"})},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -407,7 +439,9 @@ def variant_summary(out):
             "full_step_hbm_roofline_frac": cfg.get("full_step_hbm_roofline_frac"),
             "sweep_roofline_frac": out["roofline"]["frac"],
             "sweep_kernel": out["roofline"]["kernel"],
-            **{k: cfg[k] for k in ("members_failed", "min_sim_time_s")
+            **{k: cfg[k] for k in ("members_failed", "min_sim_time_s",
+                                   "sim_time_s", "time_to_t_end_s",
+                                   "paper_table2_s", "paper_hardware")
                if k in cfg}}
 
 
@@ -418,12 +452,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--precision", default=None, choices=["f64", "f32"],
-                    help="default: f64 for c2, f32 for the c3 and c4 workloads")
+                    help="default: f64 for c2 and dambreak, f32 for the c3, "
+                         "c4 and c5 workloads")
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--solve-tol", type=float, default=None,
                     help="override the workload's stop tolerance (eq. 32)")
     ap.add_argument("--manning", type=float, default=None,
                     help="Gauckler-Manning n of the friction law (default 0)")
+    ap.add_argument("--n", type=int, default=None,
+                    help="cells per side of the dam-break workload (1000)")
     ap.add_argument("--zones", type=float, default=None,
                     help="width [m] of absorbing relaxation zones on every "
                          "wall (default none)")
@@ -448,7 +485,8 @@ def main():
         copy_calibration()
     args.steps_given = args.steps is not None
     if args.precision is None:
-        args.precision = "f64" if args.workload == "c2" else "f32"
+        args.precision = ("f64" if args.workload in ("c2", "dambreak")
+                          else "f32")
     if args.workload == "c4":
         out = run_ensemble(args)
     elif args.workload == "c5":
@@ -484,6 +522,12 @@ def main():
             variants["c2_fp64_absorbing_zones"] = variant_summary(
                 run_single(v))
             note("c2 FP64 with absorbing zones done")
+            v = copy.copy(args)
+            v.workload, v.no_cpu, v.solve_tol = "dambreak", True, 1e-5
+            v.n, v.steps = 1000, None
+            variants["dambreak_1000_fp64_eps1e-5"] = variant_summary(
+                run_single(v))
+            note("dam-break of the paper's Table 2 done")
             v = copy.copy(args)
             v.workload, v.precision, v.no_cpu = "c3", "f32", True
             v.steps = 4000          # the beach workload's full run

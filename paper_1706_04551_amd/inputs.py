@@ -236,6 +236,28 @@ def case_c2(n: int = 512, steps: int = 1000, precision: str = "f64",
     return c
 
 
+def case_dambreak(n: int = 1000, eps: float = 1e-5,
+                  precision: str = "f64") -> Case:
+    """The circular dam-break of Section 7.7, the workload of the paper's
+    timings (Table 2): [-5, 5]^2 in n x n cells, still-water depth
+    H = 1 - 0.25 exp(-x^2 - y^2), h0 = H inside r <= 0.5 and H + 0.25
+    outside, at rest, CFL 0.9, open boundaries, t in [0, 1] s; eps is the
+    stop tolerance of eq. (32).  `steps` is left 0: the run goes to t = 1."""
+    dx = 10.0 / n
+    xc = -5.0 + (np.arange(n) + 0.5) * dx
+    X, Y = np.meshgrid(xc, xc)
+    H = 1.0 - 0.25 * np.exp(-X * X - Y * Y)
+    h0 = np.where(np.hypot(X, Y) <= 0.5, H, H + 0.25)
+    z = np.zeros_like(h0)
+    c = Case(f"dambreak{n}", n, n, dx, dx, H, h0, z, z.copy(), 0,
+             precision=precision, solve_tol=eps, cfl=0.9,
+             dry_eps=1e-10 if precision == "f64" else 1e-5, open_sides=15)
+    rho = jacobi_radius_bound(float(h0.max()), c.dx, c.dy)
+    c.omega = srj_schedule(rho, 64)
+    c.check_every = 64
+    return c
+
+
 def case_c3(n: int = 2048, steps: int = 4000) -> Case:
     """Plane beach: n x n (2048 by default), dx = dy = 0.05 m, x in
     [0, n dx]; still-water depth 1 m for x < 70 m, slope 1:20 up to the

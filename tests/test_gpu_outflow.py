@@ -99,3 +99,14 @@ def test_open_side_mask_is_checked():
     for op in (-1, 16):
         with pytest.raises(NhError):
             Solver(16, 16, 1.0, 1.0, open_sides=op)
+
+
+def test_the_papers_dam_break_equals_the_oracle_and_stays_symmetric():
+    # the workload of Table 2 (Section 7.7) at 128^2: open sides, CFL 0.9
+    c = I.case_dambreak(n=128, eps=1e-5)
+    g, r = gpu_state(c, 40), oracle_state(c, 40)
+    for k in FIELDS:
+        assert np.array_equal(g[k], r[k]), k
+    # radially symmetric data: the solution is symmetric under x <-> y
+    assert np.abs(g["h"] - g["h"].T).max() <= 1e-10
+    assert np.abs(g["hu"] - g["hv"].T).max() <= 1e-10
