@@ -346,7 +346,8 @@ def run_single(args):
         desc += f", absorbing zones {zones:g} m"
     ncell = case.nx * case.ny
     t_end = None
-    if args.workload == "dambreak":   # as many steps as reach t = 1 s
+    if args.workload == "dambreak" and not getattr(args, "steps_given", False):
+        # as many steps as reach t = 1 s (an explicit --steps runs that many)
         t_end, k = 1.0, 0
         while s.stats()["t"] < t_end:
             s.run(1)
@@ -524,7 +525,7 @@ def main():
             note("c2 FP64 with absorbing zones done")
             v = copy.copy(args)
             v.workload, v.no_cpu, v.solve_tol = "dambreak", True, 1e-5
-            v.n, v.steps = 1000, None
+            v.n, v.steps, v.steps_given = 1000, None, False
             variants["dambreak_1000_fp64_eps1e-5"] = variant_summary(
                 run_single(v))
             note("dam-break of the paper's Table 2 done")
