@@ -388,7 +388,9 @@ def run_single(args):
     roof = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-            "traffic": measured_traffic(args.workload, args.precision),
+            "traffic": measured_traffic(
+                f"dambreak{case.nx}" if args.workload == "dambreak"
+                else args.workload, args.precision),
             "kernel": "k_sweep_tb", "avg_launch_us": round(sweep_ms * 1e3, 3),
             "sweeps_per_launch": round(sweeps_per_launch, 3),
             "alg_bytes_per_launch": int(alg),
