@@ -104,7 +104,10 @@ TABLE2_S = {(250, 1e-3): 0.64, (500, 1e-3): 5.79, (750, 1e-3): 17.33,
             (250, 1e-4): 1.88, (500, 1e-4): 8.44, (750, 1e-4): 25.78,
             (1000, 1e-4): 57.23, (1250, 1e-4): 143.19, (1500, 1e-4): 243.86,
             (250, 1e-5): 3.47, (500, 1e-5): 33.54, (750, 1e-5): 99.58,
-            (1000, 1e-5): 198.91, (1250, 1e-5): 381.89, (1500, 1e-5): 662.51}
+            (1000, 1e-5): 198.91, (1250, 1e-5): 381.89, (1500, 1e-5): 662.51,
+            # the hydrostatic (SWE-only) code of the same table
+            (250, "swe"): 0.64, (500, "swe"): 2.29, (750, "swe"): 7.17,
+            (1000, "swe"): 16.75, (1250, "swe"): 33.88, (1500, "swe"): 56.38}
 
 
 def workload(name: str, prec: str, n=None, eps=None):
@@ -335,6 +338,9 @@ def run_single(args):
         desc = re.sub(r"tol=[0-9.e+-]+", f"tol={case.solve_tol:g}", desc)
         if "tol=" not in desc:
             desc += f", tol={case.solve_tol:g}"
+    if getattr(args, "hydrostatic", False):
+        case.nh_on = 0
+        desc += ", hydrostatic (no pressure step)"
     if getattr(args, "manning", None):
         case.manning = args.manning
         desc += f", Manning n={case.manning:g}"
@@ -423,7 +429,7 @@ def run_single(args):
                    **({} if t_end is None else {
                        "time_to_t_end_s": round(elapsed, 4),
                        "paper_table2_s": TABLE2_S.get(
-                           (case.nx, case.solve_tol)),
+                           (case.nx, case.solve_tol if case.nh_on else "swe")),
                        "paper_hardware": "GTX Titan Black, FP64 CUDA "
                                          "(context: other hardware)"})},
         "roofline": roof,
@@ -462,6 +468,8 @@ def main():
                     help="override the workload's stop tolerance (eq. 32)")
     ap.add_argument("--manning", type=float, default=None,
                     help="Gauckler-Manning n of the friction law (default 0)")
+    ap.add_argument("--hydrostatic", action="store_true",
+                    help="shallow water only: no pressure step")
     ap.add_argument("--n", type=int, default=None,
                     help="cells per side of the dam-break workload (1000)")
     ap.add_argument("--zones", type=float, default=None,
