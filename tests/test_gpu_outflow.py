@@ -110,3 +110,28 @@ def test_the_papers_dam_break_equals_the_oracle_and_stays_symmetric():
     # radially symmetric data: the solution is symmetric under x <-> y
     assert np.abs(g["h"] - g["h"].T).max() <= 1e-10
     assert np.abs(g["hu"] - g["hv"].T).max() <= 1e-10
+
+
+def test_outflow_zones_and_friction_together_match_the_oracle():
+    # the combination the paper's flume cases use: open sides, absorbing
+    # zones in front of them, Manning friction (FP64 to 1e-9: the friction
+    # factor's cube root is not bit-identical between host and device)
+    from paper_1706_04551_amd import Solver
+    c = I.case_c2(n=128)
+    c.open_sides, c.manning = 15, 0.03
+    widths = (16.0, 16.0, 16.0, 16.0)
+    s = Solver.from_case(c)
+    s.set_relaxation(widths)
+    s.run(50)
+    g = s.state()
+    s.close()
+    o = Oracle(Params(**c.param_dict()))
+    o.set_bathymetry(c.H)
+    o.set_state(c.h, c.hu, c.hv)
+    o.set_relaxation(widths)
+    assert o.run(50) == 0
+    r = o.state()
+    for k in FIELDS:
+        e = normwise(g, r, k)
+        say(f"  {k}: max rel diff {e:.3e}")
+        assert e <= 1e-9, (k, e)
