@@ -100,7 +100,7 @@ typedef struct {
                           result in wet cells: q <- q / (1 + dt g n^2 |u| /
                           h^(4/3)), |u| from the desingularised velocities.
                           Ensemble members may differ in it; the adjoint
-                          needs 0 */
+                          covers it */
   int32_t open_sides;  /* outflow boundaries (Section 4.4), a bit per side:
                           1 west (x = 0), 2 east, 4 south (y = 0), 8 north
                           (south/north ignored in 1D).  An open side has
@@ -239,7 +239,7 @@ void nh_destroy(nh_solver *s);
  * stage pressures recorded, before the adjoint goes back through it.
  *
  * Requires a 2D grid, a fixed time step (fixed_dt = 1), breaking_on = 0,
- * manning = 0, open_sides = 0 and no relaxation zones.
+ * open_sides = 0 and no relaxation zones; Manning friction is covered.
  * gauges[ngauges]: flat cell indices j*nx + i; target[nsteps][ngauges] FP64.
  * adj_tol: a transposed solve stops when its measure of eq. (32) is below
  * adj_tol * max_c |pbar_c / diag_c| (pbar: its right-hand side).

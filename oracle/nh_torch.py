@@ -40,6 +40,7 @@ class TorchParams:
     delta: float = 1e-5      # desingularisation depth (Section 4.5)
     dry_eps: float = 1e-10   # h <= dry_eps is dry
     nh_on: bool = True
+    manning: float = 0.0     # Gauckler-Manning n of the friction law (Section 2)
 
 
 # --------------------------------------------------------------------------
@@ -285,8 +286,28 @@ def correct(P: TorchParams, C: Corrector, hs, q1s, q2s, w, p, dt):
     return q1, q2, w_new
 
 
+def friction(P: TorchParams, hs, q1s, q2s, dt):
+    """Manning friction of Section 2, semi-implicit on the stage's
+    finite-volume result, in wet cells: q / (1 + dt g n^2 |u| / h^(4/3)),
+    |u| from the desingularised velocities.  |u| has derivative 0 at 0 (the
+    convention of the GPU adjoint for the norm's kink)."""
+    wet = hs > P.dry_eps
+    hw = torch.where(wet, hs, torch.ones_like(hs))
+    u, v = desing(hw, q1s, P.delta), desing(hw, q2s, P.delta)
+    s2 = u * u + v * v
+    pos = s2 > 0
+    speed = torch.where(pos, torch.sqrt(torch.where(pos, s2,
+                                                     torch.ones_like(s2))),
+                        torch.zeros_like(s2))
+    den = 1.0 + dt * P.g * P.manning ** 2 * speed / (hw * hw ** (1.0 / 3.0))
+    return (torch.where(wet, q1s / den, q1s),
+            torch.where(wet, q2s / den, q2s))
+
+
 def stage(P: TorchParams, h, q1, q2, w, H, dt):
     hs, q1s, q2s = fv_stage(P, h, q1, q2, H, dt)
+    if P.manning > 0:
+        q1s, q2s = friction(P, hs, q1s, q2s, dt)
     if not P.nh_on:
         return hs, q1s, q2s, w, None
     C = Corrector(P, hs, H)

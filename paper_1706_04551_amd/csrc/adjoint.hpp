@@ -367,6 +367,46 @@ __global__ void __launch_bounds__(kBlock)
   lH[n] = (T)((E)lH[n] - (E)b.eta);
 }
 
+// Manning friction on the stage's finite-volume result (the forward's
+// fv_finish): in wet cells q_out = q / den, den = 1 + dt fric |u| / h^(4/3),
+// |u| from the desingularised velocities of (h, q).  Given the adjoint of
+// q_out in (lqa, lqb), replaces it by the adjoint of the pre-friction q and
+// adds the friction's share to the adjoint of h (|u|' = 0 at |u| = 0).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_adj_friction(AdjGeom G, T fric, const T* __restrict__ hs,
+                   const T* __restrict__ qa, const T* __restrict__ qb,
+                   T* __restrict__ lqa, T* __restrict__ lqb,
+                   T* __restrict__ lh) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= G.nx * G.ny) return;
+  const T h = hs[n];
+  if (h <= (T)G.dry_eps) return;  // dry: q = 0, no friction
+  const T dt = (T)(*G.dtp), delta = (T)G.delta, K = dt * fric;
+  const T a = qa[n], b = qb[n];
+  const T u = desing(h, a, delta), v = desing(h, b, delta);
+  const T sp = sqrt(u * u + v * v);
+  const T h43 = h * cbrt(h);
+  const T den = T(1) + K * sp / h43;
+  const T la = lqa[n], lb = lqb[n];
+  const T lden = -(la * a + lb * b) / (den * den);
+  T lan = la / den, lbn = lb / den;
+  T lhn = -lden * K * sp * (T(4) / T(3)) / (h43 * h);
+  if (sp > T(0)) {
+    const T ls = lden * K / h43;
+    T dh, dq;
+    desing_partials(h, a, delta, dh, dq);
+    lan = lan + ls * (u / sp) * dq;
+    lhn = lhn + ls * (u / sp) * dh;
+    desing_partials(h, b, delta, dh, dq);
+    lbn = lbn + ls * (v / sp) * dq;
+    lhn = lhn + ls * (v / sp) * dh;
+  }
+  lqa[n] = lan;
+  lqb[n] = lbn;
+  lh[n] = (T)((E)lh[n] + (E)lhn);
+}
+
 // ---------------------------------------------------------------------------
 // correction (eq. 36, 41).  q = q* + dt T(p; h*, H) (zero where dry),
 // w = w_in + dt desing(h_c, p) at the corners.  Per cell i with the corner

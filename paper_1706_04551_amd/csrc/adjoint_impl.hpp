@@ -24,6 +24,7 @@ struct AdjWork {
   void *tE = nullptr, *tW = nullptr, *tN = nullptr, *tS = nullptr;
   double* mu[2][3] = {};
   double* rowbar = nullptr;  // kRowBars planes of corner cotangents (FP64)
+  void *fpre_h = nullptr, *fpre_q1 = nullptr, *fpre_q2 = nullptr;  // friction
   int mucur[2] = {0, 0};
   // tape of one segment and the checkpoints
   void* tape = nullptr;      // ce x (h, q1, q2, w) bulk + ce x (p1, p2) FP64
@@ -72,9 +73,10 @@ nh_status adj_prepare(nh_solver* s, int64_t nsteps, int ce, int ng) {
                kd = s->ncorn * sizeof(double);
   hipStream_t st = s->stream;
   nh_status r = NH_OK;
-  void** cells[] = {&w->Lh,  &w->Lq1,  &w->Lq2,  &w->LH,   &w->L2h,
-                    &w->L2q1, &w->L2q2, &w->L1h, &w->L1q1, &w->L1q2,
-                    &w->Lqs1, &w->Lqs2};
+  void** cells[] = {&w->Lh,   &w->Lq1,  &w->Lq2,    &w->LH,
+                    &w->L2h,  &w->L2q1, &w->L2q2,   &w->L1h,
+                    &w->L1q1, &w->L1q2, &w->Lqs1,   &w->Lqs2,
+                    &w->fpre_h, &w->fpre_q1, &w->fpre_q2};
   void** corners[] = {&w->Lw, &w->L2w, &w->Lw1, &w->pbar,
                       &w->tE, &w->tW,  &w->tN,  &w->tS};
   for (auto c : cells)
@@ -232,11 +234,12 @@ nh_status adj_step(nh_solver* s, AdjWork* w, const StateRec& R, double tol,
   auto P = [](void* a) { return static_cast<T*>(a); };
   auto C = [](void* a) { return static_cast<const T*>(a); };
   nh::AdjGeom G{gr.nx, gr.ny, gr.dx, gr.dy, pr.g, pr.delta, pr.dry_eps, s->dt};
+  const T fric = (T)(pr.g * pr.manning * pr.manning);  // as the forward's
   // --- recompute the stages: FV1 -> (hs, q1s, q2s), correction 1 -> U^(1)
   //     = (hs, q11, q21), w1; FV2 -> (h1, q1b, q2b)
   nh::FvArgs<T> f1{gr.nx, gr.ny, (T)gr.dx, (T)gr.dy, (T)pr.g, (T)pr.delta,
                    (T)pr.dry_eps, P(R.h), P(R.q1), P(R.q2), P(s->H), s->dt,
-                   P(s->hs), P(s->q1s), P(s->q2s), w->clamp};
+                   P(s->hs), P(s->q1s), P(s->q2s), w->clamp, fric};
   hipLaunchKernelGGL((nh::k_fv<T, false>), dim3(f1.nblocks()), B, 0, st, f1);
   if (pr.nh_on) {
     nh::CorrectArgs<T> c1{gr.nx, gr.ny, (T)gr.dx, (T)gr.dy, (T)pr.g,
@@ -253,7 +256,7 @@ nh_status adj_step(nh_solver* s, AdjWork* w, const StateRec& R, double tol,
   }
   nh::FvArgs<T> f2{gr.nx, gr.ny, (T)gr.dx, (T)gr.dy, (T)pr.g, (T)pr.delta,
                    (T)pr.dry_eps, P(s->hs), P(s->q11), P(s->q21), P(s->H),
-                   s->dt, P(s->h1), P(s->q1b), P(s->q2b), w->clamp};
+                   s->dt, P(s->h1), P(s->q1b), P(s->q2b), w->clamp, fric};
   hipLaunchKernelGGL((nh::k_fv<T, false>), dim3(f2.nblocks()), B, 0, st, f2);
 
   // --- RK average: half of the adjoint to U^n directly, half to U^(2)
@@ -305,6 +308,19 @@ nh_status adj_step(nh_solver* s, AdjWork* w, const StateRec& R, double tol,
                          P(w->Lqs2));
       hipLaunchKernelGGL((nh::k_axpy1<T>), Gk, B, 0, st, nk, C(lw_out),
                          P(lw_in));
+    }
+    // friction: the stage's pre-friction result again (friction off), then
+    // the adjoint of q_out = q / den back to it
+    if (fric > T(0)) {
+      nh::FvArgs<T> f0{gr.nx, gr.ny, (T)gr.dx, (T)gr.dy, (T)pr.g,
+                       (T)pr.delta, (T)pr.dry_eps, P(Vh), P(Vq1), P(Vq2),
+                       P(s->H), s->dt, P(w->fpre_h), P(w->fpre_q1),
+                       P(w->fpre_q2), w->clamp, T(0)};
+      hipLaunchKernelGGL((nh::k_fv<T, false>), dim3(f0.nblocks()), B, 0, st,
+                         f0);
+      hipLaunchKernelGGL((nh::k_adj_friction<T>), Gc, B, 0, st, G, fric,
+                         C(hs_), C(w->fpre_q1), C(w->fpre_q2), P(w->Lqs1),
+                         P(w->Lqs2), P(lh_out));
     }
     // finite volumes
     hipLaunchKernelGGL((nh::k_adj_fv<T, 1>), Gc, B, 0, st, G, C(Vh),
@@ -425,8 +441,6 @@ nh_status nh_adjoint_run(nh_solver* s, int64_t nsteps, int32_t ngauges,
     return fail(NH_EINVAL, "the adjoint needs a fixed dt (fixed_dt = 1)");
   if (s->par.breaking_on)
     return fail(NH_EINVAL, "the adjoint does not cover the breaking terms");
-  if (s->par.manning != 0.0)
-    return fail(NH_EINVAL, "the adjoint does not cover friction");
   if (s->relax_on)
     return fail(NH_EINVAL, "the adjoint does not cover relaxation zones");
   if (s->par.open_sides != 0)

@@ -119,3 +119,22 @@ def test_tangent_linear_model_equals_the_adjoint():
     _, tl = NT.tangent(P, eta0, H, de, db, gauges, target, steps)
     ad = float(np.sum(ge * de) + np.sum(gb * db))
     assert abs(tl - ad) <= 1e-12 * abs(ad)
+
+
+def test_torch_friction_equals_the_c_oracle():
+    """The differentiable oracle's friction against the C oracle's (pinned
+    to the exact decay of the friction law), on the island basin."""
+    from oracle.oracle import Oracle, Params
+    from paper_1706_04551_amd import inputs as I
+    c = I.case_c2(n=64)
+    dt = 0.02
+    P = NT.TorchParams(c.nx, c.ny, c.dx, c.dy, dt, manning=0.05)
+    s = NT.run(P, c.h, c.hu, c.hv, c.H, 6)
+    o = Oracle(Params(**{**c.param_dict(), "fixed_dt": 1, "dt_fixed": dt,
+                         "manning": 0.05, "solve_tol": 1e-13}))
+    o.set_bathymetry(c.H)
+    o.set_state(c.h, c.hu, c.hv)
+    assert o.run(6) == 0
+    r = o.state()
+    for k in ("h", "hu", "hv"):
+        assert np.abs(s[k] - r[k]).max() <= 1e-12 * np.abs(r[k]).max(), k
