@@ -604,7 +604,7 @@ __global__ void __launch_bounds__(kBlock)
                    const T* __restrict__ q1s, const T* __restrict__ q2s,
                    const T* __restrict__ H, const T* __restrict__ ws,
                    const double* __restrict__ p, const double* __restrict__ mu,
-                   double* __restrict__ rb, T* __restrict__ lw) {
+                   T* __restrict__ rb, T* __restrict__ lw) {
   const int nx = G.nx, ny = G.ny, ncx = nx + 1;
   const long ncorn = (long)ncx * (ny + 1);
   const int c = blockIdx.x * kBlock + threadIdx.x;
@@ -661,28 +661,28 @@ __global__ void __launch_bounds__(kBlock)
   const E Bmb = -(db * (YN - E(2) * hN) + nb * (YN + E(2) * hN)) / dy2 +
                 Bsb * q2N / dy;
   const E wc = (E)ws[c];
-  double* o = rb + c;
-  o[kBhc * ncorn] = E(2) * (Apb + Amb + Bpb + Bmb) + E(4) * wc * Bsb;
-  o[kBhE * ncorn] = E(2) * Am * (db - eb) / dx2;
-  o[kBhW * ncorn] = E(2) * Ap * (db - wb) / dx2;
-  o[kBhN * ncorn] = E(2) * Bm * (db - nb) / dy2;
-  o[kBhS * ncorn] = E(2) * Bp * (db - sb) / dy2;
-  o[kBXE * ncorn] = -Am * (db + eb) / dx2;
-  o[kBXW * ncorn] = Ap * (db + wb) / dx2;
-  o[kBYN * ncorn] = -Bm * (db + nb) / dy2;
-  o[kBYS * ncorn] = Bp * (db + sb) / dy2;
-  o[kBsx * ncorn] = Apb - Amb;
-  o[kBsy * ncorn] = Bpb - Bmb;
-  o[kBq1E * ncorn] = Bsb * Am / dx;
-  o[kBq1W * ncorn] = -Bsb * Ap / dx;
-  o[kBq2N * ncorn] = Bsb * Bm / dy;
-  o[kBq2S * ncorn] = -Bsb * Bp / dy;
+  T* o = rb + c;
+  o[kBhc * ncorn] = (T)(E(2) * (Apb + Amb + Bpb + Bmb) + E(4) * wc * Bsb);
+  o[kBhE * ncorn] = (T)(E(2) * Am * (db - eb) / dx2);
+  o[kBhW * ncorn] = (T)(E(2) * Ap * (db - wb) / dx2);
+  o[kBhN * ncorn] = (T)(E(2) * Bm * (db - nb) / dy2);
+  o[kBhS * ncorn] = (T)(E(2) * Bp * (db - sb) / dy2);
+  o[kBXE * ncorn] = (T)(-Am * (db + eb) / dx2);
+  o[kBXW * ncorn] = (T)(Ap * (db + wb) / dx2);
+  o[kBYN * ncorn] = (T)(-Bm * (db + nb) / dy2);
+  o[kBYS * ncorn] = (T)(Bp * (db + sb) / dy2);
+  o[kBsx * ncorn] = (T)(Apb - Amb);
+  o[kBsy * ncorn] = (T)(Bpb - Bmb);
+  o[kBq1E * ncorn] = (T)(Bsb * Am / dx);
+  o[kBq1W * ncorn] = (T)(-Bsb * Ap / dx);
+  o[kBq2N * ncorn] = (T)(Bsb * Bm / dy);
+  o[kBq2S * ncorn] = (T)(-Bsb * Bp / dy);
   lw[c] = (T)((E)lw[c] + E(4) * hc * Bsb);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-    k_adj_row_gather(AdjGeom G, const double* __restrict__ rb,
+    k_adj_row_gather(AdjGeom G, const T* __restrict__ rb,
                      T* __restrict__ lhs, T* __restrict__ lq1s,
                      T* __restrict__ lq2s, T* __restrict__ lH) {
   const int nx = G.nx, ny = G.ny, ncx = nx + 1;
@@ -690,7 +690,9 @@ __global__ void __launch_bounds__(kBlock)
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= nx * ny) return;
   const int jx = n % nx, jy = n / nx;
-  auto bar = [&](int q, int k, int l) { return rb[q * ncorn + l * ncx + k]; };
+  auto bar = [&](int q, int k, int l) {
+    return (E)rb[q * ncorn + l * ncx + k];
+  };
   // sums over the corners around the (unmirrored) cell position (u, v):
   // the corner at (u, .) has the cell on its east side, at (u + 1, .) west;
   // at (., v) north, at (., v + 1) south

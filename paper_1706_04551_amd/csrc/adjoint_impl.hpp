@@ -23,7 +23,7 @@ struct AdjWork {
   void *Lqs1 = nullptr, *Lqs2 = nullptr, *pbar = nullptr;
   void *tE = nullptr, *tW = nullptr, *tN = nullptr, *tS = nullptr;
   double* mu[2][3] = {};
-  double* rowbar = nullptr;  // kRowBars planes of corner cotangents (FP64)
+  void* rowbar = nullptr;  // kRowBars planes of corner cotangents (bulk type)
   void *fpre_h = nullptr, *fpre_q1 = nullptr, *fpre_q2 = nullptr;  // friction
   int mucur[2] = {0, 0};
   // tape of one segment and the checkpoints
@@ -86,7 +86,7 @@ nh_status adj_prepare(nh_solver* s, int64_t nsteps, int ce, int ng) {
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 3; ++b)
       if ((r = adj_alloc(w, (void**)&w->mu[a][b], kd, st)) != NH_OK) return r;
-  if ((r = adj_alloc(w, (void**)&w->rowbar, nh::kRowBars * kd, st)) != NH_OK)
+  if ((r = adj_alloc(w, &w->rowbar, nh::kRowBars * kb, st)) != NH_OK)
     return r;
   if ((r = adj_alloc(w, &w->tape, (size_t)ce * rec_bytes(s, 2), st)) !=
           NH_OK ||
@@ -297,9 +297,9 @@ nh_status adj_step(nh_solver* s, AdjWork* w, const StateRec& R, double tol,
       const double* mu = w->mu[idx][w->mucur[idx]];
       hipLaunchKernelGGL((nh::k_adj_row_bars<T>), Gk, B, 0, st, G, C(hs_),
                          C(q1s_), C(q2s_), C(s->H), C(w_in), p, mu,
-                         w->rowbar, P(lw_in));
+                         P(w->rowbar), P(lw_in));
       hipLaunchKernelGGL((nh::k_adj_row_gather<T>), Gc, B, 0, st, G,
-                         w->rowbar, P(lh_out), P(w->Lqs1), P(w->Lqs2),
+                         C(w->rowbar), P(lh_out), P(w->Lqs1), P(w->Lqs2),
                          P(w->LH));
     } else {
       hipLaunchKernelGGL((nh::k_copy<T>), Gc, B, 0, st, nc, C(lq1_out),
