@@ -57,8 +57,20 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert L.nh_create(ctypes.byref(g), ctypes.byref(p), None,
                        ctypes.byref(out)) == -1
     assert b"multiple" in L.nh_last_error()
+    p.check_every, p.n_omega = 1, 0
+    p.omega_schedule = None
+    p.manning = -0.01                      # friction coefficient
+    assert L.nh_create(ctypes.byref(g), ctypes.byref(p), None,
+                       ctypes.byref(out)) == -1
+    assert b"manning" in L.nh_last_error()
+    p.manning, p.open_sides = 0.0, 16      # outflow mask of 4 bits
+    assert L.nh_create(ctypes.byref(g), ctypes.byref(p), None,
+                       ctypes.byref(out)) == -1
+    assert b"open_sides" in L.nh_last_error()
     assert L.nh_step(None, None) == -1
     assert L.nh_bind_device_buffers(None, None) == -1
+    assert L.nh_set_relaxation(None, None, None, None, None, None,
+                               None) == -1
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
