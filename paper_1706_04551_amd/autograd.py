@@ -26,13 +26,17 @@ class AdjointRun(torch.autograd.Function):
         solver.set_state(h0, z, z)
         r = solver.adjoint(nsteps, gauges, target, ckpt_every, adj_tol)
         wet = (b + e > 0.0).astype(np.float64)
-        g_eta = torch.from_numpy(r["dh0"] * wet).to(eta0.dtype)
-        g_H = torch.from_numpy(r["dH"] + r["dh0"] * wet).to(H.dtype)
+        # results live where the inputs do (autograd requires gradients on
+        # the device and in the dtype of their inputs)
+        g_eta = torch.from_numpy(r["dh0"] * wet).to(device=eta0.device,
+                                                    dtype=eta0.dtype)
+        g_H = torch.from_numpy(r["dH"] + r["dh0"] * wet).to(device=H.device,
+                                                           dtype=H.dtype)
         ctx.save_for_backward(g_eta, g_H)
-        return torch.tensor(r["J"], dtype=torch.float64)
+        return torch.tensor(r["J"], dtype=torch.float64, device=eta0.device)
 
     @staticmethod
     def backward(ctx, gJ):
         g_eta, g_H = ctx.saved_tensors
-        gJ = gJ.to(g_eta.dtype)
-        return gJ * g_eta, gJ * g_H, None, None, None, None, None, None
+        return ((gJ.to(g_eta.dtype) * g_eta), (gJ.to(g_H.dtype) * g_H),
+                None, None, None, None, None, None)

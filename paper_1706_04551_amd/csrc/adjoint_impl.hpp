@@ -55,13 +55,31 @@ nh_status adj_alloc(AdjWork* w, void** p, size_t bytes, hipStream_t st) {
 
 inline size_t rec_bytes(const nh_solver* s, int np);
 
-// (re)allocate the adjoint work space for this run's sizes
+nh_status adj_alloc_all(nh_solver* s, AdjWork* w, int64_t nsteps, int ce,
+                        int ng);
+
+// (re)allocate the adjoint work space for this run's sizes.  The solver
+// keeps a work space only once every buffer of it is allocated: after a
+// failed allocation it holds none, so a later call allocates again.
 nh_status adj_prepare(nh_solver* s, int64_t nsteps, int ce, int ng) {
   AdjWork* w = s->adj;
-  const int nck = (int)((nsteps + ce - 1) / ce);
   if (w && w->nsteps == nsteps && w->ce == ce && w->ng == ng) return NH_OK;
   adj_release(w);
-  s->adj = w = new AdjWork();
+  s->adj = nullptr;
+  w = new AdjWork();
+  nh_status r = adj_alloc_all(s, w, nsteps, ce, ng);
+  if (r != NH_OK) {
+    (void)hipStreamSynchronize(s->stream);
+    adj_release(w);
+    return r;
+  }
+  s->adj = w;
+  return NH_OK;
+}
+
+nh_status adj_alloc_all(nh_solver* s, AdjWork* w, int64_t nsteps, int ce,
+                        int ng) {
+  const int nck = (int)((nsteps + ce - 1) / ce);
   w->esize = s->esize;
   w->ncell = s->ncell;
   w->ncorn = s->ncorn;

@@ -165,6 +165,50 @@ def test_autograd_function_gives_the_library_gradient():
     s.close()
 
 
+def test_autograd_function_on_device_tensors():
+    # inputs on the device: J and the gradients come back on it, in the
+    # inputs' dtype, equal to the library's gradient
+    import torch
+    from paper_1706_04551_amd.autograd import AdjointRun
+    P = problem(12, 10, steps=6)
+    s = solver_for(P)
+    dev = torch.device("cuda", 0)
+    eta0 = torch.tensor(P["eta0"], device=dev, requires_grad=True)
+    H = torch.tensor(P["H"], device=dev, requires_grad=True)
+    J = AdjointRun.apply(eta0, H, s, P["gauges"], P["target"], P["steps"], 2,
+                         1e-12)
+    assert J.device == eta0.device
+    (3.0 * J).backward()
+    assert eta0.grad.device == eta0.device and H.grad.device == H.device
+    r, _ = gpu_gradient(P, "f64", ckpt=2)
+    assert float(J.detach().cpu()) == r["J"]
+    assert np.array_equal(eta0.grad.cpu().numpy(), 3.0 * r["dh0"])
+    assert np.array_equal(H.grad.cpu().numpy(), 3.0 * (r["dH"] + r["dh0"]))
+    s.close()
+
+
+def test_adjoint_work_space_failure_is_not_kept():
+    # a run whose checkpoints cannot be allocated fails with NH_ENOMEM, and
+    # so does the same call again (the solver keeps no half-built work
+    # space); a run of ordinary size then works
+    from paper_1706_04551_amd.binding import NhError
+    P = problem(64, 64, steps=4)
+    s = solver_for(P)
+    nsteps = 3_000_000     # 3e6 checkpoints of ~0.1 MB: beyond device memory
+    target = np.zeros((nsteps, P["gauges"].size))
+    for _ in range(2):
+        with pytest.raises(NhError) as e:
+            s.adjoint(nsteps, P["gauges"], target, ckpt_every=1,
+                      adj_tol=1e-12)
+        assert e.value.status == -2, str(e.value)
+    s.set_state(np.maximum(P["H"] + P["eta0"], 0.0), np.zeros_like(P["H"]),
+                np.zeros_like(P["H"]))
+    r = s.adjoint(P["steps"], P["gauges"], P["target"], ckpt_every=2,
+                  adj_tol=1e-12)
+    assert np.isfinite(r["J"])
+    s.close()
+
+
 def test_full_size_gradient_against_central_differences():
     """The 1024^2 adjoint workload in FP64 (the kernels of the FP32 run at
     double precision), 200 steps with checkpoints every 100: the gradient
