@@ -75,6 +75,11 @@ def lib():
             raise RuntimeError(
                 f"{LIB_PATH} is missing: build it with "
                 "`python -c 'import __graft_entry__ as g; g.build()'`")
+        # torch first: it brings its own HIP runtime, and the library must
+        # bind to that same runtime (one set of devices, streams and device
+        # pointers in the process); loaded the other way round, torch finds
+        # the runtime already loaded and sees no device
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp = C.c_void_p
         L.nh_create.argtypes = [C.POINTER(NhGrid), C.POINTER(NhParams), vp,

@@ -46,8 +46,13 @@ void adj_release(AdjWork* w) {
 namespace {
 
 nh_status adj_alloc(AdjWork* w, void** p, size_t bytes, hipStream_t st) {
-  if (hipMalloc(p, bytes) != hipSuccess)
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    // the runtime keeps the failure as the thread's last error, which the
+    // caller's next check (torch's, after a launch) would report as its own
+    (void)hipGetLastError();
+    *p = nullptr;
     return fail(NH_ENOMEM, "hipMalloc failed (adjoint buffers)");
+  }
   w->allocs.push_back(*p);
   hipMemsetAsync(*p, 0, bytes, st);
   return NH_OK;

@@ -29,8 +29,13 @@ namespace {
 
 thread_local std::string g_err;
 
+// Every failing call ends here.  A failed HIP call also stays the thread's
+// "last error" in the runtime until someone reads it; it is read here, so
+// that the caller's next check (torch's, after its next launch) does not
+// report the library's failure as its own.
 nh_status fail(nh_status st, const std::string& msg) {
   g_err = msg;
+  (void)hipGetLastError();
   return st;
 }
 
@@ -199,7 +204,11 @@ namespace {
 
 nh_status dalloc(nh_solver* s, void** p, size_t bytes) {
   hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) return fail(NH_ENOMEM, "hipMalloc failed");
+  if (e != hipSuccess) {
+    (void)hipGetLastError();  // not left for the caller's next check
+    *p = nullptr;
+    return fail(NH_ENOMEM, "hipMalloc failed");
+  }
   s->allocs.push_back(*p);
   hipMemsetAsync(*p, 0, bytes, s->stream);
   return NH_OK;
