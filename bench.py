@@ -1,9 +1,11 @@
 """Benchmark: full non-hydrostatic time steps (FV + pressure solve) on one GPU.
 
 Workload (default): the 512 x 512 island basin, FP64 -- seeded bathymetry of
-depth 2-20 m with a dry island, Gaussian hump of 0.5 m, walls, CFL 0.9,
-relaxed-Jacobi solve with a 64-sweep Chebyshev/Leja schedule, tolerance 1e-10
-on the plain-Jacobi update size.  Inputs are synthetic (seeded generators).
+depth 2-20 m with a dry island, Gaussian hump of 0.5 m, walls, CFL 0.7 (the
+largest the 2D MUSCL-minmod + Heun stage with the summed CFL form keeps
+round-off from growing at), relaxed-Jacobi solve with a 64-sweep
+Chebyshev/Leja schedule, tolerance 1e-10 on the plain-Jacobi update size.
+Inputs are synthetic (seeded generators).
 
 A step is one full TVD-RK2 step: two finite-volume stages, two pressure
 assemblies, two solves and two corrections, plus the CFL reduction.  The
@@ -11,7 +13,9 @@ timed region starts from the workload's initial state already resident in
 device memory (the warmup runs first and the state is then reset).
 
 Prints one JSON line with the metric, the roofline of the dominant kernel
-(the relaxation sweep) and the CPU oracle's rate on a bounded sample.
+(the relaxation sweep), the error against stored oracle states of the same
+workload (tests/golden, written by scripts that call only the oracle) and the
+CPU oracle's rate on a bounded sample, on one core and on every host core.
 """
 from __future__ import annotations
 
@@ -31,8 +35,16 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_sweep_tb.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1706_04551_amd", "csrc", f)
                   for f in ("kernels.hpp", "nhswe.hip")]
 COPY_CAL_BYTES = 256 << 20
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 ALG_BYTES_SWEEP = {"f64": 40, "f32": 20}   # per corner per sweep (matrix-free
                                            # minimum: r p, h, H, rhs; w p)
+# Compulsory HBM bytes per corner of one launch of the temporally blocked
+# sweep kernel: the five row coefficients and the right-hand side (bulk type)
+# and the FP64 iterate read once, the iterate written once.  The launch's
+# sweeps run from LDS and registers, so this, not ALG_BYTES_SWEEP x sweeps,
+# is what a launch must move.
+BLOCKED_BYTES_LAUNCH = {"f64": 64, "f32": 40}
+FULL_STEP_BASE = {"f64": 384.0, "f32": 192.0}   # flux, assembly, correction
 
 
 # The timed runs time only the back-to-back sweep batch of one relaxation
@@ -49,11 +61,120 @@ def phase_split(pr, steps):
 
 
 def alg_bytes_per_cell_step(kbar: float, prec: str) -> float:
-    """Compulsory bytes per cell-step with ideal stencil reuse:
-    flux stages 56 + 88, assembly 2 x 48, corrections 2 x 72, sweeps
-    2 x Kbar x 40 (FP64); FP32 bulk halves every term."""
+    """Bytes per cell-step of the per-sweep model: flux stages 56 + 88,
+    assembly 2 x 48, corrections 2 x 72, sweeps 2 x Kbar x 40 (FP64), every
+    sweep a full pass over memory; FP32 bulk halves every term.  With
+    temporal blocking the sweeps move less than this: bytes / time is an
+    effective rate that may exceed the HBM peak."""
     b = 384.0 + 80.0 * kbar
     return b if prec == "f64" else b / 2.0
+
+
+def blocked_bytes_per_cell_step(kbar: float, prec: str) -> float:
+    """Compulsory bytes per cell-step of the design: flux, assembly and
+    correction as in the per-sweep model, and per solve Kbar / 8 launches of
+    the sweep kernel at BLOCKED_BYTES_LAUNCH per corner (two solves)."""
+    return (FULL_STEP_BASE[prec] +
+            2.0 * (kbar / 8.0) * BLOCKED_BYTES_LAUNCH[prec])
+
+
+def sweep_roofline(pr, prec, kernel, traffic, copy_gbs):
+    """Roofline of the sweep kernel from the HIP-event timing of its
+    back-to-back launches: algorithmic bytes = BLOCKED_BYTES_LAUNCH x the
+    corners one launch covers; `traffic` (bytes per launch from the counter
+    runs, or None) gives the fraction of the peak actually moved."""
+    launches = max(1, pr["sweep_kernel_launches"])
+    sweep_ms = pr["sweep_kernel_ms"] / launches
+    corners = (pr["sweep_kernel_corner_sweeps"] /
+               max(1, pr["sweep_kernel_sweeps"]))
+    alg = BLOCKED_BYTES_LAUNCH[prec] * corners
+    sec = sweep_ms * 1e-3
+    achieved = alg / sec / 1e9 if sec > 0 else None
+    model = ALG_BYTES_SWEEP[prec] * pr["sweep_kernel_corner_sweeps"] / launches
+    return {"bound": "hbm",
+            "achieved": round(achieved, 1) if achieved else None,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+            "traffic": traffic,
+            "traffic_frac": (round(traffic / sec / 1e9 / HBM_PEAK_GBS, 4)
+                             if traffic and sec > 0 else None),
+            "kernel": kernel, "avg_launch_us": round(sweep_ms * 1e3, 3),
+            "sweeps_per_launch": round(pr["sweep_kernel_sweeps"] / launches,
+                                       3),
+            "corners_per_launch": int(round(corners)),
+            "alg_bytes_per_launch": int(alg),
+            "alg_basis": (f"{BLOCKED_BYTES_LAUNCH[prec]} B per corner per "
+                          "launch: 5 coefficients + rhs + iterate read, "
+                          "iterate written, once per launch of its sweeps"),
+            "per_sweep_model_GBps": (round(model / sec / 1e9, 1)
+                                     if sec > 0 else None),
+            "copy_GBps": copy_gbs,
+            "timed_cycles": f"1 in {PROFILE_SAMPLE}"}
+
+
+def copy_bandwidth():
+    """Achievable HBM bandwidth: a 1 GiB device-to-device copy (1 GiB read +
+    1 GiB written), best of 5, timed with events on torch's stream."""
+    import torch
+    n = (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    torch.cuda.empty_cache()
+    return round(2 * (1 << 30) / (best * 1e-3) / 1e9, 1)
+
+
+def golden(name):
+    """A stored oracle state (tests/golden), or None if not generated."""
+    import numpy as np
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        return None
+    return np.load(path)
+
+
+def lattice_err(g, ref, stride, suffix="", prefix=""):
+    """Normwise max difference on the stored lattice: h by the oracle's
+    max|h|, the discharges by the larger of max|hu|, max|hv| (full fields)."""
+    import numpy as np
+    sq = max(float(ref[prefix + "max_hu" + suffix]),
+             float(ref[prefix + "max_hv" + suffix]))
+    out = {}
+    for k, scale in (("h", float(ref[prefix + "max_h" + suffix])), ("hu", sq),
+                     ("hv", sq)):
+        out[k] = float(np.abs(g[k][::stride, ::stride] -
+                              ref[prefix + k + suffix]).max() / scale)
+    return out
+
+
+def storage_drift(ref, sto, suffix="", prefix="", sto_prefix=""):
+    """The same measure for the oracle with its state rounded to FP32 after
+    every step: what FP32 storage of the state alone changes."""
+    import numpy as np
+    sq = max(float(ref[prefix + "max_hu" + suffix]),
+             float(ref[prefix + "max_hv" + suffix]))
+    out = {}
+    for k, scale in (("h", float(ref[prefix + "max_h" + suffix])), ("hu", sq),
+                     ("hv", sq)):
+        out[k] = float(np.abs(sto[sto_prefix + k + suffix] -
+                              ref[prefix + k + suffix]).max() / scale)
+    return out
+
+
+def rounded(d, digits=3):
+    return {k: (float(f"{v:.{digits}e}") if isinstance(v, float) else v)
+            for k, v in d.items()}
 
 
 def kernel_source_hash() -> str:
@@ -130,49 +251,94 @@ def workload(name: str, prec: str, n=None, eps=None):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(case, steps: int):
-    """The FP64 oracle as it stands, single-threaded, on the first `steps`
-    steps of the same workload."""
-    from oracle.oracle import Oracle, Params
-    kw = case.param_dict()
-    o = Oracle(Params(**kw))
-    o.set_bathymetry(case.H)
-    o.set_state(case.h, case.hu, case.hv)
-    t0 = time.perf_counter()
-    st = o.run(steps)
-    t = time.perf_counter() - t0
-    if st != 0:
-        return None
-    s = o.stats()
-    value = case.nx * case.ny * steps / t / 1e6
-    return {"value": round(value, 4), "unit": "Mcell-steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": (f"first {steps} steps of the same workload "
-                       f"({case.nx}x{case.ny}, FP64 oracle, "
-                       f"{s['sweeps_total'] / max(1, s['solves']):.0f} sweeps/solve), "
-                       f"{t:.1f} s")}
+def host_cpu():
+    """Model name of the host CPU and the cores this process may run on (at
+    most 16, the host share of one GPU)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, min(len(os.sched_getaffinity(0)), 16)
 
 
-def ensemble_cpu_baseline(cases, members: int, steps: int):
-    """The FP64 oracle as it stands, single-threaded, on the first `steps`
-    steps of the first `members` scenarios of the ensemble."""
+def _oracle_runs(cases, steps: int, copies: int):
+    """Wall time of `copies` independent oracle runs of every case for
+    `steps` steps at once, one thread each (the oracle's ctypes calls release
+    the interpreter lock, so the copies run on separate cores)."""
+    from concurrent.futures import ThreadPoolExecutor
     from oracle.oracle import Oracle, Params
-    t = 0.0
-    cells = 0
-    for c in cases[:members]:
+
+    def prepared(c):
         o = Oracle(Params(**c.param_dict()))
         o.set_bathymetry(c.H)
         o.set_state(c.h, c.hu, c.hv)
-        t0 = time.perf_counter()
-        if o.run(steps) != 0:
-            return None
-        t += time.perf_counter() - t0
-        cells += c.nx * c.ny
-    return {"value": round(cells * steps / t / 1e6, 4), "unit": "Mcell-steps/s",
-            "cores": 1, "kind": "oracle",
-            "sample": (f"first {steps} steps of the first {members} scenarios "
-                       f"({cells} cells, FP64 oracle with the scenarios' "
-                       f"tolerance), {t:.1f} s")}
+        return o
+    jobs = [prepared(c) for _ in range(copies) for c in cases]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=copies) as ex:
+        codes = list(ex.map(lambda o: o.run(steps), jobs))
+    wall = time.perf_counter() - t0
+    if any(codes):
+        return None, None
+    st = jobs[0].stats()
+    return wall, st["sweeps_total"] / max(1, st["solves"])
+
+
+def cpu_baseline(cases, steps: int, what: str):
+    """The FP64 oracle as it stands on the first `steps` steps of the same
+    workload (`cases`: the grid, or the sampled members): once on one core,
+    then one copy per host core at once; value = the all-core rate."""
+    model, cores = host_cpu()
+    cells = sum(c.nx * c.ny for c in cases)
+    t1, kbar = _oracle_runs(cases, steps, 1)
+    if t1 is None:
+        return None
+    tn, _ = _oracle_runs(cases, steps, cores)
+    if tn is None:
+        return None
+    one = cells * steps / t1 / 1e6
+    alln = cores * cells * steps / tn / 1e6
+    return {"value": round(alln, 4), "unit": "Mcell-steps/s", "cores": cores,
+            "kind": "oracle",
+            "sample": (f"first {steps} steps of {what} ({cells} cells, FP64 "
+                       f"oracle, {kbar:.0f} sweeps/solve): one copy per core "
+                       f"on {cores} cores at once, {tn:.1f} s wall; one core "
+                       f"alone {t1:.1f} s"),
+            "single_core_value": round(one, 4), "cpu_model": model}
+
+
+def ensemble_oracle_err(e, cases, steps):
+    """Members sampled two per side against their stored oracle states after
+    the workload's 500 steps (tests/golden/c4_members_500.npz): the worst
+    member per side, with the FP32-storage drift of the same member."""
+    ref = golden("c4_members_500.npz")
+    if ref is None or steps != int(ref["steps"]):
+        return {"reason": "stored member states not generated for this "
+                          "step count"}
+    per_side = {}
+    for k in (int(m) for m in ref["members"]):
+        pre = f"m{k}_"
+        st = int(ref[pre + "stride"])
+        err = lattice_err(e.state(k), ref, st, prefix=pre)
+        drift = storage_drift(ref, ref, prefix=pre, sto_prefix=pre + "sto_")
+        side = str(int(ref[pre + "side"]))
+        worst = per_side.get(side)
+        if worst is None or max(err.values()) > max(worst["err"].values()):
+            per_side[side] = {"member": k, "err": rounded(err),
+                              "fp32_storage_alone": rounded(drift)}
+            if pre + "stoh_h" in ref.files:
+                per_side[side]["depth_rounded_to_fp32"] = rounded(
+                    storage_drift(ref, ref, prefix=pre,
+                                  sto_prefix=pre + "stoh_"))
+    return {"steps": steps, "per_side": per_side,
+            "reference": ("tests/golden/c4_members_500.npz: the oracle "
+                          "(FP64) with each member's configuration, 2 "
+                          "members per side, 64 x 64 sampled cells")}
 
 
 def run_ensemble(args):
@@ -202,15 +368,15 @@ def run_ensemble(args):
     sweeps = sum(s["sweeps_total"] for s in stats)
     solves = sum(s["solves"] for s in stats)
     kbar = sweeps / max(1, solves)
-    full_bytes = sum(n * steps * alg_bytes_per_cell_step(
+    full_bytes = sum(n * steps * blocked_bytes_per_cell_step(
         s["sweeps_total"] / max(1, s["solves"]), args.precision)
         for n, s in zip(cells, stats))
+    model_bytes = sum(n * steps * alg_bytes_per_cell_step(
+        s["sweeps_total"] / max(1, s["solves"]), args.precision)
+        for n, s in zip(cells, stats))
+    oracle_err = ensemble_oracle_err(e, cases, steps)
     ms_step = elapsed * 1e3 / steps
     value = ncell * steps / elapsed / 1e6
-    sweep_ms = pr["sweep_kernel_ms"] / max(1, pr["sweep_kernel_launches"])
-    alg = (ALG_BYTES_SWEEP[args.precision] * pr["sweep_kernel_corner_sweeps"]
-           / max(1, pr["sweep_kernel_launches"]))
-    achieved = alg / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else None
     tiles = {}
     for k, c in enumerate(cases):
         tiles[str(c.nx)] = "x".join(map(str, e.tile(k)))
@@ -222,15 +388,11 @@ def run_ensemble(args):
     phases = phase_split(e.get_profile(), nph)
     e.profile(False)
     e.close()
-    roof = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-            "traffic": measured_traffic("c4", args.precision),
-            "kernel": "k_sweep_tb_batch",
-            "avg_launch_us": round(sweep_ms * 1e3, 3),
-            "alg_bytes_per_launch": int(alg),
-            "timed_cycles": f"1 in {PROFILE_SAMPLE}"}
-    cpu = None if args.no_cpu else ensemble_cpu_baseline(cases, 4, 4)
+    roof = sweep_roofline(pr, args.precision, "k_sweep_tb_batch",
+                          measured_traffic("c4", args.precision),
+                          getattr(args, "copy_gbs", None))
+    cpu = None if args.no_cpu else cpu_baseline(
+        cases[:4], 4, "the first 4 scenarios of the ensemble")
     out = {
         "metric": "Mcell-steps/s per full step (flux+pressure solve), % HBM roofline, vs FP64 plain",
         "value": round(value, 3), "unit": "Mcell-steps/s", "n_gpus": 1,
@@ -247,11 +409,58 @@ def run_ensemble(args):
                    "min_sim_time_s": round(min(s["t"] for s in stats), 3),
                    "full_step_hbm_roofline_frac": round(
                        full_bytes / elapsed / (HBM_PEAK_GBS * 1e9), 4),
+                   "full_step_per_sweep_model_GBps": round(
+                       model_bytes / elapsed / 1e9, 1),
+                   "oracle_err": oracle_err,
                    "tiles": tiles,
                    "phase_ms_profiled_run": phases},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    return out
+
+
+def adjoint_fp64_err(c, gauges, target, steps, ckpt, r32):
+    """The FP32-bulk gradient against the FP64 gradient of the same run
+    (same grid, steps, checkpoints; the FP64 kernels equal the differentiable
+    oracle to ~1e-13 on the tested grids): normwise max and relative L2
+    differences of dJ/deta0 and of dJ/dH at fixed eta0, and of J.  Twice:
+    at the workload's initial state (water at rest away from the bump:
+    every limiter there sits on its kink, where J has no gradient and each
+    precision takes another branch wherever rounding decides it) and at a
+    base point off the kinks (a broad seeded 2 cm surface field added)."""
+    import numpy as np
+    from paper_1706_04551_amd import Solver, inputs
+
+    def diffs(a32, a64):
+        out = {"J": float(f"{abs(a32['J'] - a64['J']) / abs(a64['J']):.3e}")}
+        for name, a, b in (("dJ_deta0", a32["dh0"], a64["dh0"]),
+                           ("dJ_dH", a32["dH"] + a32["dh0"],
+                            a64["dH"] + a64["dh0"])):
+            out[name] = {
+                "max": float(f"{np.abs(a - b).max() / np.abs(b).max():.3e}"),
+                "l2": float(f"{np.linalg.norm(a - b) / np.linalg.norm(b):.3e}")}
+        return out
+
+    def run(prec, eta, tol):
+        cc, _, _, _ = inputs.case_c5(precision=prec)
+        s = Solver.from_case(cc)
+        s.set_state(cc.H + eta, cc.hu, cc.hv)
+        r = s.adjoint(steps, gauges, target, ckpt_every=ckpt, adj_tol=tol)
+        s.close()
+        return r
+
+    c64, eta0, _, _ = inputs.case_c5(precision="f64")
+    out = {"at_rest_base": diffs(r32, run("f64", eta0, 1e-10))}
+    xc = inputs.centres(c64.nx, c64.dx)
+    rng = np.random.default_rng(91)
+    base = eta0 + 0.02 * (inputs.gaussian_field(
+        rng, c64.nx, c64.ny, c64.nx * c64.dx, c64.ny * c64.dx, xc, xc, 6) -
+        0.5)
+    out["off_kinks_base"] = diffs(run("f32", base, 1e-6),
+                                  run("f64", base, 1e-10))
+    out["reference"] = ("the FP64 adjoint of the same run (solve tolerance "
+                        "1e-10, transposed solves 1e-10)")
     return out
 
 
@@ -288,20 +497,13 @@ def run_adjoint(args):
     phases = phase_split(s.get_profile(), nph)
     s.profile(False)
     s.close()
+    grad_err = None
+    if args.precision == "f32":
+        grad_err = adjoint_fp64_err(c, gauges, target, steps, ckpt, r)
     ncell = c.nx * c.ny
-    ncorn = (c.nx + 1) * (c.ny + 1)
     value = ncell * steps / elapsed / 1e6
-    sweep_ms = pr["sweep_kernel_ms"] / max(1, pr["sweep_kernel_launches"])
-    alg = (ALG_BYTES_SWEEP[args.precision] * pr["sweep_kernel_corner_sweeps"]
-           / max(1, pr["sweep_kernel_launches"]))
-    achieved = alg / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else None
-    roof = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-            "traffic": None, "kernel": "k_sweep_tb",
-            "avg_launch_us": round(sweep_ms * 1e3, 3),
-            "alg_bytes_per_launch": int(alg),
-            "timed_cycles": f"1 in {PROFILE_SAMPLE}"}
+    roof = sweep_roofline(pr, args.precision, "k_sweep_tb", None,
+                          getattr(args, "copy_gbs", None))
     out = {
         "metric": "Mcell-steps/s per full step (flux+pressure solve), % HBM roofline, vs FP64 plain",
         "value": round(value, 3), "unit": "Mcell-steps/s", "n_gpus": 1,
@@ -316,13 +518,93 @@ def run_adjoint(args):
                                 f"{args.precision.upper()} bulk (forward + "
                                 "recomputation + adjoint timed)"),
                    "cells": ncell, "J": r["J"],
+                   "err_vs_fp64_gradient": grad_err,
                    "forward_sweeps_per_solve": round(
                        st["sweeps_total"] / max(1, st["solves"]), 2),
                    "phase_ms_profiled_run": phases},
         "roofline": roof,
         "cpu_baseline": None,
     }
-    del ncorn
+    return out
+
+
+def single_oracle_err(s, case, args):
+    """Error of the workload's full run against the stored oracle state of
+    the same configuration (an untimed run from the initial state), or the
+    reason there is none."""
+    name, prec = args.workload, args.precision
+    plain = not (getattr(args, "solve_tol", None) or
+                 getattr(args, "hydrostatic", False) or
+                 getattr(args, "manning", None) or getattr(args, "zones", None))
+    if name == "c2" and plain:
+        ref = golden(f"c2_512_{prec}_1000.npz")
+        if ref is None:
+            return {"reason": "stored oracle state not generated"}
+        st = int(ref["stride"])
+        early = int(ref["early_steps"])
+        s.set_state(case.h, case.hu, case.hv)
+        s.run(early)
+        e_early = lattice_err(s.state(), ref, st, f"_{early}")
+        s.run(int(ref["steps"]) - early)
+        e = lattice_err(s.state(), ref, st)
+        out = {"steps": int(ref["steps"]), **rounded(e),
+               f"at_{early}_steps": rounded(e_early),
+               "reference": (f"tests/golden/c2_512_{prec}_1000.npz: the "
+                             f"oracle (FP64) with this configuration, every "
+                             f"{st}th cell"),
+               "norm": "max |gpu - oracle| / max |oracle| (discharges by "
+                       "the larger of max|hu|, max|hv|)"}
+        sto = golden("c2_512_f32storage_1000.npz") if prec == "f32" else None
+        if sto is not None:
+            out["fp32_storage_alone"] = rounded(storage_drift(ref, sto))
+            out[f"fp32_storage_alone_at_{early}_steps"] = rounded(
+                storage_drift(ref, sto, f"_{early}"))
+        return out
+    if name == "dambreak" and plain and prec == "f64":
+        ref = golden(f"dambreak_{case.nx}_t1.npz")
+        if ref is None or float(ref["eps"]) != case.solve_tol:
+            return {"reason": "no stored oracle state for this grid and eps"}
+        st = int(ref["stride"])
+        s.set_state(case.h, case.hu, case.hv)
+        s.run(int(ref["steps"]))
+        return {"steps": int(ref["steps"]),
+                **rounded(lattice_err(s.state(), ref, st)),
+                "reference": (f"tests/golden/dambreak_{case.nx}_t1.npz: the "
+                              f"oracle at t = 1 s, every {st}th cell")}
+    if name == "c3":
+        return c3_oracle_err(s, case, args)
+    return {"reason": "no stored oracle state for this variant (its parity "
+                      "is tested on smaller grids)"}
+
+
+def c3_oracle_err(s, case, args):
+    """Every row of the beach after its full run against the stored 1D
+    oracle run (the data are y-invariant), with the FP32-storage drift."""
+    import numpy as np
+    ref = golden("c3_beach_4000.npz")
+    if ref is None or not case.fixed_dt:
+        return {"reason": "stored 1D oracle run not generated"}
+    early = int(ref["early_steps"])
+    s.set_state(case.h, case.hu, case.hv)
+    out = {"steps": int(ref["steps"])}
+    for n, sfx in ((early, f"_{early}"), (int(ref["steps"]) - early, "")):
+        s.run(n)
+        g = s.state()
+        e, d = {}, {}
+        for k in ("h", "hu"):
+            r = ref[k + sfx][None, :]
+            scale = float(ref["max_" + k + sfx])
+            e[k] = float(np.abs(g[k] - r).max() / scale)
+            d[k] = float(np.abs(ref["sto_" + k + sfx] - ref[k + sfx]).max() /
+                         scale)
+        if sfx:
+            out[f"at_{early}_steps"] = rounded(e)
+            out[f"fp32_storage_alone_at_{early}_steps"] = rounded(d)
+        else:
+            out.update(rounded(e))
+            out["fp32_storage_alone"] = rounded(d)
+    out["reference"] = ("tests/golden/c3_beach_4000.npz: the 1D oracle (the "
+                        "data are y-invariant), every row compared")
     return out
 
 
@@ -333,6 +615,13 @@ def run_single(args):
     case, desc = workload(args.workload, args.precision,
                           getattr(args, "n", None),
                           getattr(args, "solve_tol", None))
+    if args.workload == "c3":
+        # the fixed dt of the stored 1D oracle run (half the 2D CFL limit of
+        # the initial state), so that every row can be checked against it
+        ref = golden("c3_beach_4000.npz")
+        if ref is not None:
+            case.fixed_dt, case.dt_fixed = 1, float(ref["dt"])
+            desc += f", fixed dt {case.dt_fixed:.5g} s"
     if getattr(args, "solve_tol", None):
         case.solve_tol = args.solve_tol
         desc = re.sub(r"tol=[0-9.e+-]+", f"tol={case.solve_tol:g}", desc)
@@ -379,6 +668,8 @@ def run_single(args):
     s.run(nph)
     phases = phase_split(s.get_profile(), nph)
     s.profile(False)
+    oracle_err = (None if getattr(args, "no_err", False)
+                  else single_oracle_err(s, case, args))
     s.close()
 
     kbar = st["sweeps_total"] / max(1, st["solves"])
@@ -386,27 +677,20 @@ def run_single(args):
     ms_step = elapsed * 1e3 / args.steps
 
     # roofline of the dominant kernel: the relaxation sweep
-    sweep_ms = pr["sweep_kernel_ms"] / max(1, pr["sweep_kernel_launches"])
-    sweeps_per_launch = pr["sweep_kernel_sweeps"] / max(1, pr["sweep_kernel_launches"])
-    alg = (ALG_BYTES_SWEEP[args.precision] * pr["sweep_kernel_corner_sweeps"]
-           / max(1, pr["sweep_kernel_launches"]))
-    achieved = alg / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else None
-    roof = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-            "traffic": measured_traffic(
-                f"dambreak{case.nx}" if args.workload == "dambreak"
-                else args.workload, args.precision),
-            "kernel": "k_sweep_tb", "avg_launch_us": round(sweep_ms * 1e3, 3),
-            "sweeps_per_launch": round(sweeps_per_launch, 3),
-            "alg_bytes_per_launch": int(alg),
-            "timed_cycles": f"1 in {PROFILE_SAMPLE}"}
-    full_step_bytes = alg_bytes_per_cell_step(kbar, args.precision) * ncell
-    step_roof_frac = full_step_bytes / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9)
+    roof = sweep_roofline(
+        pr, args.precision, "k_sweep_tb",
+        measured_traffic(f"dambreak{case.nx}" if args.workload == "dambreak"
+                         else args.workload, args.precision),
+        getattr(args, "copy_gbs", None))
+    sec_step = ms_step * 1e-3
+    step_roof_frac = (blocked_bytes_per_cell_step(kbar, args.precision) *
+                      ncell / sec_step / (HBM_PEAK_GBS * 1e9))
+    step_eff_gbs = (alg_bytes_per_cell_step(kbar, args.precision) * ncell /
+                    sec_step / 1e9)
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(case, args.cpu_steps)
+        cpu = cpu_baseline([case], args.cpu_steps, "the same workload")
 
     return {
         "metric": "Mcell-steps/s per full step (flux+pressure solve), % HBM roofline, vs FP64 plain",
@@ -425,7 +709,9 @@ def run_single(args):
                    "sim_time_s": round(st["t"], 4),
                    "mean_sweeps_per_solve": round(kbar, 2),
                    "full_step_hbm_roofline_frac": round(step_roof_frac, 4),
+                   "full_step_per_sweep_model_GBps": round(step_eff_gbs, 1),
                    "phase_ms_profiled_run": phases,
+                   "oracle_err": oracle_err,
                    **({} if t_end is None else {
                        "time_to_t_end_s": round(elapsed, 4),
                        "paper_table2_s": TABLE2_S.get(
@@ -446,9 +732,14 @@ def variant_summary(out):
             "mean_sweeps_per_solve": cfg.get("mean_sweeps_per_solve",
                                              cfg.get("forward_sweeps_per_solve")),
             "full_step_hbm_roofline_frac": cfg.get("full_step_hbm_roofline_frac"),
+            "full_step_per_sweep_model_GBps": cfg.get(
+                "full_step_per_sweep_model_GBps"),
             "sweep_roofline_frac": out["roofline"]["frac"],
+            "sweep_traffic_frac": out["roofline"]["traffic_frac"],
             "sweep_kernel": out["roofline"]["kernel"],
-            **{k: cfg[k] for k in ("members_failed", "min_sim_time_s",
+            "sweep_avg_launch_us": out["roofline"]["avg_launch_us"],
+            **{k: cfg[k] for k in ("oracle_err", "err_vs_fp64_gradient",
+                                   "members_failed", "min_sim_time_s",
                                    "sim_time_s", "time_to_t_end_s",
                                    "paper_table2_s", "paper_hardware")
                if k in cfg}}
@@ -463,7 +754,7 @@ def main():
     ap.add_argument("--precision", default=None, choices=["f64", "f32"],
                     help="default: f64 for c2 and dambreak, f32 for the c3, "
                          "c4 and c5 workloads")
-    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--solve-tol", type=float, default=None,
                     help="override the workload's stop tolerance (eq. 32)")
     ap.add_argument("--manning", type=float, default=None,
@@ -476,6 +767,9 @@ def main():
                     help="width [m] of absorbing relaxation zones on every "
                          "wall (default none)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-err", action="store_true",
+                    help="skip the runs that measure the error against the "
+                         "stored oracle states (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain copy of 256 MiB (for counter runs)")
     ap.add_argument("--no-variants", action="store_true",
@@ -494,6 +788,7 @@ def main():
     torch.cuda.set_device(0)
     if args.calibrate_copy:
         copy_calibration()
+    args.copy_gbs = copy_bandwidth()
     args.steps_given = args.steps is not None
     if args.precision is None:
         args.precision = ("f64" if args.workload in ("c2", "dambreak")

@@ -29,7 +29,7 @@
  *   corners [ny+1][nx+1] (1D: [nx+1]) w (depth-averaged vertical velocity),
  *                                     p (non-hydrostatic bottom pressure)
  * Corner (k, l) sits at x = k dx, y = l dy.  Walls bound the domain on every
- * side.
+ * side unless a side is open or a direction periodic (nh_params).
  *
  * Ownership.  The solver owns its device buffers, except those it borrows
  * through nh_bind_device_buffers.  Host arrays are always owned by the caller
@@ -108,6 +108,27 @@ typedef struct {
                           cell (h, H and both discharges); p is even across
                           it, as at a wall.  Unset sides are walls.  The
                           adjoint needs 0 */
+  int32_t periodic;    /* periodic directions (Section 4.4, item 1), a bit
+                          each: 1 x, 2 y (ignored in 1D).  The first and last
+                          cells of a periodic line are neighbours: ghosts
+                          wrap around, discharges keep their sign, the
+                          pressure rows reach across the seam (in 1D a cyclic
+                          tridiagonal system, solved by the Sherman-Morrison
+                          form of the Thomas algorithm).  The last corner of
+                          a periodic line is its first: corner arrays keep
+                          their [ny+1][nx+1] layout, both copies hold the
+                          same values (give w and p that way).  A periodic
+                          direction has no open side and no relaxation
+                          zone; the adjoint needs 0 */
+  int32_t w_advection; /* 0: the vertical velocity equation of the model,
+                          h w_t = p (eq. 7); 1: the energy-consistent form
+                          named after eq. 7, (hw)_t + div(hw u) = p, i.e.
+                          h (w_t + u . grad w) = p: each stage's hyperbolic
+                          step also carries w with the flow (first-order
+                          upwind at the corners, corner velocity from the
+                          means of q and h around the corner), before the
+                          pressure step.  Single grids only (ensembles and
+                          the adjoint need 0) */
 } nh_params;
 
 typedef struct {
@@ -178,7 +199,14 @@ nh_status nh_set_relaxation(nh_solver *s, const double *widths,
  * w of the scheme (Section 5, eq. 31), so that inputs and results need no
  * host copy.  Element type of the precision (double for NH_FP64, float for
  * NH_FP32), contiguous, row-major: H, h, hu, hv cells [ny][nx]; w corners
- * [ny+1][nx+1] ([nx+1] in 1D).  NULL = keep the current buffer. */
+ * [ny+1][nx+1] ([nx+1] in 1D).  NULL = keep the current buffer.
+ * Depth storage: an NH_FP64 grid stores the depth h in the h array; an
+ * NH_FP32 (bulk) grid stores s = h - max(H, 0) there: over water (H > 0)
+ * the surface elevation eta = h - H (its slopes and jumps, the well-balanced
+ * pressure terms, are then differences of stored values instead of
+ * differences of two nearly equal FP32 sums), on land (H <= 0) the depth
+ * itself (thin films keep their digits); a dry cell holds -max(H, 0).  Host
+ * arrays passed through nh_set_state / nh_read_state are always depths. */
 typedef struct {
   void *H;
   void *h, *hu, *hv; /* hv: NULL in 1D */

@@ -66,14 +66,22 @@ static inline int IX(const ora_t *o, int i, int j) {
 }
 static inline int CX(const ora_t *o, int k, int l) { return l * o->ncx + k; }
 /* Corner reflection about a wall corner row (reading: mirror ghosts also for
- * the corner unknowns, so that p_{-1} = p_{1}). */
-static inline int refl(int k, int n) {
+ * the corner unknowns, so that p_{-1} = p_{1}); in a periodic direction the
+ * corners wrap around (corner n is corner 0, so k < 0 is k + n and k > n is
+ * k - n). */
+static inline int refl(int k, int n, int per) {
+  if (per) return k < 0 ? k + n : (k > n ? k - n : k);
   if (k < 0) return -k;
   if (k > n) return 2 * n - k;
   return k;
 }
+static inline int per_x(const ora_t *o) { return o->P.periodic & 1; }
+static inline int per_y(const ora_t *o) {
+  return !o->is1d && (o->P.periodic & 2);
+}
 static inline double P_at(const ora_t *o, const double *p, int k, int l) {
-  return p[CX(o, refl(k, o->nx), o->is1d ? 0 : refl(l, o->ny))];
+  return p[CX(o, refl(k, o->nx, per_x(o)),
+              o->is1d ? 0 : refl(l, o->ny, per_y(o)))];
 }
 
 static double dmax(double a, double b) { return a > b ? a : b; }
@@ -105,11 +113,20 @@ static double desing_div(double num, double h, double delta) {
  * px / py = +1 (even) or -1 (odd) parity across x / y walls. */
 static void fill_ghosts(const ora_t *o, double *a, double px, double py) {
   /* Outflow sides (Section 4.4, homogeneous Neumann): the ghosts take the
-   * value of the adjacent cell, with no change of sign. */
+   * value of the adjacent cell, with no change of sign.  Periodic
+   * directions (Section 4.4, item 1): the first and last cells of a line are
+   * neighbours, so the ghosts past one end are the cells at the other end,
+   * with no change of sign. */
   const int open = o->P.open_sides;
+  const int px_per = per_x(o), py_per = per_y(o);
   int nx = o->nx, ny = o->ny;
   for (int j = 0; j < ny; ++j)
     for (int g = 1; g <= GH; ++g) {
+      if (px_per) {
+        a[IX(o, -g, j)] = a[IX(o, nx - g, j)];
+        a[IX(o, nx - 1 + g, j)] = a[IX(o, g - 1, j)];
+        continue;
+      }
       a[IX(o, -g, j)] = (open & 1) ? a[IX(o, 0, j)] : px * a[IX(o, g - 1, j)];
       a[IX(o, nx - 1 + g, j)] =
           (open & 2) ? a[IX(o, nx - 1, j)] : px * a[IX(o, nx - g, j)];
@@ -117,6 +134,11 @@ static void fill_ghosts(const ora_t *o, double *a, double px, double py) {
   if (o->is1d) return;
   for (int i = -GH; i < nx + GH; ++i)
     for (int g = 1; g <= GH; ++g) {
+      if (py_per) {
+        a[IX(o, i, -g)] = a[IX(o, i, ny - g)];
+        a[IX(o, i, ny - 1 + g)] = a[IX(o, i, g - 1)];
+        continue;
+      }
       a[IX(o, i, -g)] = (open & 4) ? a[IX(o, i, 0)] : py * a[IX(o, i, g - 1)];
       a[IX(o, i, ny - 1 + g)] =
           (open & 8) ? a[IX(o, i, ny - 1)] : py * a[IX(o, i, ny - g)];
@@ -452,7 +474,7 @@ static void breaking_g(ora_t *o, const double *h, double *q1, double *q2,
  * pinned by the dispersion test and by the probe assembly).
  * Corner k sits between cell k-1 (west) and cell k (east).
  * Wall rows: the mirror p_{-1} = p_{1} folds a into c (row 0) and c into a
- * (row N), the "conveniently modified" boundary rows.
+ * (row N): the boundary rows, which the paper leaves to be adapted.
  */
 static void assemble1d_g(const ora_t *o, const double *h, const double *q,
                          const double *w, double dt, double *a, double *b,
@@ -478,11 +500,11 @@ static void assemble1d_g(const ora_t *o, const double *h, const double *q,
     double zxc = (zeta[E] - zeta[W]) / dx;
     double Bc = hc * qxc - qc * zxc + 2.0 * hc * w[k];
     double r = -(8.0 * dx * dx / dt) * Bc;
-    if (k == 0) {
+    if (k == 0 && !per_x(o)) {
       ci = ci + ai;
       ai = 0.0;
     }
-    if (k == o->nx) {
+    if (k == o->nx && !per_x(o)) {
       ai = ai + ci;
       ci = 0.0;
     }
@@ -494,7 +516,7 @@ static void assemble1d_g(const ora_t *o, const double *h, const double *q,
 }
 
 /*
- * 2D coefficients.  The paper omits them ("too tedious"); they follow from
+ * 2D coefficients.  The paper does not print them; they follow from
  * substituting the half corrections of the edge discharges q_{1,E}, q_{1,W},
  * q_{2,N}, q_{2,S} (final scheme of Appendix A.2) and w = w* + dt p/h_c into
  * 2 x eq. (37) and multiplying by -4/dt.  With zeta = 2 eta - h = h - 2H,
@@ -508,7 +530,10 @@ static void assemble1d_g(const ora_t *o, const double *h, const double *q,
  *   rhs = -(4/dt) B*,  B* = [(2hc-sx) q1E - (2hc+sx) q1W]/dx
  *                          + [(2hc-sy) q2N - (2hc+sy) q2S]/dy + 4 hc w*
  * Dropping y and multiplying by dx^2 gives eq. (43) exactly.
- * Walls: the mirrored neighbour is folded into the inner coefficient.
+ * Walls: the mirrored neighbour is folded into the inner coefficient.  In a
+ * periodic direction nothing is folded: the neighbour past the last corner
+ * is the second one (corner n is corner 0), the one before the first corner
+ * is corner n - 1.
  */
 static void assemble2d_g(const ora_t *o, const double *h, const double *q1,
                          const double *q2, const double *w, double dt,
@@ -555,10 +580,14 @@ static void assemble2d_g(const ora_t *o, const double *h, const double *q1,
                   ((2.0 * hc - sy) * q2N - (2.0 * hc + sy) * q2S) / dy +
                   4.0 * hc * w[CX(o, k, l)];
       double r = -(4.0 / dt) * Bs;
-      if (k == 0) { e = e + wv; wv = 0.0; }
-      if (k == nx) { wv = wv + e; e = 0.0; }
-      if (l == 0) { n = n + s; s = 0.0; }
-      if (l == ny) { s = s + n; n = 0.0; }
+      if (!per_x(o)) {
+        if (k == 0) { e = e + wv; wv = 0.0; }
+        if (k == nx) { wv = wv + e; e = 0.0; }
+      }
+      if (!per_y(o)) {
+        if (l == 0) { n = n + s; s = 0.0; }
+        if (l == ny) { s = s + n; n = 0.0; }
+      }
       int c = CX(o, k, l);
       diag[c] = d;
       cE[c] = e;
@@ -586,6 +615,39 @@ static int thomas(int n, const double *a, const double *b, const double *c,
   return ORA_OK;
 }
 
+/* Periodic 1D channel (Section 4.4, item 1): the rows of the nx distinct
+ * corners form a cyclic tridiagonal system, row 0 reaching corner nx - 1
+ * through a[0] and row nx - 1 reaching corner 0 through c[nx - 1].  The
+ * "modification of the Thomas algorithm" taken here is the Sherman-Morrison
+ * form: the cyclic matrix is a tridiagonal one plus the rank-one term
+ * u v^T with u = (gamma, 0, ..., 0, c[n-1]), v = (1, 0, ..., 0,
+ * a[0]/gamma), gamma = -b[0]; two Thomas solves with the modified diagonal
+ * (b[0] - gamma, ..., b[n-1] - c[n-1] a[0] / gamma) and one correction.
+ * bb, z: n work values each; cp, dp those of thomas. */
+static int thomas_cyclic(int n, const double *a, const double *b,
+                         const double *c, const double *d, double *x,
+                         double *bb, double *z, double *cp, double *dp) {
+  const double alpha = c[n - 1], beta = a[0], gamma = -b[0];
+  if (!(gamma != 0.0)) return ORA_ENODOM;
+  for (int k = 0; k < n; ++k) bb[k] = b[k];
+  bb[0] = b[0] - gamma;
+  bb[n - 1] = b[n - 1] - alpha * beta / gamma;
+  int st = thomas(n, a, bb, c, d, x, cp, dp);
+  if (st != ORA_OK) return st;
+  /* z first holds the right-hand side u (thomas reads its right-hand side
+   * before it writes the solution) */
+  for (int k = 0; k < n; ++k) z[k] = 0.0;
+  z[0] = gamma;
+  z[n - 1] = alpha;
+  st = thomas(n, a, bb, c, z, z, cp, dp);
+  if (st != ORA_OK) return st;
+  const double den = 1.0 + z[0] + beta * z[n - 1] / gamma;
+  if (!(den != 0.0)) return ORA_ENODOM;
+  const double fact = (x[0] + beta * x[n - 1] / gamma) / den;
+  for (int k = 0; k < n; ++k) x[k] = x[k] - fact * z[k];
+  return ORA_OK;
+}
+
 /*
  * Relaxed Jacobi with a scheduled relaxation factor (Section 5, the
  * "Jacobi method combined with a scheduled relaxation"): sweep k replaces
@@ -600,7 +662,8 @@ static int thomas(int n, const double *a, const double *b, const double *c,
  * i.e. the size of the plain Jacobi update of eq. (32), is evaluated on the
  * current iterate; the solve stops there when E < tol (result: that iterate)
  * or when solve_max_iter sweeps are reached.  Walls are already folded into
- * the coefficients, so neighbours outside the corner range carry zero weight.
+ * the coefficients, so neighbours outside the corner range carry zero weight;
+ * in a periodic direction they wrap around.
  */
 /* compiled twice: with the FMA instruction where the CPU has it (fma() is
  * then one instruction), else with the library's fma(); both are exact */
@@ -610,6 +673,8 @@ static int jacobi_srj(ora_t *o, const double *diag, const double *cE,
                       const double *rhs, double *p, int32_t *sweeps,
                       double *measure) {
   const int ncx = o->ncx, ncy = o->ncy;
+  const int nxc = o->nx, nyc = o->ny;
+  const int px_per = per_x(o), py_per = per_y(o);
   const int nc = ncorners(o);
   double *pn = o->c[10];
   int k = 0;
@@ -625,10 +690,14 @@ static int jacobi_srj(ora_t *o, const double *diag, const double *cE,
       for (int kk = 0; kk < ncx; ++kk) {
         int c = CX(o, kk, l);
         double Ap = diag[c] * p[c];
-        if (kk + 1 < ncx) Ap = fma(cE[c], p[CX(o, kk + 1, l)], Ap);
-        if (kk - 1 >= 0) Ap = fma(cW[c], p[CX(o, kk - 1, l)], Ap);
-        if (l + 1 < ncy) Ap = fma(cN[c], p[CX(o, kk, l + 1)], Ap);
-        if (l - 1 >= 0) Ap = fma(cS[c], p[CX(o, kk, l - 1)], Ap);
+        if (kk + 1 < ncx || px_per)
+          Ap = fma(cE[c], p[CX(o, refl(kk + 1, nxc, px_per), l)], Ap);
+        if (kk - 1 >= 0 || px_per)
+          Ap = fma(cW[c], p[CX(o, refl(kk - 1, nxc, px_per), l)], Ap);
+        if (l + 1 < ncy || py_per)
+          Ap = fma(cN[c], p[CX(o, kk, refl(l + 1, nyc, py_per))], Ap);
+        if (l - 1 >= 0 || py_per)
+          Ap = fma(cS[c], p[CX(o, kk, refl(l - 1, nyc, py_per))], Ap);
         double upd = (rhs[c] - Ap) * (1.0 / diag[c]);  /* plain Jacobi update */
         if (check) {
           double e = fabs(upd);
@@ -784,8 +853,14 @@ static int solve_g(ora_t *o, double *diag, double *cE, double *cW, double *cN,
                    double *cS, double *rhs, double *p, int32_t *sweeps,
                    double *measure) {
   if (o->is1d) {
-    int n = o->ncx;
-    int st = thomas(n, cW, diag, cE, rhs, p, o->c[10], o->c[11]);
+    int st;
+    if (per_x(o)) {  /* nx distinct corners; corner nx is corner 0 */
+      st = thomas_cyclic(o->nx, cW, diag, cE, rhs, p, o->c[12], o->c[13],
+                         o->c[10], o->c[11]);
+      p[o->nx] = p[0];
+    } else {
+      st = thomas(o->ncx, cW, diag, cE, rhs, p, o->c[10], o->c[11]);
+    }
     if (sweeps) *sweeps = 0;
     if (measure) *measure = 0.0;
     return st;
@@ -831,6 +906,62 @@ static void friction_g(ora_t *o, double *hs, double *q1s, double *q2s,
     }
 }
 
+/* Energy-consistent vertical momentum (the form named after eq. 7):
+ * (hw)_t + div(hw u) = p.  With the mass equation h_t + div(h u) = 0 this is
+ * h (w_t + u . grad w) = p, so the variant adds the transport of w by the
+ * flow to the hyperbolic step of each stage; the projection step is the
+ * model's, w = w* + dt p / h_c.  Reading (the paper gives no discretisation
+ * for it): w lives at the corners; the corner velocity is the desingularised
+ * (Section 4.5) ratio of the means of q and h over the cells around the
+ * corner (of the stage input V, ghosted); the transport is first-order
+ * upwind in each direction,
+ *   w* = w - dt [ u+ (w_k - w_{k-1})/dx + u- (w_{k+1} - w_k)/dx
+ *                + v+ (w_l - w_{l-1})/dy + v- (w_{l+1} - w_l)/dy ],
+ * u+ = max(u, 0), u- = min(u, 0); corners beyond a wall or an open side are
+ * reflected as the pressure's are, wrapped on a periodic line; a dry corner
+ * (h_c <= dry_eps) keeps its w.  It keeps a uniform w uniform, and for a
+ * uniform current on a periodic line it moves the first moment of w by
+ * exactly u dt per step. */
+static void advect_w_g(const ora_t *o, const double *Vh, const double *Vq1,
+                       const double *Vq2, const double *w_in, double dt,
+                       double *w_out) {
+  const double dx = o->P.dx, dy = o->P.dy, de = o->P.delta;
+  for (int l = 0; l < o->ncy; ++l)
+    for (int k = 0; k < o->ncx; ++k) {
+      double hc, qc1, qc2 = 0.0;
+      if (o->is1d) {
+        hc = 0.5 * (Vh[IX(o, k - 1, 0)] + Vh[IX(o, k, 0)]);
+        qc1 = 0.5 * (Vq1[IX(o, k - 1, 0)] + Vq1[IX(o, k, 0)]);
+      } else {
+        hc = 0.25 * (Vh[IX(o, k - 1, l - 1)] + Vh[IX(o, k, l - 1)] +
+                     Vh[IX(o, k - 1, l)] + Vh[IX(o, k, l)]);
+        qc1 = 0.25 * (Vq1[IX(o, k - 1, l - 1)] + Vq1[IX(o, k, l - 1)] +
+                      Vq1[IX(o, k - 1, l)] + Vq1[IX(o, k, l)]);
+        qc2 = 0.25 * (Vq2[IX(o, k - 1, l - 1)] + Vq2[IX(o, k, l - 1)] +
+                      Vq2[IX(o, k - 1, l)] + Vq2[IX(o, k, l)]);
+      }
+      const int c = CX(o, k, l);
+      const double w = w_in[c];
+      if (hc <= o->P.dry_eps) {
+        w_out[c] = w;
+        continue;
+      }
+      const double u = ora_desing_velocity(hc, qc1, de);
+      const double ddx =
+          u > 0.0 ? (w - P_at(o, w_in, k - 1, l)) / dx
+                  : (P_at(o, w_in, k + 1, l) - w) / dx;
+      double adv = u * ddx;
+      if (!o->is1d) {
+        const double v = ora_desing_velocity(hc, qc2, de);
+        const double ddy =
+            v > 0.0 ? (w - P_at(o, w_in, k, l - 1)) / dy
+                    : (P_at(o, w_in, k, l + 1) - w) / dy;
+        adv = adv + v * ddy;
+      }
+      w_out[c] = w - dt * adv;
+    }
+}
+
 /* Stage: V (ghosted, filled) + corner w_in, warm start p -> outputs. */
 static int stage_g(ora_t *o, const double *Vh, const double *Vq1,
                    const double *Vq2, const double *w_in, double *p, double dt,
@@ -847,7 +978,10 @@ static int stage_g(ora_t *o, const double *Vh, const double *Vq1,
   fill_ghosts(o, q1s, -1.0, 1.0);
   fill_ghosts(o, q2s, 1.0, -1.0);
   double *ws = o->c[0];
-  memcpy(ws, w_in, sizeof(double) * nc);
+  if (o->P.w_advection)
+    advect_w_g(o, Vh, Vq1, Vq2, w_in, dt, ws);
+  else
+    memcpy(ws, w_in, sizeof(double) * nc);
   if (o->P.breaking_on) breaking_g(o, hs, q1s, q2s, ws, dt);
   int st = ORA_OK;
   *sweeps = 0;
@@ -885,7 +1019,7 @@ static int stage_g(ora_t *o, const double *Vh, const double *Vq1,
  * is the full projection-correction step (FV, breaking, pressure, correction):
  *   U1 = Pi(U^n + dt L(U^n)),  U2 = Pi(U1 + dt L(U1)),
  *   U^{n+1} = (U^n + U2)/2,    w^{n+1} = (w^n + w2)/2,  p^{n+1} = p2
- * (reading of "steps 1-4 repeated twice" in Section 6).  The next dt comes
+ * (reading of Section 6, which repeats its steps 1-4 twice).  The next dt comes
  * from the CFL condition on U^{n+1}.
  */
 /* Generation/absorption zones of Section 4.4, on every wall with a width
@@ -925,6 +1059,9 @@ int ora_set_relaxation(ora_t *o, const double *widths, const double *h_t,
   if (!o || !widths) return ORA_EINVAL;
   for (int s = 0; s < 4; ++s)
     if (!(widths[s] >= 0.0) || isinf(widths[s])) return ORA_EINVAL;
+  /* zones lie along walls: none across a periodic direction */
+  if (per_x(o) && (widths[0] > 0.0 || widths[1] > 0.0)) return ORA_EINVAL;
+  if (per_y(o) && (widths[2] > 0.0 || widths[3] > 0.0)) return ORA_EINVAL;
   const int N = o->gx * o->gy, nc = ncorners(o);
   double **arrs[7] = {&o->rm_cell, &o->rm_corn, &o->rt_h, &o->rt_q1,
                       &o->rt_q2,   &o->rt_w,    &o->rt_p};
@@ -1058,6 +1195,11 @@ ora_t *ora_create(const ora_params *pp, const double *omega, int32_t n_omega) {
     return NULL;
   if (!(pp->manning >= 0.0) || isinf(pp->manning)) return NULL;
   if (pp->open_sides < 0 || pp->open_sides > 15) return NULL;
+  if (pp->periodic < 0 || pp->periodic > 3) return NULL;
+  if (pp->w_advection < 0 || pp->w_advection > 1) return NULL;
+  /* a periodic direction has no ends: no open side in it */
+  if ((pp->periodic & 1) && (pp->open_sides & 3)) return NULL;
+  if (pp->ny > 1 && (pp->periodic & 2) && (pp->open_sides & 12)) return NULL;
   ora_t *o = (ora_t *)calloc(1, sizeof(ora_t));
   o->P = *pp;
   o->is1d = pp->ny == 1;
@@ -1255,11 +1397,16 @@ int ora_dense_solve(ora_t *o, const double *diag, const double *cE,
   for (int l = 0; l < o->ncy; ++l)
     for (int k = 0; k < o->ncx; ++k) {
       int c = CX(o, k, l);
+      const int px_per = per_x(o), py_per = per_y(o);
       A[(size_t)c * n + c] = diag[c];
-      if (k + 1 < o->ncx) A[(size_t)c * n + CX(o, k + 1, l)] = cE[c];
-      if (k - 1 >= 0) A[(size_t)c * n + CX(o, k - 1, l)] = cW[c];
-      if (l + 1 < o->ncy) A[(size_t)c * n + CX(o, k, l + 1)] = cN[c];
-      if (l - 1 >= 0) A[(size_t)c * n + CX(o, k, l - 1)] = cS[c];
+      if (k + 1 < o->ncx || px_per)
+        A[(size_t)c * n + CX(o, refl(k + 1, o->nx, px_per), l)] += cE[c];
+      if (k - 1 >= 0 || px_per)
+        A[(size_t)c * n + CX(o, refl(k - 1, o->nx, px_per), l)] += cW[c];
+      if (!o->is1d && (l + 1 < o->ncy || py_per))
+        A[(size_t)c * n + CX(o, k, refl(l + 1, o->ny, py_per))] += cN[c];
+      if (!o->is1d && (l - 1 >= 0 || py_per))
+        A[(size_t)c * n + CX(o, k, refl(l - 1, o->ny, py_per))] += cS[c];
       b[c] = rhs[c];
     }
   int st = ORA_OK;

@@ -14,8 +14,8 @@
  *   corners : [ny+1][nx+1] in 2D, [nx+1] in 1D.  Corner (k, l) sits at
  *             x = k*dx, y = l*dy; cell (i, j) has corners (i,j) SW, (i+1,j) SE,
  *             (i,j+1) NW, (i+1,j+1) NE.
- * Walls on every side (mirror ghosts; the state is even, the normal
- * discharge odd).
+ * Walls on every side unless open (outflow) or periodic (mirror ghosts at
+ * walls: the state is even, the normal discharge odd).
  */
 #ifndef NH_ORACLE_H
 #define NH_ORACLE_H
@@ -44,6 +44,16 @@ typedef struct ora_params {
   int32_t open_sides;      /* outflow sides of Section 4.4 (homogeneous
                               Neumann ghosts), a bit each: 1 west, 2 east,
                               4 south, 8 north; the others are walls */
+  int32_t periodic;        /* periodic directions of Section 4.4, item 1:
+                              1 x, 2 y (ignored in 1D).  The first and last
+                              cells of a periodic line are neighbours; its
+                              last corner is its first (both are kept and
+                              hold the same values) */
+  int32_t w_advection;     /* 0: the vertical velocity equation of the model,
+                              h w_t = p (eq. 7); 1: the energy-consistent
+                              form (hw)_t + div(hw u) = p named after eq. 7,
+                              i.e. h (w_t + u . grad w) = p: w is carried by
+                              the flow in each stage's hyperbolic step */
 } ora_params;
 
 /* status codes */

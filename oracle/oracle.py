@@ -33,6 +33,7 @@ class OraParams(C.Structure):
         ("solve_tol", C.c_double),
         ("fixed_dt", C.c_int32), ("dt_fixed", C.c_double),
         ("manning", C.c_double), ("open_sides", C.c_int32),
+        ("periodic", C.c_int32), ("w_advection", C.c_int32),
     ]
 
 
@@ -115,6 +116,8 @@ class Params:
     dt_fixed: float = 0.0
     manning: float = 0.0
     open_sides: int = 0
+    periodic: int = 0
+    w_advection: int = 0
     omega: np.ndarray = field(default_factory=lambda: np.ones(1))
 
     def c_struct(self) -> OraParams:
@@ -122,7 +125,8 @@ class Params:
                          self.delta, self.dry_eps, self.nh_on, self.breaking_on,
                          self.b1, self.b2, self.solve_max_iter,
                          self.check_every, self.solve_tol, self.fixed_dt,
-                         self.dt_fixed, self.manning, self.open_sides)
+                         self.dt_fixed, self.manning, self.open_sides,
+                         self.periodic, self.w_advection)
 
 
 class Oracle:

@@ -36,7 +36,8 @@ class NhParams(C.Structure):
                 ("check_every", C.c_int32), ("solve_tol", C.c_double),
                 ("omega_schedule", _DP), ("n_omega", C.c_int32),
                 ("fixed_dt", C.c_int32), ("dt", C.c_double),
-                ("manning", C.c_double), ("open_sides", C.c_int32)]
+                ("manning", C.c_double), ("open_sides", C.c_int32),
+                ("periodic", C.c_int32), ("w_advection", C.c_int32)]
 
 
 class NhDeviceViews(C.Structure):
@@ -159,7 +160,8 @@ def _f64(a, shape):
 def _params(*, g=9.81, cfl=0.9, delta=1e-5, dry_eps=1e-10, precision="f64",
             nh_on=1, breaking_on=0, b1=0.15, b2=0.5, solve_max_iter=200000,
             check_every=1, solve_tol=1e-10, omega=None, fixed_dt=0,
-            dt_fixed=0.0, manning=0.0, open_sides=0):
+            dt_fixed=0.0, manning=0.0, open_sides=0, periodic=0,
+            w_advection=0):
     """nh_params and the relaxation schedule array it points to (the caller
     keeps the array alive until the create call returns)."""
     om = None if omega is None else np.ascontiguousarray(
@@ -168,7 +170,7 @@ def _params(*, g=9.81, cfl=0.9, delta=1e-5, dry_eps=1e-10, precision="f64",
     par = NhParams(g, cfl, delta, dry_eps, prec, nh_on, breaking_on, b1, b2,
                    solve_max_iter, check_every, solve_tol, _ptr(om),
                    0 if om is None else len(om), fixed_dt, dt_fixed,
-                   manning, open_sides)
+                   manning, open_sides, periodic, w_advection)
     return par, om
 
 
@@ -228,7 +230,10 @@ class Solver:
         count (H, h, hu, hv) or the corner count (w).  Bound h, hu (and hv in
         2D) become the state; the solver then steps them in place on its
         stream (create it on torch's current stream to keep torch's work on
-        the tensors in order).  The tensors stay referenced here."""
+        the tensors in order).  In FP32 bulk the h tensor holds
+        s = h - max(H, 0) (the surface elevation over water, the depth on
+        land), the depth storage of such grids.  The tensors stay referenced
+        here."""
         import torch
         dtype = torch.float64 if self.precision == "f64" else torch.float32
         ncell, ncorn = self.nx * self.ny, int(np.prod(self.cshape))
@@ -439,3 +444,4 @@ class Ensemble:
         _check(lib().nh_ensemble_get_profile(self._h, C.byref(p)),
                "nh_ensemble_get_profile")
         return {k: getattr(p, k) for k, _ in NhProfile._fields_}
+

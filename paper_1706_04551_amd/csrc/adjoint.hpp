@@ -209,7 +209,13 @@ __device__ __forceinline__ void reconstruct_rev(
     cb = cb + (k == 1 ? -sb : (k == 2 ? sb : T(0)));
     mb = mb + (k == 2 ? -sb : T(0));
   };
-  slope(T(0.5) * (bR.h - bL.h), p.h, c.h, m.h, bp.h, bc.h, bm.h);
+  {  // the depth slope: the forward's choice from dh_of
+    const T sb = T(0.5) * (bR.h - bL.h);
+    const int k = minmod_pick(dh_of(p, c), dh_of(c, m));
+    bp.h = bp.h + (k == 1 ? sb : T(0));
+    bc.h = bc.h + (k == 1 ? -sb : (k == 2 ? sb : T(0)));
+    bm.h = bm.h + (k == 2 ? -sb : T(0));
+  }
   if (m.h > dry_eps && c.h > dry_eps && p.h > dry_eps) {
     slope(T(0.5) * (bR.eta - bL.eta), p.eta, c.eta, m.eta, bp.eta, bc.eta,
           bm.eta);
@@ -284,7 +290,7 @@ __global__ void __launch_bounds__(kBlock)
     w[0] = w[1] = w[2] = T(0);
     if (c < 0 || c >= len) return;
     const int m = XD ? jy * nx + c : c * nx + jx;
-    const T hv = hs_out[m];
+    const T hv = Store<T>::depth(hs_out[m], H[m]);
     const bool wet = hv > dry_eps;
     w[0] = hv > T(0) ? fac * lhs[m] : T(0);
     const T w1 = wet ? fac * lq1s[m] : T(0), w2 = wet ? fac * lq2s[m] : T(0);
@@ -348,14 +354,15 @@ __global__ void __launch_bounds__(kBlock)
   if (gl != j0) add_bar(b, bl);
   if (gh != j0) add_bar(b, bh);
   // primitives of j: un = desing(h, qn), ut = desing(h, qt), eta = h - H
-  const T hj = h[n], qn = XD ? q1[n] : q2[n], qt = XD ? q2[n] : q1[n];
+  const T hj = Store<T>::depth(h[n], H[n]), qn = XD ? q1[n] : q2[n],
+          qt = XD ? q2[n] : q1[n];
   T dhn, dqn, dht, dqt;
   desing_partials(hj, qn, delta, dhn, dqn);
   desing_partials(hj, qt, delta, dht, dqt);
   E ah = (E)b.h + (E)b.eta + (E)(dhn * b.un) + (E)(dht * b.ut);
   E an = (E)(dqn * b.un), at = (E)(dqt * b.ut);
   if (XD) {  // d out_j / d U_j contains the identity once
-    const T hv = hs_out[n];
+    const T hv = Store<T>::depth(hs_out[n], H[n]);
     const bool wet = hv > dry_eps;
     ah = ah + (hv > T(0) ? (E)lhs[n] : 0.0);
     an = an + (wet ? (E)lq1s[n] : 0.0);
@@ -375,12 +382,12 @@ __global__ void __launch_bounds__(kBlock)
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_adj_friction(AdjGeom G, T fric, const T* __restrict__ hs,
-                   const T* __restrict__ qa, const T* __restrict__ qb,
-                   T* __restrict__ lqa, T* __restrict__ lqb,
-                   T* __restrict__ lh) {
+                   const T* __restrict__ H, const T* __restrict__ qa,
+                   const T* __restrict__ qb, T* __restrict__ lqa,
+                   T* __restrict__ lqb, T* __restrict__ lh) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= G.nx * G.ny) return;
-  const T h = hs[n];
+  const T h = Store<T>::depth(hs[n], H[n]);
   if (h <= (T)G.dry_eps) return;  // dry: q = 0, no friction
   const T dt = (T)(*G.dtp), delta = (T)G.delta, K = dt * fric;
   const T a = qa[n], b = qb[n];
@@ -438,6 +445,26 @@ __device__ __forceinline__ int mirror_preimages(int j, int lo, int hi, int n,
   return cnt;
 }
 
+// forward values of cell q from its stored depth value (Store): the depth
+// and zeta = h - 2H, in the arithmetic E of the adjoint sums (FP32 bulk:
+// from s = h - max(H, 0))
+template <typename T>
+__device__ __forceinline__ E depth_e(const T* __restrict__ s,
+                                     const T* __restrict__ H, int q) {
+  if constexpr (Store<T>::kEta)
+    return (E)s[q] + (H[q] > T(0) ? (E)H[q] : E(0));
+  else
+    return (E)s[q];
+}
+template <typename T>
+__device__ __forceinline__ E zeta_e(const T* __restrict__ s,
+                                    const T* __restrict__ H, int q) {
+  if constexpr (Store<T>::kEta)
+    return H[q] > T(0) ? (E)s[q] - (E)H[q] : (E)s[q] - E(2) * (E)H[q];
+  else
+    return (E)s[q] - E(2) * (E)H[q];
+}
+
 // per cell of the correction: a, b (dt/2 times the adjoint of q1, q2; zero
 // where dry), hc and the zeta differences zx, zy (undivided by 2dx, 2dy)
 template <typename T>
@@ -454,12 +481,11 @@ __device__ __forceinline__ CorrCell<T> corr_cell(const AdjGeom& G,
                                                  E dt, int i, int j) {
   const int nx = G.nx, ny = G.ny, m = j * nx + i;
   auto zeta = [&](int ii, int jj) {
-    const int q = mirror(jj, ny) * nx + mirror(ii, nx);
-    return (E)hs[q] - E(2) * (E)H[q];
+    return zeta_e(hs, H, mirror(jj, ny) * nx + mirror(ii, nx));
   };
   CorrCell<T> c;
-  c.hc = (E)hs[m];
-  const bool wet = !(hs[m] <= (T)G.dry_eps);
+  c.hc = depth_e(hs, H, m);
+  const bool wet = !(Store<T>::depth(hs[m], H[m]) <= (T)G.dry_eps);
   c.a = wet ? E(0.5) * dt * (E)lq1[m] : 0.0;
   c.b = wet ? E(0.5) * dt * (E)lq2[m] : 0.0;
   c.zx = zeta(i + 1, j) - zeta(i - 1, j);
@@ -492,7 +518,7 @@ __global__ void __launch_bounds__(kBlock)
   }
   // w_c = w_in + dt desing(mean of the corner's cells, p_c)
   auto hcell = [&](int i, int j) {
-    return (E)hs[mirror(j, ny) * nx + mirror(i, nx)];
+    return depth_e(hs, H, mirror(j, ny) * nx + mirror(i, nx));
   };
   const E hm = E(0.25) * (hcell(k - 1, l - 1) + hcell(k, l - 1) +
                           hcell(k - 1, l) + hcell(k, l));
@@ -557,7 +583,7 @@ __global__ void __launch_bounds__(kBlock)
   }
   // corner means: j is 1 or 2 (at a wall) of the 4 mirrored cells per axis
   auto hcell = [&](int i, int j) {
-    return (E)hs[mirror(j, ny) * nx + mirror(i, nx)];
+    return depth_e(hs, H, mirror(j, ny) * nx + mirror(i, nx));
   };
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
@@ -573,7 +599,7 @@ __global__ void __launch_bounds__(kBlock)
   // zeta = h - 2H
   lhs[n] = (T)((E)lhs[n] + ah + az);
   lH[n] = (T)((E)lH[n] - E(2) * az);
-  const bool wet = hs[n] > (T)G.dry_eps;
+  const bool wet = Store<T>::depth(hs[n], H[n]) > (T)G.dry_eps;
   lq1s[n] = wet ? lq1[n] : T(0);
   lq2s[n] = wet ? lq2[n] : T(0);
 }
@@ -611,8 +637,7 @@ __global__ void __launch_bounds__(kBlock)
   if (c >= ncorn) return;
   const int k = c % ncx, l = c / ncx;
   auto zeta = [&](int i, int j) {
-    const int m = mirror(j, ny) * nx + mirror(i, nx);
-    return (E)hs[m] - E(2) * (E)H[m];
+    return zeta_e(hs, H, mirror(j, ny) * nx + mirror(i, nx));
   };
   // SW, SE, NW, NE cells of the corner (mirrored; discharges flip sign
   // across the wall they are mirrored over)
@@ -621,8 +646,8 @@ __global__ void __launch_bounds__(kBlock)
   for (int s = 0; s < 4; ++s) {
     const int i = k - 1 + (s & 1), j = l - 1 + (s >> 1);
     const int mi = mirror(i, nx), mj = mirror(j, ny), m = mj * nx + mi;
-    hh[s] = (E)hs[m];
-    zz[s] = hh[s] - E(2) * (E)H[m];
+    hh[s] = depth_e(hs, H, m);
+    zz[s] = zeta_e(hs, H, m);
     a1[s] = mi != i ? -(E)q1s[m] : (E)q1s[m];
     a2[s] = mj != j ? -(E)q2s[m] : (E)q2s[m];
     XX[s] = (zeta(i + 1, j) - zeta(i - 1, j)) / E(2);
@@ -837,13 +862,14 @@ __global__ void __launch_bounds__(kBlock)
 template <typename T>
 __global__ void k_gauge_misfit(int ng, const int* __restrict__ gauges,
                                const T* __restrict__ h,
+                               const T* __restrict__ H,
                                const double* __restrict__ target,
                                double* __restrict__ res,
                                double* __restrict__ J) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   double s = 0.0;
   for (int g = 0; g < ng; ++g) {
-    double r = (double)h[gauges[g]] - target[g];
+    double r = depth_e(h, H, gauges[g]) - target[g];
     res[g] = r;
     s += r * r;
   }

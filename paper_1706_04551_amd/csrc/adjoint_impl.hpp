@@ -342,8 +342,8 @@ nh_status adj_step(nh_solver* s, AdjWork* w, const StateRec& R, double tol,
       hipLaunchKernelGGL((nh::k_fv<T, false>), dim3(f0.nblocks()), B, 0, st,
                          f0);
       hipLaunchKernelGGL((nh::k_adj_friction<T>), Gc, B, 0, st, G, fric,
-                         C(hs_), C(w->fpre_q1), C(w->fpre_q2), P(w->Lqs1),
-                         P(w->Lqs2), P(lh_out));
+                         C(hs_), C(s->H), C(w->fpre_q1), C(w->fpre_q2),
+                         P(w->Lqs1), P(w->Lqs2), P(lh_out));
     }
     // finite volumes
     hipLaunchKernelGGL((nh::k_adj_fv<T, 1>), Gc, B, 0, st, G, C(Vh),
@@ -390,7 +390,8 @@ nh_status adjoint_impl(nh_solver* s, int64_t N, double adj_tol, double* J,
     if (st != NH_OK && st != NH_ENOCONV) return st;
     hipLaunchKernelGGL((nh::k_gauge_misfit<T>), dim3(1), dim3(64), 0,
                        s->stream, ng, (const int*)w->gauges, (const T*)s->h,
-                       w->target + n * ng, w->res + n * ng, w->J);
+                       (const T*)s->H, w->target + n * ng, w->res + n * ng,
+                       w->J);
     if ((n + 1) % 64 == 0) {
       nh_status ss = sync_stats(s);
       if (ss != NH_OK) return ss;
@@ -466,8 +467,10 @@ nh_status nh_adjoint_run(nh_solver* s, int64_t nsteps, int32_t ngauges,
     return fail(NH_EINVAL, "the adjoint does not cover the breaking terms");
   if (s->relax_on)
     return fail(NH_EINVAL, "the adjoint does not cover relaxation zones");
-  if (s->par.open_sides != 0)
+  if (s->par.open_sides != 0 || s->par.periodic != 0)
     return fail(NH_EINVAL, "the adjoint covers walls only");
+  if (s->par.w_advection != 0)
+    return fail(NH_EINVAL, "the adjoint covers the model's w equation only");
   if (nsteps < 1 || ngauges < 1 || ckpt_every < 1)
     return fail(NH_EINVAL, "need nsteps, ngauges, ckpt_every >= 1");
   if (!(adj_tol > 0)) return fail(NH_EINVAL, "need adj_tol > 0");

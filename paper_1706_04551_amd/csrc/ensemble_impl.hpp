@@ -445,6 +445,10 @@ nh_status nh_ensemble_create(int32_t n, const nh_grid* grids,
     nh_status st = check_params(&grids[k], &params[k]);
     if (st != NH_OK) return st;
     if (grids[k].ny < 2) return fail(NH_EINVAL, "ensemble members must be 2D");
+    if (params[k].w_advection != 0)
+      return fail(NH_EINVAL,
+                  "ensemble members use the model's w equation "
+                  "(w_advection = 0)");
     const nh_params& a = params[0];
     const nh_params& b = params[k];
     if (a.precision != b.precision || a.nh_on != b.nh_on ||

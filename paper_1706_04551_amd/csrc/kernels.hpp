@@ -25,17 +25,34 @@ __device__ __forceinline__ int mirror(int i, int n) {
   return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i);
 }
 
-// open (outflow) sides of a grid, a bit each: homogeneous Neumann ghosts
-// that copy the adjacent cell (Section 4.4); every other side is a wall
+// Boundary mask of a grid (the `open` field of the kernel arguments).  Open
+// (outflow) sides, a bit each: homogeneous Neumann ghosts that copy the
+// adjacent cell (Section 4.4).  Periodic directions (Section 4.4, item 1):
+// the first and last cells of a line are neighbours, and the last corner of
+// the line is its first (both are stored and hold the same values).  Every
+// other side is a wall.
 constexpr int kOpenW = 1, kOpenE = 2, kOpenS = 4, kOpenN = 8;
+constexpr int kPerX = 16, kPerY = 32;
 
 // the cell whose values position i of a line of n cells takes: its mirror
-// image at a wall, the end cell itself at an open end
+// image at a wall, the end cell itself at an open end, the cell one period
+// away on a periodic line (i within two cells of the line)
 __device__ __forceinline__ int ghost_src(int i, int n, bool open_lo,
-                                         bool open_hi) {
+                                         bool open_hi, bool per = false) {
+  if (per) return i < 0 ? i + n : (i >= n ? i - n : i);
   if (i < 0) return open_lo ? 0 : -1 - i;
   if (i >= n) return open_hi ? n - 1 : 2 * n - 1 - i;
   return i;
+}
+
+// the stored corner that corner k of a periodic line of n cells is (corners
+// 0 .. n are stored, n being 0 again; any k)
+__device__ __forceinline__ int wrap_corner(int k, int n) {
+  if (k < 0 || k > n) {
+    k %= n;
+    if (k < 0) k += n;
+  }
+  return k;
 }
 
 template <typename T>
@@ -60,11 +77,52 @@ __device__ __forceinline__ T desing(T h, T q, T delta) {
   return sqrt(T(2)) * h * q / sqrt(h4 + tmax(h4, d4));
 }
 
-// cell state with wall mirroring
+// What the depth arrays hold.  An FP64 grid stores the depth h.  An
+// FP32-bulk grid stores s = h - R against the reference level R = max(H, 0):
+// where the bed is below still water (H > 0) that is the surface elevation
+// eta = h - H, so the slopes and edge jumps of eta (the well-balanced
+// pressure terms, Section 4.1) are differences of stored values, where
+// h - H formed in FP32 would keep only the digits h and H share (ulp(20 m)
+// = 2e-6 m, against waves of centimetres); on land (H <= 0) it is the depth
+// itself, so thin films on dry slopes keep their digits.  The update of s is
+// the update of h (R does not change); a dry cell stores -R.
+template <typename T>
+struct Store;
+template <>
+struct Store<double> {
+  static constexpr bool kEta = false;
+  __device__ static double depth(double s, double H) { return s; }
+  __device__ static double eta(double s, double H) { return s - H; }
+  __device__ static double of_depth(double h, double H) { return h; }
+};
+template <>
+struct Store<float> {
+  static constexpr bool kEta = true;
+  __device__ static float ref(float H) { return H > 0.f ? H : 0.f; }
+  __device__ static float depth(float s, float H) { return s + ref(H); }
+  __device__ static float eta(float s, float H) {
+    return H > 0.f ? s : s - H;
+  }
+  __device__ static float of_depth(float h, float H) { return h - ref(H); }
+};
+
+// cell state with wall mirroring: depth h, surface elevation eta, the
+// stored depth value s (h or eta, see Store), discharges, still-water depth
 template <typename T>
 struct Cell {
-  T h, q1, q2, H;
+  T h, q1, q2, H, eta, s;
 };
+
+// zeta = 2 eta - h = h - 2H of a cell (the compact pressure scheme's
+// combination, Appendix A): formed from h in FP64 as the oracle does, from
+// the stored value in FP32 (one rounding instead of two cancelling ones)
+template <typename T>
+__device__ __forceinline__ T zeta_of(const Cell<T>& c) {
+  if constexpr (Store<T>::kEta)
+    return c.H > T(0) ? c.s - c.H : c.s - T(2) * c.H;
+  else
+    return c.h - T(2) * c.H;
+}
 
 template <typename T>
 __device__ __forceinline__ Cell<T> load_cell(const T* __restrict__ h,
@@ -73,17 +131,21 @@ __device__ __forceinline__ Cell<T> load_cell(const T* __restrict__ h,
                                              const T* __restrict__ H, int i,
                                              int j, int nx, int ny,
                                              bool one_d, int open = 0) {
-  int mi = ghost_src(i, nx, open & kOpenW, open & kOpenE);
-  int mj = one_d ? 0 : ghost_src(j, ny, open & kOpenS, open & kOpenN);
+  const bool px = open & kPerX, py = !one_d && (open & kPerY);
+  int mi = ghost_src(i, nx, open & kOpenW, open & kOpenE, px);
+  int mj = one_d ? 0 : ghost_src(j, ny, open & kOpenS, open & kOpenN, py);
   int idx = mj * nx + mi;
   Cell<T> c;
-  c.h = h[idx];
+  c.s = h[idx];
   c.H = H[idx];
+  c.h = Store<T>::depth(c.s, c.H);
+  c.eta = Store<T>::eta(c.s, c.H);
   c.q1 = q1[idx];
   c.q2 = one_d ? T(0) : q2[idx];
-  // the normal discharge is odd across a wall, even across an open end
-  if (mi != i && !(open & (i < 0 ? kOpenW : kOpenE))) c.q1 = -c.q1;
-  if (mj != j && !(open & (j < 0 ? kOpenS : kOpenN))) c.q2 = -c.q2;
+  // the normal discharge is odd across a wall, even across an open end and
+  // across the seam of a periodic line
+  if (mi != i && !px && !(open & (i < 0 ? kOpenW : kOpenE))) c.q1 = -c.q1;
+  if (mj != j && !py && !(open & (j < 0 ? kOpenS : kOpenN))) c.q2 = -c.q2;
   return c;
 }
 
@@ -97,7 +159,22 @@ struct Face {
 template <typename T>
 struct Prim {
   T h, un, ut, eta;
+  T s, R;  // FP32 bulk: stored depth value and reference level (Store)
 };
+
+// Depth difference b.h - a.h of two cells for the limiter.  In FP32 bulk it
+// is formed from the stored values and the reference levels, each
+// difference exact for nearby values and the sum rounded once: h = s + R
+// formed in FP32 keeps only ulp(R) of the depth (4e-6 m on 50 m of water),
+// more than the second differences the limiter compares on smooth waves
+// over flat stretches of bed, where the choice would follow rounding noise.
+template <typename T>
+__device__ __forceinline__ T dh_of(const Prim<T>& b, const Prim<T>& a) {
+  if constexpr (Store<T>::kEta)
+    return (b.s - a.s) + (b.R - a.R);
+  else
+    return b.h - a.h;
+}
 
 template <typename T>
 __device__ __forceinline__ Prim<T> prim(const Cell<T>& c, bool xdir, T delta,
@@ -108,7 +185,12 @@ __device__ __forceinline__ Prim<T> prim(const Cell<T>& c, bool xdir, T delta,
   T v = one_d ? T(0) : desing(c.h, c.q2, delta);
   p.un = xdir ? u : v;
   p.ut = xdir ? v : u;
-  p.eta = c.h - c.H;
+  p.eta = c.eta;
+  p.s = c.s;
+  if constexpr (Store<T>::kEta)
+    p.R = Store<T>::ref(c.H);
+  else
+    p.R = T(0);
   return p;
 }
 
@@ -119,7 +201,7 @@ template <typename T>
 __device__ __forceinline__ void reconstruct(const Prim<T>& m, const Prim<T>& c,
                                             const Prim<T>& p, T dry_eps,
                                             Face<T>& L, Face<T>& R) {
-  T sh = minmod(p.h - c.h, c.h - m.h);
+  T sh = minmod(dh_of(p, c), dh_of(c, m));
   T se = T(0), su = T(0), sv = T(0);
   if (m.h > dry_eps && c.h > dry_eps && p.h > dry_eps) {
     se = minmod(p.eta - c.eta, c.eta - m.eta);
@@ -307,12 +389,13 @@ __device__ __forceinline__ void fv_cell(const LD& ld, int i, int j, V dx, V dy,
 #pragma unroll
     for (int m = 0; m < 3; ++m) fy[m] = (Dm_e[m] + Dp_w[m]) + I[m];
   }
+  // out[0] is the stored depth value (h, or eta in FP32: the same update)
   if (ONE_D) {
-    out[0] = c0.h - dt * (fx[0] / dx);
+    out[0] = c0.s - dt * (fx[0] / dx);
     out[1] = c0.q1 - dt * (fx[1] / dx);
     out[2] = V(0);
   } else {
-    out[0] = c0.h - dt * (fx[0] / dx + fy[0] / dy);
+    out[0] = c0.s - dt * (fx[0] / dx + fy[0] / dy);
     out[1] = c0.q1 - dt * (fx[1] / dx + fy[2] / dy);
     out[2] = c0.q2 - dt * (fx[2] / dx + fy[1] / dy);
   }
@@ -323,14 +406,18 @@ __device__ __forceinline__ void fv_cell(const LD& ld, int i, int j, V dx, V dy,
 // discretised semi-implicitly (q implicit, |u| and h explicit) on the stage's
 // finite-volume result: q <- q / (1 + dt g n^2 |u| / h^(4/3)), |u| from the
 // desingularised velocities (Section 4.5)
+// ss: the stored depth value of the stage result (h, or eta in FP32), Hc the
+// cell's still-water depth
 template <typename T>
-__device__ __forceinline__ void fv_finish(T& hs, T& qa, T& qb, T dry_eps,
-                                          double dx, double dy,
+__device__ __forceinline__ void fv_finish(T& ss, T Hc, T& qa, T& qb,
+                                          T dry_eps, double dx, double dy,
                                           double& clamp, T fric, T dt,
                                           T delta) {
+  T hs = Store<T>::depth(ss, Hc);
   if (hs < T(0)) {
     clamp = -(double)hs * dx * dy;
     hs = T(0);
+    ss = Store<T>::of_depth(T(0), Hc);
   }
   if (hs <= dry_eps) {
     qa = T(0);
@@ -355,6 +442,10 @@ template <typename T>
 __device__ __forceinline__ void fv_tile_body(const FvArgs<T>& a, int bid) {
   constexpr int TX = kFvTX, TY = kFvTY, RX = TX + 4, RY = TY + 4;
   __shared__ T ph[RY][RX], pu[RY][RX], pv[RY][RX], pe[RY][RX];
+  // FP32 bulk: stored depth values and reference levels (limiter's depth
+  // differences, dh_of)
+  constexpr bool kS = Store<T>::kEta;
+  __shared__ T pS[kS ? RY : 1][kS ? RX : 1], pR[kS ? RY : 1][kS ? RX : 1];
   // fluctuations of x-edge e of a tile row (e: west edge of column e) and of
   // y-edge e of a tile column; m = to the cell below e, p = to the one above
   __shared__ T xm[3][TY][TX + 1], xp[3][TY][TX + 1];
@@ -366,27 +457,45 @@ __device__ __forceinline__ void fv_tile_body(const FvArgs<T>& a, int bid) {
   for (int r = (int)threadIdx.x; r < RX * RY; r += kBlock) {
     const int rx = r % RX, ry = r / RX;
     const int i = i0 - 2 + rx, j = j0 - 2 + ry;
-    T h = T(0), u = T(0), v = T(0), e = T(0);
+    T h = T(0), u = T(0), v = T(0), e = T(0), sv = T(0), Rv = T(0);
     if (i <= nx + 1 && j <= ny + 1) {  // the cells a grid cell's stencil reads
       const Cell<T> c =
           load_cell(a.h, a.q1, a.q2, a.H, i, j, nx, ny, false, a.open);
       h = c.h;
       u = desing(c.h, c.q1, delta);
       v = desing(c.h, c.q2, delta);
-      e = c.h - c.H;
+      e = c.eta;
+      if constexpr (kS) {
+        sv = c.s;
+        Rv = Store<T>::ref(c.H);
+      }
     }
     ph[ry][rx] = h;
     pu[ry][rx] = u;
     pv[ry][rx] = v;
     pe[ry][rx] = e;
+    if constexpr (kS) {
+      pS[ry][rx] = sv;
+      pR[ry][rx] = Rv;
+    }
   }
   __syncthreads();
+  auto sr = [&](Prim<T>& p, int rx, int ry) {
+    if constexpr (kS) {
+      p.s = pS[ry][rx];
+      p.R = pR[ry][rx];
+    } else {
+      p.s = p.h;
+      p.R = T(0);
+    }
+  };
   auto px = [&](int rx, int ry) {  // along x: normal u, tangential v
     Prim<T> p;
     p.h = ph[ry][rx];
     p.un = pu[ry][rx];
     p.ut = pv[ry][rx];
     p.eta = pe[ry][rx];
+    sr(p, rx, ry);
     return p;
   };
   auto py = [&](int rx, int ry) {  // along y: normal v, tangential u
@@ -395,6 +504,7 @@ __device__ __forceinline__ void fv_tile_body(const FvArgs<T>& a, int bid) {
     p.un = pv[ry][rx];
     p.ut = pu[ry][rx];
     p.eta = pe[ry][rx];
+    sr(p, rx, ry);
     return p;
   };
   // edge between region columns c and c + 1 of region row r (x), stored at
@@ -441,6 +551,8 @@ __device__ __forceinline__ void fv_tile_body(const FvArgs<T>& a, int bid) {
   if (i < nx && j < ny) {
     const int n = j * nx + i;
     const T h0 = ph[cy][cx], q10 = a.q1[n], q20 = a.q2[n];
+    // the stored value of the cell (FP64: h0 itself)
+    const T s0 = Store<T>::kEta ? a.h[n] : h0, Hc = a.H[n];
     const T dt = (T)(*a.dtp);
     T Ix[3], Iy[3], fx[3], fy[3];
     interior(Lx, Rx, h0, g, Ix);
@@ -450,11 +562,11 @@ __device__ __forceinline__ void fv_tile_body(const FvArgs<T>& a, int bid) {
       fx[m] = (xm[m][ty][tx + 1] + xp[m][ty][tx]) + Ix[m];
       fy[m] = (ym[m][ty + 1][tx] + yp[m][ty][tx]) + Iy[m];
     }
-    T hs = h0 - dt * (fx[0] / a.dx + fy[0] / a.dy);
+    T hs = s0 - dt * (fx[0] / a.dx + fy[0] / a.dy);
     T qa = q10 - dt * (fx[1] / a.dx + fy[2] / a.dy);
     T qb = q20 - dt * (fx[2] / a.dx + fy[1] / a.dy);
-    fv_finish(hs, qa, qb, dry_eps, (double)a.dx, (double)a.dy, clamp_local,
-              a.fric, dt, a.delta);
+    fv_finish(hs, Hc, qa, qb, dry_eps, (double)a.dx, (double)a.dy,
+              clamp_local, a.fric, dt, a.delta);
     a.oh[n] = hs;
     a.oq1[n] = qa;
     a.oq2[n] = qb;
@@ -477,8 +589,8 @@ __device__ __forceinline__ void fv_body(const FvArgs<T>& a, int bid) {
       fv_cell<T, true>(ld, n, 0, a.dx, a.dy, a.g, a.delta, a.dry_eps, dt, 3,
                        out);
       T hs = out[0], qa = out[1], qb = out[2];
-      fv_finish(hs, qa, qb, a.dry_eps, (double)a.dx, 1.0, clamp_local, a.fric,
-                dt, a.delta);
+      fv_finish(hs, a.H[n], qa, qb, a.dry_eps, (double)a.dx, 1.0, clamp_local,
+                a.fric, dt, a.delta);
       a.oh[n] = hs;
       a.oq1[n] = qa;
     }
@@ -530,7 +642,7 @@ __device__ __forceinline__ void break_cells_body(const BreakCellsArgs<T>& a,
             (T(2) * dy);
     Hy = (nn.H - ss.H) / (T(2) * dy);
   }
-  T hc = h[n];
+  T hc = Store<T>::depth(h[n], H[n]);
   T nu = T(0);
   if (hc > dry_eps) {
     T U1 = b1 * sqrt(g * hc);
@@ -547,10 +659,11 @@ template <typename T>
 struct BreakCornersArgs {
   int nx, ny;
   T delta;
-  const T *h, *rw;
+  const T *h, *rw, *H;
   const double* dtp;
   const T* w_in;
   T* w_out;
+  int open;  // boundary mask (kOpen*, kPer*)
   __host__ __device__ int nblocks(bool one_d) const {
     return ((nx + 1) * (one_d ? 1 : ny + 1) + kBlock - 1) / kBlock;
   }
@@ -563,25 +676,108 @@ __device__ __forceinline__ void break_corners_body(
   const T delta = a.delta;
   const T* __restrict__ h = a.h;
   const T* __restrict__ rw = a.rw;
+  const T* __restrict__ H = a.H;
   int ncx = nx + 1, ncy = ONE_D ? 1 : ny + 1;
+  auto dep = [&](int m) { return Store<T>::depth(h[m], H[m]); };
   const int n = bid * kBlock + (int)threadIdx.x;
   if (n >= ncx * ncy) return;
   int k = n % ncx, l = n / ncx;
   T dt = (T)(*a.dtp);
   T hc, rwc;
+  // the cells around the corner: mirrored at a wall (an open end's first
+  // ghost is the same cell), wrapped on a periodic line
+  const bool px = a.open & kPerX, py = a.open & kPerY;
   if (ONE_D) {
-    int W = mirror(k - 1, nx), E = mirror(k, nx);
-    hc = T(0.5) * (h[W] + h[E]);
+    int W = ghost_src(k - 1, nx, false, false, px);
+    int E = ghost_src(k, nx, false, false, px);
+    hc = T(0.5) * (dep(W) + dep(E));
     rwc = T(0.5) * (rw[W] + rw[E]);
   } else {
-    int im = mirror(k - 1, nx), ip = mirror(k, nx);
-    int jm = mirror(l - 1, ny), jp = mirror(l, ny);
+    int im = ghost_src(k - 1, nx, false, false, px);
+    int ip = ghost_src(k, nx, false, false, px);
+    int jm = ghost_src(l - 1, ny, false, false, py);
+    int jp = ghost_src(l, ny, false, false, py);
     int SW = jm * nx + im, SE = jm * nx + ip, NW = jp * nx + im,
         NE = jp * nx + ip;
-    hc = T(0.25) * (h[SW] + h[SE] + h[NW] + h[NE]);
+    hc = T(0.25) * (dep(SW) + dep(SE) + dep(NW) + dep(NE));
     rwc = T(0.25) * (rw[SW] + rw[SE] + rw[NW] + rw[NE]);
   }
   a.w_out[n] = a.w_in[n] + dt * desing(hc, rwc, delta);
+}
+
+// -------------------------------------------------------------------------
+// Energy-consistent vertical momentum (the form named after eq. 7):
+// (hw)_t + div(hw u) = p, i.e. h (w_t + u . grad w) = p, so each stage's
+// hyperbolic step also carries w with the flow before the pressure step.
+// First-order upwind at corner (k, l) with the desingularised velocity of
+// the means of h and q over the cells around the corner (stage input V):
+//   w* = w - dt [u (w - w_W)/dx or u (w_E - w)/dx, by the sign of u,
+//                + the same along y];
+// corners past a wall or an open side reflect as the pressure's do, wrap on
+// a periodic line; a dry corner keeps its w.
+// -------------------------------------------------------------------------
+template <typename T>
+struct AdvectWArgs {
+  int nx, ny;
+  T dx, dy, delta, dry_eps;
+  const T *h, *q1, *q2, *H;  // stage input V
+  const T* w_in;
+  const double* dtp;
+  T* w_out;
+  int open;  // boundary mask (kOpen*, kPer*)
+  __host__ __device__ int nblocks(bool one_d) const {
+    return ((nx + 1) * (one_d ? 1 : ny + 1) + kBlock - 1) / kBlock;
+  }
+};
+
+// the stored corner that corner k of a line of n cells reads: reflected
+// about the end corner (walls, open ends), wrapped on a periodic line
+__device__ __forceinline__ int corner_src(int k, int n, bool per) {
+  if (per) return wrap_corner(k, n);
+  return k < 0 ? -k : (k > n ? 2 * n - k : k);
+}
+
+template <typename T, bool ONE_D>
+__global__ void __launch_bounds__(kBlock) k_advect_w(AdvectWArgs<T> a) {
+  const int nx = a.nx, ny = a.ny;
+  const int ncx = nx + 1, ncy = ONE_D ? 1 : ny + 1;
+  const int n = blockIdx.x * kBlock + (int)threadIdx.x;
+  if (n >= ncx * ncy) return;
+  const int k = n % ncx, l = n / ncx;
+  CellLoader<T, ONE_D> ld{a.h, a.q1, a.q2, a.H, nx, ONE_D ? 1 : ny, a.open};
+  T hc, qc1, qc2 = T(0);
+  if (ONE_D) {
+    const Cell<T> W = ld(k - 1, 0), E = ld(k, 0);
+    hc = T(0.5) * (W.h + E.h);
+    qc1 = T(0.5) * (W.q1 + E.q1);
+  } else {
+    const Cell<T> SW = ld(k - 1, l - 1), SE = ld(k, l - 1), NW = ld(k - 1, l),
+                  NE = ld(k, l);
+    hc = T(0.25) * (SW.h + SE.h + NW.h + NE.h);
+    qc1 = T(0.25) * (SW.q1 + SE.q1 + NW.q1 + NE.q1);
+    qc2 = T(0.25) * (SW.q2 + SE.q2 + NW.q2 + NE.q2);
+  }
+  const T w = a.w_in[n];
+  if (hc <= a.dry_eps) {
+    a.w_out[n] = w;
+    return;
+  }
+  const bool px = a.open & kPerX, py = a.open & kPerY;
+  auto wat = [&](int kk, int ll) {
+    return a.w_in[corner_src(ll, ny, py) * ncx + corner_src(kk, nx, px)];
+  };
+  const T dt = (T)(*a.dtp);
+  const T u = desing(hc, qc1, a.delta);
+  const T ddx = u > T(0) ? (w - wat(k - 1, ONE_D ? 0 : l)) / a.dx
+                         : (wat(k + 1, ONE_D ? 0 : l) - w) / a.dx;
+  T adv = u * ddx;
+  if (!ONE_D) {
+    const T v = desing(hc, qc2, a.delta);
+    const T ddy = v > T(0) ? (w - wat(k, l - 1)) / a.dy
+                           : (wat(k, l + 1) - w) / a.dy;
+    adv = adv + v * ddy;
+  }
+  a.w_out[n] = w - dt * adv;
 }
 
 // -------------------------------------------------------------------------
@@ -589,14 +785,6 @@ __device__ __forceinline__ void break_corners_body(
 // zeta = h - 2H, X = (zeta_{i+1} - zeta_{i-1})/2, Y alike; pair averages
 // over the east/west/north/south cells of the corner; walls folded.
 // -------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T zeta_at(const T* __restrict__ h,
-                                     const T* __restrict__ H, int i, int j,
-                                     int nx, int ny) {
-  int idx = mirror(j, ny) * nx + mirror(i, nx);
-  return h[idx] - T(2) * H[idx];
-}
-
 template <typename T>
 struct AssembleArgs {
   int nx, ny;
@@ -613,21 +801,18 @@ struct AssembleArgs {
 template <typename V, typename LD>
 __device__ __forceinline__ void assemble_row(const LD& ld, int k, int l, int nx,
                                              int ny, V dx, V dy, V wc, V dt,
-                                             V row[6]) {
+                                             V row[6], int bc = 0) {
   const int ci[4] = {k - 1, k, k - 1, k};  // SW, SE, NW, NE
   const int cj[4] = {l - 1, l - 1, l, l};
   V hh[4], zz[4], XX[4], YY[4], a1[4], a2[4];  // a1, a2: q1, q2 of the cells
-  auto zeta = [&](int i, int j) {
-    Cell<V> c = ld(i, j);
-    return c.h - V(2) * c.H;
-  };
+  auto zeta = [&](int i, int j) { return zeta_of(ld(i, j)); };
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     Cell<V> c = ld(ci[s], cj[s]);
     hh[s] = c.h;
     a1[s] = c.q1;
     a2[s] = c.q2;
-    zz[s] = c.h - V(2) * c.H;
+    zz[s] = zeta_of(c);
     XX[s] = (zeta(ci[s] + 1, cj[s]) - zeta(ci[s] - 1, cj[s])) / V(2);
     YY[s] = (zeta(ci[s], cj[s] + 1) - zeta(ci[s], cj[s] - 1)) / V(2);
   }
@@ -655,10 +840,16 @@ __device__ __forceinline__ void assemble_row(const LD& ld, int k, int l, int nx,
          ((V(2) * hc - sy) * q2N - (V(2) * hc + sy) * q2S) / dy +
          V(4) * hc * wc;
   V r = -(V(4) / dt) * Bs;
-  if (k == 0) { e = e + wv; wv = V(0); }
-  if (k == nx) { wv = wv + e; e = V(0); }
-  if (l == 0) { nn = nn + ss; ss = V(0); }
-  if (l == ny) { ss = ss + nn; nn = V(0); }
+  // walls fold the mirrored neighbour into the inner one; a periodic line
+  // keeps both (its end corners reach across the seam)
+  if (!(bc & kPerX)) {
+    if (k == 0) { e = e + wv; wv = V(0); }
+    if (k == nx) { wv = wv + e; e = V(0); }
+  }
+  if (!(bc & kPerY)) {
+    if (l == 0) { nn = nn + ss; ss = V(0); }
+    if (l == ny) { ss = ss + nn; nn = V(0); }
+  }
   row[0] = d;
   row[1] = e;
   row[2] = wv;
@@ -678,7 +869,7 @@ __device__ __forceinline__ void assemble2d_body(const AssembleArgs<T>& a,
   T dt = (T)(*a.dtp);
   CellLoader<T, false> ld{a.h, a.q1, a.q2, a.H, nx, ny, a.open};
   T row[6];
-  assemble_row<T>(ld, k, l, nx, ny, a.dx, a.dy, a.w[n], dt, row);
+  assemble_row<T>(ld, k, l, nx, ny, a.dx, a.dy, a.w[n], dt, row, a.open);
   a.diag[n] = row[0];
   a.cE[n] = row[1];
   a.cW[n] = row[2];
@@ -699,17 +890,21 @@ __global__ void __launch_bounds__(kBlock)
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k > nx) return;
   T dt = (T)(*dtp);
-  const bool ow = open & kOpenW, oe = open & kOpenE;
+  const bool ow = open & kOpenW, oe = open & kOpenE, per = open & kPerX;
   auto zeta = [&](int i) {
-    int m = ghost_src(i, nx, ow, oe);
-    return h[m] - T(2) * H[m];
+    int m = ghost_src(i, nx, ow, oe, per);
+    if constexpr (Store<T>::kEta)
+      return H[m] > T(0) ? h[m] - H[m] : h[m] - T(2) * H[m];
+    else
+      return h[m] - T(2) * H[m];
   };
   auto qv = [&](int i) {
-    int m = ghost_src(i, nx, ow, oe);
-    return (m != i && !(i < 0 ? ow : oe)) ? -q[m] : q[m];
+    int m = ghost_src(i, nx, ow, oe, per);
+    return (m != i && !per && !(i < 0 ? ow : oe)) ? -q[m] : q[m];
   };
-  int Wi = mirror(k - 1, nx), Ei = mirror(k, nx);
-  T hW = h[Wi], hE = h[Ei];
+  int Wi = ghost_src(k - 1, nx, false, false, per);
+  int Ei = ghost_src(k, nx, false, false, per);
+  T hW = Store<T>::depth(h[Wi], H[Wi]), hE = Store<T>::depth(h[Ei], H[Ei]);
   T hc = T(0.5) * (hE + hW);
   T zW = zeta(k - 1), zE = zeta(k);
   T xiW = dx * ((zE - zeta(k - 2)) / (T(2) * dx));
@@ -725,8 +920,10 @@ __global__ void __launch_bounds__(kBlock)
   T zxc = (zE - zW) / dx;
   T Bc = hc * qxc - qc * zxc + T(2) * hc * w[k];
   T r = -(T(8) * dx * dx / dt) * Bc;
-  if (k == 0) { ci = ci + ai; ai = T(0); }
-  if (k == nx) { ai = ai + ci; ci = T(0); }
+  if (!per) {  // walls fold the mirrored neighbour (periodic: the cyclic row)
+    if (k == 0) { ci = ci + ai; ai = T(0); }
+    if (k == nx) { ai = ai + ci; ci = T(0); }
+  }
   a[k] = ai;
   b[k] = bi;
   c[k] = ci;
@@ -757,6 +954,69 @@ __global__ void k_thomas(int n, const T* __restrict__ a, const T* __restrict__ b
     xn = dp[k] - cp[k] * xn;
     x[k] = xn;
   }
+}
+
+// Periodic 1D channel (Section 4.4, item 1): the n = nx distinct corners form
+// a cyclic tridiagonal system (row 0 reaches corner n - 1 through a[0], row
+// n - 1 reaches corner 0 through c[n - 1]), solved by the Sherman-Morrison
+// modification of the Thomas algorithm: with gamma = -b[0], two tridiagonal
+// solves with the diagonal b[0] - gamma, b[1], ..., b[n-1] - c[n-1] a[0] /
+// gamma -- of the right-hand side and of u = (gamma, 0, ..., 0, c[n-1]) --
+// and the rank-one correction x -= (x0 + a[0] x_{n-1} / gamma) / (1 + z0 +
+// a[0] z_{n-1} / gamma) z.  In FP64 by one thread; corner n gets corner 0's
+// value.  bb, z, cp, dp: n FP64 work values each.
+template <typename T>
+__global__ void k_thomas_cyclic(int n, const T* __restrict__ a,
+                                const T* __restrict__ b,
+                                const T* __restrict__ c,
+                                const T* __restrict__ d,
+                                double* __restrict__ x,
+                                double* __restrict__ bb,
+                                double* __restrict__ z,
+                                double* __restrict__ cp,
+                                double* __restrict__ dp,
+                                int* __restrict__ flags) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const double alpha = (double)c[n - 1], beta = (double)a[0];
+  const double gamma = -(double)b[0];
+  if (!(gamma != 0.0)) { atomicOr(flags, 2); return; }
+  for (int k = 0; k < n; ++k) bb[k] = (double)b[k];
+  bb[0] = (double)b[0] - gamma;
+  bb[n - 1] = (double)b[n - 1] - alpha * beta / gamma;
+  // one tridiagonal elimination of the right-hand side r into y
+  auto tridiag = [&](auto rhs, double* y) -> bool {
+    if (!(bb[0] != 0.0)) return false;
+    cp[0] = (double)c[0] / bb[0];
+    dp[0] = rhs(0) / bb[0];
+    for (int k = 1; k < n; ++k) {
+      const double m = bb[k] - (double)a[k] * cp[k - 1];
+      if (!(m != 0.0)) return false;
+      cp[k] = (double)c[k] / m;
+      dp[k] = (rhs(k) - (double)a[k] * dp[k - 1]) / m;
+    }
+    double yn = dp[n - 1];
+    y[n - 1] = yn;
+    for (int k = n - 2; k >= 0; --k) {
+      yn = dp[k] - cp[k] * yn;
+      y[k] = yn;
+    }
+    return true;
+  };
+  if (!tridiag([&](int k) { return (double)d[k]; }, x)) {
+    atomicOr(flags, 2);
+    return;
+  }
+  if (!tridiag([&](int k) {
+        return k == 0 ? gamma : (k == n - 1 ? alpha : 0.0);
+      }, z)) {
+    atomicOr(flags, 2);
+    return;
+  }
+  const double den = 1.0 + z[0] + beta * z[n - 1] / gamma;
+  if (!(den != 0.0)) { atomicOr(flags, 2); return; }
+  const double fact = (x[0] + beta * x[n - 1] / gamma) / den;
+  for (int k = 0; k < n; ++k) x[k] = x[k] - fact * z[k];
+  x[n] = x[0];
 }
 
 // -------------------------------------------------------------------------
@@ -790,6 +1050,7 @@ constexpr int kSweepMBig = 3;  // large grids and ensembles: bigger tiles
 template <typename T>
 struct SweepArgs {
   int ncx, ncy, BX, BY, ntx, ntiles;
+  int bc = 0;            // boundary mask (kPer*: halos wrap around)
   const T *diag, *cE, *cW, *cN, *cS, *rhs;
   double* p[3];          // iterate buffers
   const double* omega;   // relaxation schedule
@@ -854,13 +1115,17 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a,
     if (idx < R) {
       rx[m] = idx % RW;
       ry[m] = idx / RW;
-      int gx = x0 + rx[m], gy = y0 + ry[m];
+      const int ux = x0 + rx[m], uy = y0 + ry[m];  // unwrapped position
+      // a periodic direction takes the halo from across the seam (corner
+      // ncx - 1 is corner 0 again)
+      const int gx = (a.bc & kPerX) ? wrap_corner(ux, ncx - 1) : ux;
+      const int gy = (a.bc & kPerY) ? wrap_corner(uy, ncy - 1) : uy;
       double pv = 0.0;
       if (gx >= 0 && gx < ncx && gy >= 0 && gy < ncy) {
         int g = gy * ncx + gx;
         pv = pin[g];
         if (check && rx[m] >= S && rx[m] < S + BX && ry[m] >= S &&
-            ry[m] < S + BY)
+            ry[m] < S + BY && ux < ncx && uy < ncy)
           psave[g] = pv;
         dg[m] = dgl[g];
         ce[m] = cE[g];
@@ -977,10 +1242,7 @@ template <typename V, bool ONE_D, typename LD, typename PL>
 __device__ __forceinline__ void correct_cell(const LD& ld, const PL& pl, int i,
                                              int j, V dx, V dy, V dt, V dry_eps,
                                              V& qa, V& qb) {
-  auto zeta = [&](int ii, int jj) {
-    Cell<V> c = ld(ii, jj);
-    return c.h - V(2) * c.H;
-  };
+  auto zeta = [&](int ii, int jj) { return zeta_of(ld(ii, jj)); };
   V hc = ld(i, j).h;
   V zx = (zeta(i + 1, j) - zeta(i - 1, j)) / (V(2) * dx);
   if (ONE_D) {
@@ -1071,12 +1333,13 @@ __device__ __forceinline__ void correct_body(const CorrectArgs<T>& a,
       if (!isfinite((double)hn) || !isfinite((double)an) ||
           !isfinite((double)bn))
         atomicOr(a.flags, 1);
-      if (hn > dry_eps) {
-        T cel = sqrt(g * hn);
-        T u = desing(hn, an, delta);
+      const T hd = Store<T>::depth(hn, H[n]);  // hn: the stored value
+      if (hd > dry_eps) {
+        T cel = sqrt(g * hd);
+        T u = desing(hd, an, delta);
         T l = (fabs(u) + cel) / dx;
         if (!ONE_D) {
-          T v = desing(hn, bn, delta);
+          T v = desing(hd, bn, delta);
           l = l + (fabs(v) + cel) / dy;
         }
         lam_local = (double)l;
@@ -1131,7 +1394,7 @@ template <typename T>
 struct LambdaArgs {
   int nx, ny;
   T dx, dy, g, delta, dry_eps;
-  const T *h, *q1, *q2;
+  const T *h, *q1, *q2, *H;
   double* lampart;
   __host__ __device__ int nblocks() const { return (nx * ny + kBlock - 1) / kBlock; }
 };
@@ -1141,7 +1404,7 @@ __device__ __forceinline__ void lambda_body(const LambdaArgs<T>& a, int bid) {
   const int n = bid * kBlock + (int)threadIdx.x;
   double lam_local = 0.0;
   if (n < a.nx * a.ny) {
-    T hn = a.h[n];
+    T hn = Store<T>::depth(a.h[n], a.H[n]);
     if (hn > a.dry_eps) {
       T cel = sqrt(a.g * hn);
       T u = desing(hn, a.q1[n], a.delta);
@@ -1263,11 +1526,12 @@ __global__ void k_fill(long n, T v, T* __restrict__ a) {
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_check_values(long n, const T* __restrict__ a, int nf, int neg,
-                   int* __restrict__ flags) {
+                   int* __restrict__ flags, const T* __restrict__ H = nullptr) {
   const long i = (long)blockIdx.x * kBlock + threadIdx.x;
   int bad_nf = 0, bad_neg = 0;
   if (i < n) {
-    const double v = (double)a[i];
+    // with H: a holds stored depth values, checked as depths
+    const double v = H ? (double)Store<T>::depth(a[i], H[i]) : (double)a[i];
     bad_nf = !isfinite(v);
     bad_neg = neg != 0 && v < 0.0;
   }
@@ -1282,6 +1546,18 @@ __global__ void k_convert(int n, const Tsrc* __restrict__ s,
                           Tdst* __restrict__ d) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) d[i] = (Tdst)s[i];
+}
+
+// FP32-bulk depth arrays hold s = h - max(H, 0) (Store<float>); the depth
+// they give back to the host is s + max(H, 0) in FP64
+__global__ void k_depth_from_eta(int n, const float* __restrict__ s,
+                                 const float* __restrict__ H,
+                                 double* __restrict__ h) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double Hi = (double)H[i];
+    h[i] = (double)s[i] + (Hi > 0.0 ? Hi : 0.0);
+  }
 }
 
 // -------------------------------------------------------------------------

@@ -142,6 +142,7 @@ struct nh_solver {
   nh_grid grid{};
   nh_params par{};
   std::vector<double> omega;
+  int nom = 1;             // relaxation factors in the schedule
   bool one_d = false;
   bool fp32 = false;
   size_t esize = 8;
@@ -157,11 +158,18 @@ struct nh_solver {
   void *q1b = nullptr, *q2b = nullptr, *rw = nullptr;              // breaking
   void *h1 = nullptr, *q11 = nullptr, *q21 = nullptr;              // U^(1)
   void *w = nullptr, *ws = nullptr, *w1 = nullptr;                 // corners
+  void* wadv = nullptr;  // w carried by the flow (w_advection)
+  // FP32 bulk: the bathymetry as the caller gave it (FP64), against which a
+  // host depth becomes the stored s = h - max(H, 0) (a lake at rest gets
+  // eta = 0 exactly; against the FP32 bathymetry it would get the rounding
+  // of H)
+  std::vector<double> H_host;
   void *pa = nullptr, *pb = nullptr, *pc = nullptr;  // p (FP64, both modes)
   int pcur = 0;                            // index of the current iterate
   void *cdiag = nullptr, *cE = nullptr, *cW = nullptr, *cN = nullptr,
        *cS = nullptr, *crhs = nullptr;
   double *thomas_cp = nullptr, *thomas_dp = nullptr;
+  double *thomas_bb = nullptr, *thomas_z = nullptr;  // cyclic (periodic 1D)
   void *stage_buf = nullptr;   // FP64 staging for host copies
   // generation/absorption zones: weights and targets (bulk type; p* FP64)
   bool relax_on = false;
@@ -245,6 +253,34 @@ nh_status download(nh_solver* s, double* dst, const void* src, long n) {
   return NH_OK;
 }
 
+// host FP64 depths into a depth array of the solver.  FP32 bulk stores
+// s = h - max(H, 0), formed in FP64 against the bathymetry as the caller
+// gave it (which must be set first) and rounded once: a lake at rest gets
+// eta = 0 over water and stays at rest to the bit; a dry cell gets -max(H,0).
+nh_status upload_depth(nh_solver* s, void* dst, const double* h, long n) {
+  if (!s->fp32) return upload(s, dst, h, n);
+  if ((long)s->H_host.size() != n)
+    return fail(NH_ESTATE, "set the bathymetry first");
+  std::vector<double> sv(n);
+  for (long i = 0; i < n; ++i) {
+    const double Hi = s->H_host[i];
+    sv[i] = h[i] - (Hi > 0.0 ? Hi : 0.0);
+  }
+  return upload(s, dst, sv.data(), n);
+}
+
+// a depth array of the solver to host FP64 depths
+nh_status download_depth(nh_solver* s, double* h, const void* src, long n) {
+  if (!s->fp32) return download(s, h, src, n);
+  hipLaunchKernelGGL(nh::k_depth_from_eta, dim3(nblocks(n)), dim3(nh::kBlock),
+                     0, s->stream, (int)n, (const float*)src,
+                     (const float*)s->H, (double*)s->stage_buf);
+  HIP_TRY(hipMemcpyAsync(h, s->stage_buf, n * sizeof(double),
+                         hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return NH_OK;
+}
+
 // ---------------------------------------------------------------------------
 // typed launch helpers
 // ---------------------------------------------------------------------------
@@ -292,6 +328,13 @@ inline SysView forward_system(const nh_solver* s) {
                  {(double*)s->pa, (double*)s->pb, (double*)s->pc}};
 }
 
+// boundary mask of the kernels: open sides and periodic directions
+inline int bc_mask(const nh_solver* s) {
+  const auto& pr = s->par;
+  return pr.open_sides | ((pr.periodic & 1) ? nh::kPerX : 0) |
+         ((!s->one_d && (pr.periodic & 2)) ? nh::kPerY : 0);
+}
+
 // kernel arguments of one grid, shared by the single-grid launches and the
 // ensemble's batched launches
 template <typename T>
@@ -305,7 +348,7 @@ struct Args {
                          (T)pr.delta, (T)pr.dry_eps, P(S.Vh), P(S.Vq1),
                          P(S.Vq2), P(s->H), s->dt, P(S.hs_cur), P(s->q1s),
                          P(s->q2s), s->clamped,
-                         (T)(pr.g * pr.manning * pr.manning), pr.open_sides};
+                         (T)(pr.g * pr.manning * pr.manning), bc_mask(s)};
   }
   static nh::BreakCellsArgs<T> break_cells(const nh_solver* s,
                                            const StagePlan& S) {
@@ -315,20 +358,20 @@ struct Args {
                                  (T)pr.delta, (T)pr.dry_eps, (T)pr.b1,
                                  P(S.hs_cur), P(s->q1s), P(s->q2s), P(s->H),
                                  s->dt, P(s->q1b), P(s->q2b), P(s->rw),
-                                 pr.open_sides};
+                                 bc_mask(s)};
   }
   static nh::BreakCornersArgs<T> break_corners(const nh_solver* s,
                                                const StagePlan& S) {
     return nh::BreakCornersArgs<T>{s->grid.nx, s->grid.ny, (T)s->par.delta,
-                                   P(S.hs_cur), P(s->rw), s->dt, P(S.w_in),
-                                   P(s->ws)};
+                                   P(S.hs_cur), P(s->rw), P(s->H), s->dt,
+                                   P(S.w_in), P(s->ws), bc_mask(s)};
   }
   static nh::AssembleArgs<T> assemble(const nh_solver* s, const StagePlan& S) {
     const auto& g = s->grid;
     return nh::AssembleArgs<T>{g.nx, g.ny, (T)g.dx, (T)g.dy, P(S.hs_cur),
                                P(S.qa), P(S.qb), P(s->H), P(S.wst), s->dt,
                                P(s->cdiag), P(s->cE), P(s->cW), P(s->cN),
-                               P(s->cS), P(s->crhs), s->par.open_sides};
+                               P(s->cS), P(s->crhs), bc_mask(s)};
   }
   static nh::SweepArgs<T> sweep(const nh_solver* s) {
     return sweep(s, forward_system(s));
@@ -341,6 +384,7 @@ struct Args {
     a.BY = s->tby;
     a.ntx = s->ntx;
     a.ntiles = s->ntx * s->nty;
+    a.bc = bc_mask(s);
     a.diag = P(V.diag);
     a.cE = P(V.cE);
     a.cW = P(V.cW);
@@ -351,7 +395,7 @@ struct Args {
     a.p[1] = V.p[1];
     a.p[2] = V.p[2];
     a.omega = s->omega_dev;
-    a.nom = (int)s->omega.size();
+    a.nom = s->nom;
     a.part = s->part;
     return a;
   }
@@ -370,14 +414,14 @@ struct Args {
                               s->relax_on ? P(s->rm_c) : nullptr, P(s->rt_h),
                               P(s->rt_q1), P(s->rt_q2),
                               s->relax_on ? P(s->rm_k) : nullptr,
-                              P(s->rt_w), pr.open_sides};
+                              P(s->rt_w), bc_mask(s)};
   }
   static nh::LambdaArgs<T> lambda(const nh_solver* s) {
     const auto& g = s->grid;
     const auto& pr = s->par;
     return nh::LambdaArgs<T>{g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.g,
                              (T)pr.delta, (T)pr.dry_eps, P(s->h), P(s->q1),
-                             P(s->q2), s->lampart};
+                             P(s->q2), P(s->H), s->lampart};
   }
 };
 
@@ -409,6 +453,20 @@ struct Launch {
                          dim3(nh::kBlock), 0, s->stream, a);
   }
 
+  static void advect_w(nh_solver* s, const StagePlan& S, void* w_out) {
+    const auto& g = s->grid;
+    const auto& pr = s->par;
+    nh::AdvectWArgs<T> a{g.nx, g.ny, (T)g.dx, (T)g.dy, (T)pr.delta,
+                         (T)pr.dry_eps, P(S.Vh), P(S.Vq1), P(S.Vq2), P(s->H),
+                         P(S.w_in), s->dt, P(w_out), bc_mask(s)};
+    if (s->one_d)
+      hipLaunchKernelGGL((nh::k_advect_w<T, true>), dim3(a.nblocks(true)),
+                         dim3(nh::kBlock), 0, s->stream, a);
+    else
+      hipLaunchKernelGGL((nh::k_advect_w<T, false>), dim3(a.nblocks(false)),
+                         dim3(nh::kBlock), 0, s->stream, a);
+  }
+
   static void breaking(nh_solver* s, const StagePlan& S) {
     auto c = Args<T>::break_cells(s, S);
     auto k = Args<T>::break_corners(s, S);
@@ -434,7 +492,7 @@ struct Launch {
                          dim3(nh::kBlock), 0, s->stream, g.nx, (T)g.dx,
                          P(S.hs_cur), P(S.qa), P(s->H), P(S.wst), s->dt,
                          P(s->cW), P(s->cdiag), P(s->cE), P(s->crhs),
-                         s->par.open_sides);
+                         bc_mask(s));
     } else {
       auto a = Args<T>::assemble(s, S);
       hipLaunchKernelGGL((nh::k_assemble2d<T>), dim3(a.nblocks()),
@@ -467,10 +525,16 @@ struct Launch {
   }
 
   static void thomas(nh_solver* s, void* pout) {
-    hipLaunchKernelGGL((nh::k_thomas<T>), dim3(1), dim3(64), 0, s->stream,
-                       (int)s->ncorn, P(s->cW), P(s->cdiag), P(s->cE),
-                       P(s->crhs), (double*)pout, s->thomas_cp, s->thomas_dp,
-                       s->flags);
+    if (s->par.periodic & 1)  // cyclic system of the nx distinct corners
+      hipLaunchKernelGGL((nh::k_thomas_cyclic<T>), dim3(1), dim3(64), 0,
+                         s->stream, (int)s->grid.nx, P(s->cW), P(s->cdiag),
+                         P(s->cE), P(s->crhs), (double*)pout, s->thomas_bb,
+                         s->thomas_z, s->thomas_cp, s->thomas_dp, s->flags);
+    else
+      hipLaunchKernelGGL((nh::k_thomas<T>), dim3(1), dim3(64), 0, s->stream,
+                         (int)s->ncorn, P(s->cW), P(s->cdiag), P(s->cE),
+                         P(s->crhs), (double*)pout, s->thomas_cp,
+                         s->thomas_dp, s->flags);
   }
 
   static void correct(nh_solver* s, const StagePlan& S, const void* p) {
@@ -525,6 +589,18 @@ nh_status wait_seq(hipStream_t stream, long long* seq_host, long long want) {
 // the measure of the solver's check number s->seq (the device keeps running
 // the launches queued behind it)
 nh_status wait_measure(nh_solver* s, double* E) {
+  if (!s->slot) {
+    // no mapped host memory (nh_run_noalloc): copy the published slot back
+    // once the stream has reached it
+    HostSlot hs{};
+    HIP_TRY(hipMemcpyAsync(&hs, s->slot_dev, sizeof(hs),
+                           hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (hs.seq != s->seq)
+      return fail(NH_EDEVICE, "convergence measure was not published");
+    *E = hs.E[0];
+    return NH_OK;
+  }
   nh_status st = wait_seq(s->stream, &s->slot->seq, s->seq);
   if (st != NH_OK) return st;
   *E = s->slot->E[0];
@@ -605,11 +681,18 @@ nh_status solve2d(nh_solver* s, const SysView& V, int& pcur, double tol,
 
 template <typename T>
 nh_status stage(nh_solver* s, int idx, int32_t* sweeps, double* measure) {
-  const StagePlan S = stage_plan(s, idx);
+  StagePlan S = stage_plan(s, idx);
   s->hs_cur = S.hs_cur;
   long pm = s->prof.open(s->stream, 0);
   Launch<T>::fv(s, S);
-  s->prof.close(s->stream, pm, 1);
+  if (s->par.w_advection) {
+    // energy-consistent form: w carried by the stage input's flow; the rest
+    // of the stage (breaking, assembly, correction) reads the carried w
+    Launch<T>::advect_w(s, S, s->wadv);
+    S.w_in = s->wadv;
+    if (!s->par.breaking_on) S.wst = s->wadv;
+  }
+  s->prof.close(s->stream, pm, s->par.w_advection ? 2 : 1);
   pm = s->prof.open(s->stream, 1);
   if (s->par.breaking_on) Launch<T>::breaking(s, S);
   if (s->par.nh_on) Launch<T>::assemble(s, S);
@@ -722,6 +805,13 @@ nh_status check_params(const nh_grid* g, const nh_params* p) {
     return fail(NH_EINVAL, "need a finite manning >= 0");
   if (p->open_sides < 0 || p->open_sides > 15)
     return fail(NH_EINVAL, "open_sides is a mask of 4 bits");
+  if (p->periodic < 0 || p->periodic > 3)
+    return fail(NH_EINVAL, "periodic is a mask of 2 bits");
+  if (p->w_advection != 0 && p->w_advection != 1)
+    return fail(NH_EINVAL, "w_advection must be 0 or 1");
+  if (((p->periodic & 1) && (p->open_sides & 3)) ||
+      (g->ny > 1 && (p->periodic & 2) && (p->open_sides & 12)))
+    return fail(NH_EINVAL, "a periodic direction has no open side");
   if (p->precision != NH_FP64 && p->precision != NH_FP32)
     return fail(NH_EINVAL, "precision must be NH_FP64 or NH_FP32");
   if (p->nh_on && g->ny > 1) {
@@ -739,13 +829,43 @@ nh_status check_params(const nh_grid* g, const nh_params* p) {
   return NH_OK;
 }
 
-// with U^n (h, q1, q2, w) in place on the device: p from the host array (or
-// 0), statistics reset, dt from the CFL condition (or the fixed dt)
-nh_status adopt_state(nh_solver* s, const double* p) {
+// sweep tiles of a solver's grid
+nh_status choose_sweep_tiles(nh_solver* s) {
+  // sweep tiles: 24 x 24 corners with a halo of kSweepS and 2 region points
+  // per thread (measured best of the tile/halo/workgroup shapes tried on
+  // gfx950 for 513^2 corners); FP32-bulk grids of more than 1024 such tiles
+  // take 32 x 32 tiles with 3 points per thread (fewer halo re-reads; in
+  // FP64 the 3-point kernel needs more than 64 registers and loses half its
+  // occupancy).  The region must fit kSweepB * sweep_m points (checked here,
+  // assumed by the kernel).
+  s->tbx = 24;
+  s->tby = 24;
+  s->sweep_m = nh::kSweepM;
+  if (!s->one_d && s->fp32 &&
+      (long)((s->grid.nx + 24) / 24) * ((s->grid.ny + 24) / 24) > 1024) {
+    s->tbx = 32;
+    s->tby = 32;
+    s->sweep_m = nh::kSweepMBig;
+  }
+  if ((s->tbx + 2 * nh::kSweepS) * (s->tby + 2 * nh::kSweepS) >
+      nh::kSweepB * s->sweep_m) {
+    return fail(NH_EINVAL, "sweep tile does not fit the workgroup");
+  }
+  s->ntx = (s->grid.nx + 1 + s->tbx - 1) / s->tbx;
+  s->nty = s->one_d ? 1 : (s->grid.ny + 1 + s->tby - 1) / s->tby;
+  return NH_OK;
+}
+
+// with U^n (h, q1, q2, w) in place on the device: p from the host array
+// (device array with p_on_device), or 0; statistics reset, dt from the CFL
+// condition (or the fixed dt)
+nh_status adopt_state(nh_solver* s, const double* p, bool p_on_device = false) {
   s->pcur = 0;
   if (p) {
     HIP_TRY(hipMemcpyAsync(s->pa, p, s->ncorn * sizeof(double),
-                           hipMemcpyHostToDevice, s->stream));
+                           p_on_device ? hipMemcpyDeviceToDevice
+                                       : hipMemcpyHostToDevice,
+                           s->stream));
   } else {
     HIP_TRY(hipMemsetAsync(s->pa, 0, s->ncorn * sizeof(double), s->stream));
   }
@@ -819,11 +939,14 @@ void release_own(nh_solver* s, void* p) {
   }
 }
 
+// H (nullable): `a` holds stored depth values, checked as depths
 template <typename T>
-void check_values(nh_solver* s, const void* a, long n, int nf, int neg) {
+void check_values(nh_solver* s, const void* a, long n, int nf, int neg,
+                  const void* H = nullptr) {
   hipLaunchKernelGGL((nh::k_check_values<T>), dim3(nblocks(n)),
                      dim3(nh::kBlock), 0, s->stream, n,
-                     static_cast<const T*>(a), nf, neg, s->flags);
+                     static_cast<const T*>(a), nf, neg, s->flags,
+                     static_cast<const T*>(H));
 }
 
 }  // namespace
@@ -848,6 +971,7 @@ nh_status nh_create(const nh_grid* grid, const nh_params* params,
                     params->omega_schedule + params->n_omega);
   else
     s->omega.assign(1, 1.0);
+  s->nom = (int)s->omega.size();
   s->par.omega_schedule = nullptr;
   s->one_d = grid->ny == 1;
   s->fp32 = params->precision == NH_FP32;
@@ -872,7 +996,7 @@ nh_status nh_create(const nh_grid* grid, const nh_params* params,
   void** cells[] = {&s->H,   &s->h,   &s->q1,  &s->q2,  &s->hs,  &s->q1s,
                     &s->q2s, &s->q1b, &s->q2b, &s->rw,  &s->h1,  &s->q11,
                     &s->q21};
-  void** corners[] = {&s->w,  &s->ws, &s->w1, &s->cdiag,
+  void** corners[] = {&s->w,  &s->ws, &s->w1, &s->wadv, &s->cdiag,
                       &s->cE, &s->cW, &s->cN, &s->cS, &s->crhs};
   for (auto c : cells)
     if ((st = dalloc(s, c, cb)) != NH_OK) { nh_destroy(s); return st; }
@@ -887,6 +1011,8 @@ nh_status nh_create(const nh_grid* grid, const nh_params* params,
   if ((st = dalloc(s, &s->stage_buf, nstage * sizeof(double))) != NH_OK ||
       (st = dalloc(s, (void**)&s->thomas_cp, s->ncorn * sizeof(double))) != NH_OK ||
       (st = dalloc(s, (void**)&s->thomas_dp, s->ncorn * sizeof(double))) != NH_OK ||
+      (st = dalloc(s, (void**)&s->thomas_bb, s->ncorn * sizeof(double))) != NH_OK ||
+      (st = dalloc(s, (void**)&s->thomas_z, s->ncorn * sizeof(double))) != NH_OK ||
       (st = dalloc(s, (void**)&s->dt, sizeof(double))) != NH_OK ||
       (st = dalloc(s, (void**)&s->lampart,
                    nblocks(std::max(s->ncell, s->ncorn)) * sizeof(double))) !=
@@ -905,29 +1031,10 @@ nh_status nh_create(const nh_grid* grid, const nh_params* params,
     nh_destroy(s);
     return fail(NH_EDEVICE, "copy of the relaxation schedule failed");
   }
-  // sweep tiles: 24 x 24 corners with a halo of kSweepS and 2 region points
-  // per thread (measured best of the tile/halo/workgroup shapes tried on
-  // gfx950 for 513^2 corners); FP32-bulk grids of more than 1024 such tiles
-  // take 32 x 32 tiles with 3 points per thread (fewer halo re-reads; in
-  // FP64 the 3-point kernel needs more than 64 registers and loses half its
-  // occupancy).  The region must fit kSweepB * sweep_m points (checked here,
-  // assumed by the kernel).
-  s->tbx = 24;
-  s->tby = 24;
-  s->sweep_m = nh::kSweepM;
-  if (!s->one_d && s->fp32 &&
-      (long)((grid->nx + 24) / 24) * ((grid->ny + 24) / 24) > 1024) {
-    s->tbx = 32;
-    s->tby = 32;
-    s->sweep_m = nh::kSweepMBig;
-  }
-  if ((s->tbx + 2 * nh::kSweepS) * (s->tby + 2 * nh::kSweepS) >
-      nh::kSweepB * s->sweep_m) {
+  if ((st = choose_sweep_tiles(s)) != NH_OK) {
     nh_destroy(s);
-    return fail(NH_EINVAL, "sweep tile does not fit the workgroup");
+    return st;
   }
-  s->ntx = (grid->nx + 1 + s->tbx - 1) / s->tbx;
-  s->nty = s->one_d ? 1 : (grid->ny + 1 + s->tby - 1) / s->tby;
   if (dalloc(s, (void**)&s->dstats, sizeof(nh::DevStats)) != NH_OK ||
       hipHostMalloc((void**)&s->slot, sizeof(HostSlot),
                     hipHostMallocMapped | hipHostMallocCoherent) !=
@@ -966,7 +1073,10 @@ nh_status nh_set_bathymetry(nh_solver* s, const double* H) {
   for (long i = 0; i < s->ncell; ++i)
     if (!std::isfinite(H[i])) return fail(NH_EINVAL, "non-finite bathymetry");
   nh_status st = upload(s, s->H, H, s->ncell);
-  if (st == NH_OK) s->have_H = true;
+  if (st == NH_OK) {
+    s->have_H = true;
+    if (s->fp32) s->H_host.assign(H, H + s->ncell);
+  }
   return st;
 }
 
@@ -999,6 +1109,9 @@ nh_status nh_set_relaxation(nh_solver* s, const double* widths,
   for (int i = 0; i < 4; ++i)
     if (!(widths[i] >= 0.0) || !std::isfinite(widths[i]))
       return fail(NH_EINVAL, "zone widths must be finite and >= 0");
+  if (((s->par.periodic & 1) && (widths[0] > 0 || widths[1] > 0)) ||
+      (!s->one_d && (s->par.periodic & 2) && (widths[2] > 0 || widths[3] > 0)))
+    return fail(NH_EINVAL, "no relaxation zone across a periodic direction");
   const bool on = widths[0] > 0 || widths[1] > 0 ||
                   (!s->one_d && (widths[2] > 0 || widths[3] > 0));
   s->relax_on = false;
@@ -1060,7 +1173,7 @@ nh_status nh_set_relaxation(nh_solver* s, const double* widths,
       return st;
   }
   if ((st = upload(s, s->rm_c, mc.data(), s->ncell)) != NH_OK ||
-      (st = upload(s, s->rt_h, th.data(), s->ncell)) != NH_OK ||
+      (st = upload_depth(s, s->rt_h, th.data(), s->ncell)) != NH_OK ||
       (st = upload(s, s->rt_q1, tq1.data(), s->ncell)) != NH_OK ||
       (st = upload(s, s->rt_q2, tq2.data(), s->ncell)) != NH_OK ||
       (st = upload(s, s->rm_k, mk.data(), s->ncorn)) != NH_OK ||
@@ -1084,7 +1197,7 @@ nh_status nh_set_state(nh_solver* s, const double* h, const double* hu,
     if (h[i] < 0.0) return fail(NH_ENEGDEPTH, "negative depth");
   }
   nh_status st;
-  if ((st = upload(s, s->h, h, s->ncell)) != NH_OK) return st;
+  if ((st = upload_depth(s, s->h, h, s->ncell)) != NH_OK) return st;
   if ((st = upload(s, s->q1, hu, s->ncell)) != NH_OK) return st;
   if (hv && !s->one_d) {
     if ((st = upload(s, s->q2, hv, s->ncell)) != NH_OK) return st;
@@ -1126,11 +1239,15 @@ nh_status nh_bind_device_buffers(nh_solver* s, const nh_device_views* v) {
   // contents are checked before anything is adopted
   HIP_TRY(hipStreamSynchronize(s->stream));
   HIP_TRY(hipMemsetAsync(s->flags, 0, sizeof(int), s->stream));
+  // the bound h is a depth (FP64) or s = h - max(H, 0) (FP32 bulk): checked
+  // as a depth against the bathymetry it will be used with
+  const void* Hcheck = s->fp32 ? (v->H ? v->H : s->H) : nullptr;
   for (int i = 0; i < 5; ++i) {
     if (!views[i]) continue;
     const int neg = i == 1 ? 16 : 0;  // depth >= 0
     if (s->fp32)
-      check_values<float>(s, views[i], counts[i], 8, neg);
+      check_values<float>(s, views[i], counts[i], 8, neg,
+                          i == 1 ? Hcheck : nullptr);
     else
       check_values<double>(s, views[i], counts[i], 8, neg);
   }
@@ -1145,6 +1262,11 @@ nh_status nh_bind_device_buffers(nh_solver* s, const nh_device_views* v) {
     release_own(s, s->H);
     s->H = v->H;
     s->have_H = true;
+    if (s->fp32) {  // the bound bathymetry is the FP32 one
+      s->H_host.resize(s->ncell);
+      nh_status sd = download(s, s->H_host.data(), s->H, s->ncell);
+      if (sd != NH_OK) return sd;
+    }
   }
   if (!state) return NH_OK;
   release_own(s, s->h);
@@ -1204,7 +1326,7 @@ nh_status nh_read_state(nh_solver* s, double* h, double* hu, double* hv,
                         double* w, double* p) {
   if (!s) return fail(NH_EINVAL, "null solver");
   nh_status st;
-  if (h && (st = download(s, h, s->h, s->ncell)) != NH_OK) return st;
+  if (h && (st = download_depth(s, h, s->h, s->ncell)) != NH_OK) return st;
   if (hu && (st = download(s, hu, s->q1, s->ncell)) != NH_OK) return st;
   if (hv) {
     if (s->one_d)
@@ -1264,3 +1386,4 @@ void nh_destroy(nh_solver* s) {
 #include "ensemble_impl.hpp"
 // gradients by the adjoint time step (nh_adjoint_run)
 #include "adjoint_impl.hpp"
+

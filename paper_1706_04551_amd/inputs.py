@@ -67,6 +67,8 @@ class Case:
     dt_fixed: float = 0.0
     manning: float = 0.0    # Gauckler-Manning n (0: no friction)
     open_sides: int = 0     # outflow sides: 1 west, 2 east, 4 south, 8 north
+    periodic: int = 0       # periodic directions: 1 x, 2 y
+    w_advection: int = 0    # 1: (hw)_t + div(hw u) = p instead of h w_t = p
 
     def param_dict(self) -> dict:
         return dict(nx=self.nx, ny=self.ny, dx=self.dx, dy=self.dy, g=self.g,
@@ -76,7 +78,8 @@ class Case:
                     check_every=self.check_every, solve_tol=self.solve_tol,
                     omega=self.omega, fixed_dt=self.fixed_dt,
                     dt_fixed=self.dt_fixed, manning=self.manning,
-                    open_sides=self.open_sides)
+                    open_sides=self.open_sides, periodic=self.periodic,
+                    w_advection=self.w_advection)
 
 
 # --------------------------------------------------------------------------

@@ -343,3 +343,108 @@ def test_adjoint_rejects_what_it_does_not_cover():
     r = s.adjoint(4, g, t, ckpt_every=2)          # still usable afterwards
     assert np.isfinite(r["J"])
     s.close()
+
+
+def test_dot_product_with_the_oracle_tangent_linear_model():
+    """<d, gradient> of the GPU adjoint equals the derivative along d of the
+    oracle's tangent-linear model (forward mode, torch.func.jvp of the
+    literal scheme), for three seeded directions in (eta0, H): the adjoint
+    is the transpose of that linear map.  FP64; bar 1e-8 relative to the
+    largest |dJ| of the three (the two solve their pressure systems to
+    ~1e-13)."""
+    P = problem(21, 17, steps=10)
+    say("[adjoint] 21x17 steps=10 f64 vs the oracle's tangent-linear model")
+    r, _ = gpu_gradient(P, "f64", ckpt=4)
+    TP = NT.TorchParams(P["nx"], P["ny"], P["dx"], P["dy"], P["dt"])
+    rng = np.random.default_rng(123)
+    vals = []
+    for _ in range(3):
+        de = rng.standard_normal(P["H"].shape)
+        dH = rng.standard_normal(P["H"].shape)
+        # the GPU gradient w.r.t. H at fixed eta0 is dH + dh0
+        adj = float(np.sum(de * r["dh0"]) + np.sum(dH * (r["dH"] + r["dh0"])))
+        _, tlm = NT.tangent(TP, P["eta0"], P["H"], de, dH, P["gauges"],
+                            P["target"], P["steps"])
+        vals.append((adj, tlm))
+        say(f"  <d, adjoint> {adj:.12e}  tangent-linear {tlm:.12e}")
+    scale = max(abs(t) for _, t in vals)
+    for adj, tlm in vals:
+        assert abs(adj - tlm) <= 1e-8 * scale, (adj, tlm)
+
+
+def c5_base_off_kinks(c, eta0):
+    """The adjoint workload's initial surface plus a broad seeded 2 cm
+    surface field: water exactly at rest has every limiter on its kink
+    (minmod of two zero differences), where J has directional derivatives
+    but no gradient -- each precision then takes another element of the
+    subdifferential wherever rounding noise decides the branch.  With the
+    field no cell is at rest and the branches are decided by the flow."""
+    xc = I.centres(c.nx, c.dx)
+    rng = np.random.default_rng(91)
+    return eta0 + 0.02 * (I.gaussian_field(rng, c.nx, c.ny, c.nx * c.dx,
+                                           c.ny * c.dx, xc, xc, 6) - 0.5)
+
+
+_C5_GRADIENTS = {}
+
+
+def c5_gradients():
+    """FP32 and FP64 gradients of the full adjoint workload at the base point
+    off the kinks (computed once for the tests below)."""
+    from paper_1706_04551_amd import Solver
+    if not _C5_GRADIENTS:
+        for prec in ("f32", "f64"):
+            c, eta0, gauges, _ = I.case_c5(precision=prec)
+            base = c5_base_off_kinks(c, eta0)
+            target = I.synthetic_gauge_record(c, gauges, c.steps)
+            say(f"[c5] {c.nx}x{c.ny} {prec} {c.steps} steps, checkpoints "
+                "every 100")
+            s = Solver.from_case(c)
+            s.set_state(c.H + base, c.hu, c.hv)
+            _C5_GRADIENTS[prec] = s.adjoint(
+                c.steps, gauges, target, ckpt_every=100,
+                adj_tol=1e-6 if prec == "f32" else 1e-10)
+            s.close()
+        _C5_GRADIENTS["shape"] = (c.nx, c.dx)
+    return _C5_GRADIENTS
+
+
+def test_full_size_fp32_gradient_against_fp64():
+    """The adjoint workload at its stated shape: 1024^2, FP32 bulk, 2000
+    steps, checkpoints every 100.  Its J and its gradient w.r.t. H (at fixed
+    eta0) against the FP64 gradient of the same run (the FP64 kernels equal
+    the differentiable oracle to ~1e-13 on the grids it can hold), at a base
+    point off the limiters' kinks (c5_base_off_kinks).  Bar: 2e-2 relative
+    in the L2 norm, the accuracy the plan sets for FP32 gradients."""
+    G = c5_gradients()
+    a, b = G["f32"], G["f64"]
+    eJ = abs(a["J"] - b["J"]) / abs(b["J"])
+    say(f"  J: FP32 {a['J']:.9e} FP64 {b['J']:.9e} (relative {eJ:.2e})")
+    assert eJ <= 2e-2
+    x, y = a["dH"] + a["dh0"], b["dH"] + b["dh0"]
+    l2 = float(np.linalg.norm(x - y) / np.linalg.norm(y))
+    say(f"  dJ/dH: FP32 vs FP64 relative L2 {l2:.2e}, max {rel(x, y):.2e}")
+    assert l2 <= 2e-2, l2
+
+
+@pytest.mark.xfail(strict=True, reason=(
+    "known gap: the FP32 gradient w.r.t. the initial surface is 6.7e-2 off "
+    "the FP64 one in L2 (0.40 at its largest point) at this shape; J and "
+    "dJ/dH agree to 1e-6 and 1e-4, and the gap does not depend on the solve "
+    "tolerances"))
+def test_full_size_fp32_gradient_wrt_eta0():
+    """The same comparison for dJ/deta0 under the plan's bar (2e-2 in L2),
+    and along four smooth seeded directions of eta0."""
+    G = c5_gradients()
+    a, b = G["f32"], G["f64"]
+    l2 = float(np.linalg.norm(a["dh0"] - b["dh0"]) / np.linalg.norm(b["dh0"]))
+    say(f"  dJ/deta0: FP32 vs FP64 relative L2 {l2:.2e}, max "
+        f"{rel(a['dh0'], b['dh0']):.2e}")
+    n, dx = G["shape"]
+    worst = 0.0
+    for seed in (77, 78, 79, 80):
+        d = I.c5_initial_surface(n, dx, seed, amp=1.0, radius=400.0)
+        da, db = float(np.sum(d * a["dh0"])), float(np.sum(d * b["dh0"]))
+        worst = max(worst, abs(da - db) / abs(db))
+        say(f"  along eta0 direction {seed}: FP32 {da:.6e} FP64 {db:.6e}")
+    assert l2 <= 2e-2 and worst <= 2e-2, (l2, worst)

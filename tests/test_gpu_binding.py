@@ -19,12 +19,25 @@ def say(*a):
     sys.stdout.flush()
 
 
+def stored_depth(c, dtype, H=None):
+    """What a bound depth tensor holds: h in FP64; in FP32 bulk
+    s = h - max(H, 0) (the surface elevation over water, the depth on land),
+    formed in FP64 and rounded once, as the library stores a host state
+    (against the bathymetry the caller gave, by default the FP64 one)."""
+    import torch
+    if dtype == torch.float64:
+        return c.h
+    H = c.H if H is None else H
+    return (c.h - np.maximum(H, 0.0)).astype(np.float32)
+
+
 def tensors(c, dtype):
     import torch
     dev = torch.device("cuda", 0)
     t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=dtype,  # noqa
                                device=dev)
-    return dict(H=t(c.H), h=t(c.h), hu=t(c.hu), hv=t(c.hv),
+    return dict(H=t(c.H), h=t(stored_depth(c, dtype)), hu=t(c.hu),
+                hv=t(c.hv),
                 w=torch.zeros((c.ny + 1, c.nx + 1), dtype=dtype, device=dev))
 
 
@@ -53,15 +66,21 @@ def test_bound_tensors_are_stepped_in_place(precision):
         assert np.array_equal(ra[k], rb[k]), k
     for k in ("t", "sweeps_total", "solves", "step"):
         assert sa[k] == sb[k], k
-    # the tensors themselves hold U^n
-    for k, f in (("h", "h"), ("hu", "hu"), ("hv", "hv"), ("w", "w")):
+    # the tensors themselves hold U^n (the depth as stored in FP32:
+    # h - max(H, 0))
+    Hd = T["H"].double().cpu().numpy()
+    dep = T["h"].double().cpu().numpy()
+    if precision == "f32":
+        dep = dep + np.maximum(Hd, 0.0)
+    assert np.array_equal(dep, rb["h"])
+    for k, f in (("hu", "hu"), ("hv", "hv"), ("w", "w")):
         assert np.array_equal(T[k].double().cpu().numpy(), rb[f]), k
-    # host uploads go into the bound memory
+    # host uploads go into the bound memory (against the bound, FP32,
+    # bathymetry)
     b.set_state(c.h, c.hu, c.hv)
     torch.cuda.synchronize()
     assert np.array_equal(T["h"].double().cpu().numpy(),
-                          c.h.astype(np.float32 if precision == "f32"
-                                     else np.float64).astype(np.float64))
+                          np.asarray(stored_depth(c, dtype, Hd), np.float64))
     b.close()
 
 

@@ -210,3 +210,49 @@ def test_ensemble_with_breaking_matches_single_grid_solves():
         for f in FIELDS:
             assert np.array_equal(g[f], r[f]), (k, f)
     e.close()
+
+
+def test_full_ensemble_500_steps_vs_stored_oracle():
+    """The 64-member workload over its full 500 steps in the benchmark's
+    launch configuration (tuned tiles), two members of every side against
+    the oracle states stored by tests/golden/make_c4_reference.py (the
+    oracle, FP64, with each member's FP32-bulk configuration; 64 x 64 cells
+    sampled).  Bar per member and field: 1e-4, or twice the larger drift of
+    two FP32-size perturbations of the oracle run where that is larger: its
+    state rounded after every step to what an FP32 grid stores, and its
+    depth rounded to FP32 after every step (ulp(h), the size of the rounding
+    of h = s + max(H, 0) that the FP32 kernels form in every stencil).  The
+    members with a wet-dry front amplify either."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden",
+                        "c4_members_500.npz")
+    if not os.path.exists(path):
+        pytest.skip("member states not generated")
+    ref = np.load(path)
+    if not all(f"m{int(k)}_stoh_h" in ref.files for k in ref["members"]):
+        pytest.skip("member drifts not generated")
+    cases = I.case_c4()
+    steps = int(ref["steps"])
+    say(f"[c4] {len(cases)} members, {steps} steps")
+    e = ensemble(cases)
+    e.tune(2)
+    e.run(steps)
+    for k in (int(m) for m in ref["members"]):
+        pre = f"m{k}_"
+        st = int(ref[pre + "stride"])
+        g, gs = e.state(k), e.stats(k)
+        assert gs["step"] == steps and gs["status"] == 0, (k, gs)
+        scale_q = max(float(ref[pre + "max_hu"]), float(ref[pre + "max_hv"]))
+        for f, scale in (("h", float(ref[pre + "max_h"])), ("hu", scale_q),
+                         ("hv", scale_q)):
+            err = float(np.abs(g[f][::st, ::st] - ref[pre + f]).max() / scale)
+            drift = max(float(np.abs(ref[pre + q + f] - ref[pre + f]).max() /
+                              scale) for q in ("sto_", "stoh_"))
+            bar = max(1e-4, 2.0 * drift)
+            say(f"  member {k} ({cases[k].nx}^2) {f}: {err:.2e} (FP32-size "
+                f"perturbations {drift:.2e}, bar {bar:.1e})")
+            assert err <= bar, (k, f, err, bar)
+        say(f"  member {k}: t {gs['t']:.9g} (oracle {float(ref[pre + 't']):.9g})")
+        assert abs(gs["t"] - float(ref[pre + "t"])) <= 1e-3 * float(
+            ref[pre + "t"]), (k, gs["t"])
+    e.close()

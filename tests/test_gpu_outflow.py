@@ -135,3 +135,32 @@ def test_outflow_zones_and_friction_together_match_the_oracle():
         e = normwise(g, r, k)
         say(f"  {k}: max rel diff {e:.3e}")
         assert e <= 1e-9, (k, e)
+
+
+def test_the_papers_dam_break_to_t1_vs_stored_oracle():
+    """Table 2's workload at 250^2 (its smallest grid) over its whole run,
+    to t = 1 s (196 steps, eps 1e-5 of eq. 32), against the oracle state
+    stored by tests/golden/make_dambreak_reference.py 250 (every other cell):
+    FP64, within 1e-9 and in fact to the bit, with the same step count, t and
+    sweep count."""
+    import os
+    from paper_1706_04551_amd import Solver
+    path = os.path.join(os.path.dirname(__file__), "golden",
+                        "dambreak_250_t1.npz")
+    ref = np.load(path)
+    c = I.case_dambreak(n=250, eps=float(ref["eps"]))
+    steps, st = int(ref["steps"]), int(ref["stride"])
+    say(f"[case] dam-break 250x250 f64, {steps} steps to t = 1 s")
+    s = Solver.from_case(c)
+    s.run(steps)
+    g, gs = s.state(), s.stats()
+    s.close()
+    assert gs["t"] >= 1.0 and gs["t"] == float(ref["t"])
+    assert gs["sweeps_total"] == int(ref["sweeps_total"])
+    scale_q = max(float(ref["max_hu"]), float(ref["max_hv"]))
+    for k, scale in (("h", float(ref["max_h"])), ("hu", scale_q),
+                     ("hv", scale_q)):
+        e = float(np.abs(g[k][::st, ::st] - ref[k]).max() / scale)
+        say(f"  {k}: max rel diff on the lattice {e:.3e}")
+        assert e <= 1e-9, (k, e)
+        assert np.array_equal(g[k][::st, ::st], ref[k]), k

@@ -261,17 +261,52 @@ def test_c2_full_workload_1000_steps_fp64_vs_stored_oracle():
         assert np.array_equal(g[k][::st, ::st], ref[k]), k
 
 
-def test_c2_full_workload_1000_steps_fp32_reported():
-    # FP32 bulk on the same workload against the oracle run with the FP32
-    # configuration.  The flooding front amplifies perturbations of relative
-    # size 1e-7 (FP32 rounding) to ~1e-3 within 100 steps even with a fixed
-    # dt (measured with two oracle runs), so the 1e-4 bar cannot hold over the
-    # full 1000 steps of this workload; the difference is reported and only
-    # bounded here.  The FP32 bar is checked on the early steps of this
-    # workload and over 1000 steps of the island-free basin.
-    errs, gs, ref, _ = _run_vs_golden("f32", None)
-    for k, e in errs.items():
-        assert np.isfinite(e) and e <= 0.1, (k, e)
+def test_c2_full_workload_fp32_vs_stored_oracle():
+    """FP32 bulk on the workload as stated (512^2, dry island, 1000 steps)
+    against the oracle run with its FP32 configuration
+    (tests/golden/make_c2_reference.py f32), after 250 and 1000 steps.
+
+    Bar: 1e-4 on h, hu and hv, or twice the drift that FP32 storage of the
+    state alone causes where that is larger.  The storage drift is the oracle
+    itself (FP64 arithmetic) with its state rounded to FP32 after every step
+    (tests/golden/make_fp32_storage_bound.py island): any computation that
+    keeps this state in FP32 carries it.  On this run it stays below 1e-4
+    for the first few hundred steps and then grows past 1e-2 of the largest
+    discharge: the flooding front on the island's flanks amplifies
+    perturbations of the size of FP32 rounding."""
+    import os
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    bpath = os.path.join(here, "c2_512_f32storage_1000.npz")
+    if not os.path.exists(bpath):
+        pytest.skip("storage drift not generated")
+    rb = np.load(bpath)
+    path = os.path.join(here, "c2_512_f32_1000.npz")
+    ref = np.load(path)
+    st = int(ref["stride"])
+    early = int(ref["early_steps"])
+    c = I.case_c2(precision="f32")
+    say(f"[case] c2 512x512 f32 {early} + {c.steps - early} steps vs stored "
+        "oracle")
+    s = gpu_solver(c)
+
+    def check(g, suffix):
+        scale_q = max(float(ref["max_hu" + suffix]),
+                      float(ref["max_hv" + suffix]))
+        for k, scale in (("h", float(ref["max_h" + suffix])), ("hu", scale_q),
+                         ("hv", scale_q)):
+            e = float(np.abs(g[k][::st, ::st] - ref[k + suffix]).max() / scale)
+            e_sto = float(np.abs(rb[k + suffix] - ref[k + suffix]).max() /
+                          scale)
+            bar = max(TOL32, 2.0 * e_sto)
+            say(f"  {k}{suffix}: max rel diff on the lattice {e:.3e} "
+                f"(FP32 storage alone {e_sto:.3e}, bar {bar:.1e})")
+            assert e <= bar, (k + suffix, e, bar)
+
+    s.run(early)
+    check(s.state(), f"_{early}")
+    s.run(c.steps - early)
+    check(s.state(), "")
+    s.close()
 
 
 def test_island_free_basin_fp32_vs_stored_oracle():
@@ -280,10 +315,10 @@ def test_island_free_basin_fp32_vs_stored_oracle():
     # (tests/golden/make_c2_reference.py f32 wet), after 250 and 1000 steps.
     # The bar is 1e-4, or twice the drift that FP32 storage of the state
     # alone causes on this run where that is larger: the oracle with its
-    # state rounded to FP32 after every step
-    # (tests/golden/make_fp32_storage_bound.py) moves the discharges by
-    # ~1e-4 of their maximum after 250 steps and more later -- the run
-    # amplifies small perturbations of the state.
+    # state rounded after every step to what an FP32-bulk grid stores
+    # (h - max(H, 0), hu, hv, w; tests/golden/make_fp32_storage_bound.py wet)
+    # moves the discharges by ~1e-5 of their maximum after 250 steps and
+    # ~1e-4 after 1000 -- the run amplifies small perturbations of the state.
     import os
     here = os.path.join(os.path.dirname(__file__), "golden")
     path = os.path.join(here, "c2wet_512_f32_1000.npz")
@@ -328,8 +363,8 @@ def test_c3_full_size_beach_vs_1d_oracle(precision):
     condition).  Bars: in FP64 1e-9 (the 2D relaxation stops at its
     tolerance, the 1D solve is direct); in FP32 bulk 1e-4, or twice the
     drift that FP32 storage of the state alone causes on this run where that
-    is larger (the 1D oracle with its state rounded to FP32 after every
-    step: ~1e-4 in hu after 4000 steps)."""
+    is larger (the 1D oracle with its state rounded after every step to what
+    an FP32-bulk grid stores: h - max(H, 0), hu, w in FP32)."""
     c = I.case_c3()
     if precision == "f64":
         c.precision, c.solve_tol, c.dry_eps = "f64", 1e-10, 1e-10
@@ -349,6 +384,13 @@ def test_c3_full_size_beach_vs_1d_oracle(precision):
         ob.set_bathymetry(c.H[:1])
         ob.set_state(c.h[:1], c.hu[:1], c.hv[:1])
     f32 = lambda a: a.astype(np.float32).astype(np.float64)  # noqa: E731
+    H1 = c.H[:1]
+
+    def stored_depth(h):   # FP32 storage of h - max(H, 0); dry stays dry
+        R = np.maximum(H1, 0.0)
+        d = np.maximum(f32(h - R) + R, 0.0)
+        d[h <= 0.0] = 0.0
+        return d
     m0 = float(np.sum(c.h, dtype=np.float64))
     done = 0
     for n in (500, 3500):
@@ -358,8 +400,8 @@ def test_c3_full_size_beach_vs_1d_oracle(precision):
             for _ in range(n):
                 assert ob.step() == 0
                 rb = ob.state()
-                ob.set_state(f32(rb["h"]), f32(rb["hu"]), None, f32(rb["w"]),
-                             rb["p"])
+                ob.set_state(stored_depth(rb["h"]), f32(rb["hu"]), None,
+                             f32(rb["w"]), rb["p"])
             rb = ob.state()
         done += n
         g, r = s.state(), o.state()
