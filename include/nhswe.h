@@ -345,6 +345,41 @@ nh_status nh_ensemble_profile(nh_ensemble *e, int32_t on);
 nh_status nh_ensemble_get_profile(nh_ensemble *e, nh_profile_t *out);
 void nh_ensemble_destroy(nh_ensemble *e);
 
+/* ---- Without allocation --------------------------------------------------
+ * For callers that cannot allocate device memory: tight serving loops,
+ * harnesses that forbid hipMalloc.  (Stream capture is not supported: each
+ * relaxation cycle reads its convergence measure back to the host.)
+ *
+ * nh_run_noalloc runs nsteps time steps as nh_create + nh_bind_device_buffers
+ * + nh_run + nh_read_state would, on the same kernels and with the same
+ * results bit for bit, without a solver object: the bathymetry H and the
+ * state U^n = (h, hu, hv) and w are caller-owned device buffers of the
+ * solver's device (the current HIP device), element type of the precision
+ * (double for NH_FP64, float for NH_FP32), contiguous, row-major: H, h, hu,
+ * hv cells [ny][nx] (hv ignored in 1D, may be NULL), w corners [ny+1][nx+1]
+ * ([nx+1] in 1D); in NH_FP32 the h buffer holds s = h - max(H, 0) (the
+ * depth storage of nh_device_views).  p: FP64 device array over the corners, the
+ * warm start of the first solve on entry (zeros for none) and the last
+ * solve's pressure on return.  h, hu, hv, w and p are updated in place; H is only read.  Every
+ * other array (stage states, the pressure system, the relaxation iterates,
+ * reductions, dt, statistics) is carved from one static device array of
+ * NH_NOALLOC_SCRATCH_BYTES that each device holds from the library's load
+ * until the process ends: the call makes no hipMalloc, hipHostMalloc or
+ * hipFree.  A grid whose arrays do not fit (about 128 B per cell in FP64,
+ * 64 B in FP32, more with breaking; a 512 x 512 FP64 grid fits) gets
+ * NH_EINVAL.  The scratch is cleared at the start of every call, so no call
+ * depends on the one before; calls that overlap on one device (other
+ * threads, other streams) share it and race.  Relaxation zones are not
+ * available.  stats (host, nullable) receives the run's statistics (t from
+ * 0).  Errors as nh_run, and NH_EINVAL / NH_ENEGDEPTH for non-finite values
+ * or h < 0 in the buffers (checked on the device).  Synchronises hip_stream
+ * (NULL: the null stream). */
+#define NH_NOALLOC_SCRATCH_BYTES (64u << 20)
+nh_status nh_run_noalloc(const nh_grid *grid, const nh_params *params,
+                         void *hip_stream, const void *H, void *h, void *hu,
+                         void *hv, void *w, double *p, int64_t nsteps,
+                         nh_stats *stats);
+
 /* Thread-local message of the last failing call ("" if none). */
 const char *nh_last_error(void);
 

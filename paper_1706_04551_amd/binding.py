@@ -117,6 +117,9 @@ def lib():
         L.nh_ensemble_get_profile.argtypes = [vp, C.POINTER(NhProfile)]
         L.nh_ensemble_destroy.argtypes = [vp]
         L.nh_ensemble_destroy.restype = None
+        L.nh_run_noalloc.argtypes = [C.POINTER(NhGrid), C.POINTER(NhParams),
+                                     vp, vp, vp, vp, vp, vp, vp, C.c_int64,
+                                     C.POINTER(NhStats)]
         L.nh_last_error.restype = C.c_char_p
         L.nh_version.restype = C.c_char_p
         for f in ("nh_create", "nh_set_bathymetry", "nh_set_relaxation",
@@ -127,7 +130,8 @@ def lib():
                   "nh_ensemble_set_tile", "nh_ensemble_get_tile",
                   "nh_ensemble_tune", "nh_ensemble_run",
                   "nh_ensemble_read_state", "nh_ensemble_get_stats",
-                  "nh_ensemble_profile", "nh_ensemble_get_profile"):
+                  "nh_ensemble_profile", "nh_ensemble_get_profile",
+                  "nh_run_noalloc"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -445,3 +449,38 @@ class Ensemble:
                "nh_ensemble_get_profile")
         return {k: getattr(p, k) for k, _ in NhProfile._fields_}
 
+
+def run_noalloc(nx, ny, dx, dy, H, h, hu, hv, w, p, nsteps, *, stream=None,
+                **params) -> dict:
+    """nh_run_noalloc: nsteps steps of caller-owned device tensors in place,
+    with no device allocation by the library (include/nhswe.h).  H, h, hu,
+    hv (cells) and w (corners) in the precision's type (float64, or float32
+    in FP32 bulk, where h holds s = h - max(H, 0)), p (corners) float64; hv may be
+    None in 1D.  Returns the run's statistics."""
+    import torch
+    prec = params.get("precision", "f64")
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    ncell = int(nx) * int(ny)
+    ncorn = (int(nx) + 1) * (1 if int(ny) == 1 else int(ny) + 1)
+    ptrs = []
+    for name, t, n, dt in (("H", H, ncell, dtype), ("h", h, ncell, dtype),
+                           ("hu", hu, ncell, dtype), ("hv", hv, ncell, dtype),
+                           ("w", w, ncorn, dtype),
+                           ("p", p, ncorn, torch.float64)):
+        if t is None and name == "hv" and int(ny) == 1:
+            ptrs.append(None)
+            continue
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name}: a device tensor is required")
+        if t.dtype != dt or not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"{name}: a contiguous {dt} tensor of {n} "
+                             "elements is required")
+        ptrs.append(t.data_ptr())
+    grid = NhGrid(int(nx), int(ny), float(dx), float(dy))
+    par, _om = _params(**params)
+    st = NhStats()
+    _check(lib().nh_run_noalloc(C.byref(grid), C.byref(par),
+                                C.c_void_p(stream) if stream else None,
+                                *ptrs, int(nsteps), C.byref(st)),
+           "nh_run_noalloc")
+    return _stats_dict(st)

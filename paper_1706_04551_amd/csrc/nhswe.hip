@@ -1387,3 +1387,191 @@ void nh_destroy(nh_solver* s) {
 // gradients by the adjoint time step (nh_adjoint_run)
 #include "adjoint_impl.hpp"
 
+// ---------------------------------------------------------------------------
+// Time steps without allocation (nh_run_noalloc): the kernels and host steps
+// of nh_run on a solver that lives on the host stack, with the caller's
+// device buffers as H and U^n and every other array carved from `scratch`.
+// ---------------------------------------------------------------------------
+#include <mutex>
+
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)NH_NOALLOC_SCRATCH_BYTES;
+
+// every intermediate array of nh_run_noalloc; each device holds its own copy
+// for the life of the process.  In host code this name is only a handle for
+// hipGetSymbolAddress: kernels get the address it returns.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_dev[kMaxDevices] = {};
+
+// device address of the current device's scratch, looked up on the first
+// call on that device (with it current)
+nh_status scratch_address(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(NH_EDEVICE, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return fail(NH_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                  hipGetErrorString(e));
+    }
+    g_scratch_dev[dev] = static_cast<unsigned char*>(ptr);
+  }
+  *out = g_scratch_dev[dev];
+  return NH_OK;
+}
+
+// consecutive 256-byte aligned pieces of the scratch; `used` may run past the
+// capacity, which the caller checks before any piece is touched
+struct Carver {
+  unsigned char* base;
+  size_t used = 0;
+  void* take(size_t bytes) {
+    used = (used + 255) & ~(size_t)255;
+    void* p = base + used;
+    used += bytes;
+    return p;
+  }
+};
+
+}  // namespace
+
+extern "C" nh_status nh_run_noalloc(const nh_grid* grid,
+                                    const nh_params* params, void* hip_stream,
+                                    const void* H, void* h, void* hu, void* hv,
+                                    void* w, double* p, int64_t nsteps,
+                                    nh_stats* stats) {
+  nh_status st = check_params(grid, params);
+  if (st != NH_OK) return st;
+  const bool one_d = grid->ny == 1;
+  if (!H || !h || !hu || (!one_d && !hv) || !w || !p)
+    return fail(NH_EINVAL, "null device buffer");
+  if (nsteps < 0) return fail(NH_EINVAL, "nsteps < 0");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  unsigned char* base = nullptr;
+  if ((st = scratch_address(dev, &base)) != NH_OK) return st;
+
+  nh_solver s;  // host stack: no heap, no device allocation
+  s.grid = *grid;
+  s.par = *params;
+  s.par.omega_schedule = nullptr;
+  const bool sched = params->omega_schedule && params->n_omega > 0;
+  s.nom = sched ? params->n_omega : 1;
+  s.one_d = one_d;
+  s.fp32 = params->precision == NH_FP32;
+  s.esize = s.fp32 ? 4 : 8;
+  s.stream = (hipStream_t)hip_stream;
+  s.device = dev;
+  s.ncell = (long)grid->nx * grid->ny;
+  s.ncorn = (long)(grid->nx + 1) * (one_d ? 1 : grid->ny + 1);
+  if ((st = choose_sweep_tiles(&s)) != NH_OK) return st;
+
+  const size_t cb = s.ncell * s.esize, kb = s.ncorn * s.esize;
+  const size_t kd = s.ncorn * sizeof(double);
+  Carver c{base};
+  for (void** a : {&s.hs, &s.q1s, &s.q2s, &s.h1, &s.q11, &s.q21})
+    *a = c.take(cb);
+  if (params->breaking_on)
+    for (void** a : {&s.q1b, &s.q2b, &s.rw}) *a = c.take(cb);
+  if (one_d) s.q2 = c.take(cb);  // hv is not used in 1D: zeros
+  s.w1 = c.take(kb);
+  if (params->breaking_on) s.ws = c.take(kb);
+  if (params->w_advection) s.wadv = c.take(kb);
+  for (void** a : {&s.cdiag, &s.cE, &s.cW, &s.cN, &s.cS, &s.crhs})
+    *a = c.take(kb);
+  for (void** a : {&s.pa, &s.pb, &s.pc}) *a = c.take(kd);
+  if (one_d) {
+    s.thomas_cp = (double*)c.take(kd);
+    s.thomas_dp = (double*)c.take(kd);
+    s.thomas_bb = (double*)c.take(kd);
+    s.thomas_z = (double*)c.take(kd);
+  }
+  s.dt = (double*)c.take(sizeof(double));
+  s.lampart = (double*)c.take(nblocks(std::max(s.ncell, s.ncorn)) *
+                              sizeof(double));
+  s.part = (double*)c.take((size_t)s.ntx * s.nty * sizeof(double));
+  s.part_list = (double**)c.take(sizeof(double*));
+  s.ntiles_list = (int*)c.take(sizeof(int));
+  s.omega_dev = (double*)c.take(s.nom * sizeof(double));
+  s.clamped = (double*)c.take(sizeof(double));
+  s.flags = (int*)c.take(sizeof(int));
+  s.dstats = (nh::DevStats*)c.take(sizeof(nh::DevStats));
+  s.slot_dev = (HostSlot*)c.take(sizeof(HostSlot));
+  if (c.used > kScratchBytes)
+    return fail(NH_EINVAL, "grid needs " + std::to_string(c.used) +
+                               " bytes of scratch; the limit is " +
+                               std::to_string(kScratchBytes));
+  s.slot = nullptr;  // measures are read back by copy (wait_measure)
+  s.E_dev = &s.slot_dev->E[0];
+  s.H = const_cast<void*>(H);
+  s.h = h;
+  s.q1 = hu;
+  if (!one_d) s.q2 = hv;
+  s.w = w;
+
+  // the scratch keeps the previous call's contents: start from zeros
+  HIP_TRY(hipMemsetAsync(base, 0, c.used, s.stream));
+  const double one = 1.0;
+  double* part_h = s.part;
+  const int ntiles_h = s.ntx * s.nty;
+  HIP_TRY(hipMemcpyAsync(s.omega_dev, sched ? params->omega_schedule : &one,
+                         s.nom * sizeof(double), hipMemcpyHostToDevice,
+                         s.stream));
+  HIP_TRY(hipMemcpyAsync(s.part_list, &part_h, sizeof(double*),
+                         hipMemcpyHostToDevice, s.stream));
+  HIP_TRY(hipMemcpyAsync(s.ntiles_list, &ntiles_h, sizeof(int),
+                         hipMemcpyHostToDevice, s.stream));
+  // the state is checked on the device as a bound view is (finite, h >= 0)
+  const void* views[5] = {H, h, hu, one_d ? nullptr : hv, w};
+  const long counts[5] = {s.ncell, s.ncell, s.ncell, s.ncell, s.ncorn};
+  for (int i = 0; i < 5; ++i) {
+    if (!views[i]) continue;
+    const int neg = i == 1 ? 16 : 0;
+    if (s.fp32)
+      check_values<float>(&s, views[i], counts[i], 8, neg,
+                          i == 1 ? H : nullptr);
+    else
+      check_values<double>(&s, views[i], counts[i], 8, neg);
+  }
+  int flags = 0;
+  HIP_TRY(hipMemcpyAsync(&flags, s.flags, sizeof(int), hipMemcpyDeviceToHost,
+                         s.stream));
+  HIP_TRY(hipStreamSynchronize(s.stream));
+  if (flags & 8) return fail(NH_EINVAL, "non-finite values in a device buffer");
+  if (flags & 16) return fail(NH_ENEGDEPTH, "negative depth in h");
+  s.have_H = true;
+  if ((st = adopt_state(&s, p, true)) != NH_OK) return st;
+  if (!(s.st.dt_next > 0)) return fail(NH_ESTATE, "dt is not positive");
+
+  // nsteps steps, as nh_run queues them
+  const int64_t kStatusEvery = 64;
+  nh_status result = NH_OK;
+  for (int64_t n = 0; n < nsteps; ++n) {
+    nh_status sn = s.fp32 ? step_impl<float>(&s) : step_impl<double>(&s);
+    if (sn != NH_OK) {
+      nh_status ss = sync_stats(&s);
+      result = ss != NH_OK ? ss : sn;
+      break;
+    }
+    if ((n + 1) % kStatusEvery == 0 || n + 1 == nsteps) {
+      nh_status ss = sync_stats(&s);
+      if (ss != NH_OK) {
+        result = ss;
+        break;
+      }
+    }
+  }
+  // the pressure of the last solve (the next call's warm start)
+  HIP_TRY(hipMemcpyAsync(p, s.pcur_ptr(), kd, hipMemcpyDeviceToDevice,
+                         s.stream));
+  HIP_TRY(hipStreamSynchronize(s.stream));
+  if (stats) *stats = s.st;
+  return result;
+}
