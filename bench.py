@@ -45,6 +45,15 @@ ALG_BYTES_SWEEP = {"f64": 40, "f32": 20}   # per corner per sweep (matrix-free
 # is what a launch must move.
 BLOCKED_BYTES_LAUNCH = {"f64": 64, "f32": 40}
 FULL_STEP_BASE = {"f64": 384.0, "f32": 192.0}   # flux, assembly, correction
+# One-launch solve (k_solve_persist): per corner and sweep the update reads
+# five LDS neighbours and writes one (48 B of LDS traffic) and does 13 FP64
+# flops (a product, four fused multiply-adds, a difference, a product with
+# the reciprocal diagonal, a fused update).  Its compulsory HBM bytes are
+# those of one pass per solve: rows, rhs and iterate read, result written.
+PERSIST_FLOPS = 13
+PERSIST_LDS_BYTES = 48
+FP64_VECTOR_PEAK_TFLOPS = 78.6      # 256 CUs x 128 FP64 flops/clk x 2.4 GHz
+LDS_PEAK_GBS = 256 * 128 * 2.4      # 256 CUs x 128 B/clk x 2.4 GHz
 
 
 # The timed runs time only the back-to-back sweep batch of one relaxation
@@ -70,12 +79,51 @@ def alg_bytes_per_cell_step(kbar: float, prec: str) -> float:
     return b if prec == "f64" else b / 2.0
 
 
-def blocked_bytes_per_cell_step(kbar: float, prec: str) -> float:
+def blocked_bytes_per_cell_step(kbar: float, prec: str,
+                                one_launch: bool = False) -> float:
     """Compulsory bytes per cell-step of the design: flux, assembly and
     correction as in the per-sweep model, and per solve Kbar / 8 launches of
-    the sweep kernel at BLOCKED_BYTES_LAUNCH per corner (two solves)."""
-    return (FULL_STEP_BASE[prec] +
-            2.0 * (kbar / 8.0) * BLOCKED_BYTES_LAUNCH[prec])
+    the sweep kernel at BLOCKED_BYTES_LAUNCH per corner (two solves); with
+    one-launch solves one such pass per solve."""
+    per_solve = 1.0 if one_launch else kbar / 8.0
+    return FULL_STEP_BASE[prec] + 2.0 * per_solve * BLOCKED_BYTES_LAUNCH[prec]
+
+
+def persist_roofline(pr, prec, ncorn, traffic, copy_gbs):
+    """Roofline of the one-launch solve kernel from the HIP-event timing of
+    its launches (both solves of one step in PROFILE_SAMPLE) and the sweeps
+    those launches did (counted on the device): its work runs from registers
+    and LDS, so the roof is the FP64 vector rate (13 flops per corner-sweep);
+    the LDS rate and the compulsory HBM rate are reported beside it."""
+    launches = max(1, pr["solve_kernel_launches"])
+    sec = pr["solve_kernel_ms"] * 1e-3 / launches
+    sweeps = pr["solve_kernel_sweeps"] / launches
+    cs = ncorn * sweeps
+    flops = PERSIST_FLOPS * cs
+    achieved = flops / sec / 1e12 if sec > 0 else None
+    hbm = BLOCKED_BYTES_LAUNCH[prec] * ncorn
+    return {"bound": "alu",
+            "achieved": round(achieved, 3) if achieved else None,
+            "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": (round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4)
+                     if achieved else None),
+            "traffic": traffic,
+            "traffic_frac": (round(traffic / sec / 1e9 / HBM_PEAK_GBS, 4)
+                             if traffic and sec > 0 else None),
+            "kernel": "k_solve_persist",
+            "avg_launch_us": round(sec * 1e6, 3),
+            "sweeps_per_launch": round(sweeps, 3),
+            "corners_per_launch": int(ncorn),
+            "alg_flops_per_launch": int(flops),
+            "alg_basis": (f"{PERSIST_FLOPS} FP64 flops per corner per sweep "
+                          "(the relaxation update of eq. 32), over the "
+                          "sweeps of the launch; the FP64 vector peak"),
+            "lds_GBps": round(PERSIST_LDS_BYTES * cs / sec / 1e9, 1),
+            "lds_frac": round(PERSIST_LDS_BYTES * cs / sec / 1e9 /
+                              LDS_PEAK_GBS, 4),
+            "hbm_compulsory_GBps": round(hbm / sec / 1e9, 1),
+            "copy_GBps": copy_gbs,
+            "timed_launches": f"both solves of 1 step in {PROFILE_SAMPLE}"}
 
 
 def sweep_roofline(pr, prec, kernel, traffic, copy_gbs):
@@ -178,30 +226,35 @@ def rounded(d, digits=3):
 
 
 def kernel_source_hash() -> str:
-    """Hash of the sweep kernel's source and of its tile configuration."""
+    """Hash of the solve kernels' source and of the sweep tile
+    configuration."""
     import hashlib
     import re
     with open(KERNEL_SOURCES[0]) as fh:
         k = fh.read()
     a = k.index("constexpr int kSweepB")
     b = k.index("// correction (eq. 26-27")
+    c = k.index("// A whole relaxation solve in one cooperative launch")
+    d = k.index("k_correct(CorrectArgs<T> a)")
     with open(KERNEL_SOURCES[1]) as fh:
         host = fh.read()
     tiles = "".join(re.findall(r"s->tb[xy] = \d+;", host))
-    return hashlib.sha256((k[a:b] + tiles).encode()).hexdigest()[:16]
+    return hashlib.sha256((k[a:b] + k[c:d] + tiles).encode()).hexdigest()[:16]
 
 
-def measured_traffic(workload_name: str, prec: str):
-    """HBM bytes per sweep launch from the committed rocprofv3 counter runs
-    (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size), or None
-    when the kernel sources changed since the counters were taken."""
+def measured_traffic(workload_name: str, prec: str, kernel="k_sweep_tb"):
+    """HBM bytes per launch of the solve kernel from the committed rocprofv3
+    counter runs (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known
+    size), or None when the kernel sources changed since the counters were
+    taken."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except OSError:
         return None
     key = f"{workload_name}-{prec}"
-    if t.get("source_sha") != kernel_source_hash() or key not in t:
+    if (t.get("source_sha") != kernel_source_hash() or key not in t or
+            t[key].get("kernel", "k_sweep_tb") != kernel):
         return None
     return t[key]["bytes_per_launch"]
 
@@ -676,14 +729,26 @@ def run_single(args):
     value = ncell * args.steps / elapsed / 1e6
     ms_step = elapsed * 1e3 / args.steps
 
-    # roofline of the dominant kernel: the relaxation sweep
-    roof = sweep_roofline(
-        pr, args.precision, "k_sweep_tb",
-        measured_traffic(f"dambreak{case.nx}" if args.workload == "dambreak"
-                         else args.workload, args.precision),
-        getattr(args, "copy_gbs", None))
+    # roofline of the dominant kernel: the relaxation solve (one launch per
+    # solve where the grid fits the co-resident workgroups, else launches of
+    # 8 sweeps)
+    one_launch = pr["solve_kernel_launches"] > 0
+    wl = (f"dambreak{case.nx}" if args.workload == "dambreak"
+          else args.workload)
+    if one_launch:
+        ncorn = (case.nx + 1) * (case.ny + 1)
+        roof = persist_roofline(
+            pr, args.precision, ncorn,
+            measured_traffic(wl, args.precision, "k_solve_persist"),
+            getattr(args, "copy_gbs", None))
+    else:
+        roof = sweep_roofline(
+            pr, args.precision, "k_sweep_tb",
+            measured_traffic(wl, args.precision),
+            getattr(args, "copy_gbs", None))
     sec_step = ms_step * 1e-3
-    step_roof_frac = (blocked_bytes_per_cell_step(kbar, args.precision) *
+    step_roof_frac = (blocked_bytes_per_cell_step(kbar, args.precision,
+                                                  one_launch) *
                       ncell / sec_step / (HBM_PEAK_GBS * 1e9))
     step_eff_gbs = (alg_bytes_per_cell_step(kbar, args.precision) * ncell /
                     sec_step / 1e9)

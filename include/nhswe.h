@@ -129,6 +129,17 @@ typedef struct {
                           means of q and h around the corner), before the
                           pressure step.  Single grids only (ensembles and
                           the adjoint need 0) */
+  int32_t solve_path;  /* how a 2D pressure solve is launched (the results
+                          are the same): 0 automatic -- one cooperative
+                          launch per solve when the grid's tiles fit the
+                          co-resident workgroups of the device (each keeps
+                          its tile's rows on chip for the whole solve and
+                          decides on convergence on the device; capped
+                          solves are then reported at the next status read),
+                          else 1; 1 launches of 8 sweeps, the convergence
+                          measure read back by the host at each check;
+                          2 the cooperative launch, NH_EINVAL at create when
+                          the grid does not fit.  Ensembles ignore it */
 } nh_params;
 
 typedef struct {
@@ -158,6 +169,11 @@ typedef struct {
   int64_t sweep_kernel_sweeps; /* sweeps done by those launches */
   double sweep_kernel_corner_sweeps; /* corners x sweeps of those launches,
                                         summed over the grids they covered */
+  double solve_kernel_ms;  /* one-launch solves only (solve_path): the
+                              timed launches (every one with on = 1, both
+                              solves of one step in n with on = n >= 2) */
+  int64_t solve_kernel_launches;
+  int64_t solve_kernel_sweeps; /* sweeps done by those launches */
 } nh_profile_t;
 
 /* Create a solver for the grid and parameters on `hip_stream` (a hipStream_t;
@@ -235,7 +251,10 @@ nh_status nh_bind_device_buffers(nh_solver *s, const nh_device_views *v);
 /* One time step.  dt_used (nullable) receives the step's dt. */
 nh_status nh_step(nh_solver *s, double *dt_used);
 
-/* nsteps time steps; stops at the first failing step. */
+/* nsteps time steps, queued back to back; the device status (non-finite
+ * state, no wet cell, and with one-launch solves a solve that reached
+ * solve_max_iter) is read every 64 steps and at the end, and the run stops
+ * there with the first failure found (NH_ENOCONV leaves the state valid). */
 nh_status nh_run(nh_solver *s, int64_t nsteps);
 
 /* Copy the state to the host (each pointer nullable). */
@@ -370,7 +389,8 @@ void nh_ensemble_destroy(nh_ensemble *e);
  * NH_EINVAL.  The scratch is cleared at the start of every call, so no call
  * depends on the one before; calls that overlap on one device (other
  * threads, other streams) share it and race.  Relaxation zones are not
- * available.  stats (host, nullable) receives the run's statistics (t from
+ * available; the solves are launches of 8 sweeps (solve_path 2 gets
+ * NH_EINVAL).  stats (host, nullable) receives the run's statistics (t from
  * 0).  Errors as nh_run, and NH_EINVAL / NH_ENEGDEPTH for non-finite values
  * or h < 0 in the buffers (checked on the device).  Synchronises hip_stream
  * (NULL: the null stream). */

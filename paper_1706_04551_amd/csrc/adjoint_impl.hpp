@@ -394,14 +394,14 @@ nh_status adjoint_impl(nh_solver* s, int64_t N, double adj_tol, double* J,
                        w->J);
     if ((n + 1) % 64 == 0) {
       nh_status ss = sync_stats(s);
-      if (ss != NH_OK) return ss;
+      if (ss != NH_OK && ss != NH_ENOCONV) return ss;
     }
   }
   {
     nh_status r = copy_state(s, rec_at(s, w->ckpt, w->nck, 1), true);
     if (r != NH_OK) return r;
     nh_status ss = sync_stats(s);
-    if (ss != NH_OK) return ss;
+    if (ss != NH_OK && ss != NH_ENOCONV) return ss;
   }
   nh_stats end_stats = s->st;
   HIP_TRY(hipMemcpyAsync(J, w->J, sizeof(double), hipMemcpyDeviceToHost,
@@ -436,12 +436,21 @@ nh_status adjoint_impl(nh_solver* s, int64_t N, double adj_tol, double* J,
                            w->res + (n - 1) * ng, (T*)w->Lh);
     }
     nh_status ss = sync_stats(s);
-    if (ss != NH_OK) return ss;
+    if (ss != NH_OK && ss != NH_ENOCONV) return ss;
   }
   // ---- back to the end of the forward run
   nh_status r = copy_state(s, rec_at(s, w->ckpt, w->nck, 1), false);
   if (r != NH_OK) return r;
-  nh::DevStats dend{end_stats.t, end_stats.dt_last, end_stats.step};
+  nh::DevStats dend{};
+  dend.t = end_stats.t;
+  dend.dt_last = end_stats.dt_last;
+  dend.step = end_stats.step;
+  dend.sweeps_total = end_stats.sweeps_total;
+  dend.solves_total = end_stats.solves_total;
+  dend.noconv = s->noconv_seen;
+  dend.measure = end_stats.measure;
+  dend.sweeps[0] = end_stats.sweeps[0];
+  dend.sweeps[1] = end_stats.sweeps[1];
   HIP_TRY(hipMemcpyAsync(s->dstats, &dend, sizeof(dend),
                          hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));

@@ -1433,6 +1433,12 @@ struct DevStats {
   double t;        // simulated time
   double dt_last;  // dt of the last step
   long long step;  // steps since the state was set
+  // solves done in one launch each (k_solve_persist), whose sweep counts the
+  // host does not see
+  long long sweeps_total, solves_total, noconv;
+  double measure;  // measure at the end of the last such solve
+  int sweeps[2];   // sweeps of the last such solve of each stage
+  long long prof_sweeps;  // sweeps of the such solves the host timed
 };
 
 
@@ -1779,6 +1785,404 @@ __global__ void __launch_bounds__(B)
   Lg.iout = (L.iout + r) % 3;
   Lg.isave = (L.isave + r) % 3;
   sweep_body<T, B, S, M>(as[g], Lg, (int)blockIdx.x - pre[pos], lds);
+}
+
+// -------------------------------------------------------------------------
+// A whole relaxation solve in one cooperative launch, for grids whose tiles
+// all fit the co-resident workgroups (one tile per workgroup).  The sweeps,
+// the schedule and the checks are those of k_sweep_tb and of the host loop
+// that drives it: the same update of every corner in the same order of
+// operations, blocks of sweeps cut at every check and at the sweep cap, and
+// at each check the measure of eq. (32) of the iterate, so that the result
+// and its sweep count are the same.  What changes is where the solve lives
+// between blocks: each workgroup keeps the rows and the iterate of its
+// region (its own corners and those within S of them) in registers for the
+// whole solve, a thread holding a column segment of M points (the north and
+// south neighbours inside the segment come from its registers, the rest
+// through LDS), and only the points that other tiles own are refreshed
+// between blocks of at most S sweeps.
+//
+// Exchange: after block e a tile writes its corners into exchange buffer
+// (e + 1) % 2, each value as two 64-bit words that carry its upper and lower
+// half beside the block's tag; a tile starts block e + 1 by reading the
+// points it does not own from that buffer until both tags of each are those
+// of block e + 1.  The words are agent-scope atomics (coherent across the
+// XCDs' L2s without cache write-backs or invalidations), so no flag and no
+// fence is needed.  Two buffers suffice: tile A reads tile B exactly when B
+// reads A (each reads the corners within S of its own), so B overwrites
+// buffer e % 2 (after block e + 1, whose start read A's block e + 1 values)
+// only once A has finished block e and with it its reads of that buffer.
+// Tags grow over the solver's life (the base is the block count of all
+// earlier solves, the same on every tile), so no solve takes another's
+// values.  On a periodic line the last corner is the first one again: it
+// belongs to the tile of the first corner and is written with it into the
+// result.
+//
+// Checks: each tile writes the measure of its corners into its slot of one
+// of two slot arrays (by the parity of the check), as two tagged words like
+// the exchange, and goes on with its block; after the block it reads every
+// tile's slot until all carry the check's tag, and every workgroup takes
+// the same decision from the same values.  (Two arrays suffice: a tile
+// writes the slots of check c + 2 only after every tile has written those of
+// c + 1, after its own reads of check c.)  The input iterate of a check is
+// written to the result buffer, so that a stop leaves the result there.
+//
+// Every wait is bounded: a wait that reaches its bound, or that sees the
+// give-up bit of another workgroup, sets that bit and ends its workgroup,
+// and the host reports the failed solve.
+// -------------------------------------------------------------------------
+constexpr int kFlagWaitBound = 8;  // solver flags: a wait gave up
+constexpr int kPersistOmega = 256;  // schedule factors staged in LDS
+
+struct PersistSync {
+  unsigned long long* xch0;  // exchange buffers, 2 words per corner
+  unsigned long long* xch1;
+  unsigned* blocks;  // [0] blocks, [1] checks of all earlier solves (tag
+                     // bases)
+  unsigned long long* slots;  // per-tile measures: 2 arrays x ntiles x 2
+                              // words
+  int* flags;        // solver flags (kFlagWaitBound)
+  DevStats* st;      // solve statistics (written by workgroup 0)
+  long long bound;   // polls before a wait gives up
+};
+
+struct PersistLaunch {
+  int iin, iout;        // initial iterate, result (different buffers)
+  int kmax, ce, stage;  // sweep cap, sweeps per check, stage of the step
+  int timed;            // the host times this launch: count its sweeps
+  double tol;
+};
+
+__device__ __forceinline__ unsigned long long ld_agent_u64(
+    unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent_u64(unsigned long long* p,
+                                             unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned ld_agent_u32(unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_agent(const double* p) {
+  auto* q = reinterpret_cast<unsigned long long*>(const_cast<double*>(p));
+  return __longlong_as_double((long long)ld_agent_u64(q));
+}
+__device__ __forceinline__ void st_agent(double* p, double v) {
+  st_agent_u64(reinterpret_cast<unsigned long long*>(p),
+               (unsigned long long)__double_as_longlong(v));
+}
+// this thread's memory operations have completed (and no memory access is
+// moved across by the compiler)
+__device__ __forceinline__ void wait_memory() {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+__device__ __forceinline__ bool gave_up(int* flags) {
+  return (__hip_atomic_load(flags, __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT) &
+          kFlagWaitBound) != 0;
+}
+// position of an unwrapped corner index on a periodic line of n corners
+__device__ __forceinline__ int cyc(int u, int n) {
+  const int r = u % n;
+  return r < 0 ? r + n : r;
+}
+// a value and its tag as the two words of the exchange
+__device__ __forceinline__ unsigned long long xword(unsigned tag,
+                                                    unsigned half) {
+  return ((unsigned long long)tag << 32) | half;
+}
+
+// places of one LDS plane of the one-launch solve: RW per row, M rows for
+// every RW threads (and for the threads past the last full row)
+__host__ __device__ constexpr int persist_plane(int B, int M, int RW) {
+  return (B / RW + 1) * M * RW;
+}
+// LDS bytes of the one-launch solve: two padded FP64 planes
+__host__ __device__ constexpr long persist_lds_bytes(int B, int M, int RW) {
+  return 2L * 8 * (persist_plane(B, M, RW) + 2 * (RW + 1));
+}
+
+// kinds of a region point (pk: corner index << 4 | these bits; -1: none)
+constexpr int kPkOwn = 1, kPkRing = 2, kPkDupX = 4, kPkDupY = 8;
+
+template <typename T, int B, int S, int M>
+__global__ void __launch_bounds__(B)
+    k_solve_persist(SweepArgs<T> a, PersistLaunch L, PersistSync Y) {
+  extern __shared__ double lds[];
+  __shared__ int give_up;
+  __shared__ double wred[B / 64];
+  __shared__ double om_s[kPersistOmega];
+  const int ncx = a.ncx, ncy = a.ncy, BX = a.BX, BY = a.BY, ntx = a.ntx;
+  const int ntiles = a.ntiles;
+  const int tile = (int)blockIdx.x;  // the grid has exactly ntiles groups
+  const int tid = (int)threadIdx.x;
+  const int tx = tile % ntx, ty = tile / ntx;
+  const int RW = BX + 2 * S, RH = BY + 2 * S, R = RW * RH;
+  // the relaxation schedule in LDS (the host keeps nom <= kPersistOmega)
+  for (int i = tid; i < a.nom; i += B) om_s[i] = a.omega[i];
+  const int x0 = tx * BX - S, y0 = ty * BY - S;
+  const bool px = (a.bc & kPerX) != 0, py = (a.bc & kPerY) != 0;
+  // distinct corners of a line (on a periodic line the last one is the
+  // first one again) and the corners this tile owns
+  const int nlx = px ? ncx - 1 : ncx, nly = py ? ncy - 1 : ncy;
+  const int ox0 = tx * BX, ox1 = min(ox0 + BX, nlx);
+  const int oy0 = ty * BY, oy1 = min(oy0 + BY, nly);
+  const int nseg = (RH + M - 1) / M;
+  const int cx = tid % RW, ys = (tid / RW) * M;
+  const bool active = tid < RW * nseg;
+  // two LDS planes: rows of RW places for every thread's points (rows past
+  // the region included), padded by RW + 1 places on both sides so that
+  // the neighbours of any point are inside
+  const int PL = persist_plane(B, M, RW);
+  double* L0 = lds + RW + 1;
+  double* L1 = lds + PL + 3 * (RW + 1);
+  const int lbase = ys * RW + cx;
+  if (tid == 0) give_up = 0;
+  const unsigned base = ld_agent_u32(Y.blocks);
+  const unsigned cbase = ld_agent_u32(Y.blocks + 1);
+  const T* __restrict__ dgl = a.diag;
+  const T* __restrict__ cE = a.cE;
+  const T* __restrict__ cW = a.cW;
+  const T* __restrict__ cN = a.cN;
+  const T* __restrict__ cS = a.cS;
+  const T* __restrict__ rhs = a.rhs;
+  const double* __restrict__ p0 = a.p[L.iin];
+  // rows and iterate of the thread's points (outside the domain, and
+  // farther than S from the tile's corners: diag 1, the rest 0, and the
+  // iterate stays 0)
+  T dg[M], ce[M], cw[M], cn[M], cs[M], cr[M];
+  double rdg[M], v[M];
+  int pk[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int y = ys + m;
+    ce[m] = cw[m] = cn[m] = cs[m] = cr[m] = T(0);
+    dg[m] = T(1);
+    v[m] = 0.0;
+    pk[m] = -1;
+    if (active && y < RH) {
+      const int ux = x0 + cx, uy = y0 + y;
+      const int gx = px ? cyc(ux, nlx) : ux;
+      const int gy = py ? cyc(uy, nly) : uy;
+      if (ux >= ox0 - S && ux < ox1 + S && uy >= oy0 - S && uy < oy1 + S &&
+          gx >= 0 && gx < ncx && gy >= 0 && gy < ncy) {
+        const int g = gy * ncx + gx;
+        v[m] = p0[g];
+        dg[m] = dgl[g];
+        ce[m] = cE[g];
+        cw[m] = cW[g];
+        cn[m] = cN[g];
+        cs[m] = cS[g];
+        cr[m] = rhs[g];
+        if (ux >= ox0 && ux < ox1 && uy >= oy0 && uy < oy1)
+          pk[m] = (g << 4) | kPkOwn | (px && gx == 0 ? kPkDupX : 0) |
+                  (py && gy == 0 ? kPkDupY : 0);
+        else
+          pk[m] = (g << 4) | kPkRing;
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < M; ++m) rdg[m] = 1.0 / (double)dg[m];
+  // per point: its distance to the region's border (sweep t updates the
+  // points farther than t from it; -1: no point)
+  int dist[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int y = ys + m;
+    dist[m] = (active && y < RH)
+                  ? min(min(cx, RW - 1 - cx), min(y, RH - 1 - y))
+                  : -1;
+  }
+  double* const res = a.p[L.iout];
+  const int nom = a.nom, cev = L.ce, kmax = L.kmax;
+  int k = 0, nchk = 0, e = 0;
+  for (;;) {
+    const bool check = (k % cev) == 0 || k >= kmax;
+    const int nsw = k >= kmax ? 0 : min(min(S, cev - k % cev), kmax - k);
+    if (e > 0) {
+      // the points other tiles own, as those tiles left them after block e
+      const unsigned want = base + (unsigned)e;
+      unsigned long long* X = (e & 1) ? Y.xch1 : Y.xch0;
+      unsigned long long w0[M], w1[M];
+#pragma unroll
+      for (int m = 0; m < M; ++m) {  // all loads in flight at once
+        w0[m] = w1[m] = xword(want, 0u);
+        if (pk[m] >= 0 && (pk[m] & kPkRing)) {
+          const int g = pk[m] >> 4;
+          w0[m] = ld_agent_u64(X + 2 * g);
+          w1[m] = ld_agent_u64(X + 2 * g + 1);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        if (pk[m] >= 0 && (pk[m] & kPkRing)) {
+          const int g = pk[m] >> 4;
+          long long it = 0;
+          while ((unsigned)(w0[m] >> 32) != want ||
+                 (unsigned)(w1[m] >> 32) != want) {
+            if (++it > Y.bound || ((it & 63) == 0 && gave_up(Y.flags))) {
+              give_up = 1;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+            w0[m] = ld_agent_u64(X + 2 * g);
+            w1[m] = ld_agent_u64(X + 2 * g + 1);
+          }
+          v[m] = __hiloint2double((int)(unsigned)w0[m], (int)(unsigned)w1[m]);
+        }
+      }
+      __syncthreads();
+      if (give_up) {
+        if (tid == 0) atomicOr(Y.flags, kFlagWaitBound);
+        return;
+      }
+    }
+    double emax = 0.0;
+    const int iters = nsw > 0 ? nsw : 1;
+    // one sweep over the thread's points from LDS plane Lb; CHK: the first
+    // sweep of a check, which also takes the measure of the own points and
+    // writes their input iterate to the result buffer; UPD: update
+    auto relax = [&](auto chk, double* Lb, double om, int t, bool upd) {
+      constexpr bool CHK = decltype(chk)::value;
+      double pE[M], pW[M];
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        pE[m] = Lb[lbase + m * RW + 1];
+        pW[m] = Lb[lbase + m * RW - 1];
+      }
+      const double pTop = Lb[lbase + M * RW];
+      double below = Lb[lbase - RW];  // the input value of the point below
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const double pc = v[m];
+        T cd = dg[m], c1 = ce[m], c2 = cw[m], c3 = cn[m], c4 = cs[m],
+          c5 = cr[m];
+        if constexpr (sizeof(T) == 4) {
+          // the floats, not FP64 copies, live across the sweeps
+          asm volatile("" : "+v"(cd), "+v"(c1), "+v"(c2), "+v"(c3),
+                       "+v"(c4), "+v"(c5));
+        }
+        const double pN = (m + 1 < M) ? v[m + 1] : pTop;
+        const double pS = below;
+        below = pc;
+        double Ap = (double)cd * pc;
+        Ap = fma((double)c1, pE[m], Ap);
+        Ap = fma((double)c2, pW[m], Ap);
+        Ap = fma((double)c3, pN, Ap);
+        Ap = fma((double)c4, pS, Ap);
+        const double rd = ((double)c5 - Ap) * rdg[m];
+        const double pn = fma(om, rd, pc);
+        if constexpr (CHK) {
+          if (pk[m] >= 0 && (pk[m] & kPkOwn)) {
+            const double ar = fabs(rd);
+            emax = (ar > emax || ar != ar) ? ar : emax;
+            // the result buffer is read after the launch only
+            const int g = pk[m] >> 4;
+            res[g] = pc;
+            if (pk[m] & kPkDupX) res[g + ncx - 1] = pc;
+            if (pk[m] & kPkDupY) res[g + (ncy - 1) * ncx] = pc;
+            if ((pk[m] & (kPkDupX | kPkDupY)) == (kPkDupX | kPkDupY))
+              res[g + (ncy - 1) * ncx + ncx - 1] = pc;
+          }
+        }
+        v[m] = (upd && dist[m] > t) ? pn : pc;
+      }
+    };
+    for (int t = 0; t < iters; ++t) {
+      double* Lb = (t & 1) ? L1 : L0;
+#pragma unroll
+      for (int m = 0; m < M; ++m) Lb[lbase + m * RW] = v[m];
+      __syncthreads();
+      const double om = om_s[(k + t) % nom];
+      if (t == 0 && check)
+        relax(std::true_type{}, Lb, om, t, nsw > 0);
+      else
+        relax(std::false_type{}, Lb, om, t, true);
+      if (t == 0 && check) {
+        const double w = wave_max(emax);
+        if ((tid & 63) == 0) wred[tid >> 6] = w;
+        __syncthreads();
+        if (tid == 0) {
+          double mx = wred[0];
+          for (int i = 1; i < B / 64; ++i)
+            mx = (wred[i] > mx || wred[i] != wred[i]) ? wred[i] : mx;
+          const unsigned tag = cbase + (unsigned)nchk + 1u;
+          unsigned long long* sl =
+              Y.slots + 2 * ((size_t)(nchk & 1) * ntiles + tile);
+          st_agent_u64(sl, xword(tag, (unsigned)__double2hiint(mx)));
+          st_agent_u64(sl + 1, xword(tag, (unsigned)__double2loint(mx)));
+        }
+      }
+    }
+    if (nsw > 0) {
+      // publish the tile's corners after block e
+      const unsigned tag = base + (unsigned)e + 1u;
+      unsigned long long* X = ((e + 1) & 1) ? Y.xch1 : Y.xch0;
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+        if (pk[m] >= 0 && (pk[m] & kPkOwn)) {
+          const int g = pk[m] >> 4;
+          st_agent_u64(X + 2 * g, xword(tag, (unsigned)__double2hiint(v[m])));
+          st_agent_u64(X + 2 * g + 1,
+                       xword(tag, (unsigned)__double2loint(v[m])));
+        }
+    }
+    if (check) {
+      // every tile's measure of this check
+      const unsigned want = cbase + (unsigned)nchk + 1u;
+      unsigned long long* sl = Y.slots + 2 * (size_t)(nchk & 1) * ntiles;
+      double w = 0.0;
+      for (int i = tid; i < ntiles; i += B) {
+        unsigned long long w0 = ld_agent_u64(sl + 2 * i);
+        unsigned long long w1 = ld_agent_u64(sl + 2 * i + 1);
+        long long it = 0;
+        while ((unsigned)(w0 >> 32) != want || (unsigned)(w1 >> 32) != want) {
+          if (++it > Y.bound || ((it & 63) == 0 && gave_up(Y.flags))) {
+            give_up = 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+          w0 = ld_agent_u64(sl + 2 * i);
+          w1 = ld_agent_u64(sl + 2 * i + 1);
+        }
+        const double x = __hiloint2double((int)(unsigned)w0, (int)(unsigned)w1);
+        w = (x > w || x != x) ? x : w;
+      }
+      __syncthreads();
+      if (give_up) {
+        if (tid == 0) atomicOr(Y.flags, kFlagWaitBound);
+        return;
+      }
+      w = wave_max(w);
+      if ((tid & 63) == 0) wred[tid >> 6] = w;
+      __syncthreads();
+      double E = wred[0];
+      for (int i = 1; i < B / 64; ++i)
+        E = (wred[i] > E || wred[i] != wred[i]) ? wred[i] : E;
+      ++nchk;
+      if (E < L.tol || k >= kmax) {
+        if (tile == 0 && tid == 0) {
+          DevStats* d = Y.st;
+          d->sweeps[L.stage] = k;
+          d->measure = E;
+          d->sweeps_total += k;
+          d->solves_total += 1;
+          if (!(E < L.tol)) d->noconv += 1;
+          if (L.timed) d->prof_sweeps += k;
+          // blocks published and checks made by every tile: the next
+          // solve's tag bases
+          Y.blocks[0] = base + (unsigned)(e + (nsw > 0 ? 1 : 0));
+          Y.blocks[1] = cbase + (unsigned)nchk;
+        }
+        return;
+      }
+      __syncthreads();  // wred is written again at the next check
+    }
+    k += nsw;
+    e += 1;
+  }
 }
 
 template <typename T, bool ONE_D, bool COMBINE>

@@ -66,9 +66,11 @@ struct ProfPool {
   // few microseconds, ~13 % of a step when every phase is timed)
   int sample = 1;
   long long nbatch = 0;
+  long long nsolve = 0;  // one-launch solves seen (kind 5 samples by step)
   struct Mark {
     hipEvent_t a = nullptr, b = nullptr;
-    int kind = 0;         // 0 fv, 1 assembly, 2 solve, 3 correction, 4 sweeps
+    int kind = 0;         // 0 fv, 1 assembly, 2 solve, 3 correction,
+                          // 4 sweep launches, 5 one-launch solves
     long long count = 0;  // launches
     double work = 0.0;    // sweeps: corner-sweeps done by those launches
   };
@@ -79,7 +81,11 @@ struct ProfPool {
   // open an interval of the given kind on the stream (or -1)
   long open(hipStream_t st, int kind) {
     if (!on) return -1;
-    if (sample > 1 && (kind != 4 || (nbatch++ % sample) != 0)) return -1;
+    if (sample > 1 && kind == 5) {
+      if ((nsolve++ / 2) % sample != 0) return -1;
+    } else if (sample > 1 && (kind != 4 || (nbatch++ % sample) != 0)) {
+      return -1;
+    }
     if (used == marks.size()) {
       Mark m;
       if (hipEventCreate(&m.a) != hipSuccess) return -1;
@@ -118,6 +124,10 @@ struct ProfPool {
           pr.sweep_kernel_launches += m.count;
           pr.sweep_kernel_sweeps += m.count * nh::kSweepS;
           pr.sweep_kernel_corner_sweeps += m.work;
+          break;
+        case 5:
+          pr.solve_kernel_ms += ms;
+          pr.solve_kernel_launches += m.count;
           break;
       }
     }
@@ -191,6 +201,15 @@ struct nh_solver {
   double* omega_dev = nullptr;
   int tbx = 32, tby = 32, ntx = 1, nty = 1;  // sweep tiles
   int sweep_m = nh::kSweepM;  // region points per thread of the sweep
+  // one cooperative launch per solve (k_solve_persist): its tiles and the
+  // counters and slots its workgroups exchange through
+  bool persist = false;
+  int ptbx = 0, ptby = 0, pntx = 0, pnty = 0;
+  size_t plds = 0;
+  unsigned long long* p_xch = nullptr;  // 2 buffers x 2 words per corner
+  unsigned* p_bar = nullptr;  // tag bases: [0] blocks, [1] checks
+  unsigned long long* p_slots = nullptr;  // 2 x tiles x 2 words
+  long long noconv_seen = 0;  // capped solves already reported
   double* clamped = nullptr;
   int* flags = nullptr;
   // host mirrors
@@ -679,6 +698,53 @@ nh_status solve2d(nh_solver* s, const SysView& V, int& pcur, double tol,
   return st;
 }
 
+// The kernel instance of the one-launch solve: 1024-thread workgroups,
+// blocks of 8 sweeps, 3 points per thread (measured on 513^2 corners: per
+// sweep the blocks of 15 sweeps with 8 points per thread in 512-thread
+// workgroups took 1.3x as long, the longer blocks saving less exchange time
+// than their larger rings and lower occupancy cost)
+constexpr int kPersistB = 1024, kPersistS = 8, kPersistM = 3;
+
+template <typename T>
+const void* persist_kernel() {
+  return (const void*)&nh::k_solve_persist<T, kPersistB, kPersistS,
+                                           kPersistM>;
+}
+
+// The solve of the system V in one cooperative launch (k_solve_persist) from
+// its iterate in buffer `pcur`, which receives the buffer of the result.  The
+// host does not wait: the sweep count and the measure go to the device
+// statistics, a capped solve to their count of such solves.
+template <typename T>
+nh_status solve_persist(nh_solver* s, const SysView& V, int& pcur, double tol,
+                        int stage) {
+  nh::SweepArgs<T> a = Args<T>::sweep(s, V);
+  a.BX = s->ptbx;
+  a.BY = s->ptby;
+  a.ntx = s->pntx;
+  a.ntiles = s->pntx * s->pnty;
+  a.part = nullptr;
+  const int ce = s->par.check_every > 0 ? s->par.check_every : 1;
+  const long pk = s->prof.open(s->stream, 5);
+  nh::PersistLaunch L{pcur, (pcur + 1) % 3, s->par.solve_max_iter, ce,
+                      stage, pk >= 0 ? 1 : 0, tol};
+  // a wait gives up after ~2^21 polls (seconds; a block of sweeps takes
+  // microseconds)
+  nh::PersistSync Y{s->p_xch, s->p_xch + 2 * s->ncorn, s->p_bar,
+                    s->p_slots, s->flags, s->dstats, 1LL << 21};
+  void* args[] = {&a, &L, &Y};
+  hipError_t e = hipLaunchCooperativeKernel(
+      persist_kernel<T>(), dim3(a.ntiles), dim3(kPersistB), args,
+      (unsigned)s->plds, s->stream);
+  s->prof.close(s->stream, pk, 1);
+  if (e != hipSuccess)
+    return fail(NH_EDEVICE, std::string("cooperative solve launch: ") +
+                                hipGetErrorString(e));
+  pcur = L.iout;
+  s->solve_launches_last = 1;
+  return NH_OK;
+}
+
 template <typename T>
 nh_status stage(nh_solver* s, int idx, int32_t* sweeps, double* measure) {
   StagePlan S = stage_plan(s, idx);
@@ -707,6 +773,10 @@ nh_status stage(nh_solver* s, int idx, int32_t* sweeps, double* measure) {
     if (s->one_d) {
       Launch<T>::thomas(s, s->pcur_ptr());
       s->solve_launches_last = 1;
+    } else if (s->persist) {
+      st = solve_persist<T>(s, forward_system(s), s->pcur, s->par.solve_tol,
+                            idx);
+      if (st != NH_OK) return st;
     } else {
       st = solve2d<T>(s, forward_system(s), s->pcur, s->par.solve_tol, sweeps,
                       measure);
@@ -749,17 +819,36 @@ nh_status sync_stats(nh_solver* s) {
   s->st.step = ds.step;
   s->st.dt_next = dt_next;
   s->st.clamped_mass = clamped;
+  bool capped = false;
+  if (s->persist && s->par.nh_on) {
+    s->st.sweeps[0] = ds.sweeps[0];
+    s->st.sweeps[1] = ds.sweeps[1];
+    s->st.measure = ds.measure;
+    s->st.sweeps_total = ds.sweeps_total;
+    s->st.solves_total = ds.solves_total;
+    capped = ds.noconv > s->noconv_seen;
+    s->noconv_seen = ds.noconv;
+  }
   nh_status st = NH_OK;
   if (flags & 1) st = fail(NH_ENONFINITE, "non-finite value in the state");
   if (flags & 2 && st == NH_OK)
     st = fail(NH_EDEVICE, "singular tridiagonal system");
   if (flags & 4 && st == NH_OK)
     st = fail(NH_ESTATE, "no wet cell: the CFL time step is undefined");
+  if (flags & nh::kFlagWaitBound && st == NH_OK)
+    st = fail(NH_EDEVICE,
+              "one-launch solve: a wait between workgroups reached its bound");
   if (st != NH_OK) {
     s->st.last_status = st;
     s->have_state = false;
+    return st;
   }
-  return st;
+  if (capped) {
+    // the state stays valid
+    s->st.last_status = NH_ENOCONV;
+    return fail(NH_ENOCONV, "pressure solve reached solve_max_iter");
+  }
+  return NH_OK;
 }
 
 // One step, queued on the stream.  The host waits only for the solver's
@@ -779,11 +868,14 @@ nh_status step_impl(nh_solver* s) {
   nh::FinalizeArgs fa = finalize_args(s, true);
   hipLaunchKernelGGL(nh::k_finalize_dt, dim3(1), dim3(nh::kBlock), 0,
                      s->stream, fa);
-  s->st.sweeps[0] = sw1;
-  s->st.sweeps[1] = sw2;
-  s->st.sweeps_total += sw1 + sw2;
-  s->st.solves_total += s->par.nh_on ? 2 : 0;
-  s->st.measure = m2;
+  if (!(s->persist && s->par.nh_on)) {
+    // one-launch solves count on the device (sync_stats)
+    s->st.sweeps[0] = sw1;
+    s->st.sweeps[1] = sw2;
+    s->st.sweeps_total += sw1 + sw2;
+    s->st.solves_total += s->par.nh_on ? 2 : 0;
+    s->st.measure = m2;
+  }
   if (st == NH_ENOCONV) fail(st, "pressure solve reached solve_max_iter");
   s->st.last_status = st;
   return st;
@@ -814,6 +906,8 @@ nh_status check_params(const nh_grid* g, const nh_params* p) {
     return fail(NH_EINVAL, "a periodic direction has no open side");
   if (p->precision != NH_FP64 && p->precision != NH_FP32)
     return fail(NH_EINVAL, "precision must be NH_FP64 or NH_FP32");
+  if (p->solve_path < 0 || p->solve_path > 2)
+    return fail(NH_EINVAL, "solve_path must be 0, 1 or 2");
   if (p->nh_on && g->ny > 1) {
     if (p->solve_max_iter < 0) return fail(NH_EINVAL, "solve_max_iter < 0");
     int nom = (p->omega_schedule && p->n_omega > 0) ? p->n_omega : 1;
@@ -856,6 +950,90 @@ nh_status choose_sweep_tiles(nh_solver* s) {
   return NH_OK;
 }
 
+// Tiles of the one-launch solve: a tile's region (its corners and those
+// within kPersistS of them) must fit the workgroup's threads (a column
+// segment of kPersistM points each) and its LDS (two padded FP64 planes),
+// and the tiles -- counted over the distinct corners of a periodic line --
+// may not outnumber the workgroups of the kernel that the device holds at
+// once; of those tilings the smallest region wins.  Leaves s->persist false
+// when none fits (NH_EINVAL if solve_path demands the one launch).
+template <typename T>
+nh_status choose_persist_tiles_t(nh_solver* s) {
+  const int B = kPersistB, S = kPersistS, M = kPersistM;
+  const int ncx = s->grid.nx + 1, ncy = s->grid.ny + 1;
+  const int nlx = (s->par.periodic & 1) ? ncx - 1 : ncx;
+  const int nly = (s->par.periodic & 2) ? ncy - 1 : ncy;
+  int coop = 0, cus = 0, lds_dev = 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch,
+                            s->device) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                            s->device) != hipSuccess ||
+      hipDeviceGetAttribute(&lds_dev,
+                            hipDeviceAttributeMaxSharedMemoryPerBlock,
+                            s->device) != hipSuccess) {
+    (void)hipGetLastError();
+    coop = 0;
+  }
+  if ((long)ncx * ncy >= (1L << 27)) coop = 0;  // corner index << 4 in int
+  if (s->nom > nh::kPersistOmega) coop = 0;     // the schedule lives in LDS
+  const void* kern = persist_kernel<T>();
+  // LDS of the widest region (rows of B threads)
+  const size_t lds_cap =
+      std::min<size_t>((size_t)lds_dev, nh::persist_lds_bytes(B, M, B));
+  if (coop && lds_cap > 65536 &&
+      hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds_cap) != hipSuccess) {
+    (void)hipGetLastError();
+    coop = 0;
+  }
+  int per_cu = 0;
+  if (coop && hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                  &per_cu, kern, B, lds_cap) != hipSuccess) {
+    (void)hipGetLastError();
+    per_cu = 0;
+  }
+  const long cap = (long)per_cu * cus;
+  long best_area = 0, nt_b = 0;
+  int bx_b = 0, by_b = 0;
+  for (int bx = 1; coop && bx + 2 * S <= B; ++bx)
+    for (int by = 1; by + 2 * S <= B; ++by) {
+      const long rw = bx + 2 * S, rh = by + 2 * S;
+      if (rw * ((rh + M - 1) / M) > B) break;
+      if ((size_t)nh::persist_lds_bytes(B, M, (int)rw) > lds_cap) break;
+      const long area = rw * rh;
+      const long nt = (long)((nlx + bx - 1) / bx) * ((nly + by - 1) / by);
+      if (nt > cap) continue;
+      if (best_area == 0 || area < best_area ||
+          (area == best_area && nt < nt_b)) {
+        best_area = area;
+        bx_b = bx;
+        by_b = by;
+        nt_b = nt;
+      }
+    }
+  if (best_area == 0) {
+    if (s->par.solve_path == 2)
+      return fail(NH_EINVAL,
+                  "solve_path 2: the grid's tiles do not fit the co-resident "
+                  "workgroups of the device");
+    return NH_OK;
+  }
+  s->ptbx = bx_b;
+  s->ptby = by_b;
+  s->pntx = (nlx + bx_b - 1) / bx_b;
+  s->pnty = (nly + by_b - 1) / by_b;
+  s->plds = nh::persist_lds_bytes(B, M, bx_b + 2 * S);
+  s->persist = true;
+  return NH_OK;
+}
+
+nh_status choose_persist_tiles(nh_solver* s) {
+  s->persist = false;
+  if (s->one_d || !s->par.nh_on || s->par.solve_path == 1) return NH_OK;
+  return s->fp32 ? choose_persist_tiles_t<float>(s)
+                 : choose_persist_tiles_t<double>(s);
+}
+
 // with U^n (h, q1, q2, w) in place on the device: p from the host array
 // (device array with p_on_device), or 0; statistics reset, dt from the CFL
 // condition (or the fixed dt)
@@ -872,6 +1050,18 @@ nh_status adopt_state(nh_solver* s, const double* p, bool p_on_device = false) {
   HIP_TRY(hipMemsetAsync(s->flags, 0, sizeof(int), s->stream));
   HIP_TRY(hipMemsetAsync(s->clamped, 0, sizeof(double), s->stream));
   HIP_TRY(hipMemsetAsync(s->dstats, 0, sizeof(nh::DevStats), s->stream));
+  s->noconv_seen = 0;
+  if (s->persist) {
+    // tags from 0 again (also after a failed solve)
+    HIP_TRY(hipMemsetAsync(s->p_xch, 0,
+                           4 * (size_t)s->ncorn * sizeof(unsigned long long),
+                           s->stream));
+    HIP_TRY(hipMemsetAsync(s->p_bar, 0, 2 * sizeof(unsigned), s->stream));
+    HIP_TRY(hipMemsetAsync(
+        s->p_slots, 0,
+        4 * (size_t)s->pntx * s->pnty * sizeof(unsigned long long),
+        s->stream));
+  }
   double dt0 = 0.0;
   if (s->par.fixed_dt) {
     dt0 = s->par.dt;
@@ -1031,9 +1221,25 @@ nh_status nh_create(const nh_grid* grid, const nh_params* params,
     nh_destroy(s);
     return fail(NH_EDEVICE, "copy of the relaxation schedule failed");
   }
-  if ((st = choose_sweep_tiles(s)) != NH_OK) {
+  if ((st = choose_sweep_tiles(s)) != NH_OK ||
+      (st = choose_persist_tiles(s)) != NH_OK) {
     nh_destroy(s);
     return st;
+  }
+  if (s->persist) {
+    const size_t nt = (size_t)s->pntx * s->pnty;
+    const size_t xb = 4 * (size_t)s->ncorn * sizeof(unsigned long long);
+    const size_t sb = 4 * nt * sizeof(unsigned long long);
+    if (dalloc(s, (void**)&s->p_xch, xb) != NH_OK ||
+        dalloc(s, (void**)&s->p_bar, 2 * sizeof(unsigned)) != NH_OK ||
+        dalloc(s, (void**)&s->p_slots, sb) != NH_OK ||
+        hipMemset(s->p_xch, 0, xb) != hipSuccess ||
+        hipMemset(s->p_bar, 0, 2 * sizeof(unsigned)) != hipSuccess ||
+        hipMemset(s->p_slots, 0, sb) != hipSuccess) {
+      nh_destroy(s);
+      return fail(NH_ENOMEM, "allocation of the one-launch solve's counters "
+                             "failed");
+    }
   }
   if (dalloc(s, (void**)&s->dstats, sizeof(nh::DevStats)) != NH_OK ||
       hipHostMalloc((void**)&s->slot, sizeof(HostSlot),
@@ -1357,7 +1563,15 @@ nh_status nh_profile(nh_solver* s, int32_t on) {
   s->prof.on = on > 0;
   s->prof.sample = on > 1 ? on : 1;
   s->prof.nbatch = 0;
-  if (s->prof.on) std::memset(&s->prof.pr, 0, sizeof(s->prof.pr));
+  s->prof.nsolve = 0;
+  if (s->prof.on) {
+    std::memset(&s->prof.pr, 0, sizeof(s->prof.pr));
+    if (s->dstats) {
+      HIP_TRY(hipMemsetAsync(&s->dstats->prof_sweeps, 0, sizeof(long long),
+                             s->stream));
+      HIP_TRY(hipStreamSynchronize(s->stream));
+    }
+  }
   return NH_OK;
 }
 
@@ -1366,6 +1580,12 @@ nh_status nh_get_profile(nh_solver* s, nh_profile_t* out) {
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->prof.flush();
   *out = s->prof.pr;
+  if (s->persist && s->dstats) {
+    long long sw = 0;
+    HIP_TRY(hipMemcpy(&sw, &s->dstats->prof_sweeps, sizeof(sw),
+                      hipMemcpyDeviceToHost));
+    out->solve_kernel_sweeps = sw;
+  }
   return NH_OK;
 }
 
@@ -1453,6 +1673,9 @@ extern "C" nh_status nh_run_noalloc(const nh_grid* grid,
   if (!H || !h || !hu || (!one_d && !hv) || !w || !p)
     return fail(NH_EINVAL, "null device buffer");
   if (nsteps < 0) return fail(NH_EINVAL, "nsteps < 0");
+  if (params->solve_path == 2)
+    return fail(NH_EINVAL, "nh_run_noalloc solves with launches of 8 sweeps "
+                           "(solve_path 0 or 1)");
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   unsigned char* base = nullptr;

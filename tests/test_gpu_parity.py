@@ -421,16 +421,18 @@ def test_c3_full_size_beach_vs_1d_oracle(precision):
     s.close()
 
 
-def test_profiling_modes_do_not_change_results():
+@pytest.mark.parametrize("path", [1, 2])
+def test_profiling_modes_do_not_change_results(path):
     # events on the solver's stream (every phase, or the sweep batch of one
-    # relaxation cycle in n) only observe the run
+    # relaxation cycle in n, or both one-launch solves of one step in n) only
+    # observe the run
     c = I.case_c2(n=96)
     out = {}
     for mode in (0, 1, 8):
-        s = gpu_solver(c)
+        s = gpu_solver(c, solve_path=path)
         s.profile(mode)
-        s.run(10)
-        out[mode] = (s.state(), s.get_profile())
+        s.run(17)
+        out[mode] = (s.state(), s.get_profile(), s.stats())
         s.close()
     for mode in (1, 8):
         for k in ("h", "hu", "hv", "w", "p"):
@@ -438,8 +440,19 @@ def test_profiling_modes_do_not_change_results():
     full, sampled = out[1][1], out[8][1]
     assert full["fv_ms"] > 0 and full["solve_ms"] > 0
     assert sampled["fv_ms"] == 0 and sampled["solve_ms"] == 0
-    assert 0 < sampled["sweep_kernel_launches"] < full["sweep_kernel_launches"]
-    assert sampled["sweep_kernel_ms"] > 0
+    if path == 1:
+        assert (0 < sampled["sweep_kernel_launches"] <
+                full["sweep_kernel_launches"])
+        assert sampled["sweep_kernel_ms"] > 0
+        assert full["solve_kernel_launches"] == 0
+    else:
+        # every solve timed with 1, both solves of steps 0, 8, 16 with 8
+        assert full["solve_kernel_launches"] == 34
+        assert full["solve_kernel_sweeps"] == out[1][2]["sweeps_total"]
+        assert sampled["solve_kernel_launches"] == 6
+        assert 0 < sampled["solve_kernel_sweeps"] < full["solve_kernel_sweeps"]
+        assert sampled["solve_kernel_ms"] > 0
+        assert full["sweep_kernel_launches"] == 0
 
 
 def test_large_grid_fp64():
