@@ -1950,15 +1950,15 @@ __global__ void __launch_bounds__(B)
   const double* __restrict__ p0 = a.p[L.iin];
   // rows and iterate of the thread's points (outside the domain, and
   // farther than S from the tile's corners: diag 1, the rest 0, and the
-  // iterate stays 0)
-  T dg[M], ce[M], cw[M], cn[M], cs[M], cr[M];
+  // iterate stays 0); the rows widened to FP64 once (exact for FP32 rows)
+  double dg[M], ce[M], cw[M], cn[M], cs[M], cr[M];
   double rdg[M], v[M];
   int pk[M];
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     const int y = ys + m;
-    ce[m] = cw[m] = cn[m] = cs[m] = cr[m] = T(0);
-    dg[m] = T(1);
+    ce[m] = cw[m] = cn[m] = cs[m] = cr[m] = 0.0;
+    dg[m] = 1.0;
     v[m] = 0.0;
     pk[m] = -1;
     if (active && y < RH) {
@@ -1969,12 +1969,12 @@ __global__ void __launch_bounds__(B)
           gx >= 0 && gx < ncx && gy >= 0 && gy < ncy) {
         const int g = gy * ncx + gx;
         v[m] = p0[g];
-        dg[m] = dgl[g];
-        ce[m] = cE[g];
-        cw[m] = cW[g];
-        cn[m] = cN[g];
-        cs[m] = cS[g];
-        cr[m] = rhs[g];
+        dg[m] = (double)dgl[g];
+        ce[m] = (double)cE[g];
+        cw[m] = (double)cW[g];
+        cn[m] = (double)cN[g];
+        cs[m] = (double)cS[g];
+        cr[m] = (double)rhs[g];
         if (ux >= ox0 && ux < ox1 && uy >= oy0 && uy < oy1)
           pk[m] = (g << 4) | kPkOwn | (px && gx == 0 ? kPkDupX : 0) |
                   (py && gy == 0 ? kPkDupY : 0);
@@ -1984,7 +1984,7 @@ __global__ void __launch_bounds__(B)
     }
   }
 #pragma unroll
-  for (int m = 0; m < M; ++m) rdg[m] = 1.0 / (double)dg[m];
+  for (int m = 0; m < M; ++m) rdg[m] = 1.0 / dg[m];
   // per point: its distance to the region's border (sweep t updates the
   // points farther than t from it; -1: no point)
   int dist[M];
@@ -2057,22 +2057,18 @@ __global__ void __launch_bounds__(B)
 #pragma unroll
       for (int m = 0; m < M; ++m) {
         const double pc = v[m];
-        T cd = dg[m], c1 = ce[m], c2 = cw[m], c3 = cn[m], c4 = cs[m],
-          c5 = cr[m];
-        if constexpr (sizeof(T) == 4) {
-          // the floats, not FP64 copies, live across the sweeps
-          asm volatile("" : "+v"(cd), "+v"(c1), "+v"(c2), "+v"(c3),
-                       "+v"(c4), "+v"(c5));
-        }
         const double pN = (m + 1 < M) ? v[m + 1] : pTop;
         const double pS = below;
         below = pc;
-        double Ap = (double)cd * pc;
-        Ap = fma((double)c1, pE[m], Ap);
-        Ap = fma((double)c2, pW[m], Ap);
-        Ap = fma((double)c3, pN, Ap);
-        Ap = fma((double)c4, pS, Ap);
-        const double rd = ((double)c5 - Ap) * rdg[m];
+        // a wave none of whose lanes updates (or, at a check, measures)
+        // this point skips it
+        if (!__any((CHK || upd) && dist[m] > t)) continue;
+        double Ap = dg[m] * pc;
+        Ap = fma(ce[m], pE[m], Ap);
+        Ap = fma(cw[m], pW[m], Ap);
+        Ap = fma(cn[m], pN, Ap);
+        Ap = fma(cs[m], pS, Ap);
+        const double rd = (cr[m] - Ap) * rdg[m];
         const double pn = fma(om, rd, pc);
         if constexpr (CHK) {
           if (pk[m] >= 0 && (pk[m] & kPkOwn)) {
