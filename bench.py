@@ -31,7 +31,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_sweep_tb.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_solve_kernels.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1706_04551_amd", "csrc", f)
                   for f in ("kernels.hpp", "nhswe.hip")]
 COPY_CAL_BYTES = 256 << 20
@@ -90,6 +90,7 @@ def blocked_bytes_per_cell_step(kbar: float, prec: str,
 
 
 def persist_roofline(pr, prec, ncorn, traffic, copy_gbs):
+    # traffic: HBM bytes per sweep of the grid from the counter runs, or None
     """Roofline of the one-launch solve kernel from the HIP-event timing of
     its launches (both solves of one step in PROFILE_SAMPLE) and the sweeps
     those launches did (counted on the device): its work runs from registers
@@ -98,6 +99,8 @@ def persist_roofline(pr, prec, ncorn, traffic, copy_gbs):
     launches = max(1, pr["solve_kernel_launches"])
     sec = pr["solve_kernel_ms"] * 1e-3 / launches
     sweeps = pr["solve_kernel_sweeps"] / launches
+    if traffic:   # bytes per sweep of the grid -> per launch
+        traffic = int(traffic * sweeps)
     cs = ncorn * sweeps
     flops = PERSIST_FLOPS * cs
     achieved = flops / sec / 1e12 if sec > 0 else None
@@ -243,10 +246,11 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic(workload_name: str, prec: str, kernel="k_sweep_tb"):
-    """HBM bytes per launch of the solve kernel from the committed rocprofv3
-    counter runs (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known
-    size), or None when the kernel sources changed since the counters were
-    taken."""
+    """HBM bytes of the solve kernel from the committed rocprofv3 counter
+    runs (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size): per
+    launch of 8 sweeps, or for the one-launch solve per sweep of the grid
+    (its launches differ in their sweep counts); None when the kernel
+    sources changed since the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -256,6 +260,8 @@ def measured_traffic(workload_name: str, prec: str, kernel="k_sweep_tb"):
     if (t.get("source_sha") != kernel_source_hash() or key not in t or
             t[key].get("kernel", "k_sweep_tb") != kernel):
         return None
+    if kernel == "k_solve_persist":
+        return t[key]["bytes_per_sweep"]
     return t[key]["bytes_per_launch"]
 
 
@@ -293,8 +299,9 @@ def workload(name: str, prec: str, n=None, eps=None):
                    f"open sides, CFL 0.9, to t = 1 s, {prec.upper()}, "
                    f"Jacobi+SRJ(64) tol={eps:g}")
     if name == "c2":
-        c = inputs.case_c2(precision=prec)
-        desc = (f"island basin 512x512 dx=1m, depth 2-20 m + dry island, "
+        n = n or 512
+        c = inputs.case_c2(n=n, precision=prec)
+        desc = (f"island basin {n}x{n} dx=1m, depth 2-20 m + dry island, "
                 f"hump 0.5 m, walls, {prec.upper()}, Jacobi+SRJ(64) "
                 f"tol={c.solve_tol:g}")
         return c, desc
@@ -589,7 +596,7 @@ def single_oracle_err(s, case, args):
     plain = not (getattr(args, "solve_tol", None) or
                  getattr(args, "hydrostatic", False) or
                  getattr(args, "manning", None) or getattr(args, "zones", None))
-    if name == "c2" and plain:
+    if name == "c2" and plain and case.nx == 512:
         ref = golden(f"c2_512_{prec}_1000.npz")
         if ref is None:
             return {"reason": "stored oracle state not generated"}
@@ -687,7 +694,10 @@ def run_single(args):
         case.manning = args.manning
         desc += f", Manning n={case.manning:g}"
     stream = torch.cuda.current_stream()
-    s = Solver.from_case(case, stream=stream.cuda_stream)
+    path = getattr(args, "solve_path", 0)
+    s = Solver.from_case(case, stream=stream.cuda_stream, solve_path=path)
+    if path == 1:
+        desc += ", pressure solves in launches of 8 sweeps"
     zones = getattr(args, "zones", None)
     if zones:
         s.set_relaxation((zones,) * 4)   # absorbing zones on every wall
@@ -734,6 +744,7 @@ def run_single(args):
     # 8 sweeps)
     one_launch = pr["solve_kernel_launches"] > 0
     wl = (f"dambreak{case.nx}" if args.workload == "dambreak"
+          else f"c2_{case.nx}" if args.workload == "c2" and case.nx != 512
           else args.workload)
     if one_launch:
         ncorn = (case.nx + 1) * (case.ny + 1)
@@ -831,6 +842,9 @@ def main():
     ap.add_argument("--zones", type=float, default=None,
                     help="width [m] of absorbing relaxation zones on every "
                          "wall (default none)")
+    ap.add_argument("--solve-path", type=int, default=0, choices=[0, 1, 2],
+                    help="launch form of the pressure solve: 0 automatic, 1 "
+                         "launches of 8 sweeps, 2 one cooperative launch")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-err", action="store_true",
                     help="skip the runs that measure the error against the "
@@ -893,6 +907,17 @@ def main():
             variants["c2_fp64_absorbing_zones"] = variant_summary(
                 run_single(v))
             note("c2 FP64 with absorbing zones done")
+            v = copy.copy(args)
+            v.no_cpu, v.solve_path = True, 1
+            variants["c2_fp64_8sweep_launches"] = variant_summary(
+                run_single(v))
+            note("c2 FP64 with launches of 8 sweeps done")
+            v = copy.copy(args)
+            v.workload, v.precision, v.no_cpu, v.no_err = "c2", "f32", True, True
+            v.n, v.steps = 4096, 10
+            variants["c2_4096_fp32_hbm_calibration"] = variant_summary(
+                run_single(v))
+            note("c2 geometry at 4096^2 FP32 (out of the MALL) done")
             v = copy.copy(args)
             v.workload, v.no_cpu, v.solve_tol = "dambreak", True, 1e-5
             v.n, v.steps, v.steps_given = 1000, None, False
