@@ -152,8 +152,21 @@ typedef struct {
   double measure;       /* convergence measure at the end of the last solve */
   int64_t sweeps_total; /* sweeps since nh_set_state */
   int64_t solves_total; /* pressure solves since nh_set_state */
-  double clamped_mass;  /* mass added by the positivity clamp [m^3] */
+  double clamped_mass;  /* mass added by the positivity clamp [m^3], summed
+                           over the stages (the RK2 average keeps half of
+                           it in the state) */
   int32_t last_status;
+  double mass;          /* water volume sum h dx dy (1D: sum h dx) of the
+                           state at the last status read [m^3] (0 right
+                           after nh_set_state); a closed domain keeps
+                           mass - clamped_mass / 2 constant */
+  int64_t nondominant;  /* rows of the two pressure systems of the last step
+                           that are not strictly diagonally dominant
+                           (Gershgorin check of Section 5, |diag| against
+                           the sum of the |off-diagonals|; reported, not
+                           enforced: the paper checked dominance on its
+                           cases, and steep free-surface curvature can lose
+                           it).  FP32 bulk checks its FP32 rows */
 } nh_stats;
 
 /* Per-phase device time (ms) accumulated between events on the solver's

@@ -51,7 +51,8 @@ class NhStats(C.Structure):
                 ("dt_last", C.c_double), ("step", C.c_int64),
                 ("sweeps", C.c_int32 * 2), ("measure", C.c_double),
                 ("sweeps_total", C.c_int64), ("solves_total", C.c_int64),
-                ("clamped_mass", C.c_double), ("last_status", C.c_int32)]
+                ("clamped_mass", C.c_double), ("last_status", C.c_int32),
+                ("mass", C.c_double), ("nondominant", C.c_int64)]
 
 
 class NhProfile(C.Structure):
@@ -186,7 +187,8 @@ def _stats_dict(s: "NhStats") -> dict:
     return dict(t=s.t, dt=s.dt_next, dt_last=s.dt_last, step=s.step,
                 sweeps1=s.sweeps[0], sweeps2=s.sweeps[1], measure=s.measure,
                 sweeps_total=s.sweeps_total, solves=s.solves_total,
-                clamped=s.clamped_mass, status=s.last_status)
+                clamped=s.clamped_mass, status=s.last_status, mass=s.mass,
+                nondominant=s.nondominant)
 
 
 class Solver:

@@ -451,6 +451,7 @@ nh_status adjoint_impl(nh_solver* s, int64_t N, double adj_tol, double* J,
   dend.measure = end_stats.measure;
   dend.sweeps[0] = end_stats.sweeps[0];
   dend.sweeps[1] = end_stats.sweeps[1];
+  dend.nondom_last = end_stats.nondominant;
   HIP_TRY(hipMemcpyAsync(s->dstats, &dend, sizeof(dend),
                          hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));

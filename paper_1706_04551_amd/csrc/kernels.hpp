@@ -793,8 +793,20 @@ struct AssembleArgs {
   const double* dtp;
   T *diag, *cE, *cW, *cN, *cS, *rhs;
   int open;  // open sides (kOpen*)
+  unsigned* nondom;  // count of rows not strictly dominant (or null)
   __host__ __device__ int nblocks() const { return ((nx + 1) * (ny + 1) + kBlock - 1) / kBlock; }
 };
+
+// the Gershgorin check of Section 5 on one assembled row, in FP64 with the
+// absolute values summed E, W, N, S
+template <typename T>
+__device__ __forceinline__ void count_nondominant(unsigned* cnt, T d, T e,
+                                                  T w, T n, T s) {
+  if (!cnt) return;
+  const double off = fabs((double)e) + fabs((double)w) + fabs((double)n) +
+                     fabs((double)s);
+  if (!((double)d > off)) atomicAdd(cnt, 1u);
+}
 
 // The five-point row and right-hand side at corner (k, l) from the mirrored
 // cells of `ld`; wc = w* at the corner.  Out: diag, cE, cW, cN, cS, rhs.
@@ -876,6 +888,7 @@ __device__ __forceinline__ void assemble2d_body(const AssembleArgs<T>& a,
   a.cN[n] = row[3];
   a.cS[n] = row[4];
   a.rhs[n] = row[5];
+  count_nondominant(a.nondom, row[0], row[1], row[2], row[3], row[4]);
 }
 
 // 1D: eq. (43) coefficients, rows scaled by dx^2, with the right-hand side
@@ -886,7 +899,7 @@ __global__ void __launch_bounds__(kBlock)
                  const T* __restrict__ q, const T* __restrict__ H,
                  const T* __restrict__ w, const double* __restrict__ dtp,
                  T* __restrict__ a, T* __restrict__ b, T* __restrict__ c,
-                 T* __restrict__ rhs, int open) {
+                 T* __restrict__ rhs, int open, unsigned* nondom) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k > nx) return;
   T dt = (T)(*dtp);
@@ -928,6 +941,7 @@ __global__ void __launch_bounds__(kBlock)
   b[k] = bi;
   c[k] = ci;
   rhs[k] = r;
+  count_nondominant(nondom, bi, ci, ai, T(0), T(0));
 }
 
 // Thomas algorithm (Section 4.3) for the tridiagonal system (42), in FP64 by
@@ -1439,6 +1453,12 @@ struct DevStats {
   double measure;  // measure at the end of the last such solve
   int sweeps[2];   // sweeps of the last such solve of each stage
   long long prof_sweeps;  // sweeps of the such solves the host timed
+  double depth_sum;       // sum of the depths at the last status read
+  // rows of the pressure systems that are not strictly diagonally dominant
+  // (Section 5: reported, not enforced): counted by the running step's
+  // assemblies, moved to nondom_last at its end
+  unsigned nondom_run;
+  long long nondom_last;
 };
 
 
@@ -1474,6 +1494,8 @@ __device__ __forceinline__ void finalize_body(const FinalizeArgs& a) {
     a.st->t += used;
     a.st->dt_last = used;
     a.st->step += 1;
+    a.st->nondom_last = a.st->nondom_run;
+    a.st->nondom_run = 0u;
   }
   if (!a.fixed) {
     if (l > 0.0 && isfinite(l)) {
@@ -1552,6 +1574,44 @@ __global__ void k_convert(int n, const Tsrc* __restrict__ s,
                           Tdst* __restrict__ d) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) d[i] = (Tdst)s[i];
+}
+
+// per-workgroup sums of the depth (in FP64, a fixed tree per workgroup) for
+// the water volume
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_depth_sums(long n, const T* __restrict__ h, const T* __restrict__ H,
+                 double* __restrict__ part) {
+  const long i = (long)blockIdx.x * kBlock + threadIdx.x;
+  double v = i < n ? (double)Store<T>::depth(h[i], H[i]) : 0.0;
+  __shared__ double ws[kBlock / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) s += ws[w];
+    part[blockIdx.x] = s;
+  }
+}
+
+// the sum of the per-workgroup sums (one workgroup, a fixed order)
+__global__ void __launch_bounds__(kBlock)
+    k_sum_parts(int n, const double* __restrict__ part,
+                DevStats* __restrict__ st) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) v += part[i];
+  __shared__ double ws[kBlock / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) s += ws[w];
+    st->depth_sum = s;
+  }
 }
 
 // FP32-bulk depth arrays hold s = h - max(H, 0) (Store<float>); the depth

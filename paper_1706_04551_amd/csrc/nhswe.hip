@@ -390,7 +390,8 @@ struct Args {
     return nh::AssembleArgs<T>{g.nx, g.ny, (T)g.dx, (T)g.dy, P(S.hs_cur),
                                P(S.qa), P(S.qb), P(s->H), P(S.wst), s->dt,
                                P(s->cdiag), P(s->cE), P(s->cW), P(s->cN),
-                               P(s->cS), P(s->crhs), bc_mask(s)};
+                               P(s->cS), P(s->crhs), bc_mask(s),
+                               s->dstats ? &s->dstats->nondom_run : nullptr};
   }
   static nh::SweepArgs<T> sweep(const nh_solver* s) {
     return sweep(s, forward_system(s));
@@ -511,7 +512,8 @@ struct Launch {
                          dim3(nh::kBlock), 0, s->stream, g.nx, (T)g.dx,
                          P(S.hs_cur), P(S.qa), P(s->H), P(S.wst), s->dt,
                          P(s->cW), P(s->cdiag), P(s->cE), P(s->crhs),
-                         bc_mask(s));
+                         bc_mask(s),
+                         s->dstats ? &s->dstats->nondom_run : nullptr);
     } else {
       auto a = Args<T>::assemble(s, S);
       hipLaunchKernelGGL((nh::k_assemble2d<T>), dim3(a.nblocks()),
@@ -801,6 +803,18 @@ nh_status stage(nh_solver* s, int idx, int32_t* sweeps, double* measure) {
 // Host view of the device-side statistics (t, dt, flags, clamped mass),
 // refreshed at synchronisation points.
 nh_status sync_stats(nh_solver* s) {
+  // the water volume of the state (per-workgroup sums, then one workgroup)
+  const unsigned nbc = nblocks(s->ncell);
+  if (s->fp32)
+    hipLaunchKernelGGL((nh::k_depth_sums<float>), dim3(nbc), dim3(nh::kBlock),
+                       0, s->stream, s->ncell, (const float*)s->h,
+                       (const float*)s->H, s->lampart);
+  else
+    hipLaunchKernelGGL((nh::k_depth_sums<double>), dim3(nbc),
+                       dim3(nh::kBlock), 0, s->stream, s->ncell,
+                       (const double*)s->h, (const double*)s->H, s->lampart);
+  hipLaunchKernelGGL(nh::k_sum_parts, dim3(1), dim3(nh::kBlock), 0, s->stream,
+                     (int)nbc, (const double*)s->lampart, s->dstats);
   nh::DevStats ds{};
   int flags = 0;
   double dt_next = 0.0, clamped = 0.0;
@@ -819,6 +833,8 @@ nh_status sync_stats(nh_solver* s) {
   s->st.step = ds.step;
   s->st.dt_next = dt_next;
   s->st.clamped_mass = clamped;
+  s->st.mass = ds.depth_sum * s->grid.dx * (s->one_d ? 1.0 : s->grid.dy);
+  s->st.nondominant = ds.nondom_last;
   bool capped = false;
   if (s->persist && s->par.nh_on) {
     s->st.sweeps[0] = ds.sweeps[0];

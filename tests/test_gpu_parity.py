@@ -489,3 +489,47 @@ def test_large_grid_fp32_sweep_configuration():
     for k in ("h", "hu", "hv", "w", "p"):
         assert np.array_equal(g[k], r[k]), k
     compare(c, steps, TOL32, fields=("h", "hu"))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_stats_mass_is_the_water_volume(prec):
+    # nh_stats.mass: the volume of the state at the status read; walls keep
+    # the initial volume plus half of what the positivity clamp added over
+    # the stages (the RK2 average halves each stage's addition; the
+    # oracle's run gives the same relation)
+    c = I.case_c2(n=96, precision=prec)
+    say(f"[case] water volume in the statistics, basin 96 {prec}")
+    s = gpu_solver(c)
+    s.run(40)
+    st = s.stats()
+    g = s.state()
+    vol = float(np.sum(g["h"])) * c.dx * c.dy
+    vol0 = float(np.sum(c.h)) * c.dx * c.dy
+    tol = 1e-12 if prec == "f64" else 1e-6
+    assert abs(st["mass"] - vol) <= tol * vol, (st["mass"], vol)
+    assert abs(st["mass"] - 0.5 * st["clamped"] - vol0) <= 10 * tol * vol0, (
+        st["mass"], st["clamped"], vol0)
+
+
+@pytest.mark.parametrize("which", ["c1", "c2"])
+def test_nondominant_rows_match_the_oracle(which):
+    # the Gershgorin check of Section 5 on the assembled rows: the count of
+    # rows that are not strictly dominant in the last step's two systems is
+    # the oracle's, step by step (FP64 rows are the oracle's to the bit)
+    c = I.case_c1(steps=40) if which == "c1" else I.case_c2(n=96)
+    say(f"[case] non-dominant rows per step, {which}")
+    g = gpu_solver(c)
+    o = oracle_for(c)
+    counts = []
+    for _ in range(25):
+        g.step()
+        assert o.step() == 0
+        gs, os_ = g.stats(), o.stats()
+        assert gs["nondominant"] == os_["nondominant"], (
+            gs["step"], gs["nondominant"], os_["nondominant"])
+        counts.append(gs["nondominant"])
+    say(f"  counts {counts}")
+    if which == "c1":
+        # the channel's wall rows lose dominance (an observation of the
+        # oracle's pins), so the check has something to count
+        assert max(counts) > 0
