@@ -1963,8 +1963,32 @@ __host__ __device__ constexpr long persist_lds_bytes(int B, int M, int RW) {
   return 2L * 8 * (persist_plane(B, M, RW) + 2 * (RW + 1));
 }
 
-// kinds of a region point (pk: corner index << 4 | these bits; -1: none)
-constexpr int kPkOwn = 1, kPkRing = 2, kPkDupX = 4, kPkDupY = 8;
+// The exchange buffers through a buffer resource: a corner's two words
+// {upper half, tag, lower half, tag} move as one 16-byte access at device
+// scope (coherent across the XCDs' L2s); a torn access shows as differing
+// tags and is read again.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kCoherent = 16;  // cache policy bits: device scope (sc1)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t xrsrc(
+    unsigned long long* p, long ncorn) {
+  // raw (unformatted) buffer of 16 bytes per corner
+  return __builtin_amdgcn_make_buffer_rsrc(p, 0, (int)(16 * ncorn),
+                                           0x00020000);
+}
+__device__ __forceinline__ u32x4 xload(__amdgpu_buffer_rsrc_t r, int g) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, g * 16, 0, kCoherent);
+}
+__device__ __forceinline__ void xstore(__amdgpu_buffer_rsrc_t r, int g,
+                                       unsigned tag, double v) {
+  const u32x4 w = {(unsigned)__double2hiint(v), tag,
+                   (unsigned)__double2loint(v), tag};
+  __builtin_amdgcn_raw_buffer_store_b128(w, r, g * 16, 0, kCoherent);
+}
+
+// kinds of a region point (pk: corner index << 5 | these bits; -1: none);
+// kPkPub: an own corner that other tiles read (within S of the tile's edge)
+constexpr int kPkOwn = 1, kPkRing = 2, kPkDupX = 4, kPkDupY = 8,
+              kPkPub = 16, kPkShift = 5;
 
 template <typename T, int B, int S, int M>
 __global__ void __launch_bounds__(B)
@@ -2035,26 +2059,27 @@ __global__ void __launch_bounds__(B)
         cn[m] = (double)cN[g];
         cs[m] = (double)cS[g];
         cr[m] = (double)rhs[g];
-        if (ux >= ox0 && ux < ox1 && uy >= oy0 && uy < oy1)
-          pk[m] = (g << 4) | kPkOwn | (px && gx == 0 ? kPkDupX : 0) |
+        if (ux >= ox0 && ux < ox1 && uy >= oy0 && uy < oy1) {
+          const bool pub = ux - ox0 < S || ox1 - 1 - ux < S ||
+                           uy - oy0 < S || oy1 - 1 - uy < S;
+          pk[m] = (g << kPkShift) | kPkOwn | (pub ? kPkPub : 0) |
+                  (px && gx == 0 ? kPkDupX : 0) |
                   (py && gy == 0 ? kPkDupY : 0);
-        else
-          pk[m] = (g << 4) | kPkRing;
+        } else {
+          pk[m] = (g << kPkShift) | kPkRing;
+        }
       }
     }
   }
 #pragma unroll
   for (int m = 0; m < M; ++m) rdg[m] = 1.0 / dg[m];
-  // per point: its distance to the region's border (sweep t updates the
-  // points farther than t from it; -1: no point)
-  int dist[M];
-#pragma unroll
-  for (int m = 0; m < M; ++m) {
+  // a point's distance to the region's border (sweep t updates the points
+  // farther than t from it; -1: no point), from its column's and its row's
+  const int distx = active ? min(cx, RW - 1 - cx) : -1;
+  auto dist = [&](int m) {
     const int y = ys + m;
-    dist[m] = (active && y < RH)
-                  ? min(min(cx, RW - 1 - cx), min(y, RH - 1 - y))
-                  : -1;
-  }
+    return y < RH ? min(distx, min(y, RH - 1 - y)) : -1;
+  };
   double* const res = a.p[L.iout];
   const int nom = a.nom, cev = L.ce, kmax = L.kmax;
   int k = 0, nchk = 0, e = 0;
@@ -2064,33 +2089,29 @@ __global__ void __launch_bounds__(B)
     if (e > 0) {
       // the points other tiles own, as those tiles left them after block e
       const unsigned want = base + (unsigned)e;
-      unsigned long long* X = (e & 1) ? Y.xch1 : Y.xch0;
-      unsigned long long w0[M], w1[M];
+      const __amdgpu_buffer_rsrc_t X =
+          xrsrc((e & 1) ? Y.xch1 : Y.xch0, (long)ncx * ncy);
+      u32x4 w[M];
 #pragma unroll
       for (int m = 0; m < M; ++m) {  // all loads in flight at once
-        w0[m] = w1[m] = xword(want, 0u);
-        if (pk[m] >= 0 && (pk[m] & kPkRing)) {
-          const int g = pk[m] >> 4;
-          w0[m] = ld_agent_u64(X + 2 * g);
-          w1[m] = ld_agent_u64(X + 2 * g + 1);
-        }
+        w[m] = u32x4{0u, want, 0u, want};
+        if (pk[m] >= 0 && (pk[m] & kPkRing))
+          w[m] = xload(X, pk[m] >> kPkShift);
       }
 #pragma unroll
       for (int m = 0; m < M; ++m) {
         if (pk[m] >= 0 && (pk[m] & kPkRing)) {
-          const int g = pk[m] >> 4;
           long long it = 0;
-          while ((unsigned)(w0[m] >> 32) != want ||
-                 (unsigned)(w1[m] >> 32) != want) {
+          while (w[m].y != want || w[m].w != want) {
             if (++it > Y.bound || ((it & 63) == 0 && gave_up(Y.flags))) {
               give_up = 1;
               break;
             }
             __builtin_amdgcn_s_sleep(2);
-            w0[m] = ld_agent_u64(X + 2 * g);
-            w1[m] = ld_agent_u64(X + 2 * g + 1);
+            asm volatile("" ::: "memory");  // a new load every poll
+            w[m] = xload(X, pk[m] >> kPkShift);
           }
-          v[m] = __hiloint2double((int)(unsigned)w0[m], (int)(unsigned)w1[m]);
+          v[m] = __hiloint2double((int)w[m].x, (int)w[m].z);
         }
       }
       __syncthreads();
@@ -2122,7 +2143,8 @@ __global__ void __launch_bounds__(B)
         below = pc;
         // a wave none of whose lanes updates (or, at a check, measures)
         // this point skips it
-        if (!__any((CHK || upd) && dist[m] > t)) continue;
+        const bool live = dist(m) > t;
+        if (!__any((CHK || upd) && live)) continue;
         double Ap = dg[m] * pc;
         Ap = fma(ce[m], pE[m], Ap);
         Ap = fma(cw[m], pW[m], Ap);
@@ -2135,7 +2157,7 @@ __global__ void __launch_bounds__(B)
             const double ar = fabs(rd);
             emax = (ar > emax || ar != ar) ? ar : emax;
             // the result buffer is read after the launch only
-            const int g = pk[m] >> 4;
+            const int g = pk[m] >> kPkShift;
             res[g] = pc;
             if (pk[m] & kPkDupX) res[g + ncx - 1] = pc;
             if (pk[m] & kPkDupY) res[g + (ncy - 1) * ncx] = pc;
@@ -2143,7 +2165,7 @@ __global__ void __launch_bounds__(B)
               res[g + (ncy - 1) * ncx + ncx - 1] = pc;
           }
         }
-        v[m] = (upd && dist[m] > t) ? pn : pc;
+        v[m] = (upd && live) ? pn : pc;
       }
     };
     for (int t = 0; t < iters; ++t) {
@@ -2173,17 +2195,14 @@ __global__ void __launch_bounds__(B)
       }
     }
     if (nsw > 0) {
-      // publish the tile's corners after block e
+      // publish the tile's corners that others read, after block e
       const unsigned tag = base + (unsigned)e + 1u;
-      unsigned long long* X = ((e + 1) & 1) ? Y.xch1 : Y.xch0;
+      const __amdgpu_buffer_rsrc_t X =
+          xrsrc(((e + 1) & 1) ? Y.xch1 : Y.xch0, (long)ncx * ncy);
 #pragma unroll
       for (int m = 0; m < M; ++m)
-        if (pk[m] >= 0 && (pk[m] & kPkOwn)) {
-          const int g = pk[m] >> 4;
-          st_agent_u64(X + 2 * g, xword(tag, (unsigned)__double2hiint(v[m])));
-          st_agent_u64(X + 2 * g + 1,
-                       xword(tag, (unsigned)__double2loint(v[m])));
-        }
+        if (pk[m] >= 0 && (pk[m] & kPkPub))
+          xstore(X, pk[m] >> kPkShift, tag, v[m]);
     }
     if (check) {
       // every tile's measure of this check

@@ -990,7 +990,7 @@ nh_status choose_persist_tiles_t(nh_solver* s) {
     (void)hipGetLastError();
     coop = 0;
   }
-  if ((long)ncx * ncy >= (1L << 27)) coop = 0;  // corner index << 4 in int
+  if ((long)ncx * ncy >= (1L << 26)) coop = 0;  // corner index << 5 in int
   if (s->nom > nh::kPersistOmega) coop = 0;     // the schedule lives in LDS
   const void* kern = persist_kernel<T>();
   // LDS of the widest region (rows of B threads)
