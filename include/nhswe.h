@@ -140,6 +140,13 @@ typedef struct {
                           measure read back by the host at each check;
                           2 the cooperative launch, NH_EINVAL at create when
                           the grid does not fit.  Ensembles ignore it */
+  int32_t solve_norm;  /* stop measure of a 2D relaxation solve: 0 the size
+                          of a plain Jacobi update, max |(rhs - A p)/diag|
+                          (eq. 32, solve_tol as stated above); 1 the
+                          relative residual max |rhs - A p| / max |rhs| (the
+                          absolute one when rhs = 0).  Single grids through
+                          nh_create only (ensembles, the adjoint and
+                          nh_run_noalloc need 0) */
 } nh_params;
 
 typedef struct {

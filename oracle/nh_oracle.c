@@ -682,6 +682,14 @@ static int jacobi_srj(ora_t *o, const double *diag, const double *cE,
   int kmax = o->P.solve_max_iter;
   double E = 0.0;
   int status = ORA_OK;
+  /* the residual measure is relative to the right-hand side's size */
+  const int resid = o->P.solve_norm == 1;
+  double rmax = 0.0;
+  if (resid)
+    for (int c = 0; c < nc; ++c) {
+      double a = fabs(rhs[c]);
+      if (a > rmax) rmax = a;
+    }
   for (;;) {
     int check = (k % ce == 0) || (k >= kmax);
     E = 0.0;
@@ -700,11 +708,12 @@ static int jacobi_srj(ora_t *o, const double *diag, const double *cE,
           Ap = fma(cS[c], p[CX(o, kk, refl(l - 1, nyc, py_per))], Ap);
         double upd = (rhs[c] - Ap) * (1.0 / diag[c]);  /* plain Jacobi update */
         if (check) {
-          double e = fabs(upd);
+          double e = resid ? fabs(rhs[c] - Ap) : fabs(upd);
           if (!(e <= E)) E = (e == e) ? e : INFINITY;
         }
         pn[c] = fma(om, upd, p[c]);
       }
+    if (check && resid && rmax > 0.0) E = E / rmax;
     if (check && E < o->P.solve_tol) break;
     if (k >= kmax) {
       status = ORA_ENOCONV;
@@ -1197,6 +1206,7 @@ ora_t *ora_create(const ora_params *pp, const double *omega, int32_t n_omega) {
   if (pp->open_sides < 0 || pp->open_sides > 15) return NULL;
   if (pp->periodic < 0 || pp->periodic > 3) return NULL;
   if (pp->w_advection < 0 || pp->w_advection > 1) return NULL;
+  if (pp->solve_norm < 0 || pp->solve_norm > 1) return NULL;
   /* a periodic direction has no ends: no open side in it */
   if ((pp->periodic & 1) && (pp->open_sides & 3)) return NULL;
   if (pp->ny > 1 && (pp->periodic & 2) && (pp->open_sides & 12)) return NULL;

@@ -54,6 +54,11 @@ typedef struct ora_params {
                               form (hw)_t + div(hw u) = p named after eq. 7,
                               i.e. h (w_t + u . grad w) = p: w is carried by
                               the flow in each stage's hyperbolic step */
+  int32_t solve_norm;      /* stop measure of the relaxation (2D): 0 the size
+                              of a plain Jacobi update, max |(rhs - A p) /
+                              diag| (eq. 32); 1 the relative residual
+                              max |rhs - A p| / max |rhs| (the absolute one
+                              when rhs = 0) */
 } ora_params;
 
 /* status codes */

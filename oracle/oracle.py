@@ -34,6 +34,7 @@ class OraParams(C.Structure):
         ("fixed_dt", C.c_int32), ("dt_fixed", C.c_double),
         ("manning", C.c_double), ("open_sides", C.c_int32),
         ("periodic", C.c_int32), ("w_advection", C.c_int32),
+        ("solve_norm", C.c_int32),
     ]
 
 
@@ -118,6 +119,7 @@ class Params:
     open_sides: int = 0
     periodic: int = 0
     w_advection: int = 0
+    solve_norm: int = 0
     omega: np.ndarray = field(default_factory=lambda: np.ones(1))
 
     def c_struct(self) -> OraParams:
@@ -126,7 +128,7 @@ class Params:
                          self.b1, self.b2, self.solve_max_iter,
                          self.check_every, self.solve_tol, self.fixed_dt,
                          self.dt_fixed, self.manning, self.open_sides,
-                         self.periodic, self.w_advection)
+                         self.periodic, self.w_advection, self.solve_norm)
 
 
 class Oracle:

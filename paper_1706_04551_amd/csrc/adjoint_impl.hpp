@@ -214,7 +214,7 @@ nh_status adj_solve(nh_solver* s, AdjWork* w, int stage, double rel_tol,
   hipLaunchKernelGGL(nh::k_reduce_measure, dim3(1), dim3(nh::kBlock), 0,
                      s->stream, (const double* const*)w->spart_list,
                      (const int*)w->spart_n, 1, s->E_dev, &s->slot_dev->seq,
-                     s->seq);
+                     s->seq, (const double*)nullptr);
   double scale = 0.0;
   nh_status st = wait_measure(s, &scale);
   if (st != NH_OK) return st;
@@ -481,6 +481,10 @@ nh_status nh_adjoint_run(nh_solver* s, int64_t nsteps, int32_t ngauges,
     return fail(NH_EINVAL, "the adjoint covers walls only");
   if (s->par.w_advection != 0)
     return fail(NH_EINVAL, "the adjoint covers the model's w equation only");
+  if (s->par.solve_norm != 0)
+    return fail(NH_EINVAL,
+                "the adjoint's solves stop on the measure of eq. (32) "
+                "(solve_norm = 0)");
   if (nsteps < 1 || ngauges < 1 || ckpt_every < 1)
     return fail(NH_EINVAL, "need nsteps, ngauges, ckpt_every >= 1");
   if (!(adj_tol > 0)) return fail(NH_EINVAL, "need adj_tol > 0");

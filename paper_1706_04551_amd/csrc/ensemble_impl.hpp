@@ -449,6 +449,10 @@ nh_status nh_ensemble_create(int32_t n, const nh_grid* grids,
       return fail(NH_EINVAL,
                   "ensemble members use the model's w equation "
                   "(w_advection = 0)");
+    if (params[k].solve_norm != 0)
+      return fail(NH_EINVAL,
+                  "ensemble members stop on the measure of eq. (32) "
+                  "(solve_norm = 0)");
     const nh_params& a = params[0];
     const nh_params& b = params[k];
     if (a.precision != b.precision || a.nh_on != b.nh_on ||

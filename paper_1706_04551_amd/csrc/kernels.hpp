@@ -1070,8 +1070,48 @@ struct SweepArgs {
   const double* omega;   // relaxation schedule
   int nom;
   double* part;          // per-tile convergence measures
+  // stop on the relative residual: max |rhs| of the system (null: the
+  // plain-update measure of eq. 32)
+  const double* rmax = nullptr;
   __host__ __device__ int nblocks() const { return 8 * ((ntiles + 7) / 8); }
 };
+
+// the measure of one corner at a check: the size of its plain Jacobi
+// update, or (relative residual) of its residual
+__device__ __forceinline__ double check_term(bool resid, double r,
+                                             double rdiag) {
+  return resid ? fabs(r) : fabs(r * rdiag);
+}
+// the check's measure from the maximum of the corner terms
+__device__ __forceinline__ double check_measure(const double* rmax,
+                                                double m) {
+  if (rmax && *rmax > 0.0) return m / *rmax;
+  return m;
+}
+
+// max |a| of n values (one workgroup; the order does not matter)
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_absmax(long n, const T* __restrict__ a, double* __restrict__ out) {
+  double v = 0.0;
+  for (long i = threadIdx.x; i < n; i += kBlock) {
+    const double x = fabs((double)a[i]);
+    v = x > v ? x : v;
+  }
+  __shared__ double ws[kBlock / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double x = __shfl_xor(v, o, 64);
+    v = x > v ? x : v;
+  }
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = ws[0];
+    for (int w = 1; w < kBlock / 64; ++w) m = ws[w] > m ? ws[w] : m;
+    *out = m;
+  }
+}
 
 // per-launch arguments (common to every grid of a batch)
 struct SweepLaunch {
@@ -1182,10 +1222,11 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a,
         Ap = fma((double)c2, src[idx - 1], Ap);
         Ap = fma((double)c3, src[idx + RW], Ap);
         Ap = fma((double)c4, src[idx - RW], Ap);
-        const double rd = ((double)c5 - Ap) * rdg[m];
+        const double res = (double)c5 - Ap;
+        const double rd = res * rdg[m];
         const double pn = fma(om, rd, pc);
         if (t == 0 && check && x >= S && x < S + BX && y >= S && y < S + BY) {
-          double ar = fabs(rd);
+          const double ar = check_term(a.rmax != nullptr, res, rdg[m]);
           e = (ar > e || ar != ar) ? ar : e;
         }
         if (nsw > 0) dst[idx] = pn;
@@ -1513,7 +1554,7 @@ __global__ void __launch_bounds__(kBlock)
     k_reduce_measure(const double* const* __restrict__ parts,
                      const int* __restrict__ nparts, int ngrids,
                      double* __restrict__ E, long long* seq_slot,
-                     long long seq) {
+                     long long seq, const double* rmax = nullptr) {
   __shared__ double wmax[kBlock / 64];
   for (int gi = 0; gi < ngrids; ++gi) {
     const double* part = parts[gi];
@@ -1529,7 +1570,7 @@ __global__ void __launch_bounds__(kBlock)
       double m = wmax[0];
       for (int w = 1; w < kBlock / 64; ++w)
         m = (wmax[w] > m || wmax[w] != wmax[w]) ? wmax[w] : m;
-      E[gi] = m;
+      E[gi] = check_measure(rmax, m);
     }
     __syncthreads();
   }
@@ -1815,7 +1856,7 @@ __global__ void __launch_bounds__(B)
       double m = wmax[0];
       for (int w = 1; w < B / 64; ++w)
         m = (wmax[w] > m || wmax[w] != wmax[w]) ? wmax[w] : m;
-      *L.E_host = m;
+      *L.E_host = check_measure(a.rmax, m);
       __threadfence_system();
       __hip_atomic_store(L.seq_slot, L.seq, __ATOMIC_RELEASE,
                          __HIP_MEMORY_SCOPE_SYSTEM);
@@ -2082,6 +2123,7 @@ __global__ void __launch_bounds__(B)
   };
   double* const res = a.p[L.iout];
   const int nom = a.nom, cev = L.ce, kmax = L.kmax;
+  const bool resid = a.rmax != nullptr;
   int k = 0, nchk = 0, e = 0;
   for (;;) {
     const bool check = (k % cev) == 0 || k >= kmax;
@@ -2150,11 +2192,12 @@ __global__ void __launch_bounds__(B)
         Ap = fma(cw[m], pW[m], Ap);
         Ap = fma(cn[m], pN, Ap);
         Ap = fma(cs[m], pS, Ap);
-        const double rd = (cr[m] - Ap) * rdg[m];
+        const double rr = cr[m] - Ap;
+        const double rd = rr * rdg[m];
         const double pn = fma(om, rd, pc);
         if constexpr (CHK) {
           if (pk[m] >= 0 && (pk[m] & kPkOwn)) {
-            const double ar = fabs(rd);
+            const double ar = check_term(resid, rr, rdg[m]);
             emax = (ar > emax || ar != ar) ? ar : emax;
             // the result buffer is read after the launch only
             const int g = pk[m] >> kPkShift;
@@ -2236,6 +2279,7 @@ __global__ void __launch_bounds__(B)
       double E = wred[0];
       for (int i = 1; i < B / 64; ++i)
         E = (wred[i] > E || wred[i] != wred[i]) ? wred[i] : E;
+      E = check_measure(a.rmax, E);
       ++nchk;
       if (E < L.tol || k >= kmax) {
         if (tile == 0 && tid == 0) {

@@ -210,6 +210,7 @@ struct nh_solver {
   unsigned* p_bar = nullptr;  // tag bases: [0] blocks, [1] checks
   unsigned long long* p_slots = nullptr;  // 2 x tiles x 2 words
   long long noconv_seen = 0;  // capped solves already reported
+  double* rhs_max = nullptr;  // max |rhs| of the system (solve_norm 1)
   double* clamped = nullptr;
   int* flags = nullptr;
   // host mirrors
@@ -417,6 +418,7 @@ struct Args {
     a.omega = s->omega_dev;
     a.nom = s->nom;
     a.part = s->part;
+    a.rmax = s->par.solve_norm ? s->rhs_max : nullptr;
     return a;
   }
   // p: the solved pressure (ignored when the system is hydrostatic)
@@ -518,6 +520,10 @@ struct Launch {
       auto a = Args<T>::assemble(s, S);
       hipLaunchKernelGGL((nh::k_assemble2d<T>), dim3(a.nblocks()),
                          dim3(nh::kBlock), 0, s->stream, a);
+      if (s->par.solve_norm && s->rhs_max)  // the scale of the residual
+        hipLaunchKernelGGL((nh::k_absmax<T>), dim3(1), dim3(nh::kBlock), 0,
+                           s->stream, (long)s->ncorn, P(s->crhs),
+                           s->rhs_max);
     }
   }
 
@@ -677,7 +683,9 @@ nh_status solve2d(nh_solver* s, const SysView& V, int& pcur, double tol,
       hipLaunchKernelGGL(nh::k_reduce_measure, dim3(1), dim3(nh::kBlock), 0,
                          s->stream, (const double* const*)s->part_list,
                          (const int*)s->ntiles_list, 1, s->E_dev,
-                         &s->slot_dev->seq, s->seq);
+                         &s->slot_dev->seq, s->seq,
+                         (const double*)(s->par.solve_norm ? s->rhs_max
+                                                           : nullptr));
     nh_status ws = wait_measure(s, &E);
     if (ws != NH_OK) return ws;
     if (E < tol || kc >= kmax) {
@@ -924,6 +932,8 @@ nh_status check_params(const nh_grid* g, const nh_params* p) {
     return fail(NH_EINVAL, "precision must be NH_FP64 or NH_FP32");
   if (p->solve_path < 0 || p->solve_path > 2)
     return fail(NH_EINVAL, "solve_path must be 0, 1 or 2");
+  if (p->solve_norm != 0 && p->solve_norm != 1)
+    return fail(NH_EINVAL, "solve_norm must be 0 or 1");
   if (p->nh_on && g->ny > 1) {
     if (p->solve_max_iter < 0) return fail(NH_EINVAL, "solve_max_iter < 0");
     int nom = (p->omega_schedule && p->n_omega > 0) ? p->n_omega : 1;
@@ -1241,6 +1251,11 @@ nh_status nh_create(const nh_grid* grid, const nh_params* params,
       (st = choose_persist_tiles(s)) != NH_OK) {
     nh_destroy(s);
     return st;
+  }
+  if (s->par.solve_norm && s->par.nh_on && !s->one_d &&
+      dalloc(s, (void**)&s->rhs_max, sizeof(double)) != NH_OK) {
+    nh_destroy(s);
+    return fail(NH_ENOMEM, "allocation of the residual scale failed");
   }
   if (s->persist) {
     const size_t nt = (size_t)s->pntx * s->pnty;
@@ -1692,6 +1707,9 @@ extern "C" nh_status nh_run_noalloc(const nh_grid* grid,
   if (params->solve_path == 2)
     return fail(NH_EINVAL, "nh_run_noalloc solves with launches of 8 sweeps "
                            "(solve_path 0 or 1)");
+  if (params->solve_norm != 0)
+    return fail(NH_EINVAL, "nh_run_noalloc stops on the measure of eq. (32) "
+                           "(solve_norm 0)");
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   unsigned char* base = nullptr;

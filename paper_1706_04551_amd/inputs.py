@@ -69,6 +69,7 @@ class Case:
     open_sides: int = 0     # outflow sides: 1 west, 2 east, 4 south, 8 north
     periodic: int = 0       # periodic directions: 1 x, 2 y
     w_advection: int = 0    # 1: (hw)_t + div(hw u) = p instead of h w_t = p
+    solve_norm: int = 0     # 1: stop on the relative residual, not eq. (32)
 
     def param_dict(self) -> dict:
         return dict(nx=self.nx, ny=self.ny, dx=self.dx, dy=self.dy, g=self.g,
@@ -79,7 +80,7 @@ class Case:
                     omega=self.omega, fixed_dt=self.fixed_dt,
                     dt_fixed=self.dt_fixed, manning=self.manning,
                     open_sides=self.open_sides, periodic=self.periodic,
-                    w_advection=self.w_advection)
+                    w_advection=self.w_advection, solve_norm=self.solve_norm)
 
 
 # --------------------------------------------------------------------------

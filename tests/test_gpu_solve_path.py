@@ -195,3 +195,45 @@ def test_solve_path_checks():
     # the automatic choice takes the cycle launches there
     s = Solver(1024, 1024, 1.0, 1.0, solve_path=0)
     s.close()
+
+
+@pytest.mark.parametrize("path", [1, 2])
+def test_relative_residual_stop_equals_the_oracle(path):
+    # solve_norm 1: the solves stop on max |rhs - A p| / max |rhs|; the GPU
+    # (either launch form) takes the oracle's decisions and so its iterates,
+    # sweep counts and state to the bit
+    c = basin(96)
+    c.solve_norm = 1
+    c.solve_tol = 1e-9
+    steps = 15
+    say(f"[case] basin 96, relative-residual stop, solve_path {path}")
+    g = solver(c, path)
+    o = oracle_for(c)
+    g.run(steps)
+    assert o.run(steps) == 0
+    sg, so = g.state(), o.state()
+    for k in FIELDS:
+        assert np.array_equal(sg[k], so[k]), (k, np.abs(sg[k] - so[k]).max())
+    gs, os_ = g.stats(), o.stats()
+    assert gs["sweeps_total"] == os_["sweeps_total"]
+    assert gs["measure"] == os_["measure"] and gs["measure"] < 1e-9
+    # and another measure than the default one (with checks every 64
+    # sweeps both may stop at the same check)
+    c0 = basin(96)
+    c0.solve_tol = 1e-9
+    g0 = solver(c0, path)
+    g0.run(steps)
+    assert g0.stats()["measure"] != gs["measure"]
+
+
+def test_relative_residual_stop_is_refused_where_not_built():
+    from paper_1706_04551_amd import Ensemble, NhError, Solver
+    with pytest.raises(NhError):
+        Solver(16, 16, 1.0, 1.0, solve_norm=2)
+    c = basin(64)
+    c.solve_norm = 1
+    with pytest.raises(NhError):
+        Ensemble.from_cases([c, c])
+    s = solver(c, 0)
+    with pytest.raises(NhError):
+        s.adjoint(2, [5], np.zeros((2, 1)), ckpt_every=1)

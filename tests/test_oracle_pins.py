@@ -556,3 +556,36 @@ def test_breaking_momentum_source_has_the_sign_of_eq12():
     inner = slice(2, nx - 2)
     assert np.all(q1[0, inner] < q[inner])
     assert np.all(w1[2:nx - 2] < 0.0)
+
+
+@pytest.mark.parametrize("nx,ny", [(8, 8), (6, 9)])
+def test_relative_residual_stop_measure(nx, ny):
+    # solve_norm 1: the relaxation stops on max |rhs - A p| / max |rhs|.
+    # The measure the oracle reports equals that quantity formed here from
+    # the dense matrix and the returned iterate, and is below the tolerance;
+    # the plain-update measure (solve_norm 0) of the same system is another
+    # number
+    dx, dy, dt = 0.25, 0.3, 0.02
+    H, h, hu, hv, w = _rand_2d(nx * 31 + ny, nx, ny, dx, dy)
+    rho = I.jacobi_radius_bound(h.max(), dx, dy, margin=1.3)
+    out = {}
+    for norm in (0, 1):
+        P = Params(nx=nx, ny=ny, dx=dx, dy=dy, omega=I.srj_schedule(rho, 8),
+                   check_every=8, solve_tol=1e-9, solve_max_iter=400000,
+                   solve_norm=norm)
+        o = Oracle(P)
+        o.set_bathymetry(H)
+        c = o.assemble(h, hu, hv, w, dt)
+        p, st, sweeps, meas = o.solve(c)
+        assert st == 0
+        A = _dense(c, nx + 1, ny + 1)
+        r = c["rhs"].ravel() - A @ p.ravel()
+        rel = np.abs(r).max() / np.abs(c["rhs"]).max()
+        upd = np.abs(r / c["diag"].ravel()).max()
+        out[norm] = (meas, rel, upd, sweeps)
+    meas, rel, upd, _ = out[1]
+    assert meas < 1e-9
+    np.testing.assert_allclose(meas, rel, rtol=1e-6)
+    meas0, rel0, upd0, _ = out[0]
+    np.testing.assert_allclose(meas0, upd0, rtol=1e-6)
+    assert abs(meas0 - rel0) > 1e-3 * max(meas0, rel0)
