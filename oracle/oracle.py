@@ -44,8 +44,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            from . import build_oracle  # noqa: F401  (package-relative use)
+        src = os.path.join(os.path.dirname(LIB_PATH), "nh_oracle.c")
+        if (not os.path.exists(LIB_PATH) or
+                os.path.getmtime(LIB_PATH) < os.path.getmtime(src)):
+            # missing or older than its source: compile it first
+            from . import build_oracle
+            build_oracle.build()
         _lib = C.CDLL(LIB_PATH)
         L = _lib
         L.ora_create.restype = C.c_void_p
