@@ -269,7 +269,7 @@ __global__ void __launch_bounds__(kBlock)
              T* __restrict__ lH) {
   constexpr bool XD = DIR == 1;
   const int nx = G.nx, ny = G.ny;
-  const int n = blockIdx.x * kBlock + threadIdx.x;
+  const int n = xcd_bid() * kBlock + (int)threadIdx.x;
   if (n >= nx * ny) return;
   const int jx = n % nx, jy = n / nx;
   const int len = XD ? nx : ny, j0 = XD ? jx : jy;
@@ -385,7 +385,7 @@ __global__ void __launch_bounds__(kBlock)
                    const T* __restrict__ H, const T* __restrict__ qa,
                    const T* __restrict__ qb, T* __restrict__ lqa,
                    T* __restrict__ lqb, T* __restrict__ lh) {
-  const int n = blockIdx.x * kBlock + threadIdx.x;
+  const int n = xcd_bid() * kBlock + (int)threadIdx.x;
   if (n >= G.nx * G.ny) return;
   const T h = Store<T>::depth(hs[n], H[n]);
   if (h <= (T)G.dry_eps) return;  // dry: q = 0, no friction
@@ -500,7 +500,7 @@ __global__ void __launch_bounds__(kBlock)
                     const T* __restrict__ lq1, const T* __restrict__ lq2,
                     const T* __restrict__ lw, T* __restrict__ pbar) {
   const int nx = G.nx, ny = G.ny, ncx = nx + 1;
-  const int c = blockIdx.x * kBlock + threadIdx.x;
+  const int c = xcd_bid() * kBlock + (int)threadIdx.x;
   if (c >= ncx * (ny + 1)) return;
   const int k = c % ncx, l = c / ncx;
   const E dx = G.dx, dy = G.dy, dt = *G.dtp;
@@ -537,7 +537,7 @@ __global__ void __launch_bounds__(kBlock)
                     T* __restrict__ lH, T* __restrict__ lq1s,
                     T* __restrict__ lq2s) {
   const int nx = G.nx, ny = G.ny, ncx = nx + 1;
-  const int n = blockIdx.x * kBlock + threadIdx.x;
+  const int n = xcd_bid() * kBlock + (int)threadIdx.x;
   if (n >= nx * ny) return;
   const int jx = n % nx, jy = n / nx;
   const E dx = G.dx, dy = G.dy, dt = *G.dtp;
@@ -633,7 +633,7 @@ __global__ void __launch_bounds__(kBlock)
                    T* __restrict__ rb, T* __restrict__ lw) {
   const int nx = G.nx, ny = G.ny, ncx = nx + 1;
   const long ncorn = (long)ncx * (ny + 1);
-  const int c = blockIdx.x * kBlock + threadIdx.x;
+  const int c = xcd_bid() * kBlock + (int)threadIdx.x;
   if (c >= ncorn) return;
   const int k = c % ncx, l = c / ncx;
   auto zeta = [&](int i, int j) {
@@ -712,7 +712,7 @@ __global__ void __launch_bounds__(kBlock)
                      T* __restrict__ lq2s, T* __restrict__ lH) {
   const int nx = G.nx, ny = G.ny, ncx = nx + 1;
   const long ncorn = (long)ncx * (ny + 1);
-  const int n = blockIdx.x * kBlock + threadIdx.x;
+  const int n = xcd_bid() * kBlock + (int)threadIdx.x;
   if (n >= nx * ny) return;
   const int jx = n % nx, jy = n / nx;
   auto bar = [&](int q, int k, int l) {
@@ -800,7 +800,7 @@ __global__ void __launch_bounds__(kBlock)
                      T* __restrict__ tW, T* __restrict__ tN,
                      T* __restrict__ tS) {
   const int ncx = nx + 1;
-  const int c = blockIdx.x * kBlock + threadIdx.x;
+  const int c = xcd_bid() * kBlock + (int)threadIdx.x;
   if (c >= ncx * (ny + 1)) return;
   const int k = c % ncx, l = c / ncx;
   tE[c] = k < nx ? cW[c + 1] : T(0);

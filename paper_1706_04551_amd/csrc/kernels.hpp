@@ -21,6 +21,18 @@ namespace nh {
 
 constexpr int kBlock = 256;
 
+// The workgroups of a launch go to the chip's 8 XCDs in turn (workgroup b
+// to XCD b mod 8), and each XCD has an L2 of its own.  Numbering the work
+// so that every XCD takes one contiguous run of it keeps the rows that
+// neighbouring workgroups share (stencil halos, corner rows) in one L2
+// instead of fetching them into two or three.  A bijection of [0, nb).
+__device__ __forceinline__ int xcd_bid() {
+  constexpr int kX = 8;
+  const int b = (int)blockIdx.x, nb = (int)gridDim.x;
+  const int q = nb / kX, r = nb % kX, x = b % kX;
+  return x * q + min(x, r) + b / kX;
+}
+
 __device__ __forceinline__ int mirror(int i, int n) {
   return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i);
 }
@@ -431,136 +443,158 @@ __device__ __forceinline__ void fv_finish(T& ss, T Hc, T& qa, T& qb,
 }
 
 // The 2D stage on a tile of kFvTX x kFvTY cells: the primitive values of the
-// tile and of a halo of 2 cells are formed once into LDS; each thread then
-// evaluates the east and north edges of its cell (the tile's first column
-// and row also get their west and south edges), and every edge's
-// fluctuations go to both of its cells.  Each cell sums them with its volume
-// terms exactly as fv_cell does, so the result is the same to the bit, with
-// one evaluation of each edge and of each cell's primitive values instead of
-// two and five.
+// tile and of a halo of 2 cells are formed once into LDS; the tile's edges
+// (its (TX+1) x TY x-edges, then its TX x (TY+1) y-edges) are then spread
+// over the threads in rounds, each edge evaluated once by a routine that
+// takes the direction as data (no divergence between the two kinds), and
+// every edge's fluctuations go to both of its cells.  Each cell sums them
+// with its volume terms exactly as fv_cell does, so the result is the same
+// to the bit, with one evaluation of each edge and of each cell's primitive
+// values instead of two and five.  The last, partial round falls to one
+// wave, which one depends on the tile, so that the SIMDs of a CU share it.
 template <typename T>
 __device__ __forceinline__ void fv_tile_body(const FvArgs<T>& a, int bid) {
   constexpr int TX = kFvTX, TY = kFvTY, RX = TX + 4, RY = TY + 4;
-  __shared__ T ph[RY][RX], pu[RY][RX], pv[RY][RX], pe[RY][RX];
+  __shared__ T ph[RY * RX], pu[RY * RX], pv[RY * RX], pe[RY * RX];
   // FP32 bulk: stored depth values and reference levels (limiter's depth
   // differences, dh_of)
   constexpr bool kS = Store<T>::kEta;
-  __shared__ T pS[kS ? RY : 1][kS ? RX : 1], pR[kS ? RY : 1][kS ? RX : 1];
+  __shared__ T pS[kS ? RY * RX : 1], pR[kS ? RY * RX : 1];
   // fluctuations of x-edge e of a tile row (e: west edge of column e) and of
   // y-edge e of a tile column; m = to the cell below e, p = to the one above
-  __shared__ T xm[3][TY][TX + 1], xp[3][TY][TX + 1];
-  __shared__ T ym[3][TY + 1][TX], yp[3][TY + 1][TX];
+  constexpr int NXE = (TX + 1) * TY, NYE = TX * (TY + 1);
+  __shared__ T xm[3 * NXE], xp[3 * NXE];
+  __shared__ T ym[3 * NYE], yp[3 * NYE];
   const int nx = a.nx, ny = a.ny;
   const int txs = a.tiles_x();
   const int i0 = (bid % txs) * TX, j0 = (bid / txs) * TY;
   const T g = a.g, delta = a.delta, dry_eps = a.dry_eps;
-  for (int r = (int)threadIdx.x; r < RX * RY; r += kBlock) {
-    const int rx = r % RX, ry = r / RX;
-    const int i = i0 - 2 + rx, j = j0 - 2 + ry;
-    T h = T(0), u = T(0), v = T(0), e = T(0), sv = T(0), Rv = T(0);
-    if (i <= nx + 1 && j <= ny + 1) {  // the cells a grid cell's stencil reads
-      const Cell<T> c =
-          load_cell(a.h, a.q1, a.q2, a.H, i, j, nx, ny, false, a.open);
+  const int tid = (int)threadIdx.x;
+  const int tx = tid % TX, ty = tid / TX;
+  const int cx = tx + 2, cy = ty + 2;  // the thread's cell in the region
+  const int i = i0 + tx, j = j0 + ty;
+  const bool own = i < nx && j < ny;
+  const int n = j * nx + i;
+  // the thread's own inputs, in flight while the tile is formed
+  T q10 = T(0), q20 = T(0), s0 = T(0), Hc = T(0);
+  if (own) {
+    q10 = a.q1[n];
+    q20 = a.q2[n];
+    if constexpr (kS) s0 = a.h[n];
+    Hc = a.H[n];
+  }
+  const T dt = (T)(*a.dtp);
+  constexpr int NRG = (RX * RY + kBlock - 1) / kBlock;
+  Cell<T> cl[NRG];
+#pragma unroll
+  for (int u = 0; u < NRG; ++u) {  // every load of the tile issued first
+    const int r = tid + u * kBlock;
+    const int ii = i0 - 2 + r % RX, jj = j0 - 2 + r / RX;
+    // the cells a grid cell's stencil reads
+    if (r < RX * RY && ii <= nx + 1 && jj <= ny + 1)
+      cl[u] = load_cell(a.h, a.q1, a.q2, a.H, ii, jj, nx, ny, false, a.open);
+  }
+#pragma unroll
+  for (int u = 0; u < NRG; ++u) {
+    const int r = tid + u * kBlock;
+    if (r >= RX * RY) break;
+    const int ii = i0 - 2 + r % RX, jj = j0 - 2 + r / RX;
+    T h = T(0), uu = T(0), vv = T(0), e = T(0), sv = T(0), Rv = T(0);
+    if (ii <= nx + 1 && jj <= ny + 1) {
+      const Cell<T>& c = cl[u];
       h = c.h;
-      u = desing(c.h, c.q1, delta);
-      v = desing(c.h, c.q2, delta);
+      uu = desing(c.h, c.q1, delta);
+      vv = desing(c.h, c.q2, delta);
       e = c.eta;
       if constexpr (kS) {
         sv = c.s;
         Rv = Store<T>::ref(c.H);
       }
     }
-    ph[ry][rx] = h;
-    pu[ry][rx] = u;
-    pv[ry][rx] = v;
-    pe[ry][rx] = e;
+    ph[r] = h;
+    pu[r] = uu;
+    pv[r] = vv;
+    pe[r] = e;
     if constexpr (kS) {
-      pS[ry][rx] = sv;
-      pR[ry][rx] = Rv;
+      pS[r] = sv;
+      pR[r] = Rv;
     }
   }
   __syncthreads();
-  auto sr = [&](Prim<T>& p, int rx, int ry) {
+  // primitive values at region place q with the normal velocity from un
+  // and the tangential one from ut
+  auto prim_at = [&](int q, const T* un, const T* ut) {
+    Prim<T> p;
+    p.h = ph[q];
+    p.un = un[q];
+    p.ut = ut[q];
+    p.eta = pe[q];
     if constexpr (kS) {
-      p.s = pS[ry][rx];
-      p.R = pR[ry][rx];
+      p.s = pS[q];
+      p.R = pR[q];
     } else {
       p.s = p.h;
       p.R = T(0);
     }
-  };
-  auto px = [&](int rx, int ry) {  // along x: normal u, tangential v
-    Prim<T> p;
-    p.h = ph[ry][rx];
-    p.un = pu[ry][rx];
-    p.ut = pv[ry][rx];
-    p.eta = pe[ry][rx];
-    sr(p, rx, ry);
     return p;
   };
-  auto py = [&](int rx, int ry) {  // along y: normal v, tangential u
-    Prim<T> p;
-    p.h = ph[ry][rx];
-    p.un = pv[ry][rx];
-    p.ut = pu[ry][rx];
-    p.eta = pe[ry][rx];
-    sr(p, rx, ry);
-    return p;
-  };
-  // edge between region columns c and c + 1 of region row r (x), stored at
-  // tile edge index e of tile row (r - 2)
-  auto x_edge = [&](int c, int r, int e) {
-    Face<T> La, Ra, Lb, Rb;
-    reconstruct(px(c - 1, r), px(c, r), px(c + 1, r), dry_eps, La, Ra);
-    reconstruct(px(c, r), px(c + 1, r), px(c + 2, r), dry_eps, Lb, Rb);
-    T Dm[3], Dp[3];
-    pvm(Ra, Lb, g, dry_eps, Dm, Dp);
+  {
+    const int rot = bid & 3;
+    const int slot = (tid + kBlock - 64 * rot) & (kBlock - 1);
+    for (int e = slot; e < NXE + NYE; e += kBlock) {
+      // x-edge: between region columns c and c + 1 of region row r, kept
+      // at index e of its tile row; y-edge: between region rows r and
+      // r + 1 of region column c, kept at index e of its tile column
+      const bool dy = e >= NXE;
+      const int f = dy ? e - NXE : e;
+      const int r = dy ? f / TX + 1 : f / (TX + 1) + 2;
+      const int c = dy ? f % TX + 2 : f % (TX + 1) + 1;
+      const int q = r * RX + c, st = dy ? RX : 1;
+      const T* un = dy ? pv : pu;
+      const T* ut = dy ? pu : pv;
+      Face<T> La, Ra, Lb, Rb;
+      reconstruct(prim_at(q - st, un, ut), prim_at(q, un, ut),
+                  prim_at(q + st, un, ut), dry_eps, La, Ra);
+      reconstruct(prim_at(q, un, ut), prim_at(q + st, un, ut),
+                  prim_at(q + 2 * st, un, ut), dry_eps, Lb, Rb);
+      T Dm[3], Dp[3];
+      pvm(Ra, Lb, g, dry_eps, Dm, Dp);
+      const int o = dy ? (r - 1) * TX + (c - 2) : (r - 2) * (TX + 1) + (c - 1);
+      const int ps = dy ? NYE : NXE;
+      T* om = (dy ? ym : xm) + o;
+      T* op = (dy ? yp : xp) + o;
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      xm[m][r - 2][e] = Dm[m];
-      xp[m][r - 2][e] = Dp[m];
+      for (int m = 0; m < 3; ++m) {
+        om[m * ps] = Dm[m];
+        op[m * ps] = Dp[m];
+      }
     }
-  };
-  auto y_edge = [&](int c, int r, int e) {
-    Face<T> La, Ra, Lb, Rb;
-    reconstruct(py(c, r - 1), py(c, r), py(c, r + 1), dry_eps, La, Ra);
-    reconstruct(py(c, r), py(c, r + 1), py(c, r + 2), dry_eps, Lb, Rb);
-    T Dm[3], Dp[3];
-    pvm(Ra, Lb, g, dry_eps, Dm, Dp);
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      ym[m][e][c - 2] = Dm[m];
-      yp[m][e][c - 2] = Dp[m];
-    }
-  };
-  const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;
-  const int cx = tx + 2, cy = ty + 2;  // the thread's cell in the region
-  x_edge(cx, cy, tx + 1);              // east edge
-  y_edge(cx, cy, ty + 1);              // north edge
-  if ((int)threadIdx.x < TY)           // west edges of the tile's rows
-    x_edge(1, (int)threadIdx.x + 2, 0);
-  else if ((int)threadIdx.x >= 64 && (int)threadIdx.x < 64 + TX)
-    y_edge((int)threadIdx.x - 64 + 2, 1, 0);  // south edges of its columns
+  }
   // the cell's own reconstructions for its volume terms
   Face<T> Lx, Rx, Ly, Ry;
-  reconstruct(px(cx - 1, cy), px(cx, cy), px(cx + 1, cy), dry_eps, Lx, Rx);
-  reconstruct(py(cx, cy - 1), py(cx, cy), py(cx, cy + 1), dry_eps, Ly, Ry);
+  {
+    const int q = cy * RX + cx;
+    reconstruct(prim_at(q - 1, pu, pv), prim_at(q, pu, pv),
+                prim_at(q + 1, pu, pv), dry_eps, Lx, Rx);
+    reconstruct(prim_at(q - RX, pv, pu), prim_at(q, pv, pu),
+                prim_at(q + RX, pv, pu), dry_eps, Ly, Ry);
+  }
   __syncthreads();
-  const int i = i0 + tx, j = j0 + ty;
   double clamp_local = 0.0;
-  if (i < nx && j < ny) {
-    const int n = j * nx + i;
-    const T h0 = ph[cy][cx], q10 = a.q1[n], q20 = a.q2[n];
+  if (own) {
+    const T h0 = ph[cy * RX + cx];
     // the stored value of the cell (FP64: h0 itself)
-    const T s0 = Store<T>::kEta ? a.h[n] : h0, Hc = a.H[n];
-    const T dt = (T)(*a.dtp);
+    if constexpr (!kS) s0 = h0;
     T Ix[3], Iy[3], fx[3], fy[3];
     interior(Lx, Rx, h0, g, Ix);
     interior(Ly, Ry, h0, g, Iy);
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-      fx[m] = (xm[m][ty][tx + 1] + xp[m][ty][tx]) + Ix[m];
-      fy[m] = (ym[m][ty + 1][tx] + yp[m][ty][tx]) + Iy[m];
+      fx[m] = (xm[m * NXE + ty * (TX + 1) + tx + 1] +
+               xp[m * NXE + ty * (TX + 1) + tx]) +
+              Ix[m];
+      fy[m] = (ym[m * NYE + (ty + 1) * TX + tx] + yp[m * NYE + ty * TX + tx]) +
+              Iy[m];
     }
     T hs = s0 - dt * (fx[0] / a.dx + fy[0] / a.dy);
     T qa = q10 - dt * (fx[1] / a.dx + fy[2] / a.dy);
@@ -741,7 +775,7 @@ template <typename T, bool ONE_D>
 __global__ void __launch_bounds__(kBlock) k_advect_w(AdvectWArgs<T> a) {
   const int nx = a.nx, ny = a.ny;
   const int ncx = nx + 1, ncy = ONE_D ? 1 : ny + 1;
-  const int n = blockIdx.x * kBlock + (int)threadIdx.x;
+  const int n = xcd_bid() * kBlock + (int)threadIdx.x;
   if (n >= ncx * ncy) return;
   const int k = n % ncx, l = n / ncx;
   CellLoader<T, ONE_D> ld{a.h, a.q1, a.q2, a.H, nx, ONE_D ? 1 : ny, a.open};
@@ -1791,51 +1825,55 @@ __device__ __forceinline__ int batch_grid(const int* __restrict__ prefix,
 
 template <typename T, bool ONE_D>
 __global__ void __launch_bounds__(kBlock) k_fv(FvArgs<T> a) {
-  fv_body<T, ONE_D>(a, (int)blockIdx.x);
+  fv_body<T, ONE_D>(a, xcd_bid());
 }
 template <typename T, bool ONE_D>
 __global__ void __launch_bounds__(kBlock)
     k_fv_batch(const FvArgs<T>* __restrict__ as, const int* __restrict__ pre,
                int ngrids) {
-  int g = batch_grid(pre, ngrids, (int)blockIdx.x);
-  fv_body<T, ONE_D>(as[g], (int)blockIdx.x - pre[g]);
+  const int bb = xcd_bid();
+  int g = batch_grid(pre, ngrids, bb);
+  fv_body<T, ONE_D>(as[g], bb - pre[g]);
 }
 
 template <typename T, bool ONE_D>
 __global__ void __launch_bounds__(kBlock) k_break_cells(BreakCellsArgs<T> a) {
-  break_cells_body<T, ONE_D>(a, (int)blockIdx.x);
+  break_cells_body<T, ONE_D>(a, xcd_bid());
 }
 template <typename T, bool ONE_D>
 __global__ void __launch_bounds__(kBlock)
     k_break_cells_batch(const BreakCellsArgs<T>* __restrict__ as,
                         const int* __restrict__ pre, int ngrids) {
-  int g = batch_grid(pre, ngrids, (int)blockIdx.x);
-  break_cells_body<T, ONE_D>(as[g], (int)blockIdx.x - pre[g]);
+  const int bb = xcd_bid();
+  int g = batch_grid(pre, ngrids, bb);
+  break_cells_body<T, ONE_D>(as[g], bb - pre[g]);
 }
 
 template <typename T, bool ONE_D>
 __global__ void __launch_bounds__(kBlock)
     k_break_corners(BreakCornersArgs<T> a) {
-  break_corners_body<T, ONE_D>(a, (int)blockIdx.x);
+  break_corners_body<T, ONE_D>(a, xcd_bid());
 }
 template <typename T, bool ONE_D>
 __global__ void __launch_bounds__(kBlock)
     k_break_corners_batch(const BreakCornersArgs<T>* __restrict__ as,
                           const int* __restrict__ pre, int ngrids) {
-  int g = batch_grid(pre, ngrids, (int)blockIdx.x);
-  break_corners_body<T, ONE_D>(as[g], (int)blockIdx.x - pre[g]);
+  const int bb = xcd_bid();
+  int g = batch_grid(pre, ngrids, bb);
+  break_corners_body<T, ONE_D>(as[g], bb - pre[g]);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_assemble2d(AssembleArgs<T> a) {
-  assemble2d_body<T>(a, (int)blockIdx.x);
+  assemble2d_body<T>(a, xcd_bid());
 }
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_assemble2d_batch(const AssembleArgs<T>* __restrict__ as,
                        const int* __restrict__ pre, int ngrids) {
-  int g = batch_grid(pre, ngrids, (int)blockIdx.x);
-  assemble2d_body<T>(as[g], (int)blockIdx.x - pre[g]);
+  const int bb = xcd_bid();
+  int g = batch_grid(pre, ngrids, bb);
+  assemble2d_body<T>(as[g], bb - pre[g]);
 }
 
 template <typename T, int B, int S, int M>
@@ -2043,7 +2081,7 @@ __global__ void __launch_bounds__(B)
   const int tile = (int)blockIdx.x;  // the grid has exactly ntiles groups
   const int tid = (int)threadIdx.x;
   const int tx = tile % ntx, ty = tile / ntx;
-  const int RW = BX + 2 * S, RH = BY + 2 * S, R = RW * RH;
+  const int RW = BX + 2 * S, RH = BY + 2 * S;
   // the relaxation schedule in LDS (the host keeps nom <= kPersistOmega)
   for (int i = tid; i < a.nom; i += B) om_s[i] = a.omega[i];
   const int x0 = tx * BX - S, y0 = ty * BY - S;
@@ -2306,7 +2344,7 @@ __global__ void __launch_bounds__(B)
 
 template <typename T, bool ONE_D, bool COMBINE>
 __global__ void __launch_bounds__(kBlock) k_correct(CorrectArgs<T> a) {
-  correct_body<T, ONE_D, COMBINE>(a, (int)blockIdx.x);
+  correct_body<T, ONE_D, COMBINE>(a, xcd_bid());
 }
 // batch: the pressure of member g is its logical iterate 0, buffer rot[g]
 template <typename T, bool ONE_D, bool COMBINE>
@@ -2315,22 +2353,24 @@ __global__ void __launch_bounds__(kBlock)
                     const int* __restrict__ pre, int ngrids,
                     const SweepArgs<T>* __restrict__ sw,
                     const EnsMember* __restrict__ mem) {
-  int g = batch_grid(pre, ngrids, (int)blockIdx.x);
+  const int bb = xcd_bid();
+  int g = batch_grid(pre, ngrids, bb);
   CorrectArgs<T> a = as[g];
   if (a.have_p) a.p = sw[g].p[mem[g].rot];
-  correct_body<T, ONE_D, COMBINE>(a, (int)blockIdx.x - pre[g]);
+  correct_body<T, ONE_D, COMBINE>(a, bb - pre[g]);
 }
 
 template <typename T, bool ONE_D>
 __global__ void __launch_bounds__(kBlock) k_lambda(LambdaArgs<T> a) {
-  lambda_body<T, ONE_D>(a, (int)blockIdx.x);
+  lambda_body<T, ONE_D>(a, xcd_bid());
 }
 template <typename T, bool ONE_D>
 __global__ void __launch_bounds__(kBlock)
     k_lambda_batch(const LambdaArgs<T>* __restrict__ as,
                    const int* __restrict__ pre, int ngrids) {
-  int g = batch_grid(pre, ngrids, (int)blockIdx.x);
-  lambda_body<T, ONE_D>(as[g], (int)blockIdx.x - pre[g]);
+  const int bb = xcd_bid();
+  int g = batch_grid(pre, ngrids, bb);
+  lambda_body<T, ONE_D>(as[g], bb - pre[g]);
 }
 
 __global__ void __launch_bounds__(kBlock) k_finalize_dt(FinalizeArgs a) {
