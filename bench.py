@@ -163,6 +163,34 @@ def sweep_roofline(pr, prec, kernel, traffic, copy_gbs):
             "timed_cycles": f"1 in {PROFILE_SAMPLE}"}
 
 
+def ens_solve_roofline(pr, prec, stats, corners):
+    """Roofline of the one-launch ensemble solve from the HIP-event timing of
+    the solves of one step in PROFILE_SAMPLE: the blocked algorithmic bytes
+    of its 8-sweep blocks (BLOCKED_BYTES_LAUNCH per corner and block; each
+    member's mean sweeps per solve over the run / 8 blocks) over the mean
+    solve time.  The sweep launches it replaces are priced the same way."""
+    n = max(1, pr["solve_kernel_launches"])
+    ms = pr["solve_kernel_ms"] / n
+    blocks = sum(c * s["sweeps_total"] / max(1, s["solves"]) / 8.0
+                 for c, s in zip(corners, stats))
+    alg = BLOCKED_BYTES_LAUNCH[prec] * blocks
+    sec = ms * 1e-3
+    achieved = alg / sec / 1e9 if sec > 0 else None
+    return {"bound": "hbm",
+            "achieved": round(achieved, 1) if achieved else None,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+            "traffic": None, "traffic_frac": None,
+            "kernel": "k_ens_solve", "avg_launch_us": round(ms * 1e3, 3),
+            "corner_blocks_per_launch": int(round(blocks)),
+            "alg_bytes_per_launch": int(alg),
+            "alg_basis": (f"{BLOCKED_BYTES_LAUNCH[prec]} B per corner per "
+                          "block of 8 sweeps (5 coefficients + rhs + iterate "
+                          "read, iterate written), the members' mean sweeps "
+                          "per solve"),
+            "timed_launches": f"both solves of 1 step in {PROFILE_SAMPLE}"}
+
+
 def copy_bandwidth():
     """Achievable HBM bandwidth: a 1 GiB device-to-device copy (1 GiB read +
     1 GiB written), best of 5, timed with events on torch's stream."""
@@ -409,7 +437,8 @@ def run_ensemble(args):
     cases = inputs.case_c4(precision=args.precision)
     steps = args.steps if args.steps_given else cases[0].steps
     stream = torch.cuda.current_stream()
-    e = Ensemble.from_cases(cases, stream=stream.cuda_stream)
+    e = Ensemble.from_cases(cases, stream=stream.cuda_stream,
+                            solve_path=getattr(args, "solve_path", 0))
     e.tune(3)
     e.run(args.warmup)
     for k, c in enumerate(cases):
@@ -448,9 +477,13 @@ def run_ensemble(args):
     phases = phase_split(e.get_profile(), nph)
     e.profile(False)
     e.close()
-    roof = sweep_roofline(pr, args.precision, "k_sweep_tb_batch",
-                          measured_traffic("c4", args.precision),
-                          getattr(args, "copy_gbs", None))
+    if pr["solve_kernel_launches"] > 0:
+        roof = ens_solve_roofline(pr, args.precision, stats,
+                                  [(c.nx + 1) * (c.ny + 1) for c in cases])
+    else:
+        roof = sweep_roofline(pr, args.precision, "k_sweep_tb_batch",
+                              measured_traffic("c4", args.precision),
+                              getattr(args, "copy_gbs", None))
     cpu = None if args.no_cpu else cpu_baseline(
         cases[:4], 4, "the first 4 scenarios of the ensemble")
     out = {

@@ -139,7 +139,15 @@ typedef struct {
                           else 1; 1 launches of 8 sweeps, the convergence
                           measure read back by the host at each check;
                           2 the cooperative launch, NH_EINVAL at create when
-                          the grid does not fit.  Ensembles ignore it */
+                          the grid does not fit.  Ensembles (all members
+                          alike): 0 and 1 launches of 8 sweeps over every
+                          member still active, the number of those read by
+                          the host at each check; 2 one cooperative launch
+                          per solve of all members (sweeps and checks as
+                          phases between grid barriers, the host takes no
+                          decision; at most 1024 members; NH_EINVAL at the
+                          first run where cooperative launches are not
+                          available).  The results are the same either way */
   int32_t solve_norm;  /* stop measure of a 2D relaxation solve: 0 the size
                           of a plain Jacobi update, max |(rhs - A p)/diag|
                           (eq. 32, solve_tol as stated above); 1 the
@@ -343,7 +351,9 @@ nh_status nh_adjoint_run(nh_solver *s, int64_t nsteps, int32_t ngauges,
  */
 typedef struct nh_ensemble nh_ensemble;
 
-/* grids[n], params[n] (copied).  Allocates every member's device memory. */
+/* grids[n], params[n] (copied).  Allocates every member's device memory.
+ * The members share precision, nh_on, breaking_on, solve_max_iter,
+ * check_every and solve_path (NH_EINVAL otherwise). */
 nh_status nh_ensemble_create(int32_t n, const nh_grid *grids,
                              const nh_params *params, void *hip_stream,
                              nh_ensemble **out);

@@ -5,10 +5,14 @@
 // kernels map their workgroups onto the members through per-kernel prefix
 // tables of workgroup counts, and every member runs exactly the arithmetic of
 // its single-grid launch.  The pressure solves of all members run in
-// lockstep relaxation cycles; k_ens_check decides on the device which
+// lockstep relaxation cycles; the checks decide on the device which
 // members leave at each convergence check, so the members' results and sweep
-// counts are those of their own single-grid solves.  Each member is an
-// nh_solver (its buffers, dt, statistics) bound to the ensemble's stream.
+// counts are those of their own single-grid solves.  A solve is launches of
+// 8 sweeps with the number of members still active read by the host at each
+// check, or (solve_path 2) one cooperative launch (k_ens_solve: sweeps and
+// checks as phases between grid barriers, no host decision inside).  Each
+// member is an nh_solver (its buffers, dt, statistics) bound to the
+// ensemble's stream.
 
 // ensemble slot in mapped host memory: sequence number of the last check,
 // members still active, per-member measures and active flags
@@ -26,6 +30,11 @@ struct nh_ensemble {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int nh_on = 1, breaking_on = 0, kmax = 0, check_every = 1;
+  int solve_path = 0;          // 2: one launch per solve; 0, 1: cycles
+  int persist_grid = 0;        // workgroups of the one-launch solve (0: none)
+  // one-launch solve: [0] barrier arrivals, [1] low word: flags, [2..9]
+  // item counters
+  unsigned long long* psync = nullptr;
   std::vector<nh_solver*> mem;
   std::vector<int> live;       // members in the batch tables (state set, ok)
   std::vector<char> failed;    // member stopped by an error
@@ -95,6 +104,48 @@ nh_status set_member_tile(nh_solver* m, int bx, int by) {
   m->tby = by;
   m->ntx = ntx;
   m->nty = nty;
+  return NH_OK;
+}
+
+template <typename T>
+const void* ens_persist_kernel(int m) {
+  if (m == nh::kSweepMBig)
+    return (const void*)nh::k_ens_solve<T, nh::kSweepB, nh::kSweepS,
+                                        nh::kSweepMBig>;
+  return (const void*)nh::k_ens_solve<T, nh::kSweepB, nh::kSweepS,
+                                      nh::kSweepM>;
+}
+
+// Workgroups of the one-launch solve (solve_path 2): as many as can be
+// co-resident (a multiple of 8, so that an item keeps its XCD), at most one
+// per item; 0 when the solve runs as launches of 8 sweeps.  The launches of
+// 8 sweeps stay the default: on the 64-member workload they are ~11 %
+// faster, the one launch reading the iterate at device scope (past the L2)
+// where the launches find the tiles' shared halos in L2.
+template <typename T>
+nh_status ens_persist_grid(nh_ensemble* e) {
+  e->persist_grid = 0;
+  if (e->solve_path != 2 || e->tot_sweep <= 0) return NH_OK;
+  if ((int)e->live.size() > nh::kEnsPersistMax)
+    return fail(NH_EINVAL, "solve_path 2: more than 1024 members");
+  int dev = 0, coop = 0, cus = 0, per_cu = 0;
+  const void* kern = ens_persist_kernel<T>(e->sweep_m);
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch,
+                            dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                            dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, kern, nh::kSweepB, e->sweep_lds) != hipSuccess) {
+    (void)hipGetLastError();
+    coop = 0;
+  }
+  const long cap = coop ? ((long)per_cu * cus) / 8 * 8 : 0;
+  if (cap < 8)
+    return fail(NH_EINVAL,
+                "solve_path 2: no cooperative launch of the ensemble solve "
+                "on this device");
+  e->persist_grid = (int)std::min<long>(cap, e->tot_sweep);
   return NH_OK;
 }
 
@@ -199,6 +250,8 @@ nh_status ens_build(nh_ensemble* e) {
   e->tot_asm = tot[3];
   e->tot_sweep = tot[4];
   e->tot_corr = tot[5];
+  nh_status ps = ens_persist_grid<T>(e);
+  if (ps != NH_OK) return ps;
   e->dirty = false;
   return NH_OK;
 }
@@ -252,7 +305,24 @@ nh_status ens_solve(nh_ensemble* e, int stage) {
   const int S = nh::kSweepS;
   const int kAhead = 1;
   hipLaunchKernelGGL(nh::k_ens_begin, dim3(1), dim3(256), 0, e->stream,
-                     e->dmem_live, L);
+                     e->dmem_live, L, e->persist_grid > 0 ? e->psync : nullptr);
+  if (e->persist_grid > 0) {
+    const auto* as = (const nh::SweepArgs<T>*)e->sweep;
+    const int* pre = e->pre_sweep;
+    nh::EnsMember* mem = e->dmem_live;
+    int Lm = L;
+    nh::EnsPersist P{kmax, ce, stage, e->psync, e->psync + 2,
+                     reinterpret_cast<int*>(e->psync + 1), 1LL << 21};
+    void* args[] = {(void*)&as, (void*)&pre, (void*)&Lm, (void*)&mem,
+                    (void*)&P};
+    long pm = e->prof.open(e->stream, 5);
+    HIP_TRY(hipLaunchCooperativeKernel(ens_persist_kernel<T>(e->sweep_m),
+                                       dim3(e->persist_grid),
+                                       dim3(nh::kSweepB), args, e->sweep_lds,
+                                       e->stream));
+    e->prof.close(e->stream, pm, 1);
+    return NH_OK;
+  }
   int k = 0, cur = 0;
   int* act = e->active_host;
   // launch table: every member for the first check, then the members still
@@ -385,6 +455,12 @@ nh_status ens_step(nh_ensemble* e) {
 // batch (its status is kept in member_status).
 nh_status ens_sync(nh_ensemble* e) {
   HIP_TRY(hipStreamSynchronize(e->stream));
+  int eflags = 0;
+  HIP_TRY(hipMemcpy(&eflags, e->psync + 1, sizeof(int), hipMemcpyDeviceToHost));
+  if (eflags & nh::kFlagWaitBound)
+    return fail(NH_EDEVICE,
+                "ensemble solve: a grid barrier wait gave up (workgroups not "
+                "co-resident)");
   std::vector<nh::EnsMember> rec(e->live.size());
   if (!rec.empty())
     HIP_TRY(hipMemcpy(rec.data(), e->dmem_live,
@@ -458,11 +534,12 @@ nh_status nh_ensemble_create(int32_t n, const nh_grid* grids,
     if (a.precision != b.precision || a.nh_on != b.nh_on ||
         a.breaking_on != b.breaking_on ||
         a.solve_max_iter != b.solve_max_iter ||
+        a.solve_path != b.solve_path ||
         (a.check_every > 0 ? a.check_every : 1) !=
             (b.check_every > 0 ? b.check_every : 1))
       return fail(NH_EINVAL,
                   "members must share precision, nh_on, breaking_on, "
-                  "solve_max_iter and check_every");
+                  "solve_max_iter, solve_path and check_every");
   }
   nh_ensemble* e = new nh_ensemble();
   e->n = n;
@@ -472,6 +549,7 @@ nh_status nh_ensemble_create(int32_t n, const nh_grid* grids,
   e->breaking_on = params[0].breaking_on;
   e->kmax = params[0].solve_max_iter;
   e->check_every = params[0].check_every > 0 ? params[0].check_every : 1;
+  e->solve_path = params[0].solve_path;
   if (hip_stream) {
     e->stream = (hipStream_t)hip_stream;
   } else {
@@ -485,7 +563,10 @@ nh_status nh_ensemble_create(int32_t n, const nh_grid* grids,
   e->member_status.assign(n, NH_OK);
   for (int k = 0; k < n; ++k) {
     nh_solver* m = nullptr;
-    nh_status st = nh_create(&grids[k], &params[k], e->stream, &m);
+    // the member's own solve path is never taken: the ensemble solves it
+    nh_params pk = params[k];
+    pk.solve_path = 1;
+    nh_status st = nh_create(&grids[k], &pk, e->stream, &m);
     if (st != NH_OK) {
       std::string msg = g_err;
       nh_ensemble_destroy(e);
@@ -503,7 +584,9 @@ nh_status nh_ensemble_create(int32_t n, const nh_grid* grids,
                     hipHostMallocMapped | hipHostMallocCoherent) !=
           hipSuccess ||
       hipHostGetDevicePointer((void**)&e->slot_dev, e->slot, 0) !=
-          hipSuccess) {
+          hipSuccess ||
+      hipMalloc((void**)&e->psync, 256) != hipSuccess ||
+      hipMemset(e->psync, 0, 256) != hipSuccess) {
     nh_ensemble_destroy(e);
     return fail(NH_ENOMEM, "allocation of the ensemble records failed");
   }
@@ -788,6 +871,7 @@ void nh_ensemble_destroy(nh_ensemble* e) {
   if (e->dmem) hipFree(e->dmem);
   if (e->dmem_live) hipFree(e->dmem_live);
   if (e->slot) hipHostFree(e->slot);
+  if (e->psync) hipFree(e->psync);
   e->prof.release();
   if (e->own_stream) hipStreamDestroy(e->stream);
   delete e;

@@ -1147,6 +1147,38 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+constexpr int kFlagWaitBound = 8;  // solver flags: a wait gave up
+constexpr int kPersistOmega = 256;  // schedule factors staged in LDS
+
+__device__ __forceinline__ unsigned long long ld_agent_u64(
+    unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent_u64(unsigned long long* p,
+                                             unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned ld_agent_u32(unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_agent(const double* p) {
+  auto* q = reinterpret_cast<unsigned long long*>(const_cast<double*>(p));
+  return __longlong_as_double((long long)ld_agent_u64(q));
+}
+__device__ __forceinline__ void st_agent(double* p, double v) {
+  st_agent_u64(reinterpret_cast<unsigned long long*>(p),
+               (unsigned long long)__double_as_longlong(v));
+}
+// this thread's memory operations have completed (and no memory access is
+// moved across by the compiler)
+__device__ __forceinline__ void wait_memory() {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+__device__ __forceinline__ bool gave_up(int* flags) {
+  return (__hip_atomic_load(flags, __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT) &
+          kFlagWaitBound) != 0;
+}
 // per-launch arguments (common to every grid of a batch)
 struct SweepLaunch {
   int iin, iout, isave;  // buffers read, written, saved (check launch)
@@ -1160,7 +1192,10 @@ struct SweepLaunch {
   long long seq;
 };
 
-template <typename T, int B, int S, int M>
+// COH: the iterate, the saved iterate and the per-tile measures are read and
+// written at device scope (coherent across the XCDs' L2s), for the solve
+// that runs its launches' work inside one kernel between grid barriers
+template <typename T, int B, int S, int M, bool COH = false>
 __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a,
                                            const SweepLaunch& L, int bid,
                                            double* lds) {
@@ -1211,10 +1246,17 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a,
       double pv = 0.0;
       if (gx >= 0 && gx < ncx && gy >= 0 && gy < ncy) {
         int g = gy * ncx + gx;
-        pv = pin[g];
+        if constexpr (COH)
+          pv = ld_agent(pin + g);
+        else
+          pv = pin[g];
         if (check && rx[m] >= S && rx[m] < S + BX && ry[m] >= S &&
-            ry[m] < S + BY && ux < ncx && uy < ncy)
-          psave[g] = pv;
+            ry[m] < S + BY && ux < ncx && uy < ncy) {
+          if constexpr (COH)
+            st_agent(psave + g, pv);
+          else
+            psave[g] = pv;
+        }
         dg[m] = dgl[g];
         ce[m] = cE[g];
         cw[m] = cW[g];
@@ -1275,8 +1317,12 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a,
       const int x = rx[m], y = ry[m];
       if (x >= S && x < S + BX && y >= S && y < S + BY) {
         int gx = x0 + x, gy = y0 + y;
-        if (gx < ncx && gy < ncy)
-          pout[gy * ncx + gx] = fin[(int)threadIdx.x + B * m];
+        if (gx < ncx && gy < ncy) {
+          if constexpr (COH)
+            st_agent(pout + gy * ncx + gx, fin[(int)threadIdx.x + B * m]);
+          else
+            pout[gy * ncx + gx] = fin[(int)threadIdx.x + B * m];
+        }
       }
     }
   }
@@ -1289,7 +1335,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a,
       double mx = wmax[0];
       for (int w = 1; w < B / 64; ++w)
         mx = (wmax[w] > mx || wmax[w] != wmax[w]) ? wmax[w] : mx;
-      a.part[tile] = mx;
+      if constexpr (COH)
+        st_agent(a.part + tile, mx);
+      else
+        a.part[tile] = mx;
     }
   }
 }
@@ -1718,15 +1767,111 @@ struct EnsMember {
   long long solves_total;
 };
 
-__global__ void k_ens_begin(EnsMember* __restrict__ mem, int n) {
+// every member takes part in the solve about to start; sync (or null): the
+// grid-barrier arrivals (sync[0]) and the 8 item counters (sync[2..9]) of a
+// one-launch ensemble solve start from 0
+__global__ void k_ens_begin(EnsMember* __restrict__ mem, int n,
+                            unsigned long long* sync) {
   for (int g = threadIdx.x; g < n; g += blockDim.x) mem[g].active = 1;
+  if (sync && threadIdx.x < 10 && threadIdx.x != 1) sync[threadIdx.x] = 0ull;
 }
 
-// Convergence check of every active member, one workgroup per member: the
-// max of its per-tile measures of the iterate p^kc; a member stops when it
-// is below its tolerance, when kc reached the sweep cap or when it is not
-// finite, and its saved iterate p^kc (logical buffer `save`) becomes logical
-// buffer 0.  The measure and the active flag go to mapped host memory.
+// Convergence check of one active member by one workgroup: the max of its
+// per-tile measures of the iterate p^kc; the member stops when it is below
+// its tolerance, when kc reached the sweep cap or when it is not finite, and
+// its saved iterate p^kc (logical buffer `save`) becomes logical buffer 0.
+// COH: every access to the measures and to the member's record is at device
+// scope (the one-launch ensemble solve, where other XCDs read them next).
+template <bool COH>
+__device__ __forceinline__ int ens_ld(int* p) {
+  if constexpr (COH)
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    return *p;
+}
+template <bool COH>
+__device__ __forceinline__ void ens_st(int* p, int v) {
+  if constexpr (COH)
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    *p = v;
+}
+template <bool COH>
+__device__ __forceinline__ long long ens_ld(long long* p) {
+  if constexpr (COH)
+    return (long long)ld_agent_u64(reinterpret_cast<unsigned long long*>(p));
+  else
+    return *p;
+}
+template <bool COH>
+__device__ __forceinline__ void ens_st(long long* p, long long v) {
+  if constexpr (COH)
+    st_agent_u64(reinterpret_cast<unsigned long long*>(p),
+                 (unsigned long long)v);
+  else
+    *p = v;
+}
+template <bool COH>
+__device__ __forceinline__ double ens_ld(double* p) {
+  if constexpr (COH)
+    return ld_agent(p);
+  else
+    return *p;
+}
+template <bool COH>
+__device__ __forceinline__ void ens_st(double* p, double v) {
+  if constexpr (COH)
+    st_agent(p, v);
+  else
+    *p = v;
+}
+
+template <typename T, bool COH>
+__device__ __forceinline__ void ens_check_body(const SweepArgs<T>& a,
+                                               EnsMember& m, int kc, int kmax,
+                                               int save, int stage,
+                                               double* E_host,
+                                               int* active_host, int g) {
+  const double* part = a.part;
+  const int nt = a.ntiles;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+    double x;
+    if constexpr (COH)
+      x = ld_agent(part + i);
+    else
+      x = part[i];
+    v = (x > v || x != x) ? x : v;
+  }
+  __shared__ double wmax[1024 / 64];  // any workgroup size
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    v = wmax[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+      v = (wmax[w] > v || wmax[w] != wmax[w]) ? wmax[w] : v;
+    const bool ok = v < ens_ld<COH>(&m.tol);
+    const bool stop = ok || kc >= kmax || !(v == v) || isinf(v);
+    if (stop) {
+      ens_st<COH>(&m.rot, (ens_ld<COH>(&m.rot) + save) % 3);
+      ens_st<COH>(&m.sweeps[stage], kc);
+      ens_st<COH>(&m.measure, v);
+      ens_st<COH>(&m.sweeps_total, ens_ld<COH>(&m.sweeps_total) + kc);
+      ens_st<COH>(&m.solves_total, ens_ld<COH>(&m.solves_total) + 1);
+      if (!ok) ens_st<COH>(&m.noconv, ens_ld<COH>(&m.noconv) + 1);
+      ens_st<COH>(&m.active, 0);
+    }
+    if (E_host) {
+      E_host[g] = v;
+      active_host[g] = stop ? 0 : 1;
+    }
+  }
+  __syncthreads();  // wmax is written again by the next check
+}
+
+// The check of every active member, one workgroup per member.  The measure
+// and the active flag go to mapped host memory.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_ens_check(const SweepArgs<T>* __restrict__ as,
@@ -1735,35 +1880,8 @@ __global__ void __launch_bounds__(kBlock)
                 int* __restrict__ active_host) {
   const int g = blockIdx.x;
   if (!mem[g].active) return;  // uniform over the workgroup
-  const double* part = as[g].part;
-  const int nt = as[g].ntiles;
-  double v = 0.0;
-  for (int i = threadIdx.x; i < nt; i += blockDim.x) {
-    double x = part[i];
-    v = (x > v || x != x) ? x : v;
-  }
-  __shared__ double wmax[kBlock / 64];
-  v = wave_max(v);
-  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  v = wmax[0];
-  for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
-    v = (wmax[w] > v || wmax[w] != wmax[w]) ? wmax[w] : v;
-  EnsMember& m = mem[g];
-  const bool ok = v < m.tol;
-  const bool stop = ok || kc >= kmax || !(v == v) || isinf(v);
-  if (stop) {
-    m.active = 0;
-    m.rot = (m.rot + save) % 3;
-    m.sweeps[stage] = kc;
-    m.measure = v;
-    m.sweeps_total += kc;
-    m.solves_total += 1;
-    if (!ok) m.noconv += 1;
-  }
-  E_host[g] = v;
-  active_host[g] = stop ? 0 : 1;
+  ens_check_body<T, false>(as[g], mem[g], kc, kmax, save, stage, E_host,
+                           active_host, g);
 }
 
 // After k_ens_check: the number of members still active goes to mapped host
@@ -1927,6 +2045,172 @@ __global__ void __launch_bounds__(B)
 }
 
 // -------------------------------------------------------------------------
+// The lockstep solve of an ensemble in one cooperative launch: the launches
+// of 8 sweeps over every member's tiles and the convergence checks between
+// them become phases of one kernel, separated by grid barriers, so that the
+// host takes no decision during a solve and a whole step is a fixed sequence
+// of launches.  Every phase does the work of the launch it replaces, in the
+// same order of blocks and checks, so that the members' iterates, sweep
+// counts and measures are the same to the bit:
+//   - a sweep phase: the workgroups take the (member, tile) items of the
+//     members still active, from a table of those members that every
+//     workgroup forms after each check.  Items are handed out as they are
+//     asked for (an atomic counter per XCD class: workgroup w takes items
+//     i = w mod 8 (mod 8), so that a tile keeps the XCD it has in the sweep
+//     launches), which keeps the workgroups busy to the end of the phase
+//     however the items' costs differ;
+//   - a check phase: one workgroup per member still active.
+// The iterate, the saved iterate, the per-tile measures and the member
+// records are read and written at device scope: a phase reads what other
+// XCDs wrote in the one before, once every workgroup has passed the barrier
+// between them.  A barrier counts arrivals in one 64-bit word (zeroed before
+// the launch); every wait is bounded and gives up through the flags word.
+// -------------------------------------------------------------------------
+struct EnsPersist {
+  int kmax, ce, stage;        // sweep cap, sweeps per check, stage
+  unsigned long long* bar;    // barrier arrivals (0 at the launch)
+  unsigned long long* items;  // 8 item counters (0 at the launch)
+  int* flags;                 // kFlagWaitBound when a wait gave up
+  long long bound;            // polls before a wait gives up
+};
+constexpr int kEnsPersistMax = 1024;  // members of a one-launch solve
+
+// two 1024-thread workgroups per CU, as the sweep launches have (64
+// registers per thread)
+template <typename T, int B, int S, int M>
+__global__ void __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(8, 8)))
+    k_ens_solve(const SweepArgs<T>* __restrict__ as,
+                const int* __restrict__ pre, int L,
+                EnsMember* __restrict__ mem, EnsPersist P) {
+  extern __shared__ double lds[];
+  // the members still active in order, the prefix of their items, and
+  // every member's buffer rotation (the table of a compacted launch)
+  __shared__ int s_ids[kEnsPersistMax], s_pre[kEnsPersistMax + 1];
+  __shared__ int s_rot[kEnsPersistMax];
+  __shared__ int s_give_up, s_nact, s_next;
+  const int G = (int)gridDim.x, tid = (int)threadIdx.x;
+  // this workgroup's XCD class and its item counter; every workgroup of a
+  // class makes exactly one grab past the end of each phase, so the class's
+  // counter advances by its items plus G / 8 per phase
+  const int xc = (int)blockIdx.x & 7;
+  unsigned long long* const ctr = P.items + xc;
+  unsigned long long cbase = 0;
+  auto grab = [&]() {
+    return __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+  };
+  if (tid == 0) s_give_up = 0;
+  unsigned long long nbar = 0;
+  // every workgroup's device-scope writes of the phase have completed
+  // before any workgroup reads them in the next one
+  auto barrier = [&]() {
+    wait_memory();
+    __syncthreads();
+    if (tid == 0) {
+      __hip_atomic_fetch_add(P.bar, 1ull, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned long long want = (nbar + 1) * (unsigned long long)G;
+      long long it = 0;
+      while (ld_agent_u64(P.bar) < want) {
+        if (++it > P.bound || ((it & 63) == 0 && gave_up(P.flags))) {
+          s_give_up = 1;
+          atomicOr(P.flags, kFlagWaitBound);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __syncthreads();
+    ++nbar;
+    return s_give_up == 0;
+  };
+  // the table, from the member records (every workgroup forms the same)
+  auto table = [&]() {
+    for (int g = tid; g < L; g += B) {
+      s_ids[g] = ens_ld<true>(&mem[g].active);
+      s_rot[g] = ens_ld<true>(&mem[g].rot);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int m = 0, acc = 0;
+      for (int g = 0; g < L; ++g) {
+        if (!s_ids[g]) continue;
+        s_ids[m] = g;  // m <= g: read before written
+        s_pre[m] = acc;
+        acc += pre[g + 1] - pre[g];
+        ++m;
+      }
+      s_pre[m] = acc;
+      s_nact = m;
+    }
+    __syncthreads();
+  };
+  // the items of the active members (the prefix holds multiples of 8: the
+  // items of a class are it = 8 j + xc, j < total / 8)
+  auto sweeps = [&](const SweepLaunch& Lc) {
+    const int nact = s_nact, total = s_pre[nact], per = total / 8;
+    if (tid == 0) s_next = (int)(grab() - cbase);
+    __syncthreads();
+    int j = s_next;
+    __syncthreads();
+    while (j < per) {
+      // the next item is asked for while this one is swept
+      unsigned long long nx = 0;
+      if (tid == 0) nx = grab();
+      const int it = 8 * j + xc;
+      int lo = 0, hi = nact - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_pre[mid] <= it) lo = mid; else hi = mid - 1;
+      }
+      const int g = s_ids[lo], r = s_rot[g];
+      SweepLaunch Lg = Lc;
+      Lg.iin = (Lc.iin + r) % 3;
+      Lg.iout = (Lc.iout + r) % 3;
+      Lg.isave = (Lc.isave + r) % 3;
+      sweep_body<T, B, S, M, true>(as[g], Lg, it - s_pre[lo], lds);
+      if (tid == 0) s_next = (int)(nx - cbase);
+      __syncthreads();  // the LDS planes are filled again by the next item
+      j = s_next;
+      __syncthreads();
+    }
+    cbase += (unsigned long long)(per + G / 8);
+  };
+  const int ce = P.ce, kmax = P.kmax, stage = P.stage;
+  int k = 0, cur = 0;
+  table();
+  for (;;) {
+    const int save = (cur + 2) % 3, out = (cur + 1) % 3;
+    const int kc = k;
+    const int nsw = k >= kmax ? 0 : min(min(S, ce), kmax - k);
+    sweeps(SweepLaunch{cur, out, save, k, nsw, 1, 0, nullptr, nullptr, 0});
+    if (!barrier()) return;
+    for (int i = (int)blockIdx.x; i < s_nact; i += G) {
+      const int g = s_ids[i];
+      ens_check_body<T, true>(as[g], mem[g], kc, kmax, save, stage, nullptr,
+                              nullptr, g);
+    }
+    if (!barrier()) return;
+    if (nsw > 0) {
+      cur = out;
+      k += nsw;
+    }
+    table();
+    if (s_nact == 0) return;  // every member has stopped
+    int other = 3 - cur - save;
+    while (k % ce != 0 && k < kmax) {
+      const int n2 = min(min(S, ce - k % ce), kmax - k);
+      sweeps(SweepLaunch{cur, other, other, k, n2, 0, 0, nullptr, nullptr, 0});
+      if (!barrier()) return;
+      const int t = cur;
+      cur = other;
+      other = t;
+      k += n2;
+    }
+  }
+}
+
+// -------------------------------------------------------------------------
 // A whole relaxation solve in one cooperative launch, for grids whose tiles
 // all fit the co-resident workgroups (one tile per workgroup).  The sweeps,
 // the schedule and the checks are those of k_sweep_tb and of the host loop
@@ -1970,9 +2254,11 @@ __global__ void __launch_bounds__(B)
 // give-up bit of another workgroup, sets that bit and ends its workgroup,
 // and the host reports the failed solve.
 // -------------------------------------------------------------------------
-constexpr int kFlagWaitBound = 8;  // solver flags: a wait gave up
-constexpr int kPersistOmega = 256;  // schedule factors staged in LDS
-
+// position of an unwrapped corner index on a periodic line of n corners
+__device__ __forceinline__ int cyc(int u, int n) {
+  const int r = u % n;
+  return r < 0 ? r + n : r;
+}
 struct PersistSync {
   unsigned long long* xch0;  // exchange buffers, 2 words per corner
   unsigned long long* xch1;
@@ -1992,40 +2278,6 @@ struct PersistLaunch {
   double tol;
 };
 
-__device__ __forceinline__ unsigned long long ld_agent_u64(
-    unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent_u64(unsigned long long* p,
-                                             unsigned long long v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned ld_agent_u32(unsigned* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double ld_agent(const double* p) {
-  auto* q = reinterpret_cast<unsigned long long*>(const_cast<double*>(p));
-  return __longlong_as_double((long long)ld_agent_u64(q));
-}
-__device__ __forceinline__ void st_agent(double* p, double v) {
-  st_agent_u64(reinterpret_cast<unsigned long long*>(p),
-               (unsigned long long)__double_as_longlong(v));
-}
-// this thread's memory operations have completed (and no memory access is
-// moved across by the compiler)
-__device__ __forceinline__ void wait_memory() {
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-}
-__device__ __forceinline__ bool gave_up(int* flags) {
-  return (__hip_atomic_load(flags, __ATOMIC_RELAXED,
-                            __HIP_MEMORY_SCOPE_AGENT) &
-          kFlagWaitBound) != 0;
-}
-// position of an unwrapped corner index on a periodic line of n corners
-__device__ __forceinline__ int cyc(int u, int n) {
-  const int r = u % n;
-  return r < 0 ? r + n : r;
-}
 // a value and its tag as the two words of the exchange
 __device__ __forceinline__ unsigned long long xword(unsigned tag,
                                                     unsigned half) {
