@@ -130,16 +130,23 @@ typedef struct {
                           pressure step.  Single grids only (ensembles and
                           the adjoint need 0) */
   int32_t solve_path;  /* how a 2D pressure solve is launched (the results
-                          are the same): 0 automatic -- one cooperative
-                          launch per solve when the grid's tiles fit the
-                          co-resident workgroups of the device (each keeps
-                          its tile's rows on chip for the whole solve and
-                          decides on convergence on the device; capped
-                          solves are then reported at the next status read),
-                          else 1; 1 launches of 8 sweeps, the convergence
-                          measure read back by the host at each check;
-                          2 the cooperative launch, NH_EINVAL at create when
-                          the grid does not fit.  Ensembles (all members
+                          are the same): 0 automatic -- one launch per solve
+                          when the grid's tiles fit the co-resident
+                          workgroups of the device (each keeps its tile's
+                          rows on chip for the whole solve and decides on
+                          convergence on the device; capped solves are then
+                          reported at the next status read), else 1.  That
+                          launch is a plain one of no more workgroups than
+                          the device holds at once; should other work on the
+                          device keep some of them waiting for longer than
+                          the solve's bounded waits (seconds), the run
+                          reports NH_EDEVICE;
+                          1 launches of 8 sweeps, the convergence measure
+                          read back by the host at each check;
+                          2 the one launch per solve as a cooperative launch
+                          (residency of every workgroup guaranteed by the
+                          runtime, ~20 us more per solve), NH_EINVAL at
+                          create when the grid does not fit.  Ensembles (all members
                           alike): 0 and 1 launches of 8 sweeps over every
                           member still active, the number of those read by
                           the host at each check; 2 one cooperative launch

@@ -2501,7 +2501,9 @@ __global__ void __launch_bounds__(B)
         v[m] = (upd && live) ? pn : pc;
       }
     };
-    for (int t = 0; t < iters; ++t) {
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      if (t >= iters) break;
       double* Lb = (t & 1) ? L1 : L0;
 #pragma unroll
       for (int m = 0; m < M; ++m) Lb[lbase + m * RW] = v[m];

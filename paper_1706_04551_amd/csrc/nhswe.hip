@@ -743,12 +743,23 @@ nh_status solve_persist(nh_solver* s, const SysView& V, int& pcur, double tol,
   nh::PersistSync Y{s->p_xch, s->p_xch + 2 * s->ncorn, s->p_bar,
                     s->p_slots, s->flags, s->dstats, 1LL << 21};
   void* args[] = {&a, &L, &Y};
-  hipError_t e = hipLaunchCooperativeKernel(
-      persist_kernel<T>(), dim3(a.ntiles), dim3(kPersistB), args,
-      (unsigned)s->plds, s->stream);
+  // solve_path 2 asks the runtime to guarantee that every workgroup is
+  // resident (a cooperative launch, ~20 us more per solve on the device's
+  // timeline); otherwise a plain launch of no more workgroups than the
+  // device holds at once: with the stream's earlier work complete they are
+  // all resident, and if other work on the device delays some, the waits
+  // of the others are bounded and the run reports NH_EDEVICE
+  hipError_t e =
+      s->par.solve_path == 2
+          ? hipLaunchCooperativeKernel(persist_kernel<T>(), dim3(a.ntiles),
+                                       dim3(kPersistB), args,
+                                       (unsigned)s->plds, s->stream)
+          : hipLaunchKernel(persist_kernel<T>(), dim3(a.ntiles),
+                            dim3(kPersistB), args, (unsigned)s->plds,
+                            s->stream);
   s->prof.close(s->stream, pk, 1);
   if (e != hipSuccess)
-    return fail(NH_EDEVICE, std::string("cooperative solve launch: ") +
+    return fail(NH_EDEVICE, std::string("one-launch solve: ") +
                                 hipGetErrorString(e));
   pcur = L.iout;
   s->solve_launches_last = 1;
@@ -861,7 +872,9 @@ nh_status sync_stats(nh_solver* s) {
     st = fail(NH_ESTATE, "no wet cell: the CFL time step is undefined");
   if (flags & nh::kFlagWaitBound && st == NH_OK)
     st = fail(NH_EDEVICE,
-              "one-launch solve: a wait between workgroups reached its bound");
+              "one-launch solve: a wait between workgroups reached its bound "
+              "(other work on the device kept some workgroups out; "
+              "solve_path 2 launches cooperatively)");
   if (st != NH_OK) {
     s->st.last_status = st;
     s->have_state = false;

@@ -77,6 +77,21 @@ def test_one_launch_equals_cycle_launches_fp64(n, island, kw):
     same_runs(c, 40, f"basin {n} island={island} {kw} f64")
 
 
+def test_plain_and_cooperative_one_launch_agree():
+    # solve_path 0 launches the one-launch solve plainly (no more
+    # workgroups than are co-resident), 2 cooperatively: the same kernel
+    c = basin(130)
+    say("[case] basin 130: solve_path 0 (plain launch) and 2 (cooperative)")
+    a = solver(c, 0)
+    b = solver(c, 2)
+    a.run(30)
+    b.run(30)
+    for k in FIELDS:
+        assert np.array_equal(a.state()[k], b.state()[k]), k
+    for k in ("t", "sweeps_total", "measure"):
+        assert a.stats()[k] == b.stats()[k], k
+
+
 def test_one_launch_equals_cycle_launches_fp32():
     c = basin(96, precision="f32")
     same_runs(c, 40, "basin 96 f32")
