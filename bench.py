@@ -45,6 +45,13 @@ ALG_BYTES_SWEEP = {"f64": 40, "f32": 20}   # per corner per sweep (matrix-free
 # is what a launch must move.
 BLOCKED_BYTES_LAUNCH = {"f64": 64, "f32": 40}
 FULL_STEP_BASE = {"f64": 384.0, "f32": 192.0}   # flux, assembly, correction
+# Compulsory bytes per cell of one adjoint step outside its transposed
+# solves: per stage the derivative kernels' arrays, each read or written once
+# (FP32 bulk: flux derivatives 48 + 64, pressure-row cotangents 104 + 92,
+# correction 32 + 44, transposed rows 32, scaled max 8, halvings 24, axpy 12 =
+# 460 B; FP64: 888 B), both stages, plus the forward stage re-evaluation of
+# the step (FULL_STEP_BASE).
+ADJ_STEP_BASE = {"f64": 2 * 888.0 + 384.0, "f32": 2 * 460.0 + 192.0}
 # One-launch solve (k_solve_persist): per corner and sweep the update reads
 # five LDS neighbours and writes one (48 B of LDS traffic) and does 13 FP64
 # flops (a product, four fused multiply-adds, a difference, a product with
@@ -590,8 +597,16 @@ def run_adjoint(args):
     phases = phase_split(s.get_profile(), nph)
     s.profile(False)
     s.close()
+    # compulsory bytes of one gradient step: the forward step twice (the run
+    # and the recomputation of its segments), the adjoint's derivative
+    # kernels, and its transposed solves (their sweeps counted by the library)
+    kbar_f = st["sweeps_total"] / max(1, st["solves"])
+    kbar_a = st["adjoint_sweeps"] / max(1, 2 * steps)
+    step_bytes = (2.0 * blocked_bytes_per_cell_step(kbar_f, args.precision) +
+                  ADJ_STEP_BASE[args.precision] +
+                  2.0 * kbar_a / 8.0 * BLOCKED_BYTES_LAUNCH[args.precision])
     grad_err = None
-    if args.precision == "f32":
+    if args.precision == "f32" and not getattr(args, "no_err", False):
         grad_err = adjoint_fp64_err(c, gauges, target, steps, ckpt, r)
     ncell = c.nx * c.ny
     value = ncell * steps / elapsed / 1e6
@@ -612,8 +627,12 @@ def run_adjoint(args):
                                 "recomputation + adjoint timed)"),
                    "cells": ncell, "J": r["J"],
                    "err_vs_fp64_gradient": grad_err,
-                   "forward_sweeps_per_solve": round(
-                       st["sweeps_total"] / max(1, st["solves"]), 2),
+                   "forward_sweeps_per_solve": round(kbar_f, 2),
+                   "adjoint_sweeps_per_solve": round(kbar_a, 2),
+                   "full_step_hbm_roofline_frac": round(
+                       c.nx * c.ny * steps * step_bytes / elapsed /
+                       (HBM_PEAK_GBS * 1e9), 4),
+                   "full_step_bytes_per_cell": round(step_bytes, 1),
                    "phase_ms_profiled_run": phases},
         "roofline": roof,
         "cpu_baseline": None,

@@ -189,6 +189,9 @@ typedef struct {
                            enforced: the paper checked dominance on its
                            cases, and steep free-surface curvature can lose
                            it).  FP32 bulk checks its FP32 rows */
+  int64_t adjoint_sweeps; /* relaxation sweeps of the transposed solves of
+                             the last nh_adjoint_run (both stages of every
+                             step; 0 before one) */
 } nh_stats;
 
 /* Per-phase device time (ms) accumulated between events on the solver's

@@ -52,7 +52,8 @@ class NhStats(C.Structure):
                 ("sweeps", C.c_int32 * 2), ("measure", C.c_double),
                 ("sweeps_total", C.c_int64), ("solves_total", C.c_int64),
                 ("clamped_mass", C.c_double), ("last_status", C.c_int32),
-                ("mass", C.c_double), ("nondominant", C.c_int64)]
+                ("mass", C.c_double), ("nondominant", C.c_int64),
+                ("adjoint_sweeps", C.c_int64)]
 
 
 class NhProfile(C.Structure):
@@ -189,7 +190,7 @@ def _stats_dict(s: "NhStats") -> dict:
                 sweeps1=s.sweeps[0], sweeps2=s.sweeps[1], measure=s.measure,
                 sweeps_total=s.sweeps_total, solves=s.solves_total,
                 clamped=s.clamped_mass, status=s.last_status, mass=s.mass,
-                nondominant=s.nondominant)
+                nondominant=s.nondominant, adjoint_sweeps=s.adjoint_sweeps)
 
 
 class Solver:

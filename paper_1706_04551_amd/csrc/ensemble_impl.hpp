@@ -840,6 +840,7 @@ nh_status nh_ensemble_get_stats(const nh_ensemble* e, int32_t k,
   if (st != NH_OK) return st;
   if (!out) return fail(NH_EINVAL, "null argument");
   *out = e->mem[k]->st;
+  out->adjoint_sweeps = 0;
   if (e->failed[k]) out->last_status = e->member_status[k];
   return NH_OK;
 }

@@ -443,15 +443,14 @@ __device__ __forceinline__ void fv_finish(T& ss, T Hc, T& qa, T& qb,
 }
 
 // The 2D stage on a tile of kFvTX x kFvTY cells: the primitive values of the
-// tile and of a halo of 2 cells are formed once into LDS; the tile's edges
-// (its (TX+1) x TY x-edges, then its TX x (TY+1) y-edges) are then spread
-// over the threads in rounds, each edge evaluated once by a routine that
-// takes the direction as data (no divergence between the two kinds), and
-// every edge's fluctuations go to both of its cells.  Each cell sums them
-// with its volume terms exactly as fv_cell does, so the result is the same
-// to the bit, with one evaluation of each edge and of each cell's primitive
-// values instead of two and five.  The last, partial round falls to one
-// wave, which one depends on the tile, so that the SIMDs of a CU share it.
+// tile and of a halo of 2 cells are formed once into LDS (the loads of the
+// halo and of the thread's own cell issued first); each thread then
+// evaluates the east and north edges of its cell (the tile's first column
+// and row also get their west and south edges), and every edge's
+// fluctuations go to both of its cells.  Each cell sums them with its volume
+// terms exactly as fv_cell does, so the result is the same to the bit, with
+// one evaluation of each edge and of each cell's primitive values instead of
+// two and five.
 template <typename T>
 __device__ __forceinline__ void fv_tile_body(const FvArgs<T>& a, int bid) {
   constexpr int TX = kFvTX, TY = kFvTY, RX = TX + 4, RY = TY + 4;
@@ -538,38 +537,45 @@ __device__ __forceinline__ void fv_tile_body(const FvArgs<T>& a, int bid) {
     }
     return p;
   };
-  {
-    const int rot = bid & 3;
-    const int slot = (tid + kBlock - 64 * rot) & (kBlock - 1);
-    for (int e = slot; e < NXE + NYE; e += kBlock) {
-      // x-edge: between region columns c and c + 1 of region row r, kept
-      // at index e of its tile row; y-edge: between region rows r and
-      // r + 1 of region column c, kept at index e of its tile column
-      const bool dy = e >= NXE;
-      const int f = dy ? e - NXE : e;
-      const int r = dy ? f / TX + 1 : f / (TX + 1) + 2;
-      const int c = dy ? f % TX + 2 : f % (TX + 1) + 1;
-      const int q = r * RX + c, st = dy ? RX : 1;
-      const T* un = dy ? pv : pu;
-      const T* ut = dy ? pu : pv;
-      Face<T> La, Ra, Lb, Rb;
-      reconstruct(prim_at(q - st, un, ut), prim_at(q, un, ut),
-                  prim_at(q + st, un, ut), dry_eps, La, Ra);
-      reconstruct(prim_at(q, un, ut), prim_at(q + st, un, ut),
-                  prim_at(q + 2 * st, un, ut), dry_eps, Lb, Rb);
-      T Dm[3], Dp[3];
-      pvm(Ra, Lb, g, dry_eps, Dm, Dp);
-      const int o = dy ? (r - 1) * TX + (c - 2) : (r - 2) * (TX + 1) + (c - 1);
-      const int ps = dy ? NYE : NXE;
-      T* om = (dy ? ym : xm) + o;
-      T* op = (dy ? yp : xp) + o;
+  // edge between region columns c and c + 1 of region row r (x), kept at
+  // index e of tile row r - 2; between region rows r and r + 1 of region
+  // column c (y), kept at index e of tile column c - 2
+  auto x_edge = [&](int c, int r, int e) {
+    Face<T> La, Ra, Lb, Rb;
+    const int q = r * RX + c;
+    reconstruct(prim_at(q - 1, pu, pv), prim_at(q, pu, pv),
+                prim_at(q + 1, pu, pv), dry_eps, La, Ra);
+    reconstruct(prim_at(q, pu, pv), prim_at(q + 1, pu, pv),
+                prim_at(q + 2, pu, pv), dry_eps, Lb, Rb);
+    T Dm[3], Dp[3];
+    pvm(Ra, Lb, g, dry_eps, Dm, Dp);
 #pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        om[m * ps] = Dm[m];
-        op[m * ps] = Dp[m];
-      }
+    for (int m = 0; m < 3; ++m) {
+      xm[m * NXE + (r - 2) * (TX + 1) + e] = Dm[m];
+      xp[m * NXE + (r - 2) * (TX + 1) + e] = Dp[m];
     }
-  }
+  };
+  auto y_edge = [&](int c, int r, int e) {
+    Face<T> La, Ra, Lb, Rb;
+    const int q = r * RX + c;
+    reconstruct(prim_at(q - RX, pv, pu), prim_at(q, pv, pu),
+                prim_at(q + RX, pv, pu), dry_eps, La, Ra);
+    reconstruct(prim_at(q, pv, pu), prim_at(q + RX, pv, pu),
+                prim_at(q + 2 * RX, pv, pu), dry_eps, Lb, Rb);
+    T Dm[3], Dp[3];
+    pvm(Ra, Lb, g, dry_eps, Dm, Dp);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      ym[m * NYE + e * TX + (c - 2)] = Dm[m];
+      yp[m * NYE + e * TX + (c - 2)] = Dp[m];
+    }
+  };
+  x_edge(cx, cy, tx + 1);  // east edge
+  y_edge(cx, cy, ty + 1);  // north edge
+  if (tid < TY)            // west edges of the tile's rows
+    x_edge(1, tid + 2, 0);
+  else if (tid >= 64 && tid < 64 + TX)
+    y_edge(tid - 64 + 2, 1, 0);  // south edges of its columns
   // the cell's own reconstructions for its volume terms
   Face<T> Lx, Rx, Ly, Ry;
   {

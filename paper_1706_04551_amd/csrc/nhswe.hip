@@ -1597,6 +1597,7 @@ nh_status nh_read_state(nh_solver* s, double* h, double* hu, double* hv,
 nh_status nh_get_stats(const nh_solver* s, nh_stats* out) {
   if (!s || !out) return fail(NH_EINVAL, "null argument");
   *out = s->st;
+  out->adjoint_sweeps = s->adj_sweeps_last;
   return NH_OK;
 }
 
