@@ -444,16 +444,22 @@ def run_ensemble(args):
     cases = inputs.case_c4(precision=args.precision)
     steps = args.steps if args.steps_given else cases[0].steps
     stream = torch.cuda.current_stream()
+    graph = getattr(args, "graph", False)
     e = Ensemble.from_cases(cases, stream=stream.cuda_stream,
-                            solve_path=getattr(args, "solve_path", 0))
+                            solve_path=2 if graph else
+                            getattr(args, "solve_path", 0))
     e.tune(3)
-    e.run(args.warmup)
+    run = e.run_graph if graph else e.run
+    run(args.warmup)
     for k, c in enumerate(cases):
         e.set_state(k, c.h, c.hu, c.hv)
+    if graph:
+        run(0)            # captures the step for the new tables
     torch.cuda.synchronize()
-    e.profile(PROFILE_SAMPLE)
+    # a graph replays without the timing events of the profile
+    e.profile(False if graph else PROFILE_SAMPLE)
     t0 = time.perf_counter()
-    e.run(steps)
+    run(steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     pr = e.get_profile()
@@ -484,7 +490,9 @@ def run_ensemble(args):
     phases = phase_split(e.get_profile(), nph)
     e.profile(False)
     e.close()
-    if pr["solve_kernel_launches"] > 0:
+    if graph:
+        roof = None       # no timing events inside a graph replay
+    elif pr["solve_kernel_launches"] > 0:
         roof = ens_solve_roofline(pr, args.precision, stats,
                                   [(c.nx + 1) * (c.ny + 1) for c in cases])
     else:
@@ -504,6 +512,11 @@ def run_ensemble(args):
                                 f"{args.precision.upper()} bulk, Jacobi+SRJ(64) "
                                 f"tol={cases[0].solve_tol:g}, tuned tiles"),
                    "cells": ncell, "members": len(cases), "steps": steps,
+                   "solve_form": ("one launch per solve, each step replayed "
+                                  "from a HIP graph" if graph else
+                                  "one cooperative launch per solve"
+                                  if getattr(args, "solve_path", 0) == 2
+                                  else "launches of 8 sweeps"),
                    "mean_sweeps_per_solve": round(kbar, 2),
                    "members_failed": sum(1 for s in stats if s["status"] != 0),
                    "min_sim_time_s": round(min(s["t"] for s in stats), 3),
@@ -894,6 +907,9 @@ def main():
     ap.add_argument("--zones", type=float, default=None,
                     help="width [m] of absorbing relaxation zones on every "
                          "wall (default none)")
+    ap.add_argument("--graph", action="store_true",
+                    help="c4: one-launch solves, each step replayed from a "
+                         "HIP graph (nh_ensemble_run_graph)")
     ap.add_argument("--solve-path", type=int, default=0, choices=[0, 1, 2],
                     help="launch form of the pressure solve: 0 automatic, 1 "
                          "launches of 8 sweeps, 2 one cooperative launch")

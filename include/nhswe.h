@@ -392,6 +392,17 @@ nh_status nh_ensemble_tune(nh_ensemble *e, int32_t reps);
  * the first status of a member that failed (the others still completed the
  * steps). */
 nh_status nh_ensemble_run(nh_ensemble *e, int64_t nsteps);
+/* As nh_ensemble_run, for an ensemble whose solves are one launch each
+ * (solve_path 2): a step is then a fixed sequence of launches that waits for
+ * nothing on the host, captured once into a HIP graph (again after the
+ * members' tables change) and replayed nsteps times on the ensemble's
+ * stream, with the statuses read every 64 steps.  The solves in the graph
+ * are plain launches of no more workgroups than the device holds at once
+ * (graphs take no cooperative launch); their waits are bounded.  Results
+ * equal nh_ensemble_run's to the bit.  NH_EINVAL for other solve paths or
+ * while profiling; a member that fails stops the replay at the next status
+ * read. */
+nh_status nh_ensemble_run_graph(nh_ensemble *e, int64_t nsteps);
 nh_status nh_ensemble_read_state(nh_ensemble *e, int32_t member, double *h,
                                  double *hu, double *hv, double *w, double *p);
 /* Member statistics as of the end of the last run.  last_status is the

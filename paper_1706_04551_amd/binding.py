@@ -116,6 +116,7 @@ def lib():
                                            C.POINTER(i32)]
         L.nh_ensemble_tune.argtypes = [vp, i32]
         L.nh_ensemble_run.argtypes = [vp, C.c_int64]
+        L.nh_ensemble_run_graph.argtypes = [vp, C.c_int64]
         L.nh_ensemble_read_state.argtypes = [vp, i32, _DP, _DP, _DP, _DP,
                                              _DP]
         L.nh_ensemble_get_stats.argtypes = [vp, i32, C.POINTER(NhStats)]
@@ -135,6 +136,7 @@ def lib():
                   "nh_ensemble_set_bathymetry", "nh_ensemble_set_state",
                   "nh_ensemble_set_tile", "nh_ensemble_get_tile",
                   "nh_ensemble_tune", "nh_ensemble_run",
+                  "nh_ensemble_run_graph",
                   "nh_ensemble_read_state", "nh_ensemble_get_stats",
                   "nh_ensemble_profile", "nh_ensemble_get_profile",
                   "nh_run_noalloc"):
@@ -429,6 +431,11 @@ class Ensemble:
 
     def run_status(self, n: int) -> int:
         return lib().nh_ensemble_run(self._h, int(n))
+
+    def run_graph(self, n: int):
+        """n steps replayed from a graph of one step (solve_path 2)."""
+        _check(lib().nh_ensemble_run_graph(self._h, int(n)),
+               "nh_ensemble_run_graph")
 
     def state(self, k):
         sh, cs = self.shapes[k], self.cshapes[k]

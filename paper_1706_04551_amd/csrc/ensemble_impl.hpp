@@ -35,6 +35,10 @@ struct nh_ensemble {
   // one-launch solve: [0] barrier arrivals, [1] low word: flags, [2..9]
   // item counters
   unsigned long long* psync = nullptr;
+  // graph of one step (nh_ensemble_run_graph), captured for the current
+  // tables; the solves inside are plain launches (capturing)
+  hipGraphExec_t step_graph = nullptr;
+  bool capturing = false;
   std::vector<nh_solver*> mem;
   std::vector<int> live;       // members in the batch tables (state set, ok)
   std::vector<char> failed;    // member stopped by an error
@@ -153,6 +157,10 @@ nh_status ens_persist_grid(nh_ensemble* e) {
 template <typename T>
 nh_status ens_build(nh_ensemble* e) {
   const int L = (int)e->live.size();
+  if (e->step_graph) {  // captured with the tables about to be replaced
+    HIP_TRY(hipGraphExecDestroy(e->step_graph));
+    e->step_graph = nullptr;
+  }
   std::vector<nh::FvArgs<T>> fv[2];
   std::vector<nh::BreakCellsArgs<T>> brc[2];
   std::vector<nh::BreakCornersArgs<T>> brk[2];
@@ -316,10 +324,17 @@ nh_status ens_solve(nh_ensemble* e, int stage) {
     void* args[] = {(void*)&as, (void*)&pre, (void*)&Lm, (void*)&mem,
                     (void*)&P};
     long pm = e->prof.open(e->stream, 5);
-    HIP_TRY(hipLaunchCooperativeKernel(ens_persist_kernel<T>(e->sweep_m),
-                                       dim3(e->persist_grid),
-                                       dim3(nh::kSweepB), args, e->sweep_lds,
-                                       e->stream));
+    // a graph takes the solve as a plain launch of the same workgroups (no
+    // more than are co-resident; the waits are bounded)
+    if (e->capturing)
+      HIP_TRY(hipLaunchKernel(ens_persist_kernel<T>(e->sweep_m),
+                              dim3(e->persist_grid), dim3(nh::kSweepB), args,
+                              e->sweep_lds, e->stream));
+    else
+      HIP_TRY(hipLaunchCooperativeKernel(ens_persist_kernel<T>(e->sweep_m),
+                                         dim3(e->persist_grid),
+                                         dim3(nh::kSweepB), args,
+                                         e->sweep_lds, e->stream));
     e->prof.close(e->stream, pm, 1);
     return NH_OK;
   }
@@ -822,6 +837,67 @@ nh_status nh_ensemble_run(nh_ensemble* e, int64_t nsteps) {
   return NH_OK;
 }
 
+nh_status nh_ensemble_run_graph(nh_ensemble* e, int64_t nsteps) {
+  if (!e) return fail(NH_EINVAL, "null ensemble");
+  if (nsteps < 0) return fail(NH_EINVAL, "nsteps < 0");
+  if (e->solve_path != 2)
+    return fail(NH_EINVAL,
+                "graph replay needs one-launch solves (solve_path 2)");
+  if (e->prof.on)
+    return fail(NH_EINVAL, "graph replay runs without profiling");
+  if (e->live.empty()) return fail(NH_ESTATE, "no member has a valid state");
+  for (int id : e->live)
+    if (!(e->mem[id]->st.dt_next > 0))
+      return fail(NH_ESTATE, "member " + std::to_string(id) +
+                                 ": dt is not positive");
+  nh_status st;
+  if (e->dirty) {
+    st = e->fp32 ? ens_build<float>(e) : ens_build<double>(e);
+    if (st != NH_OK) return st;
+  }
+  if ((st = ens_gather(e, true)) != NH_OK) return st;
+  if (!e->step_graph) {
+    // one step as a graph: every launch of ens_step, none of which waits
+    // for the host with one-launch solves
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    HIP_TRY(hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal));
+    e->capturing = true;
+    st = e->fp32 ? ens_step<float>(e) : ens_step<double>(e);
+    e->capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(e->stream, &g);
+    if (st != NH_OK) {
+      if (g) hipGraphDestroy(g);
+      return st;
+    }
+    if (ce != hipSuccess || !g)
+      return fail(NH_EDEVICE, std::string("step capture: ") +
+                                  hipGetErrorString(ce));
+    const hipError_t ie =
+        hipGraphInstantiate(&e->step_graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+      e->step_graph = nullptr;
+      return fail(NH_EDEVICE, std::string("step graph: ") +
+                                  hipGetErrorString(ie));
+    }
+  }
+  const int64_t kStatusEvery = 64;
+  nh_status worst = NH_OK;
+  for (int64_t n = 0; n < nsteps; ++n) {
+    HIP_TRY(hipGraphLaunch(e->step_graph, e->stream));
+    if ((n + 1) % kStatusEvery == 0 || n + 1 == nsteps) {
+      nh_status ss = ens_sync(e);
+      if (ss != NH_OK && worst == NH_OK) worst = ss;
+      if (e->dirty) break;  // a member failed: the tables change
+    }
+  }
+  if ((st = ens_gather(e, false)) != NH_OK) return st;
+  HIP_TRY(hipStreamSynchronize(e->stream));
+  if (worst != NH_OK) return fail(worst, "a member failed (see its stats)");
+  return NH_OK;
+}
+
 nh_status nh_ensemble_read_state(nh_ensemble* e, int32_t k, double* h,
                                  double* hu, double* hv, double* w,
                                  double* p) {
@@ -873,6 +949,7 @@ void nh_ensemble_destroy(nh_ensemble* e) {
   if (e->dmem_live) hipFree(e->dmem_live);
   if (e->slot) hipHostFree(e->slot);
   if (e->psync) hipFree(e->psync);
+  if (e->step_graph) hipGraphExecDestroy(e->step_graph);
   e->prof.release();
   if (e->own_stream) hipStreamDestroy(e->stream);
   delete e;

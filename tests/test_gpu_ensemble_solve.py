@@ -134,3 +134,37 @@ def test_solve_path_is_shared_by_the_members():
         params.append(kw)
     with pytest.raises(NhError):
         Ensemble(grids, params)
+
+
+def test_graph_replay_equals_run():
+    # with one-launch solves a step waits for nothing on the host: captured
+    # once into a graph and replayed, it gives nh_ensemble_run's results
+    from paper_1706_04551_amd import Ensemble, NhError
+    cases = members("f64", (64, 97, 80))
+    cases[1].solve_tol = 1e-9
+    say("[ensemble solve] graph replay of 3 members, 70 steps (a status "
+        "read inside), solve_path 2")
+    a = Ensemble.from_cases(cases, solve_path=2)
+    b = Ensemble.from_cases(cases, solve_path=2)
+    a.run(70)
+    b.run_graph(30)
+    b.run_graph(40)                       # the same graph, replayed again
+    for k in range(len(cases)):
+        for f in FIELDS:
+            assert np.array_equal(a.state(k)[f], b.state(k)[f]), (k, f)
+        for key in KEYS:
+            assert a.stats(k)[key] == b.stats(k)[key], (k, key)
+    # a new state rebuilds the tables, and the graph with them
+    c = cases[0]
+    a.set_state(0, c.h, c.hu, c.hv)
+    b.set_state(0, c.h, c.hu, c.hv)
+    a.run(5)
+    b.run_graph(5)
+    for f in FIELDS:
+        assert np.array_equal(a.state(0)[f], b.state(0)[f]), f
+    a.close()
+    b.close()
+    e = Ensemble.from_cases(cases[:1], solve_path=1)
+    with pytest.raises(NhError):
+        e.run_graph(1)
+    e.close()
