@@ -570,8 +570,14 @@ def adjoint_fp64_err(c, gauges, target, steps, ckpt, r32):
     base = eta0 + 0.02 * (inputs.gaussian_field(
         rng, c64.nx, c64.ny, c64.nx * c64.dx, c64.ny * c64.dx, xc, xc, 6) -
         0.5)
-    out["off_kinks_base"] = diffs(run("f32", base, 1e-6),
-                                  run("f64", base, 1e-10))
+    g64 = run("f64", base, 1e-10)
+    out["off_kinks_base"] = diffs(run("f32", base, 1e-6), g64)
+    # the FP64 gradient's own change under seeded +-5e-8 m of noise in eta0
+    # (about one FP32 rounding of the surface): dJ/deta0 is ill-conditioned
+    # at that scale wherever the limiters' two slopes nearly tie
+    noise = 1e-7 * (np.random.default_rng(7).random(base.shape) - 0.5)
+    out["fp64_change_under_5e-8m_noise"] = diffs(run("f64", base + noise,
+                                                     1e-10), g64)
     out["reference"] = ("the FP64 adjoint of the same run (solve tolerance "
                         "1e-10, transposed solves 1e-10)")
     return out
