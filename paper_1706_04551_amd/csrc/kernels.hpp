@@ -2290,14 +2290,26 @@ __device__ __forceinline__ unsigned long long xword(unsigned tag,
   return ((unsigned long long)tag << 32) | half;
 }
 
-// places of one LDS plane of the one-launch solve: RW per row, M rows for
-// every RW threads (and for the threads past the last full row)
-__host__ __device__ constexpr int persist_plane(int B, int M, int RW) {
-  return (B / RW + 1) * M * RW;
+// LDS planes of the one-launch solve.  The RW threads of a thread row hold
+// M region rows of RW places; consecutive thread rows are a pitch apart
+// that is congruent to RW modulo 32 places (256 bytes, one pass of the LDS
+// banks), so that the lanes of a wave that run from the end of one thread
+// row into the next read consecutive banks as lanes within a row do.
+__host__ __device__ constexpr int persist_pitch(int M, int RW) {
+  return M * RW + (((RW - M * RW) % 32) + 32) % 32;
 }
-// LDS bytes of the one-launch solve: two padded FP64 planes
+// places before a plane's first thread row: the point below it is read
+__host__ __device__ constexpr int persist_front(int M, int RW) {
+  return persist_pitch(M, RW) - (M - 1) * RW + 1;
+}
+// places of one plane: the thread rows of all B threads, the point above
+// the last one and the padding before the first
+__host__ __device__ constexpr int persist_plane(int B, int M, int RW) {
+  return persist_front(M, RW) + (B / RW + 1) * persist_pitch(M, RW) + RW + 1;
+}
+// LDS bytes of the one-launch solve: two FP64 planes
 __host__ __device__ constexpr long persist_lds_bytes(int B, int M, int RW) {
-  return 2L * 8 * (persist_plane(B, M, RW) + 2 * (RW + 1));
+  return 2L * 8 * persist_plane(B, M, RW);
 }
 
 // The exchange buffers through a buffer resource: a corner's two words
@@ -2352,13 +2364,13 @@ __global__ void __launch_bounds__(B)
   const int nseg = (RH + M - 1) / M;
   const int cx = tid % RW, ys = (tid / RW) * M;
   const bool active = tid < RW * nseg;
-  // two LDS planes: rows of RW places for every thread's points (rows past
-  // the region included), padded by RW + 1 places on both sides so that
-  // the neighbours of any point are inside
-  const int PL = persist_plane(B, M, RW);
-  double* L0 = lds + RW + 1;
-  double* L1 = lds + PL + 3 * (RW + 1);
-  const int lbase = ys * RW + cx;
+  // two LDS planes: the thread rows' M region rows of RW places each, a
+  // bank-aligned pitch apart (rows past the region included), padded so
+  // that the neighbours of any point are inside
+  const int PT = persist_pitch(M, RW), PL = persist_plane(B, M, RW);
+  double* L0 = lds + persist_front(M, RW);
+  double* L1 = L0 + PL;
+  const int lbase = (tid / RW) * PT + cx;
   if (tid == 0) give_up = 0;
   const unsigned base = ld_agent_u32(Y.blocks);
   const unsigned cbase = ld_agent_u32(Y.blocks + 1);
@@ -2471,8 +2483,9 @@ __global__ void __launch_bounds__(B)
         pE[m] = Lb[lbase + m * RW + 1];
         pW[m] = Lb[lbase + m * RW - 1];
       }
-      const double pTop = Lb[lbase + M * RW];
-      double below = Lb[lbase - RW];  // the input value of the point below
+      const double pTop = Lb[lbase + PT];  // the next thread row's first
+      // the input value of the point below: the previous thread row's last
+      double below = Lb[lbase - PT + (M - 1) * RW];
 #pragma unroll
       for (int m = 0; m < M; ++m) {
         const double pc = v[m];
