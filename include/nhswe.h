@@ -162,6 +162,13 @@ typedef struct {
                           absolute one when rhs = 0).  Single grids through
                           nh_create only (ensembles, the adjoint and
                           nh_run_noalloc need 0) */
+  int32_t wait_polls;  /* polls of a wait between the workgroups of a
+                          one-launch solve (single grid or ensemble) before
+                          it gives up and the run reports NH_EDEVICE at its
+                          next status read: 0 the default, 2^21 (seconds);
+                          negative: every such wait gives up at once, which
+                          exercises that path (tests).  An ensemble takes
+                          its first member's */
 } nh_params;
 
 typedef struct {

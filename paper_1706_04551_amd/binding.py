@@ -38,7 +38,8 @@ class NhParams(C.Structure):
                 ("fixed_dt", C.c_int32), ("dt", C.c_double),
                 ("manning", C.c_double), ("open_sides", C.c_int32),
                 ("periodic", C.c_int32), ("w_advection", C.c_int32),
-                ("solve_path", C.c_int32), ("solve_norm", C.c_int32)]
+                ("solve_path", C.c_int32), ("solve_norm", C.c_int32),
+                ("wait_polls", C.c_int32)]
 
 
 class NhDeviceViews(C.Structure):
@@ -173,7 +174,7 @@ def _params(*, g=9.81, cfl=0.9, delta=1e-5, dry_eps=1e-10, precision="f64",
             nh_on=1, breaking_on=0, b1=0.15, b2=0.5, solve_max_iter=200000,
             check_every=1, solve_tol=1e-10, omega=None, fixed_dt=0,
             dt_fixed=0.0, manning=0.0, open_sides=0, periodic=0,
-            w_advection=0, solve_path=0, solve_norm=0):
+            w_advection=0, solve_path=0, solve_norm=0, wait_polls=0):
     """nh_params and the relaxation schedule array it points to (the caller
     keeps the array alive until the create call returns)."""
     om = None if omega is None else np.ascontiguousarray(
@@ -183,7 +184,7 @@ def _params(*, g=9.81, cfl=0.9, delta=1e-5, dry_eps=1e-10, precision="f64",
                    solve_max_iter, check_every, solve_tol, _ptr(om),
                    0 if om is None else len(om), fixed_dt, dt_fixed,
                    manning, open_sides, periodic, w_advection, solve_path,
-                   solve_norm)
+                   solve_norm, wait_polls)
     return par, om
 
 

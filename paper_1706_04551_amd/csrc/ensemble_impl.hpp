@@ -31,6 +31,7 @@ struct nh_ensemble {
   bool own_stream = false;
   int nh_on = 1, breaking_on = 0, kmax = 0, check_every = 1;
   int solve_path = 0;          // 2: one launch per solve; 0, 1: cycles
+  int wait_polls = 0;          // of the one-launch solve's waits
   int persist_grid = 0;        // workgroups of the one-launch solve (0: none)
   // one-launch solve: [0] barrier arrivals, [1] low word: flags, [2..9]
   // item counters
@@ -320,7 +321,8 @@ nh_status ens_solve(nh_ensemble* e, int stage) {
     nh::EnsMember* mem = e->dmem_live;
     int Lm = L;
     nh::EnsPersist P{kmax, ce, stage, e->psync, e->psync + 2,
-                     reinterpret_cast<int*>(e->psync + 1), 1LL << 21};
+                     reinterpret_cast<int*>(e->psync + 1),
+                     wait_bound(e->wait_polls)};
     void* args[] = {(void*)&as, (void*)&pre, (void*)&Lm, (void*)&mem,
                     (void*)&P};
     long pm = e->prof.open(e->stream, 5);
@@ -565,6 +567,7 @@ nh_status nh_ensemble_create(int32_t n, const nh_grid* grids,
   e->kmax = params[0].solve_max_iter;
   e->check_every = params[0].check_every > 0 ? params[0].check_every : 1;
   e->solve_path = params[0].solve_path;
+  e->wait_polls = params[0].wait_polls;
   if (hip_stream) {
     e->stream = (hipStream_t)hip_stream;
   } else {

@@ -2117,7 +2117,8 @@ __global__ void __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(8, 8)))
                              __HIP_MEMORY_SCOPE_AGENT);
       const unsigned long long want = (nbar + 1) * (unsigned long long)G;
       long long it = 0;
-      while (ld_agent_u64(P.bar) < want) {
+      // (a negative bound gives up at once: the host asks for that path)
+      while (ld_agent_u64(P.bar) < want || P.bound < 0) {
         if (++it > P.bound || ((it & 63) == 0 && gave_up(P.flags))) {
           s_give_up = 1;
           atomicOr(P.flags, kFlagWaitBound);
@@ -2452,7 +2453,7 @@ __global__ void __launch_bounds__(B)
       for (int m = 0; m < M; ++m) {
         if (pk[m] >= 0 && (pk[m] & kPkRing)) {
           long long it = 0;
-          while (w[m].y != want || w[m].w != want) {
+          while (w[m].y != want || w[m].w != want || Y.bound < 0) {
             if (++it > Y.bound || ((it & 63) == 0 && gave_up(Y.flags))) {
               give_up = 1;
               break;
@@ -2567,7 +2568,8 @@ __global__ void __launch_bounds__(B)
         unsigned long long w0 = ld_agent_u64(sl + 2 * i);
         unsigned long long w1 = ld_agent_u64(sl + 2 * i + 1);
         long long it = 0;
-        while ((unsigned)(w0 >> 32) != want || (unsigned)(w1 >> 32) != want) {
+        while ((unsigned)(w0 >> 32) != want || (unsigned)(w1 >> 32) != want ||
+               Y.bound < 0) {
           if (++it > Y.bound || ((it & 63) == 0 && gave_up(Y.flags))) {
             give_up = 1;
             break;

@@ -725,6 +725,11 @@ const void* persist_kernel() {
 // its iterate in buffer `pcur`, which receives the buffer of the result.  The
 // host does not wait: the sweep count and the measure go to the device
 // statistics, a capped solve to their count of such solves.
+// polls before a wait between workgroups gives up (negative: at once)
+long long wait_bound(int32_t wait_polls) {
+  return wait_polls == 0 ? (1LL << 21) : (long long)wait_polls;
+}
+
 template <typename T>
 nh_status solve_persist(nh_solver* s, const SysView& V, int& pcur, double tol,
                         int stage) {
@@ -739,9 +744,10 @@ nh_status solve_persist(nh_solver* s, const SysView& V, int& pcur, double tol,
   nh::PersistLaunch L{pcur, (pcur + 1) % 3, s->par.solve_max_iter, ce,
                       stage, pk >= 0 ? 1 : 0, tol};
   // a wait gives up after ~2^21 polls (seconds; a block of sweeps takes
-  // microseconds)
+  // microseconds), or at once for a negative wait_polls
   nh::PersistSync Y{s->p_xch, s->p_xch + 2 * s->ncorn, s->p_bar,
-                    s->p_slots, s->flags, s->dstats, 1LL << 21};
+                    s->p_slots, s->flags, s->dstats,
+                    wait_bound(s->par.wait_polls)};
   void* args[] = {&a, &L, &Y};
   // solve_path 2 asks the runtime to guarantee that every workgroup is
   // resident (a cooperative launch, ~20 us more per solve on the device's

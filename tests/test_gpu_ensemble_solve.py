@@ -168,3 +168,23 @@ def test_graph_replay_equals_run():
     with pytest.raises(NhError):
         e.run_graph(1)
     e.close()
+
+
+def test_a_wait_that_gives_up_ends_the_ensemble_run():
+    # wait_polls < 0: every grid-barrier wait of the one-launch ensemble
+    # solve gives up at once; the run reports NH_EDEVICE, eagerly and from
+    # a graph replay, and a new ensemble runs
+    from paper_1706_04551_amd import Ensemble, NhError
+    cases = members("f64", (64, 72))
+    say("[ensemble solve] forced give-up of the grid barriers")
+    e = Ensemble.from_cases(cases, solve_path=2, wait_polls=-1)
+    assert e.run_status(2) == -3
+    e.close()
+    e = Ensemble.from_cases(cases, solve_path=2, wait_polls=-1)
+    with pytest.raises(NhError) as x:
+        e.run_graph(2)
+    assert x.value.status == -3
+    e.close()
+    ok = Ensemble.from_cases(cases, solve_path=2)
+    assert ok.run_status(2) == 0
+    ok.close()

@@ -252,3 +252,20 @@ def test_relative_residual_stop_is_refused_where_not_built():
     s = solver(c, 0)
     with pytest.raises(NhError):
         s.adjoint(2, [5], np.zeros((2, 1)), ckpt_every=1)
+
+
+@pytest.mark.parametrize("path", [0, 2])
+def test_a_wait_that_gives_up_ends_the_run(path):
+    # wait_polls < 0 makes every wait between workgroups give up at once:
+    # every workgroup leaves the launch, the run reports NH_EDEVICE at its
+    # next status read and the solver refuses further steps; the device
+    # stays usable
+    c = basin(64)
+    say(f"[case] forced give-up of the one-launch solve, solve_path {path}")
+    s = solver(c, path, wait_polls=-1)
+    assert s.run_status(3) == -3
+    assert s.run_status(1) == -8
+    s.close()
+    ok = solver(c, path)
+    assert ok.run_status(3) == 0
+    ok.close()
