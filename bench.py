@@ -272,12 +272,15 @@ def kernel_source_hash() -> str:
         k = fh.read()
     a = k.index("constexpr int kSweepB")
     b = k.index("// correction (eq. 26-27")
-    c = k.index("// A whole relaxation solve in one cooperative launch")
+    c = k.index("// A whole relaxation solve in one launch")
     d = k.index("k_correct(CorrectArgs<T> a)")
     with open(KERNEL_SOURCES[1]) as fh:
         host = fh.read()
     tiles = "".join(re.findall(r"s->tb[xy] = \d+;", host))
-    return hashlib.sha256((k[a:b] + k[c:d] + tiles).encode()).hexdigest()[:16]
+    # the code only: comments may change without new counter runs
+    code = re.sub(r"//[^\n]*", "", k[a:b] + k[c:d])
+    code = re.sub(r"\s+", " ", code)
+    return hashlib.sha256((code + tiles).encode()).hexdigest()[:16]
 
 
 def measured_traffic(workload_name: str, prec: str, kernel="k_sweep_tb"):

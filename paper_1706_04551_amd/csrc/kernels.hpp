@@ -2218,8 +2218,9 @@ __global__ void __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(8, 8)))
 }
 
 // -------------------------------------------------------------------------
-// A whole relaxation solve in one cooperative launch, for grids whose tiles
-// all fit the co-resident workgroups (one tile per workgroup).  The sweeps,
+// A whole relaxation solve in one launch, for grids whose tiles all fit
+// the co-resident workgroups (one tile per workgroup; launched with no more
+// workgroups than the device holds at once, cooperatively on request).  The sweeps,
 // the schedule and the checks are those of k_sweep_tb and of the host loop
 // that drives it: the same update of every corner in the same order of
 // operations, blocks of sweeps cut at every check and at the sweep cap, and
