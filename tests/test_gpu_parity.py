@@ -261,6 +261,40 @@ def test_c2_full_workload_1000_steps_fp64_vs_stored_oracle():
         assert np.array_equal(g[k][::st, ::st], ref[k]), k
 
 
+def test_c2_full_workload_every_value_equals_the_oracle():
+    """The benchmark's workload (512^2 FP64, default launch form) against
+    SHA-256 digests of the oracle's whole state -- every cell of h, hu, hv
+    and every corner of w and p -- after 250 and 1000 steps, written by
+    tests/golden/make_c2_digest.py from the oracle alone."""
+    import hashlib
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden",
+                        "c2_512_f64_digests.json")
+    if not os.path.exists(path):
+        pytest.skip("digests not generated")
+    with open(path) as fh:
+        ref = json.load(fh)
+
+    def digest(a):
+        return hashlib.sha256(
+            np.ascontiguousarray(a, dtype="<f8").tobytes()).hexdigest()
+    c = I.case_c2(precision="f64")
+    say("[case] c2 512x512 f64: digests of the whole state at "
+        f"{ref['steps']} steps")
+    s = gpu_solver(c)
+    done = 0
+    for n in ref["steps"]:
+        s.run(n - done)
+        done = n
+        g = s.state()
+        got = {k: digest(g[k]) for k in ("h", "hu", "hv", "w", "p")}
+        bad = [k for k, v in got.items() if v != ref["sha256"][str(n)][k]]
+        say(f"  step {n}: {'every value equal' if not bad else bad}")
+        assert not bad, (n, bad)
+        assert s.stats()["t"] == ref["t"][str(n)]
+
+
 def test_c2_full_workload_fp32_vs_stored_oracle():
     """FP32 bulk on the workload as stated (512^2, dry island, 1000 steps)
     against the oracle run with its FP32 configuration
