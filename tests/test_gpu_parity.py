@@ -261,28 +261,31 @@ def test_c2_full_workload_1000_steps_fp64_vs_stored_oracle():
         assert np.array_equal(g[k][::st, ::st], ref[k]), k
 
 
-def test_c2_full_workload_every_value_equals_the_oracle():
-    """The benchmark's workload (512^2 FP64, default launch form) against
-    SHA-256 digests of the oracle's whole state -- every cell of h, hu, hv
-    and every corner of w and p -- after 250 and 1000 steps, written by
+@pytest.mark.parametrize("path", [0, 1, 2])
+def test_c2_full_workload_every_value_equals_the_oracle(path):
+    """The benchmark's workload (512^2 FP64) in each launch form of the
+    solve (0: one plain launch per solve, the benchmark's; 1: launches of 8
+    sweeps; 2: one cooperative launch) against SHA-256 digests of the
+    oracle's whole state -- every cell of h, hu, hv and every corner of w
+    and p -- after 250 and 1000 steps, written by
     tests/golden/make_c2_digest.py from the oracle alone."""
     import hashlib
     import json
     import os
-    path = os.path.join(os.path.dirname(__file__), "golden",
-                        "c2_512_f64_digests.json")
-    if not os.path.exists(path):
+    fname = os.path.join(os.path.dirname(__file__), "golden",
+                         "c2_512_f64_digests.json")
+    if not os.path.exists(fname):
         pytest.skip("digests not generated")
-    with open(path) as fh:
+    with open(fname) as fh:
         ref = json.load(fh)
 
     def digest(a):
         return hashlib.sha256(
             np.ascontiguousarray(a, dtype="<f8").tobytes()).hexdigest()
     c = I.case_c2(precision="f64")
-    say("[case] c2 512x512 f64: digests of the whole state at "
-        f"{ref['steps']} steps")
-    s = gpu_solver(c)
+    say(f"[case] c2 512x512 f64, solve_path {path}: digests of the whole "
+        f"state at {ref['steps']} steps")
+    s = gpu_solver(c, solve_path=path)
     done = 0
     for n in ref["steps"]:
         s.run(n - done)
