@@ -876,6 +876,7 @@ def run_single(args):
 def variant_summary(out):
     """The figures of a variant run, for the headline line."""
     cfg = out["config"]
+    roof = out["roofline"] or {}   # none for a graph replay (no events)
     return {"workload": cfg["workload"], "value": out["value"],
             "unit": out["unit"], "dtype": out["dtype"], "steps": out["steps"],
             "ms_per_step": out["ms_per_step"],
@@ -884,14 +885,15 @@ def variant_summary(out):
             "full_step_hbm_roofline_frac": cfg.get("full_step_hbm_roofline_frac"),
             "full_step_per_sweep_model_GBps": cfg.get(
                 "full_step_per_sweep_model_GBps"),
-            "sweep_roofline_frac": out["roofline"]["frac"],
-            "sweep_traffic_frac": out["roofline"]["traffic_frac"],
-            "sweep_kernel": out["roofline"]["kernel"],
-            "sweep_avg_launch_us": out["roofline"]["avg_launch_us"],
+            "sweep_roofline_frac": roof.get("frac"),
+            "sweep_traffic_frac": roof.get("traffic_frac"),
+            "sweep_kernel": roof.get("kernel"),
+            "sweep_avg_launch_us": roof.get("avg_launch_us"),
             **{k: cfg[k] for k in ("oracle_err", "err_vs_fp64_gradient",
                                    "members_failed", "min_sim_time_s",
                                    "sim_time_s", "time_to_t_end_s",
-                                   "paper_table2_s", "paper_hardware")
+                                   "paper_table2_s", "paper_hardware",
+                                   "solve_form")
                if k in cfg}}
 
 
@@ -1011,6 +1013,14 @@ def main():
             v.steps, v.steps_given = None, False
             variants["c4_ensemble_fp32"] = variant_summary(run_ensemble(v))
             note("c4 ensemble done")
+            # the same workload with each solve one persistent launch over
+            # all members and each step replayed from a HIP graph
+            v = copy.copy(args)
+            v.workload, v.precision, v.no_cpu = "c4", "f32", True
+            v.steps, v.steps_given, v.graph = None, False, True
+            variants["c4_ensemble_fp32_one_launch_graph"] = variant_summary(
+                run_ensemble(v))
+            note("c4 ensemble (graph) done")
             v = copy.copy(args)
             v.workload, v.precision, v.no_cpu, v.warmup = "c5", "f32", True, 0
             v.steps, v.steps_given = None, False
