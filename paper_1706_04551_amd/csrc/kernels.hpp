@@ -834,8 +834,15 @@ struct AssembleArgs {
   T *diag, *cE, *cW, *cN, *cS, *rhs;
   int open;  // open sides (kOpen*)
   unsigned* nondom;  // count of rows not strictly dominant (or null)
-  __host__ __device__ int nblocks() const { return ((nx + 1) * (ny + 1) + kBlock - 1) / kBlock; }
+  // one workgroup per tile of kAsmTX x kAsmTY corners
+  __host__ __device__ int nblocks() const;
 };
+constexpr int kAsmTX = 32, kAsmTY = 8;
+static_assert(kAsmTX * kAsmTY == kBlock, "one thread per tile corner");
+template <typename T>
+__host__ __device__ int AssembleArgs<T>::nblocks() const {
+  return ((nx + 1 + kAsmTX - 1) / kAsmTX) * ((ny + 1 + kAsmTY - 1) / kAsmTY);
+}
 
 // the Gershgorin check of Section 5 on one assembled row, in FP64 with the
 // absolute values summed E, W, N, S
@@ -910,18 +917,46 @@ __device__ __forceinline__ void assemble_row(const LD& ld, int k, int l, int nx,
   row[5] = r;
 }
 
+// The rows of a tile of kAsmTX x kAsmTY corners: the (mirrored) cells the
+// tile's rows read -- those around its corners and their neighbours, a
+// block of (TX + 3) x (TY + 3) -- are loaded once into LDS, and every corner
+// forms its row from them with assemble_row, as from the bulk arrays.
 template <typename T>
 __device__ __forceinline__ void assemble2d_body(const AssembleArgs<T>& a,
                                                 int bid) {
+  constexpr int TX = kAsmTX, TY = kAsmTY, RX = TX + 3, RY = TY + 3;
+  __shared__ T ch[RY * RX], cq1[RY * RX], cq2[RY * RX], cs[RY * RX],
+      cH[RY * RX];
   const int nx = a.nx, ny = a.ny;
-  int ncx = nx + 1, ncy = ny + 1;
-  const int n = bid * kBlock + (int)threadIdx.x;
-  if (n >= ncx * ncy) return;
-  int k = n % ncx, l = n / ncx;
-  T dt = (T)(*a.dtp);
-  CellLoader<T, false> ld{a.h, a.q1, a.q2, a.H, nx, ny, a.open};
+  const int ncx = nx + 1, ncy = ny + 1;
+  const int tpx = (ncx + TX - 1) / TX;
+  const int k0 = (bid % tpx) * TX, l0 = (bid / tpx) * TY;
+  const int tid = (int)threadIdx.x;
+  const int k = k0 + tid % TX, l = l0 + tid / TX;
+  const bool own = k < ncx && l < ncy;
+  const int n = l * ncx + k;
+  const T wc = own ? a.w[n] : T(0);
+  const T dt = (T)(*a.dtp);
+  for (int r = tid; r < RX * RY; r += kBlock) {
+    const int i = k0 - 2 + r % RX, j = l0 - 2 + r / RX;
+    Cell<T> c{T(0), T(0), T(0), T(0), T(0), T(0)};
+    if (i <= nx + 1 && j <= ny + 1)  // the cells a row reads
+      c = load_cell(a.h, a.q1, a.q2, a.H, i, j, nx, ny, false, a.open);
+    ch[r] = c.h;
+    cq1[r] = c.q1;
+    cq2[r] = c.q2;
+    cs[r] = c.s;
+    cH[r] = c.H;
+  }
+  __syncthreads();
+  if (!own) return;
+  // the staged cell at grid position (i, j) (eta is not read by the row)
+  auto ld = [&](int i, int j) {
+    const int r = (j - l0 + 2) * RX + (i - k0 + 2);
+    return Cell<T>{ch[r], cq1[r], cq2[r], cH[r], T(0), cs[r]};
+  };
   T row[6];
-  assemble_row<T>(ld, k, l, nx, ny, a.dx, a.dy, a.w[n], dt, row, a.open);
+  assemble_row<T>(ld, k, l, nx, ny, a.dx, a.dy, wc, dt, row, a.open);
   a.diag[n] = row[0];
   a.cE[n] = row[1];
   a.cW[n] = row[2];
